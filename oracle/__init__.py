@@ -1,0 +1,30 @@
+"""FP64 CPU oracle for the multiscale spectral multigrid solve path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product path (the
+HIP library and its Python binding) never imports, links or executes it, and
+this package imports nothing from the product path.
+
+Each module follows the paper (arXiv 2403.19342) step by step, in float64,
+with plain NumPy/SciPy building blocks and no blocking or fusion:
+
+  assembly   Section 2.2: harmonic-mean transmissibilities, the TPFA matrix A
+             obtained by velocity elimination, the weight S = diag(tr K~).
+  spectral   Section 3: local generalized eigenproblems (eq. spepb) on the
+             coarse elements, their restriction to the coarse space for the
+             coarser levels (eq. spectral cc), the Galerkin chain.
+  smoothers  Section 5: block-Jacobi smoothers with incomplete Cholesky blocks.
+  vcycle     Algorithm 1 (three-grid iteration) applied recursively, with the
+             pseudo-inverse at the coarsest level.
+  pcg        Preconditioned conjugate gradients around the V-cycle.
+  dense      Brute-force dense references for tiny grids.
+"""
+from .assembly import Grid, transmissibilities, assemble, weight_diag, neumann_local
+from .spectral import Hierarchy, build_hierarchy, cluster_cut
+from .vcycle import Preconditioner
+from .pcg import pcg
+
+__all__ = [
+    "Grid", "transmissibilities", "assemble", "weight_diag", "neumann_local",
+    "Hierarchy", "build_hierarchy", "cluster_cut", "Preconditioner", "pcg",
+]
