@@ -1,0 +1,156 @@
+/*
+ * specmg: multiscale spectral multigrid preconditioned CG for the TPFA
+ * pressure system of Darcy flow on a 3D Cartesian grid (arXiv 2403.19342),
+ * implemented with hand-written HIP kernels for gfx950 (MI355X).
+ *
+ * Problem (Section 2): -div(K grad p) = f in the unit box with no-flow
+ * boundaries, K = kappa I, discretised by lowest-order Raviart-Thomas
+ * elements with trapezoidal quadrature; eliminating the velocity gives the
+ * symmetric positive semidefinite system A p = f (eq. p), a 7-point stencil
+ * whose face coefficients are harmonic means of kappa/h^2 (eq. discrete
+ * varia and fig. kappa edge).  The source must have zero sum and the
+ * returned pressure has zero mean (Section 2.1, space W).
+ *
+ * Conventions shared by every entry point:
+ *  - Cell vectors are float64 arrays of nx*ny*nz values, index
+ *    i + nx*(j + ny*k) (x fastest), resident in device memory and owned by
+ *    the caller; the library never frees or retains them past the call.
+ *  - `stream` is a hipStream_t (may be NULL for the null stream).  Work is
+ *    enqueued on it; calls return after the work they enqueued is complete
+ *    unless stated otherwise.
+ *  - Every int-returning call returns SPECMG_OK (0) or a negative error
+ *    code; specmg_last_error() then holds a message for the calling thread.
+ *    A context stays usable after SPECMG_ENOCONV and SPECMG_EBREAKDOWN.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef SPECMG_H
+#define SPECMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPECMG_OK 0
+#define SPECMG_EINVAL (-1)       /* bad sizes, options or pointers          */
+#define SPECMG_EINVAL_PERM (-2)  /* permeability not positive and finite    */
+#define SPECMG_ERHS (-3)         /* |sum f| > 1e-12 sum |f| (no compatible source) */
+#define SPECMG_ENOCONV (-4)      /* max_iter reached; x holds the last iterate */
+#define SPECMG_EBREAKDOWN (-5)   /* p^T A p <= 0 or not finite in CG        */
+#define SPECMG_EEIG (-6)         /* a local eigensolve did not converge     */
+#define SPECMG_EFACT (-7)        /* a smoother pivot or the coarsest factor is not SPD */
+#define SPECMG_EDEVICE (-8)      /* HIP runtime error                       */
+
+#define SPECMG_FP64 0            /* every level in float64                  */
+#define SPECMG_FP32_VCYCLE 1     /* V-cycle in float32, CG and coarsest in float64 */
+
+#define SPECMG_WS_NONE 0         /* cold-started local eigensolves          */
+#define SPECMG_WS_CNN 1          /* warm starts predicted by the 3D CNN     */
+
+typedef struct specmg_ctx specmg_ctx;
+
+/* Grid: nx, ny, nz cells with spacings hx, hy, hz (Section 5 uses the unit
+ * cube, h = 1/N).  `sub` is the edge of the level-2 elements in cells (the
+ * coarse grid T_c; only 8 is supported), `agg` the number of level-l
+ * elements per axis in one level-(l+1) element (2 or 4).  Each of nx, ny, nz
+ * must be divisible by sub * agg^(levels-2). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double hx, hy, hz;
+    int32_t sub;
+    int32_t agg;
+} specmg_grid;
+
+/* Options.  levels >= 2 is the number of grids (Algorithm 1 has three);
+ * eigs_per_subdomain is the target count of eigenvectors kept per element at
+ * every coarse level (strategy 1 of Section 5), grown or shrunk by at most 3
+ * so that no cluster of equal eigenvalues is split (relative gap
+ * cluster_rtol).  nu is the number of smoothing sweeps (only 1, the paper's
+ * value, is supported).  eig_tol is the residual tolerance of the local
+ * eigensolves relative to the spectral radius of the local pencil. */
+typedef struct {
+    int32_t levels;
+    int32_t eigs_per_subdomain;
+    int32_t nu;
+    int32_t precision;       /* SPECMG_FP64 or SPECMG_FP32_VCYCLE */
+    int32_t warm_start;      /* SPECMG_WS_NONE or SPECMG_WS_CNN   */
+    const void* cnn_weights; /* device pointer to the CNN parameter blob (WS_CNN only) */
+    double eig_tol;          /* default 1e-12 when <= 0 */
+    double cluster_rtol;     /* default 1e-6 when <= 0  */
+    double ws_resid_tol;     /* default 1e-3 when <= 0: warm starts with a larger
+                                Rayleigh-quotient residual fall back to the cold solve */
+} specmg_opts;
+
+/* Outcome of a solve.  iters counts products A p (one per CG iteration). */
+typedef struct {
+    int32_t iters;
+    int32_t converged;
+    double rel_resid;        /* recursive ||r|| / ||b|| at exit        */
+    double rel_resid_true;   /* ||b - A x|| / ||b|| of the returned x  */
+    double setup_ms;         /* wall time of specmg_setup               */
+    double solve_ms;         /* wall time of this solve                 */
+    int32_t n_levels;
+    int32_t dims[8];         /* dims[0] = n, dims[l-1] = dim W_l        */
+    int32_t eig_unconverged; /* local eigensolves that hit the cycle cap */
+    int32_t ws_fallbacks;    /* warm starts rejected by the residual test */
+    int32_t replacements;    /* true-residual replacements in CG        */
+} specmg_solve_info;
+
+/* Set-up phase (Section 3 and Section 5): harmonic-mean transmissibilities,
+ * local spectral problems on every element of every coarse level (eq. spepb,
+ * eq. spectral cc), Galerkin coarse operators A_{l+1} = R A_l R^T, IC(0)
+ * and block-IC(0) smoother factors, and the factored coarsest operator.
+ * perm_dev: device float64 array of kappa, nx*ny*nz values (perm_components
+ * must be 1: isotropic K = kappa I).  Read during the call only.
+ * On success *out receives a new context, released with specmg_destroy.
+ * Errors: SPECMG_EINVAL, SPECMG_EINVAL_PERM, SPECMG_EEIG (context still
+ * returned; info reports the count), SPECMG_EFACT, SPECMG_EDEVICE. */
+int specmg_setup(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
+                 const specmg_opts* opts, void* stream, specmg_ctx** out);
+
+/* One application of the preconditioner, z = P^{-1} r: Algorithm 1 applied
+ * recursively (pre-smooth, restrict, coarse map, prolong, post-smooth) with
+ * the pseudo-inverse at the coarsest level.  r_dev, z_dev: device float64
+ * cell vectors (must not alias).  Asynchronous: returns once enqueued. */
+int specmg_apply_precond(specmg_ctx* ctx, const double* r_dev, double* z_dev, void* stream);
+
+/* Preconditioned CG on A x = rhs to ||b - A x|| <= tol ||b||.  rhs_dev must
+ * sum to zero (SPECMG_ERHS otherwise).  x_dev: in: initial guess when
+ * use_x0 != 0, out: solution shifted to zero mean.  info may be NULL.
+ * Errors: SPECMG_ERHS, SPECMG_EINVAL (tol <= 0, max_iter < 1),
+ * SPECMG_ENOCONV, SPECMG_EBREAKDOWN, SPECMG_EDEVICE. */
+int specmg_pcg_solve(specmg_ctx* ctx, const double* rhs_dev, double* x_dev, int32_t use_x0,
+                     double tol, int32_t max_iter, specmg_solve_info* info, void* stream);
+
+/* y = A x with the fine TPFA operator (eq. p).  Asynchronous. */
+int specmg_apply_operator(specmg_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
+
+/* Set-up information: dims[l-1] = dim W_l for l = 1..levels, the element
+ * counts per level, and the padded per-element width Lmax (the target count
+ * plus 3).  Arrays must hold 8 entries. */
+int specmg_get_info(specmg_ctx* ctx, int32_t* levels, int32_t* dims, int32_t* elems,
+                    int32_t* lmax, specmg_solve_info* setup_info);
+
+/* Copy one set-up array of coarse level `level` (2..levels) to host memory,
+ * for inspection and tests.  `which`:
+ *   0 nkeep   int32  [m]
+ *   1 lambda  float64 [m][Lmax]       ascending local eigenvalues (padded with 0)
+ *   2 basis   float64 level 2: [m][Lmax][512] columns of R_c^T per element,
+ *             S-normalised; level >= 3: [m][Lmax][agg^3*Lmax] columns of R^T
+ *   3 Adiag   float64 [m][Lmax][Lmax] diagonal blocks of A_l
+ *   4 Aoff    float64 [m][3][Lmax][Lmax] blocks A_l(e, e + x|y|z)
+ * `bytes` must equal the array size; returns SPECMG_EINVAL otherwise. */
+int specmg_copy_level(specmg_ctx* ctx, int32_t level, int32_t which, void* host_dst, size_t bytes);
+
+/* Releases every device and host resource of the context (NULL is a no-op). */
+void specmg_destroy(specmg_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* specmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,219 @@
+// Internal declarations shared by the specmg HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace specmg {
+
+constexpr int kSub = 8;             // level-2 element edge in cells
+constexpr int kSub3 = 512;          // cells per level-2 element
+constexpr int kPlanes = 22;         // hyperplanes i+j+k = s in an 8^3 block
+constexpr int kMaxRedBlocks = 262144;
+
+// ---------------------------------------------------------------------------
+// Device-resident CG scalars.  Kernels read and update them so that a whole
+// CG iteration runs without a host round trip.
+struct Scalars {
+    double rz;        // r.z of the current iterate
+    double rz_new;    // r.z after the latest preconditioner application
+    double pq;        // p.A p
+    double alpha;     // step length of the current iteration
+    double alpha_x;   // step still to be added to x (x += alpha_x p_old)
+    double beta;
+    double rr;        // ||r||^2
+    double thresh2;   // (tol ||b||)^2
+    double zq;        // z_new . q (flexible beta)
+    double sum;       // generic reduction result
+    double sum2;
+    int done;         // 0 running, 1 converged, 2 breakdown
+    int iter;         // number of A p products so far
+    int flexible;     // 1: Polak-Ribiere beta
+    int pbuf;         // index of the p buffer written by the last spmv
+};
+
+// Scratch for grid-wide deterministic reductions: per-block partials plus
+// one arrival counter per reduction site.
+struct RedBuf {
+    double* partial;      // [kMaxRedBlocks * 2]
+    unsigned* counter;    // [16]
+};
+
+enum RedSite { RS_PQ = 0, RS_RR = 1, RS_RZ = 2, RS_GEN = 3, RS_GEN2 = 4, RS_EIG = 5 };
+
+// ---------------------------------------------------------------------------
+// wavefront / block reductions (wave64); fixed combination order, so results
+// are reproducible run to run.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the block; every thread receives the result.  `sh` holds at
+// least blockDim.x/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ double atomic_load_relaxed(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid-wide reduction of NV values per block (blockDim.x <= 256).  Every
+// block calls it once with its block sums (valid in thread 0).  Returns true
+// in exactly one block, the last to arrive; there thread 0's out[] holds the
+// totals, summed in a fixed order (strided per thread, then by thread).
+template <int NV>
+__device__ bool grid_reduce(const double (&v)[NV], RedBuf rb, int site, double (&out)[NV]) {
+    __shared__ int s_last;
+    __shared__ double sh[NV][256];
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+        for (int k = 0; k < NV; ++k) rb.partial[(size_t)k * kMaxRedBlocks + b] = v[k];
+        __threadfence();
+        const unsigned t = atomicAdd(&rb.counter[site], 1u);
+        s_last = (t == (unsigned)(nb - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            s += atomic_load_relaxed(&rb.partial[(size_t)k * kMaxRedBlocks + i]);
+        sh[k][threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < NV; ++k) {
+            double t = 0.0;
+            for (int i = 0; i < (int)blockDim.x; ++i) t += sh[k][i];
+            out[k] = t;
+        }
+        rb.counter[site] = 0u;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of the fine grid and its tiling.  A tile is EX level-2 elements
+// along x (8*EX x 8 x 8 cells); one wavefront per element.
+struct FineGeom {
+    int nx, ny, nz;
+    int mx, my, mz;       // level-2 elements per axis
+    int ex;               // elements per tile along x (1, 2 or 4)
+    int ntx, nty, ntz;    // tiles per axis
+    int ntiles;
+    int xcd_remap;        // 1: blockIdx -> tile mapping keeps each XCD on a slab
+};
+
+// Coarse level l >= 2: elements on an (mx,my,mz) grid, padded width L.
+struct CoarseGeom {
+    int mx, my, mz, m;
+    int L;                 // padded per-element width (target + 3)
+    int agg;               // children per axis of a parent (level l+1)
+    int px, py, pz, M;     // parents per axis / total (0 if l is the coarsest)
+};
+
+// ---------------------------------------------------------------------------
+// launchers (k_fine.hip)
+template <typename T>
+void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q,
+                       T* u, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
+template <typename T>
+void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
+                           const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
+                    Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
+                        const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
+void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
+                     double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first,
+                     hipStream_t s);
+void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
+                    int resid, hipStream_t s);
+void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* invd32, int* bad,
+                     hipStream_t s);
+void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n,
+                       int* bad, hipStream_t s);
+
+// vector utilities (k_fine.hip)
+void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,
+                hipStream_t s);
+void launch_sum_abs(const double* a, int64_t n, double* out_sum, double* out_abs, RedBuf rb,
+                    hipStream_t s);
+void launch_axpy_x(double* x, const double* p0, const double* p1, Scalars* sc, int64_t n,
+                   hipStream_t s);
+void launch_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+void launch_fill(double* dst, double v, int64_t n, hipStream_t s);
+void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s);
+
+// coarse levels (k_coarse.hip)
+template <typename T>
+void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* Aoff, const T* r, T* u,
+                          const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r,
+                                  const T* u, const T* V, const int* nkeep_up, int Lup, T* rup,
+                                  const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nkeep_up, int Lup,
+                           const T* eup, const Scalars* sc, int check_done, hipStream_t s);
+template <typename T>
+void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff,
+                                const T* r, const T* u, T* e, const Scalars* sc, int check_done,
+                                hipStream_t s);
+template <typename T>
+void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e,
+                     const Scalars* sc, int check_done, hipStream_t s);
+
+// set-up (k_coarse.hip)
+void launch_galerkin2(const FineGeom& g, const double* kt, const double* phi, const int* nkeep, int L,
+                      double* D, double* Aoff, hipStream_t s);
+void launch_galerkin_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Dlo,
+                        const double* Aofflo, const double* V, const int* nkeep_up, double* Dup,
+                        double* Aoffup, hipStream_t s);
+void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double* D, double* Ad,
+                          hipStream_t s);
+void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
+                          double* Dinv, int* bad, hipStream_t s);
+void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* Aoff,
+                           const int* cmap_inv, int np, double* dense, hipStream_t s);
+template <typename S, typename T>
+void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s);
+
+// local eigensolves (k_eig.hip)
+void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
+                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc,
+                 hipStream_t s);
+void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
+                   const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
+                   int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,
+                   double* Aint, double* zup, int* status, hipStream_t s);
+
+// dense coarsest factorization (k_dense.hip); np is a multiple of 32
+int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s);
+void launch_pinv_finish(double* a, int np, int n, const double* z, double alpha, hipStream_t s);
+void launch_add_rank1(double* a, int np, int n, const double* z, double alpha, hipStream_t s);
+void launch_pad_identity(double* a, int np, int n, hipStream_t s);
+
+}  // namespace specmg

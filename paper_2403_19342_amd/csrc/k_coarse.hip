@@ -1,0 +1,657 @@
+// Coarse levels of the V-cycle (Algorithm 1 steps 3-7, applied recursively)
+// and their set-up.
+//
+// A coarse level l >= 2 has one block of L (padded) unknowns per element;
+// its Galerkin operator A_l = R_l A_{l-1} R_l^T (text above Algorithm 1) is
+// a block 7-point stencil stored as
+//   Ad[e]        diagonal block  (L x L)
+//   Aoff[e][d]   coupling A_l(e, e + unit vector d), d = x, y, z (L x L)
+// The level-l smoother is one block-Jacobi sweep whose blocks are the
+// level-(l+1) parent elements, each factored by block IC(0) over its agg^3
+// children in lexicographic order (Section 5): pivots
+//   D_c = Ad_c - sum_{lower neighbour c'} A(c, c') D_c'^{-1} A(c', c),
+// stored inverted in Dinv.  Padded slots carry an identity pivot and zero
+// couplings, so they stay zero.
+#include "common.hpp"
+
+namespace specmg {
+
+__device__ __forceinline__ int child_of(const CoarseGeom& g, int E, int p) {
+    const int a = g.agg;
+    const int Ex = E % g.px, Ey = (E / g.px) % g.py, Ez = E / (g.px * g.py);
+    const int qx = p % a, qy = (p / a) % a, qz = p / (a * a);
+    return (Ex * a + qx) + g.mx * ((Ey * a + qy) + g.my * (Ez * a + qz));
+}
+
+// positions of the agg^3 children sorted by qx+qy+qz, built in LDS
+__device__ void build_planes(int agg, int* pos, int* off) {
+    if (threadIdx.x == 0) {
+        int k = 0;
+        for (int s = 0; s <= 3 * (agg - 1); ++s) {
+            off[s] = k;
+            for (int p = 0; p < agg * agg * agg; ++p) {
+                const int q = p % agg + (p / agg) % agg + p / (agg * agg);
+                if (q == s) pos[k++] = p;
+            }
+        }
+        off[3 * (agg - 1) + 1] = k;
+    }
+    __syncthreads();
+}
+
+// y_c = (A_l u)_c for row a of child element c (neighbours read from global)
+template <typename T>
+__device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __restrict__ Ad,
+                                             const T* __restrict__ Aoff, const T* __restrict__ u, int c,
+                                             int a) {
+    const int L = g.L;
+    const int cx = c % g.mx, cy = (c / g.mx) % g.my, cz = c / (g.mx * g.my);
+    T s = T(0);
+    const T* ad = Ad + ((size_t)c * L + a) * L;
+    const T* uc = u + (size_t)c * L;
+    for (int b = 0; b < L; ++b) s += ad[b] * uc[b];
+    const int cc[3] = {cx, cy, cz};
+    const int ext[3] = {g.mx, g.my, g.mz};
+    const int stride[3] = {1, g.mx, g.mx * g.my};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (cc[ax] + 1 < ext[ax]) {
+            const int cn = c + stride[ax];
+            const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
+            const T* un = u + (size_t)cn * L;
+            for (int b = 0; b < L; ++b) s += o[b] * un[b];
+        }
+        if (cc[ax] > 0) {
+            const int cn = c - stride[ax];
+            const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
+            const T* un = u + (size_t)cn * L;
+            for (int b = 0; b < L; ++b) s += o[b * L + a] * un[b];
+        }
+    }
+    return s;
+}
+
+// Block IC(0) forward/backward substitution over the children of parent E.
+// sY[p*L + a] holds the right-hand side on entry and the result on exit.
+template <typename T>
+__device__ void block_ic_sweep(const CoarseGeom& g, int E, const T* __restrict__ Dinv,
+                               const T* __restrict__ Aoff, T* sY, T* tmp, const int* pos, const int* off) {
+    const int L = g.L, agg = g.agg;
+    const int nplanes = 3 * (agg - 1) + 1;
+    const int k = threadIdx.x / L, a = threadIdx.x % L;
+    for (int s = 0; s < nplanes; ++s) {
+        const int cnt = off[s + 1] - off[s];
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int c = child_of(g, E, p);
+            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
+            const int pstep[3] = {1, agg, agg * agg};
+            const int cstep[3] = {1, g.mx, g.mx * g.my};
+            T acc = sY[p * L + a];
+            for (int ax = 0; ax < 3; ++ax) {
+                if (q[ax] > 0) {
+                    // A(c, c') = Aoff[c'][ax]^T with c' = c - e_ax
+                    const int cn = c - cstep[ax], pn = p - pstep[ax];
+                    const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
+                    for (int b = 0; b < L; ++b) acc -= o[b * L + a] * sY[pn * L + b];
+                }
+            }
+            tmp[k * L + a] = acc;
+        }
+        __syncthreads();
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int c = child_of(g, E, p);
+            const T* di = Dinv + ((size_t)c * L + a) * L;
+            T y = T(0);
+            for (int b = 0; b < L; ++b) y += di[b] * tmp[k * L + b];
+            sY[p * L + a] = y;
+        }
+        __syncthreads();
+    }
+    for (int s = nplanes - 1; s >= 0; --s) {
+        const int cnt = off[s + 1] - off[s];
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int c = child_of(g, E, p);
+            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
+            const int pstep[3] = {1, agg, agg * agg};
+            T acc = T(0);
+            for (int ax = 0; ax < 3; ++ax) {
+                if (q[ax] < agg - 1) {
+                    const int pn = p + pstep[ax];
+                    const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
+                    for (int b = 0; b < L; ++b) acc += o[b] * sY[pn * L + b];
+                }
+            }
+            tmp[k * L + a] = acc;
+        }
+        __syncthreads();
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int c = child_of(g, E, p);
+            const T* di = Dinv + ((size_t)c * L + a) * L;
+            T z = T(0);
+            for (int b = 0; b < L; ++b) z += di[b] * tmp[k * L + b];
+            sY[p * L + a] -= z;
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kCoarseThreads = 256;
+constexpr int kMaxChildren = 64;   // agg <= 4
+constexpr int kMaxL = 16;
+
+// u = M_l^{-1} r
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_smooth(CoarseGeom g, const T* __restrict__ Dinv,
+                                                                 const T* __restrict__ Aoff,
+                                                                 const T* __restrict__ r, T* __restrict__ u,
+                                                                 const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    __shared__ T sY[kMaxChildren * kMaxL];
+    __shared__ T tmp[12 * kMaxL];
+    __shared__ int pos[kMaxChildren], off[12];
+    const int E = blockIdx.x;
+    const int L = g.L, nc = g.agg * g.agg * g.agg;
+    build_planes(g.agg, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        sY[t] = r[(size_t)child_of(g, E, p) * L + a];
+    }
+    __syncthreads();
+    block_ic_sweep<T>(g, E, Dinv, Aoff, sY, tmp, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        u[(size_t)child_of(g, E, p) * L + a] = sY[t];
+    }
+}
+
+// e = u + M_l^{-1} (r - A_l u)
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_smooth(
+    CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Dinv, const T* __restrict__ Aoff,
+    const T* __restrict__ r, const T* __restrict__ u, T* __restrict__ e, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    __shared__ T sY[kMaxChildren * kMaxL];
+    __shared__ T tmp[12 * kMaxL];
+    __shared__ int pos[kMaxChildren], off[12];
+    const int E = blockIdx.x;
+    const int L = g.L, nc = g.agg * g.agg * g.agg;
+    build_planes(g.agg, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        const int c = child_of(g, E, p);
+        sY[t] = r[(size_t)c * L + a] - block_row_apply<T>(g, Ad, Aoff, u, c, a);
+    }
+    __syncthreads();
+    block_ic_sweep<T>(g, E, Dinv, Aoff, sY, tmp, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        const size_t i = (size_t)child_of(g, E, p) * L + a;
+        e[i] = u[i] + sY[t];
+    }
+}
+
+// s = r - A_l u on the children of E, then r_up[E] = V_E^T s
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
+    CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Aoff, const T* __restrict__ r,
+    const T* __restrict__ u, const T* __restrict__ V, const int* __restrict__ nkeep_up, int Lup,
+    T* __restrict__ rup, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    __shared__ T sS[kMaxChildren * kMaxL];
+    __shared__ double sred[kCoarseThreads / 64];
+    const int E = blockIdx.x;
+    const int L = g.L, nc = g.agg * g.agg * g.agg, n = nc * L;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        const int c = child_of(g, E, p);
+        sS[t] = r[(size_t)c * L + a] - block_row_apply<T>(g, Ad, Aoff, u, c, a);
+    }
+    __syncthreads();
+    const int nk = nkeep_up[E];
+    for (int j = 0; j < Lup; ++j) {
+        double v = 0.0;
+        if (j < nk) {
+            const T* vj = V + ((size_t)E * Lup + j) * n;
+            for (int t = threadIdx.x; t < n; t += blockDim.x) v += (double)vj[t] * (double)sS[t];
+        }
+        const double s = block_sum(v, sred);
+        if (threadIdx.x == 0) rup[(size_t)E * Lup + j] = (T)s;
+    }
+}
+
+// u += V_E e_up[E] on the children of E
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g, T* __restrict__ u,
+                                                                  const T* __restrict__ V,
+                                                                  const int* __restrict__ nkeep_up, int Lup,
+                                                                  const T* __restrict__ eup, const Scalars* sc,
+                                                                  int check_done) {
+    if (check_done && sc->done) return;
+    const int E = blockIdx.x;
+    const int L = g.L, nc = g.agg * g.agg * g.agg, n = nc * L;
+    const int nk = nkeep_up[E];
+    const T* ee = eup + (size_t)E * Lup;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        T acc = T(0);
+        for (int j = 0; j < nk; ++j) acc += V[((size_t)E * Lup + j) * n + t] * ee[j];
+        u[(size_t)child_of(g, E, p) * L + a] += acc;
+    }
+}
+
+// e = A_L^+ r at the coarsest level: dense symmetric product over the
+// compact unknowns (cmap: compact index -> padded index)
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* __restrict__ Pinv,
+                                                   const int* __restrict__ cmap, const T* __restrict__ r,
+                                                   T* __restrict__ e, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    extern __shared__ double srz[];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) srz[j] = (double)r[cmap[j]];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int rows_per_block = 16;
+    for (int rr = w; rr < rows_per_block; rr += 4) {
+        const int i = blockIdx.x * rows_per_block + rr;
+        if (i >= n) break;
+        const double* pr = Pinv + (size_t)i * np;
+        double s = 0.0;
+        for (int j = lane; j < n; j += 64) s += pr[j] * srz[j];
+        s = wave_sum(s);
+        if (lane == 0) e[cmap[i]] = (T)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+
+// Level-2 face blocks from the fine faces on the element boundary:
+//   D[e][d] = sum_{tau on face d} T_f phi(tau) phi(tau)^T       (d = -x,+x,-y,+y,-z,+z)
+//   Aoff[e][ax] = -sum_{tau on face +ax} T_f phi_e(tau) phi_{e+ax}(tau')^T
+// (the terms of eq. discrete varia for faces between elements)
+__global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __restrict__ kt,
+                                                   const double* __restrict__ phi, const int* __restrict__ nkeep,
+                                                   int L, double* __restrict__ D, double* __restrict__ Aoff) {
+    __shared__ double sT[6][64];
+    __shared__ double sP[6][kMaxL][64];    // own face rows
+    __shared__ double sN[3][kMaxL][64];    // neighbour face rows (+ faces)
+    const int e = blockIdx.x;
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    auto gid = [&](int x, int y, int z) {
+        return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    };
+    for (int t = threadIdx.x; t < 6 * 64; t += blockDim.x) {
+        const int d = t / 64, f = t % 64;
+        const int ax = d >> 1;
+        const bool plus = d & 1;
+        const int u = f & 7, v = f >> 3;     // in-face coordinates
+        int i, j, k;
+        if (ax == 0) { i = plus ? 7 : 0; j = u; k = v; }
+        else if (ax == 1) { i = u; j = plus ? 7 : 0; k = v; }
+        else { i = u; j = v; k = plus ? 7 : 0; }
+        const int gx = ex * 8 + i, gy = ey * 8 + j, gz = ez * 8 + k;
+        const int nx_ = gx + (ax == 0 ? (plus ? 1 : -1) : 0);
+        const int ny_ = gy + (ax == 1 ? (plus ? 1 : -1) : 0);
+        const int nz_ = gz + (ax == 2 ? (plus ? 1 : -1) : 0);
+        const bool inside = nx_ >= 0 && nx_ < g.nx && ny_ >= 0 && ny_ < g.ny && nz_ >= 0 && nz_ < g.nz;
+        double T = 0.0;
+        if (inside) {
+            const double a = kt[gid(gx, gy, gz)], b = kt[gid(nx_, ny_, nz_)];
+            T = 2.0 * a * b / (a + b);
+        }
+        sT[d][f] = T;
+        const int c = i + 8 * (j + 8 * k);
+        for (int jj = 0; jj < L; ++jj) sP[d][jj][f] = phi[((size_t)e * L + jj) * 512 + c];
+        if (plus) {
+            const int en = e + (ax == 0 ? 1 : (ax == 1 ? g.mx : g.mx * g.my));
+            const int ci = ax == 0 ? 0 : i, cj = ax == 1 ? 0 : j, ck = ax == 2 ? 0 : k;
+            const int cn = ci + 8 * (cj + 8 * ck);
+            for (int jj = 0; jj < L; ++jj)
+                sN[ax][jj][f] = inside ? phi[((size_t)en * L + jj) * 512 + cn] : 0.0;
+        }
+    }
+    __syncthreads();
+    const int LL = L * L;
+    for (int t = threadIdx.x; t < 9 * LL; t += blockDim.x) {
+        const int blk = t / LL, a = (t % LL) / L, b = t % L;
+        double s = 0.0;
+        if (blk < 6) {
+            for (int f = 0; f < 64; ++f) s += sT[blk][f] * sP[blk][a][f] * sP[blk][b][f];
+            D[((size_t)e * 6 + blk) * LL + a * L + b] = s;
+        } else {
+            const int ax = blk - 6;
+            const int d = 2 * ax + 1;
+            for (int f = 0; f < 64; ++f) s += sT[d][f] * sP[d][a][f] * sN[ax][b][f];
+            Aoff[((size_t)e * 3 + ax) * LL + a * L + b] = -s;
+        }
+    }
+}
+
+// Face blocks of level l+1 from those of level l (Galerkin with V_E):
+//   D_up[E][d] = sum_{c on face d of E} V_c^T D[c][d] V_c
+//   Aoff_up[E][ax] = sum_{c on face +ax of E} V_c^T Aoff[c][ax] V'_{c+ax}
+__global__ __launch_bounds__(256) void k_galerkin_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Dlo,
+                                                     const double* __restrict__ Aofflo,
+                                                     const double* __restrict__ V,
+                                                     const int* __restrict__ nkeep_up, double* __restrict__ Dup,
+                                                     double* __restrict__ Aoffup) {
+    __shared__ double sB[kMaxL * kMaxL];     // level-l block
+    __shared__ double sV[kMaxL * kMaxL];     // V_c   (Lp x Lu)
+    __shared__ double sW[kMaxL * kMaxL];     // V'_c' (Lp x Lu)
+    __shared__ double sBW[kMaxL * kMaxL];    // B V'  (Lp x Lu)
+    const int E = blockIdx.x;
+    const int agg = lo.agg, Lp = lo.L, Lu = up.L;
+    const int n = agg * agg * agg * Lp;
+    const int Ex = E % up.mx, Ey = (E / up.mx) % up.my, Ez = E / (up.mx * up.my);
+    const int Ec[3] = {Ex, Ey, Ez};
+    const int ext[3] = {up.mx, up.my, up.mz};
+    const int estride[3] = {1, up.mx, up.mx * up.my};
+    const int cstride[3] = {1, lo.mx, lo.mx * lo.my};
+    for (int blk = 0; blk < 9; ++blk) {
+        const bool isD = blk < 6;
+        const int d = isD ? blk : 2 * (blk - 6) + 1;
+        const int ax = d >> 1;
+        const bool plus = d & 1;
+        const bool has_nb = isD || (Ec[ax] + 1 < ext[ax]);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (has_nb) {
+            for (int f = 0; f < agg * agg; ++f) {
+                const int u = f % agg, v = f / agg;
+                int q[3];
+                q[ax] = plus ? agg - 1 : 0;
+                q[(ax + 1) % 3] = u;
+                q[(ax + 2) % 3] = v;
+                const int p = q[0] + agg * (q[1] + agg * q[2]);
+                const int c = (Ex * agg + q[0]) + lo.mx * ((Ey * agg + q[1]) + lo.my * (Ez * agg + q[2]));
+                // stage B, V_c and (for couplings) V'_{c'}
+                for (int t = threadIdx.x; t < Lp * Lp; t += blockDim.x)
+                    sB[t] = isD ? Dlo[((size_t)c * 6 + d) * Lp * Lp + t] : Aofflo[((size_t)c * 3 + ax) * Lp * Lp + t];
+                for (int t = threadIdx.x; t < Lp * Lu; t += blockDim.x) {
+                    const int b = t / Lu, j = t % Lu;
+                    sV[t] = V[((size_t)E * Lu + j) * n + p * Lp + b];
+                    if (isD) {
+                        sW[t] = sV[t];
+                    } else {
+                        int qn[3] = {q[0], q[1], q[2]};
+                        qn[ax] = 0;
+                        const int pn = qn[0] + agg * (qn[1] + agg * qn[2]);
+                        const int En = E + estride[ax];
+                        sW[t] = V[((size_t)En * Lu + j) * n + pn * Lp + b];
+                    }
+                }
+                __syncthreads();
+                for (int t = threadIdx.x; t < Lp * Lu; t += blockDim.x) {
+                    const int a = t / Lu, j = t % Lu;
+                    double s = 0.0;
+                    for (int b = 0; b < Lp; ++b) s += sB[a * Lp + b] * sW[b * Lu + j];
+                    sBW[t] = s;
+                }
+                __syncthreads();
+                for (int t = threadIdx.x, k = 0; t < Lu * Lu; t += blockDim.x, ++k) {
+                    const int i = t / Lu, j = t % Lu;
+                    double s = 0.0;
+                    for (int a = 0; a < Lp; ++a) s += sV[a * Lu + i] * sBW[a * Lu + j];
+                    acc[k] += s;
+                }
+                __syncthreads();
+                (void)cstride;
+            }
+        }
+        for (int t = threadIdx.x, k = 0; t < Lu * Lu; t += blockDim.x, ++k) {
+            if (isD) Dup[((size_t)E * 6 + d) * Lu * Lu + t] = acc[k];
+            else Aoffup[((size_t)E * 3 + ax) * Lu * Lu + t] = acc[k];
+        }
+    }
+    (void)nkeep_up;
+}
+
+// Ad = Aint + sum_d D[e][d]
+__global__ void k_assemble_diag(CoarseGeom g, const double* __restrict__ Aint, const double* __restrict__ D,
+                                double* __restrict__ Ad) {
+    const int e = blockIdx.x;
+    const int LL = g.L * g.L;
+    for (int t = threadIdx.x; t < LL; t += blockDim.x) {
+        double v = Aint[(size_t)e * LL + t];
+        for (int d = 0; d < 6; ++d) v += D[((size_t)e * 6 + d) * LL + t];
+        Ad[(size_t)e * LL + t] = v;
+    }
+}
+
+// in-place inverse of an SPD n x n matrix (n <= kMaxL) by one thread;
+// padded slots (index >= nk) get identity.  Returns false if not SPD.
+__device__ bool small_spd_inverse(double* A, int n, int nk, double* Lw) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            if (i >= nk || j >= nk) A[i * n + j] = (i == j) ? 1.0 : 0.0;
+    bool ok = true;
+    // Cholesky A = L L^T (lower, in Lw)
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= Lw[j * n + k] * Lw[j * n + k];
+        if (!(d > 0.0)) {
+            ok = false;
+            d = 1.0;
+        }
+        const double ljj = sqrt(d);
+        Lw[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= Lw[i * n + k] * Lw[j * n + k];
+            Lw[i * n + j] = v / ljj;
+        }
+        for (int i = 0; i < j; ++i) Lw[i * n + j] = 0.0;
+    }
+    // A^{-1} column by column: solve L y = e_k, L^T x = y
+    for (int kcol = 0; kcol < n; ++kcol) {
+        double y[kMaxL];
+        for (int i = 0; i < n; ++i) {
+            double v = (i == kcol) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= Lw[i * n + k] * y[k];
+            y[i] = v / Lw[i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < n; ++k) v -= Lw[k * n + i] * y[k];
+            y[i] = v / Lw[i * n + i];
+        }
+        for (int i = 0; i < n; ++i) A[i * n + kcol] = y[i];
+    }
+    return ok;
+}
+
+// block IC(0) pivots of the level-l smoother, one workgroup per parent;
+// children of one hyperplane are factored in parallel, one thread each
+__global__ __launch_bounds__(64) void k_blockic_setup(CoarseGeom g, const double* __restrict__ Ad,
+                                                      const double* __restrict__ Aoff,
+                                                      const int* __restrict__ nkeep, double* Dinv, int* bad) {
+    __shared__ int pos[kMaxChildren], off[12];
+    __shared__ double work[12][2][kMaxL * kMaxL];
+    const int E = blockIdx.x;
+    const int L = g.L, agg = g.agg, LL = L * L;
+    build_planes(agg, pos, off);
+    const int nplanes = 3 * (agg - 1) + 1;
+    for (int s = 0; s < nplanes; ++s) {
+        const int cnt = off[s + 1] - off[s];
+        const int k = threadIdx.x;
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int c = child_of(g, E, p);
+            double* P = work[k][0];
+            double* T = work[k][1];
+            for (int t = 0; t < LL; ++t) P[t] = Ad[(size_t)c * LL + t];
+            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
+            const int cstep[3] = {1, g.mx, g.mx * g.my};
+            for (int ax = 0; ax < 3; ++ax) {
+                if (q[ax] == 0) continue;
+                const int cn = c - cstep[ax];
+                const double* O = Aoff + ((size_t)cn * 3 + ax) * LL;   // A(cn, c)
+                const double* Di = Dinv + (size_t)cn * LL;
+                // T = Dinv_cn O ; P -= O^T T
+                for (int i = 0; i < L; ++i)
+                    for (int j = 0; j < L; ++j) {
+                        double v = 0.0;
+                        for (int b = 0; b < L; ++b) v += Di[i * L + b] * O[b * L + j];
+                        T[i * L + j] = v;
+                    }
+                for (int i = 0; i < L; ++i)
+                    for (int j = 0; j < L; ++j) {
+                        double v = 0.0;
+                        for (int b = 0; b < L; ++b) v += O[b * L + i] * T[b * L + j];
+                        P[i * L + j] -= v;
+                    }
+            }
+            // symmetrise, invert
+            for (int i = 0; i < L; ++i)
+                for (int j = i + 1; j < L; ++j) {
+                    const double v = 0.5 * (P[i * L + j] + P[j * L + i]);
+                    P[i * L + j] = v;
+                    P[j * L + i] = v;
+                }
+            if (!small_spd_inverse(P, L, nkeep[c], T)) atomicOr(bad, 2);
+            for (int t = 0; t < LL; ++t) Dinv[(size_t)c * LL + t] = P[t];
+        }
+        __threadfence();
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+}
+
+// coarsest dense matrix over the compact unknowns (cinv: padded -> compact
+// or -1); the matrix must be zeroed beforehand
+__global__ void k_build_coarsest(CoarseGeom g, const double* __restrict__ Ad, const double* __restrict__ Aoff,
+                                 const int* __restrict__ cinv, int np, double* __restrict__ dense) {
+    const int e = blockIdx.x;
+    const int L = g.L, LL = L * L;
+    const int cx = e % g.mx, cy = (e / g.mx) % g.my, cz = e / (g.mx * g.my);
+    const int cc[3] = {cx, cy, cz};
+    const int ext[3] = {g.mx, g.my, g.mz};
+    const int stride[3] = {1, g.mx, g.mx * g.my};
+    for (int t = threadIdx.x; t < LL; t += blockDim.x) {
+        const int a = t / L, b = t % L;
+        const int i = cinv[e * L + a];
+        if (i < 0) continue;
+        const int jd = cinv[e * L + b];
+        if (jd >= 0) dense[(size_t)i * np + jd] = Ad[(size_t)e * LL + t];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (cc[ax] + 1 >= ext[ax]) continue;
+            const int en = e + stride[ax];
+            const int j = cinv[en * L + b];
+            if (j < 0) continue;
+            const double v = Aoff[((size_t)e * 3 + ax) * LL + t];
+            dense[(size_t)i * np + j] = v;
+            dense[(size_t)j * np + i] = v;
+        }
+    }
+}
+
+template <typename S, typename T>
+__global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (T)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+template <typename T>
+void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* Aoff, const T* r, T* u, const Scalars* sc,
+                          int check_done, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_smooth<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Dinv, Aoff, r, u, sc,
+                       check_done);
+}
+
+template <typename T>
+void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
+                                  const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
+                                  int check_done, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_resid_restrict<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Ad, Aoff, r, u, V,
+                       nkeep_up, Lup, rup, sc, check_done);
+}
+
+template <typename T>
+void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nkeep_up, int Lup, const T* eup,
+                           const Scalars* sc, int check_done, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, u, V, nkeep_up, Lup, eup,
+                       sc, check_done);
+}
+
+template <typename T>
+void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* r,
+                                const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
+    hipLaunchKernelGGL((k_coarse_resid_smooth<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Ad, Dinv, Aoff, r, u,
+                       e, sc, check_done);
+}
+
+template <typename T>
+void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, const Scalars* sc,
+                     int check_done, hipStream_t s) {
+    const int blocks = (n + 15) / 16;
+    hipLaunchKernelGGL((k_coarsest<T>), dim3(blocks), dim3(256), (size_t)n * sizeof(double), s, n, np, Pinv, cmap, r,
+                       e, sc, check_done);
+}
+
+void launch_galerkin2(const FineGeom& g, const double* kt, const double* phi, const int* nkeep, int L, double* D,
+                      double* Aoff, hipStream_t s) {
+    hipLaunchKernelGGL(k_galerkin2, dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, kt, phi, nkeep, L, D, Aoff);
+}
+
+void launch_galerkin_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Dlo, const double* Aofflo,
+                        const double* V, const int* nkeep_up, double* Dup, double* Aoffup, hipStream_t s) {
+    hipLaunchKernelGGL(k_galerkin_up, dim3(up.m), dim3(256), 0, s, lo, up, Dlo, Aofflo, V, nkeep_up, Dup, Aoffup);
+}
+
+void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double* D, double* Ad, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble_diag, dim3(g.m), dim3(128), 0, s, g, Aint, D, Ad);
+}
+
+void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
+                          double* Dinv, int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64), 0, s, g, Ad, Aoff, nkeep, Dinv, bad);
+}
+
+void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* cinv, int np,
+                           double* dense, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_coarsest, dim3(g.m), dim3(128), 0, s, g, Ad, Aoff, cinv, np, dense);
+}
+
+template <typename S, typename T>
+void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s) {
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    hipLaunchKernelGGL((k_convert<S, T>), dim3((int)b), dim3(256), 0, s, src, dst, n);
+}
+
+template void launch_coarse_smooth<double>(const CoarseGeom&, const double*, const double*, const double*, double*,
+                                           const Scalars*, int, hipStream_t);
+template void launch_coarse_smooth<float>(const CoarseGeom&, const float*, const float*, const float*, float*,
+                                          const Scalars*, int, hipStream_t);
+template void launch_coarse_resid_restrict<double>(const CoarseGeom&, const double*, const double*, const double*,
+                                                   const double*, const double*, const int*, int, double*,
+                                                   const Scalars*, int, hipStream_t);
+template void launch_coarse_resid_restrict<float>(const CoarseGeom&, const float*, const float*, const float*,
+                                                  const float*, const float*, const int*, int, float*,
+                                                  const Scalars*, int, hipStream_t);
+template void launch_coarse_prolong<double>(const CoarseGeom&, double*, const double*, const int*, int,
+                                            const double*, const Scalars*, int, hipStream_t);
+template void launch_coarse_prolong<float>(const CoarseGeom&, float*, const float*, const int*, int, const float*,
+                                           const Scalars*, int, hipStream_t);
+template void launch_coarse_resid_smooth<double>(const CoarseGeom&, const double*, const double*, const double*,
+                                                 const double*, const double*, double*, const Scalars*, int,
+                                                 hipStream_t);
+template void launch_coarse_resid_smooth<float>(const CoarseGeom&, const float*, const float*, const float*,
+                                                const float*, const float*, float*, const Scalars*, int,
+                                                hipStream_t);
+template void launch_coarsest<double>(int, int, const double*, const int*, const double*, double*, const Scalars*,
+                                      int, hipStream_t);
+template void launch_coarsest<float>(int, int, const double*, const int*, const float*, float*, const Scalars*, int,
+                                     hipStream_t);
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+
+}  // namespace specmg

@@ -1,0 +1,890 @@
+// Batched local eigensolves of the set-up phase (Section 3).
+//
+// Level 2 (eq. spepb): on every 8^3 element K, the smallest eigenpairs of
+//   A_K phi = lambda S_K phi,  S_K = diag(tr kappa~),
+// solved in the symmetric form A~ x = lambda x with A~ = S^-1/2 A_K S^-1/2,
+// phi = S^-1/2 x (so phi^T S phi = 1, the normalisation of Section 3).
+// Levels >= 3 (eq. spectral cc): on every parent element E the restricted
+// problem H_E v = lambda v with H_E = B_E^T A_E B_E assembled from the level
+// below (its Gram is the identity for S-normalised bases).
+//
+// Method: Chebyshev-filtered subspace iteration.  One workgroup per element
+// holds a block of M vectors; each cycle applies a degree-DEG Chebyshev
+// polynomial that damps the unwanted interval [a, b] (b: Gershgorin bound,
+// a: largest Ritz value of the block), re-orthonormalises by Cholesky-QR
+// (twice) and performs Rayleigh-Ritz with a one-wavefront parallel cyclic
+// Jacobi eigensolver.  Only operator applications and M x M reductions are
+// needed, so the whole solve stays in registers and LDS.
+#include "common.hpp"
+
+namespace specmg {
+
+constexpr int kDeg = 20;          // Chebyshev degree per cycle
+constexpr int kMaxCycles = 120;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double hash_noise(unsigned a, unsigned b, unsigned c) {
+    unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return (double)(h & 0xFFFFFF) / 8388608.0 - 1.0;   // [-1, 1)
+}
+
+// low-frequency cosine modes (p, q, r) by increasing p^2+q^2+r^2
+__constant__ unsigned char kModes[16][3] = {
+    {0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1},
+    {2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {2, 1, 0}, {1, 2, 0}, {2, 0, 1}, {0, 2, 1}, {1, 0, 2}};
+
+template <typename T>
+__device__ __forceinline__ T harm_e(T a, T b) {
+    const T s = a + b;
+    return s > T(0) ? (T(2) * a * b) / s : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// small dense helpers on LDS, run by one thread or one wavefront
+
+// Round-robin tournament: player at position k in round r (M players).
+__device__ __forceinline__ int rr_player(int k, int r, int M) {
+    return k == 0 ? 0 : 1 + ((k - 1 + r) % (M - 1));
+}
+
+// Symmetric eigendecomposition H = Q diag(th) Q^T, eigenvalues ascending,
+// by parallel cyclic Jacobi in wavefront 0.  H (M*M) is destroyed; Q (M*M)
+// receives the eigenvectors as columns.  Must be called by all threads.
+template <int M>
+__device__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
+    static_assert(M % 2 == 0 && M <= 16, "Jacobi block size");
+    constexpr int MM = M * M;
+    constexpr int PER = (MM + 63) / 64;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        double* cs = scr;          // [M] cosine per index
+        double* sn = scr + M;      // [M] sine per index
+        int* lo = iscr;            // [M] smaller index of the pair
+        int* hi = iscr + M;        // [M] larger index of the pair
+        for (int t = lane; t < MM; t += 64) Q[t] = (t / M == t % M) ? 1.0 : 0.0;
+        wave_sync();
+#pragma unroll 1
+        for (int sweep = 0; sweep < 24; ++sweep) {
+            double off = 0.0, dg = 0.0;
+            for (int t = lane; t < MM; t += 64) {
+                const int i = t / M, j = t % M;
+                if (i != j) off = fmax(off, fabs(H[t]));
+                else dg = fmax(dg, fabs(H[t]));
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                off = fmax(off, __shfl_xor(off, o, 64));
+                dg = fmax(dg, __shfl_xor(dg, o, 64));
+            }
+            if (off <= 1e-18 * dg || off == 0.0) break;
+#pragma unroll 1
+            for (int r = 0; r < M - 1; ++r) {
+                if (lane < M / 2) {
+                    int p = rr_player(lane, r, M), q = rr_player(M - 1 - lane, r, M);
+                    if (p > q) {
+                        const int t = p;
+                        p = q;
+                        q = t;
+                    }
+                    const double hpp = H[p * M + p], hqq = H[q * M + q], hpq = H[p * M + q];
+                    double c = 1.0, s = 0.0;
+                    if (hpq != 0.0) {
+                        const double tt = (hqq - hpp) / (2.0 * hpq);
+                        const double t = (tt >= 0.0 ? 1.0 : -1.0) / (fabs(tt) + sqrt(tt * tt + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        s = t * c;
+                    }
+                    cs[p] = c;
+                    cs[q] = c;
+                    sn[p] = s;
+                    sn[q] = s;
+                    lo[p] = p;
+                    lo[q] = p;
+                    hi[p] = q;
+                    hi[q] = q;
+                }
+                wave_sync();
+                double nh[PER], nq[PER];
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int t = lane + 64 * u;
+                    nh[u] = 0.0;
+                    nq[u] = 0.0;
+                    if (t < MM) {
+                        const int i = t / M, j = t % M;
+                        const int ai = lo[i], bi = hi[i], aj = lo[j], bj = hi[j];
+                        const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
+                        const double wra = (i == ai) ? ci : si, wrb = (i == ai) ? -si : ci;
+                        const double wca = (j == aj) ? cj : sj, wcb = (j == aj) ? -sj : cj;
+                        nh[u] = wra * (wca * H[ai * M + aj] + wcb * H[ai * M + bj]) +
+                                wrb * (wca * H[bi * M + aj] + wcb * H[bi * M + bj]);
+                        nq[u] = wca * Q[i * M + aj] + wcb * Q[i * M + bj];
+                    }
+                }
+                wave_sync();
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int t = lane + 64 * u;
+                    if (t < MM) {
+                        H[t] = nh[u];
+                        Q[t] = nq[u];
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // sort ascending (selection sort by lane 0), permute the columns of Q
+        if (lane == 0) {
+            int* perm = iscr;
+            for (int k = 0; k < M; ++k) perm[k] = k;
+            for (int k = 0; k < M; ++k) {
+                int best = k;
+                for (int l = k + 1; l < M; ++l)
+                    if (H[perm[l] * M + perm[l]] < H[perm[best] * M + perm[best]]) best = l;
+                const int t = perm[k];
+                perm[k] = perm[best];
+                perm[best] = t;
+            }
+            for (int k = 0; k < M; ++k) th[k] = H[perm[k] * M + perm[k]];
+        }
+        wave_sync();
+        double nq[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = lane + 64 * u;
+            if (t < MM) nq[u] = Q[(t / M) * M + iscr[t % M]];
+        }
+        wave_sync();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = lane + 64 * u;
+            if (t < MM) Q[t] = nq[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Cholesky of the SPD M x M matrix G (upper factor R, G = R^T R) and the
+// inverse of R, by thread 0.  Returns false (in every thread) when G is not
+// numerically positive definite.
+template <int M>
+__device__ bool chol_inv_upper(const double* G, double* Rinv, double* scr, int* flag) {
+    if (threadIdx.x == 0) {
+        double* R = scr;   // M*M
+        int ok = 1;
+        for (int i = 0; i < M * M; ++i) R[i] = 0.0;
+        for (int j = 0; j < M; ++j) {
+            double d = G[j * M + j];
+            for (int k = 0; k < j; ++k) d -= R[k * M + j] * R[k * M + j];
+            if (!(d > 0.0)) {
+                ok = 0;
+                d = 1.0;
+            }
+            const double rjj = sqrt(d);
+            R[j * M + j] = rjj;
+            for (int i = j + 1; i < M; ++i) {
+                double v = G[j * M + i];
+                for (int k = 0; k < j; ++k) v -= R[k * M + j] * R[k * M + i];
+                R[j * M + i] = v / rjj;
+            }
+        }
+        // Rinv upper triangular: R Rinv = I
+        for (int i = 0; i < M * M; ++i) Rinv[i] = 0.0;
+        for (int j = 0; j < M; ++j) {
+            Rinv[j * M + j] = 1.0 / R[j * M + j];
+            for (int i = j - 1; i >= 0; --i) {
+                double v = 0.0;
+                for (int k = i + 1; k <= j; ++k) v += R[i * M + k] * Rinv[k * M + j];
+                Rinv[i * M + j] = -v / R[i * M + i];
+            }
+        }
+        *flag = ok;
+    }
+    __syncthreads();
+    const bool ok = *flag != 0;
+    __syncthreads();
+    return ok;
+}
+
+// Cluster rule on ascending values th[0..n-1] (n >= target+4 or all values):
+// keep `target`, grow to the end of a cluster of equal values up to
+// target+3, or shrink before the cluster when it runs past that cap.
+__device__ int cluster_cut_dev(const double* th, int n, int target, double rtol) {
+    if (target >= n) return n;
+    auto same = [&](int k) { return th[k] - th[k - 1] <= rtol * fmax(fabs(th[k]), 1e-12); };
+    int k = target;
+    const int cap = target + 3 < n ? target + 3 : n;
+    while (k < cap && same(k)) ++k;
+    if (k == cap && k < n && same(k)) {
+        k = target;
+        while (k > 1 && same(k)) --k;
+    }
+    return k;
+}
+
+// ---------------------------------------------------------------------------
+// Block storage: the current block lives in LDS as Y[j * ld + row] (ld odd,
+// so column-strided reads spread over the banks); each thread owns rows
+// threadIdx.x + r * blockDim.x, r < R, and keeps at most three M-vectors of
+// them in registers.
+
+template <int M>
+struct EigShared {
+    double red[8 * M * M];
+    double G[M * M];
+    double Q[M * M];
+    double Rinv[M * M];
+    double scr[M * M];
+    double th[M];
+    double nrm[M];
+    double misc[8];
+    int iscr[2 * M];
+    int flag;
+};
+
+// G = Y^T Y from LDS (symmetric)
+template <int M>
+__device__ void gram_lds(const double* Y, int ld, int n, double* G, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll 1
+    for (int i = 0; i < M; ++i) {
+#pragma unroll 1
+        for (int j = i; j < M; ++j) {
+            double v = 0.0;
+            for (int row = threadIdx.x; row < n; row += blockDim.x) v += Y[i * ld + row] * Y[j * ld + row];
+            v = wave_sum(v);
+            if (lane == 0) red[w * M * M + i * M + j] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+        const int i = t / M, j = t % M;
+        if (i <= j) {
+            double s = 0.0;
+            for (int ww = 0; ww < nw; ++ww) s += red[ww * M * M + t];
+            G[t] = s;
+            G[j * M + i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// G = sym(Y^T Z): Y in LDS, Z in registers (rows of this thread)
+template <int M, int R>
+__device__ void gram_lds_reg(const double* Y, int ld, int n, const double (&Z)[R][M], double* G,
+                             double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll 1
+    for (int i = 0; i < M; ++i) {
+        double yi[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = threadIdx.x + r * blockDim.x;
+            yi[r] = row < n ? Y[i * ld + row] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v += yi[r] * Z[r][j];
+            v = wave_sum(v);
+            if (lane == 0) red[w * M * M + i * M + j] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+        const int i = t / M, j = t % M;
+        if (i <= j) {
+            double a = 0.0, b = 0.0;
+            for (int ww = 0; ww < nw; ++ww) {
+                a += red[ww * M * M + i * M + j];
+                b += red[ww * M * M + j * M + i];
+            }
+            const double s = 0.5 * (a + b);
+            G[i * M + j] = s;
+            G[j * M + i] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// column sums of squares of registers A into out[M]
+template <int M, int R>
+__device__ void colnorm2(const double (&A)[R][M], double* out, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v += A[r][j] * A[r][j];
+        v = wave_sum(v);
+        if (lane == 0) red[w * M + j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double s = 0.0;
+        for (int ww = 0; ww < nw; ++ww) s += red[ww * M + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// registers A <- A C (C: M*M in LDS)
+template <int M, int R>
+__device__ __forceinline__ void rmul(double (&A)[R][M], const double* C) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        double t[M];
+#pragma unroll
+        for (int j = 0; j < M; ++j) t[j] = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < M; ++i) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < M; ++k) a = (k == i) ? A[r][k] : a;
+#pragma unroll
+            for (int j = 0; j < M; ++j) t[j] += a * C[i * M + j];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) A[r][j] = t[j];
+    }
+}
+
+// LDS block Y <- Y C (rows of this thread), C: M*M in LDS
+template <int M, int R>
+__device__ void lds_rmul(double* Y, int ld, int n, const double* C) {
+    double t[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+#pragma unroll
+        for (int j = 0; j < M; ++j) t[r][j] = 0.0;
+        if (row < n) {
+#pragma unroll 1
+            for (int i = 0; i < M; ++i) {
+                const double y = Y[i * ld + row];
+#pragma unroll
+                for (int j = 0; j < M; ++j) t[r][j] += y * C[i * M + j];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+        if (row < n) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) Y[j * ld + row] = t[r][j];
+        }
+    }
+    __syncthreads();
+}
+
+template <int M, int R>
+__device__ __forceinline__ void store_block(double* Y, int ld, int n, const double (&A)[R][M]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+        if (row < n) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) Y[j * ld + row] = A[r][j];
+        }
+    }
+}
+
+template <int M, int R>
+__device__ __forceinline__ void load_block(const double* Y, int ld, int n, double (&A)[R][M]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+#pragma unroll
+        for (int j = 0; j < M; ++j) A[r][j] = row < n ? Y[j * ld + row] : 0.0;
+    }
+}
+
+// Orthonormalise the LDS block (Cholesky-QR, twice).
+template <int M, int R>
+__device__ void orthonormalise(double* Y, int ld, int n, EigShared<M>& sh) {
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+        gram_lds<M>(Y, ld, n, sh.G, sh.red);
+        if (!chol_inv_upper<M>(sh.G, sh.Rinv, sh.scr, &sh.flag)) {
+            if (threadIdx.x == 0) {
+                double mx = 0.0;
+                for (int i = 0; i < M; ++i) mx = fmax(mx, sh.G[i * M + i]);
+                for (int i = 0; i < M; ++i) sh.G[i * M + i] += 1e-12 * mx + 1e-300;
+            }
+            __syncthreads();
+            chol_inv_upper<M>(sh.G, sh.Rinv, sh.scr, &sh.flag);
+        }
+        lds_rmul<M, R>(Y, ld, n, sh.Rinv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// operators: out = A * (block in LDS), rows of this thread
+
+// Level 2: A~ = S^-1/2 A_K S^-1/2 on one 8^3 element, thread = cell.
+struct Op2 {
+    double diag;
+    double off[6];
+    int nb[6];
+    template <int M>
+    __device__ __forceinline__ void apply(const double* Y, int ld, double (&out)[1][M]) const {
+        const int c = threadIdx.x;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double s = diag * Y[j * ld + c];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) s -= off[d] * Y[j * ld + nb[d]];
+            out[0][j] = s;
+        }
+    }
+};
+
+// Levels >= 3: block 7-point H_E on the agg^3 children of E; row
+// r = p * Lp + a (child position p, slot a).
+template <int R>
+struct OpUp {
+    const double* Hd;     // [m_lo][Lp][Lp] child diagonal blocks (interior to E)
+    const double* Aoff;   // [m_lo][3][Lp][Lp]
+    int Lp, agg;
+    int row_child[R];     // child element of each row (-1: padded row)
+    int row_slot[R];
+    int row_pos[R];
+    int nbc[R][6];        // neighbour child inside E per direction (-1: none)
+    template <int M>
+    __device__ __forceinline__ void apply(const double* Y, int ld, double (&out)[R][M]) const {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) out[r][j] = 0.0;
+            const int c = row_child[r];
+            if (c < 0) continue;
+            const int a = row_slot[r], p = row_pos[r];
+            const double* hd = Hd + ((size_t)c * Lp + a) * Lp;
+#pragma unroll 1
+            for (int b = 0; b < Lp; ++b) {
+                const double h = hd[b];
+                if (h != 0.0) {
+#pragma unroll
+                    for (int j = 0; j < M; ++j) out[r][j] += h * Y[j * ld + p * Lp + b];
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                const int cn = nbc[r][d];
+                if (cn < 0) continue;
+                const int ax = d >> 1;
+                const int step = (ax == 0) ? 1 : (ax == 1 ? agg : agg * agg);
+                const int pn = (d & 1) ? p + step : p - step;
+#pragma unroll 1
+                for (int b = 0; b < Lp; ++b) {
+                    // + direction: A(c, cn) = Aoff[c][ax]; - direction: Aoff[cn][ax]^T
+                    const double h = (d & 1) ? Aoff[(((size_t)c * 3 + ax) * Lp + a) * Lp + b]
+                                             : Aoff[(((size_t)cn * 3 + ax) * Lp + b) * Lp + a];
+                    if (h != 0.0) {
+#pragma unroll
+                        for (int j = 0; j < M; ++j) out[r][j] += h * Y[j * ld + pn * Lp + b];
+                    }
+                }
+            }
+        }
+    }
+};
+
+// Chebyshev filter of degree kDeg applied to X (registers); the filtered
+// block is left in LDS.  Wanted spectrum below a, damped interval [a, b],
+// a0 below the whole spectrum.
+template <int M, int R, class OP>
+__device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, int n, double a, double b,
+                            double a0) {
+    const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
+    double sigma = e / (a0 - cc);
+    const double tau = 2.0 / sigma;
+    double T[R][M];
+    store_block<M, R>(Y, ld, n, X);
+    __syncthreads();
+    op.template apply<M>(Y, ld, T);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < M; ++j) T[r][j] = (T[r][j] - cc * X[r][j]) * (sigma / e);
+    __syncthreads();
+    store_block<M, R>(Y, ld, n, T);
+    __syncthreads();
+#pragma unroll 1
+    for (int it = 2; it <= kDeg; ++it) {
+        const double sn = 1.0 / (tau - sigma);
+        op.template apply<M>(Y, ld, T);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = threadIdx.x + r * blockDim.x;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double yc = row < n ? Y[j * ld + row] : 0.0;
+                T[r][j] = (T[r][j] - cc * yc) * (2.0 * sn / e) - (sigma * sn) * X[r][j];
+                X[r][j] = yc;
+            }
+        }
+        __syncthreads();
+        store_block<M, R>(Y, ld, n, T);
+        __syncthreads();
+        sigma = sn;
+    }
+}
+
+// Rayleigh-Ritz on the orthonormal LDS block Y: X = Y Q, AX = A X,
+// sh.th ascending.
+template <int M, int R, class OP>
+__device__ void rayleigh_ritz(const OP& op, const double* Y, int ld, int n, double (&X)[R][M],
+                              double (&AX)[R][M], EigShared<M>& sh) {
+    op.template apply<M>(Y, ld, AX);
+    gram_lds_reg<M, R>(Y, ld, n, AX, sh.G, sh.red);
+    jacobi_eig<M>(sh.G, sh.Q, sh.th, sh.scr, sh.iscr);
+    load_block<M, R>(Y, ld, n, X);
+    rmul<M, R>(X, sh.Q);
+    rmul<M, R>(AX, sh.Q);
+}
+
+// Full CheFSI loop.  X holds the start block on entry and the Ritz vectors
+// on exit, AX = A X.  Returns the number of cycles, or -1 when the residual
+// tolerance (relative to bnd) was not met within kMaxCycles.
+template <int M, int R, class OP>
+__device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M], double (&AX)[R][M],
+                      double bnd, int need, double tol, EigShared<M>& sh) {
+    store_block<M, R>(Y, ld, n, X);
+    __syncthreads();
+    orthonormalise<M, R>(Y, ld, n, sh);
+    for (int cyc = 0;; ++cyc) {
+        rayleigh_ritz<M, R>(op, Y, ld, n, X, AX, sh);
+        {
+            double Rs[R][M];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int j = 0; j < M; ++j) Rs[r][j] = AX[r][j] - sh.th[j] * X[r][j];
+            colnorm2<M, R>(Rs, sh.nrm, sh.red);
+        }
+        double worst = 0.0;
+        for (int j = 0; j < need; ++j) worst = fmax(worst, sqrt(sh.nrm[j]));
+        if (worst <= tol * bnd) return cyc;
+        if (cyc >= kMaxCycles) return -1;
+        const double a = fmin(sh.th[M - 1], 0.5 * bnd);
+        const double a0 = fmin(sh.th[0], 0.0) - 1e-3 * bnd;
+        __syncthreads();
+        cheb_filter<M, R>(op, X, Y, ld, n, a, bnd, a0);
+        orthonormalise<M, R>(Y, ld, n, sh);
+    }
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t = fmax(t, sh[i]);
+    __syncthreads();
+    return t;
+}
+
+// Per-column sums over all rows of registers A, written (by threads < cnt) to
+// dst[j] (j < nk) and zero for nk <= j < cnt.
+template <int M, int R>
+__device__ void column_sums(const double (&A)[R][M], double* dst, int cnt, int nk, double* red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v += A[r][j];
+        v = wave_sum(v);
+        if (lane == 0) red[w * M + j] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+        double s = 0.0;
+        for (int ww = 0; ww < nw; ++ww) s += red[ww * M + threadIdx.x];
+        dst[threadIdx.x] = ((int)threadIdx.x < nk) ? s : 0.0;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// level 2 kernel: one 512-thread workgroup per 8^3 element
+template <int M>
+__global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restrict__ kt, int target, int L,
+                                              double tol, double crtol, double* __restrict__ phi,
+                                              double* __restrict__ lam, int* __restrict__ nkeep,
+                                              double* __restrict__ Aint, double* __restrict__ zc,
+                                              int* __restrict__ status) {
+    constexpr int LD = 513;
+    __shared__ double sY[M * LD];
+    __shared__ EigShared<M> sh;
+    const int e = blockIdx.x;
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    const int c = threadIdx.x;
+    const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+    auto gid = [&](int x, int y, int z) {
+        return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    };
+    const double kc = kt[gid(ex * 8 + i, ey * 8 + j, ez * 8 + k)];
+    const double S = 3.0 * kc;
+    const double sq = sqrt(S);
+    Op2 op;
+    double diag = 0.0, rowsum = 0.0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int ii = i + (d == 0 ? -1 : (d == 1 ? 1 : 0));
+        const int jj = j + (d == 2 ? -1 : (d == 3 ? 1 : 0));
+        const int kk = k + (d == 4 ? -1 : (d == 5 ? 1 : 0));
+        op.off[d] = 0.0;
+        op.nb[d] = c;
+        if (ii >= 0 && ii < 8 && jj >= 0 && jj < 8 && kk >= 0 && kk < 8) {
+            const double kn = kt[gid(ex * 8 + ii, ey * 8 + jj, ez * 8 + kk)];
+            const double T = harm_e(kc, kn);
+            diag += T;
+            op.off[d] = T / (sq * sqrt(3.0 * kn));
+            op.nb[d] = ii + 8 * (jj + 8 * kk);
+            rowsum += op.off[d];
+        }
+    }
+    op.diag = diag / S;
+    const double bnd = block_max(op.diag + rowsum, sh.misc);
+
+    double X[1][M], AX[1][M];
+    const double pi8 = 3.14159265358979323846 / 8.0;
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) {
+        const double md = cos(pi8 * kModes[jj][0] * (i + 0.5)) * cos(pi8 * kModes[jj][1] * (j + 0.5)) *
+                          cos(pi8 * kModes[jj][2] * (k + 0.5));
+        X[0][jj] = sq * (md + 0.05 * hash_noise((unsigned)e, (unsigned)jj, (unsigned)c));
+    }
+    const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
+    const int cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, sh);
+
+    if (threadIdx.x == 0) {
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        sh.flag = nk;
+        nkeep[e] = nk;
+        status[e] = cyc;
+        for (int a = 0; a < L; ++a) lam[(size_t)e * L + a] = sh.th[a];
+    }
+    __syncthreads();
+    const int nk = sh.flag;
+    __syncthreads();
+    // interior block X^T A~ X on the kept vectors (= Phi^T A_K Phi)
+    store_block<M, 1>(sY, LD, 512, X);
+    __syncthreads();
+    gram_lds_reg<M, 1>(sY, LD, 512, AX, sh.G, sh.red);
+    for (int t = threadIdx.x; t < L * L; t += blockDim.x) {
+        const int a = t / L, b = t % L;
+        Aint[(size_t)e * L * L + t] = (a < nk && b < nk) ? sh.G[a * M + b] : 0.0;
+    }
+    // coefficients of the constant function: Phi^T S 1 = X^T S^1/2 1
+    double zv[1][M];
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) zv[0][jj] = X[0][jj] * sq;
+    column_sums<M, 1>(zv, zc + (size_t)e * L, L, nk, sh.red);
+#pragma unroll
+    for (int jj = 0; jj < M; ++jj) {
+        if (jj < L) phi[((size_t)e * L + jj) * 512 + c] = (jj < nk) ? X[0][jj] / sq : 0.0;
+    }
+}
+
+// Hd[c] = Aint[c] + sum of D[c][d] over the faces of c interior to its parent
+__global__ void k_build_hd(CoarseGeom lo, const double* __restrict__ Aint, const double* __restrict__ D,
+                           double* __restrict__ Hd) {
+    const int c = blockIdx.x;
+    const int L = lo.L;
+    const int cx = c % lo.mx, cy = (c / lo.mx) % lo.my, cz = c / (lo.mx * lo.my);
+    const int q0 = cx % lo.agg, q1 = cy % lo.agg, q2 = cz % lo.agg;
+    for (int t = threadIdx.x; t < L * L; t += blockDim.x) {
+        double v = Aint[(size_t)c * L * L + t];
+        for (int d = 0; d < 6; ++d) {
+            const int ax = d >> 1;
+            const int q = ax == 0 ? q0 : (ax == 1 ? q1 : q2);
+            const bool interior = (d & 1) ? (q < lo.agg - 1) : (q > 0);
+            if (interior) v += D[((size_t)c * 6 + d) * L * L + t];
+        }
+        Hd[(size_t)c * L * L + t] = v;
+    }
+}
+
+// level >= 3 kernel: one 512-thread workgroup per parent element E
+template <int M, int R>
+__global__ __launch_bounds__(512) void k_eig_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Hd,
+                                                const double* __restrict__ Aoff,
+                                                const int* __restrict__ nkeep_lo,
+                                                const double* __restrict__ zlo, int target, double tol,
+                                                double crtol, double* __restrict__ V,
+                                                double* __restrict__ lam, int* __restrict__ nkeep,
+                                                double* __restrict__ Aint, double* __restrict__ zup,
+                                                int* __restrict__ status) {
+    extern __shared__ double dyn[];
+    __shared__ EigShared<M> sh;
+    const int E = blockIdx.x;
+    const int agg = lo.agg, Lp = lo.L, Lu = up.L;
+    const int n = agg * agg * agg * Lp;
+    const int ld = n | 1;
+    const int Ex = E % up.mx, Ey = (E / up.mx) % up.my, Ez = E / (up.mx * up.my);
+    OpUp<R> op;
+    op.Hd = Hd;
+    op.Aoff = Aoff;
+    op.Lp = Lp;
+    op.agg = agg;
+    double rb = 0.0;
+    double X[R][M], AX[R][M];
+    double zr[R];
+    const double pa = 3.14159265358979323846 / agg;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+        op.row_child[r] = -1;
+        op.row_slot[r] = 0;
+        op.row_pos[r] = 0;
+        zr[r] = 0.0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) op.nbc[r][d] = -1;
+#pragma unroll
+        for (int j = 0; j < M; ++j) X[r][j] = 0.0;
+        if (row >= n) continue;
+        const int p = row / Lp, a = row % Lp;
+        const int qx = p % agg, qy = (p / agg) % agg, qz = p / (agg * agg);
+        const int c = (Ex * agg + qx) + lo.mx * ((Ey * agg + qy) + lo.my * (Ez * agg + qz));
+        if (a >= nkeep_lo[c]) continue;
+        op.row_child[r] = c;
+        op.row_slot[r] = a;
+        op.row_pos[r] = p;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int ax = d >> 1;
+            const int q = ax == 0 ? qx : (ax == 1 ? qy : qz);
+            const int stride = ax == 0 ? 1 : (ax == 1 ? lo.mx : lo.mx * lo.my);
+            const bool in = (d & 1) ? (q < agg - 1) : (q > 0);
+            if (in) op.nbc[r][d] = (d & 1) ? c + stride : c - stride;
+        }
+        double s = 0.0;
+        for (int b = 0; b < Lp; ++b) s += fabs(Hd[((size_t)c * Lp + a) * Lp + b]);
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            const int cn = op.nbc[r][d];
+            if (cn < 0) continue;
+            const int ax = d >> 1;
+            for (int b = 0; b < Lp; ++b)
+                s += fabs((d & 1) ? Aoff[(((size_t)c * 3 + ax) * Lp + a) * Lp + b]
+                                  : Aoff[(((size_t)cn * 3 + ax) * Lp + b) * Lp + a]);
+        }
+        rb = fmax(rb, s);
+        zr[r] = zlo[(size_t)c * Lp + a];
+        // start block: the constant function, smooth weights of the
+        // children's constant modes, and noise on every kept slot
+        const double az = fabs(zr[r]) + 1e-300;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
+            if (j == 0) v = zr[r];
+            else if (a == 0)
+                v += zr[r] * cos(pa * kModes[j & 15][0] * (qx + 0.5)) * cos(pa * kModes[j & 15][1] * (qy + 0.5)) *
+                     cos(pa * kModes[j & 15][2] * (qz + 0.5));
+            X[r][j] = v;
+        }
+    }
+    const double bnd = block_max(rb, sh.misc);
+    const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
+    const int cyc = chefsi<M, R>(op, dyn, ld, n, X, AX, bnd, need, tol, sh);
+    if (threadIdx.x == 0) {
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        sh.flag = nk;
+        nkeep[E] = nk;
+        status[E] = cyc;
+        for (int a = 0; a < Lu; ++a) lam[(size_t)E * Lu + a] = sh.th[a];
+    }
+    __syncthreads();
+    const int nk = sh.flag;
+    __syncthreads();
+    store_block<M, R>(dyn, ld, n, X);
+    __syncthreads();
+    gram_lds_reg<M, R>(dyn, ld, n, AX, sh.G, sh.red);
+    for (int t = threadIdx.x; t < Lu * Lu; t += blockDim.x) {
+        const int a = t / Lu, b = t % Lu;
+        Aint[(size_t)E * Lu * Lu + t] = (a < nk && b < nk) ? sh.G[a * M + b] : 0.0;
+    }
+    double zv[R][M];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int jj = 0; jj < M; ++jj) zv[r][jj] = X[r][jj] * zr[r];
+    column_sums<M, R>(zv, zup + (size_t)E * Lu, Lu, nk, sh.red);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = threadIdx.x + r * blockDim.x;
+        if (row >= n) continue;
+#pragma unroll
+        for (int jj = 0; jj < M; ++jj)
+            if (jj < Lu) V[((size_t)E * Lu + jj) * n + row] = (jj < nk) ? X[r][jj] : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+#define SPECMG_M_DISPATCH(MV, ...)                   \
+    switch (MV) {                                    \
+        case 10: {                                   \
+            constexpr int M = 10;                    \
+            __VA_ARGS__;                             \
+        } break;                                     \
+        case 12: {                                   \
+            constexpr int M = 12;                    \
+            __VA_ARGS__;                             \
+        } break;                                     \
+        default: {                                   \
+            constexpr int M = 14;                    \
+            __VA_ARGS__;                             \
+        } break;                                     \
+    }
+
+void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
+                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, hipStream_t s) {
+    const int m = g.mx * g.my * g.mz;
+    const int L = target + 3;
+    SPECMG_M_DISPATCH(nvec, hipLaunchKernelGGL((k_eig2<M>), dim3(m), dim3(512), 0, s, g, kt, target, L, tol,
+                                               crtol, phi, lam, nkeep, Aint, zc, status));
+}
+
+void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
+                   const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
+                   int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,
+                   double* Aint, double* zup, int* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_hd, dim3(lo.m), dim3(128), 0, s, lo, Aint_lo, Dlo, Hd_work);
+    const int n = lo.agg * lo.agg * lo.agg * lo.L;
+    const size_t shmem = (size_t)nvec * (n | 1) * sizeof(double);
+    if (n <= 512) {
+        SPECMG_M_DISPATCH(nvec, hipFuncSetAttribute((const void*)k_eig_up<M, 1>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+                          hipLaunchKernelGGL((k_eig_up<M, 1>), dim3(up.m), dim3(512), shmem, s, lo, up, Hd_work,
+                                             Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint,
+                                             zup, status));
+    } else {
+        SPECMG_M_DISPATCH(nvec, hipFuncSetAttribute((const void*)k_eig_up<M, 2>,
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+                          hipLaunchKernelGGL((k_eig_up<M, 2>), dim3(up.m), dim3(512), shmem, s, lo, up, Hd_work,
+                                             Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint,
+                                             zup, status));
+    }
+}
+
+}  // namespace specmg

@@ -1,0 +1,712 @@
+// Fine-level kernels: the 7-point TPFA operator (eq. p / eq. discrete varia
+// with harmonic-mean faces, fig. kappa edge), the block-Jacobi IC(0)
+// smoother on the 8^3 coarse elements (Section 5), restriction/prolongation
+// through the level-2 spectral bases (Algorithm 1, steps 2 and 8) and the
+// fused CG vector updates.
+//
+// Tiling: a workgroup owns EX level-2 elements along x, i.e. an (8 EX)x8x8
+// cell tile, with one wavefront per element.  Stencil phases stage the tile
+// plus a one-cell halo in LDS; the IC(0) sweeps walk the 22 hyperplanes
+// i+j+k = s of each element (cells on a hyperplane only depend on the
+// previous one for lexicographic IC(0)).
+#include "common.hpp"
+
+namespace specmg {
+
+// ---------------------------------------------------------------------------
+// hyperplane table of an 8^3 block: cells sorted by i+j+k
+struct PlaneTable {
+    unsigned short cell[512];
+    unsigned short off[23];
+};
+
+constexpr PlaneTable make_planes() {
+    PlaneTable t{};
+    int p = 0;
+    for (int s = 0; s < kPlanes; ++s) {
+        t.off[s] = (unsigned short)p;
+        for (int k = 0; k < 8; ++k)
+            for (int j = 0; j < 8; ++j) {
+                int i = s - j - k;
+                if (i >= 0 && i < 8) t.cell[p++] = (unsigned short)(i + 8 * (j + 8 * k));
+            }
+    }
+    t.off[kPlanes] = (unsigned short)p;
+    return t;
+}
+
+__constant__ PlaneTable kPT = make_planes();
+
+template <typename T>
+__device__ __forceinline__ T harm(T a, T b) {
+    // harmonic mean 2ab/(a+b); zero when a neighbour is outside the domain
+    const T s = a + b;
+    return s > T(0) ? (T(2) * a * b) / s : T(0);
+}
+
+template <int EX>
+struct TileT {
+    static constexpr int TX = 8 * EX;
+    static constexpr int NT = 64 * EX;
+    static constexpr int HX = TX + 2;
+    static constexpr int HXY = HX * 10;
+    static constexpr int NH = HX * 100;
+    static constexpr int NC = TX * 64;
+};
+
+__device__ __forceinline__ void tile_origin(const FineGeom& g, int& x0, int& y0, int& z0) {
+    int t = blockIdx.x;
+    if (g.xcd_remap) {
+        const int per = g.ntiles >> 3;
+        t = (t & 7) * per + (t >> 3);
+    }
+    const int tx = t % g.ntx;
+    const int r = t / g.ntx;
+    x0 = tx * 8 * g.ex;
+    y0 = (r % g.nty) * 8;
+    z0 = (r / g.nty) * 8;
+}
+
+__device__ __forceinline__ size_t gidx(const FineGeom& g, int x, int y, int z) {
+    return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+}
+
+// tile (with one-cell halo) of a global cell array into LDS, zero outside Omega
+template <int EX, typename S, typename D>
+__device__ __forceinline__ void load_halo(const FineGeom& g, const S* __restrict__ src, D* dst, int x0,
+                                          int y0, int z0) {
+    using TT = TileT<EX>;
+    for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
+        const int hx = h % TT::HX;
+        const int r = h / TT::HX;
+        const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, z = z0 + (r / 10) - 1;
+        D v = D(0);
+        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) v = (D)src[gidx(g, x, y, z)];
+        dst[h] = v;
+    }
+}
+
+// p = z + beta * pold on the haloed tile
+template <int EX>
+__device__ __forceinline__ void load_halo_p(const FineGeom& g, const double* __restrict__ z,
+                                            const double* __restrict__ pold, double beta, int first,
+                                            double* dst, int x0, int y0, int z0) {
+    using TT = TileT<EX>;
+    for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
+        const int hx = h % TT::HX;
+        const int r = h / TT::HX;
+        const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, zz = z0 + (r / 10) - 1;
+        double v = 0.0;
+        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && zz >= 0 && zz < g.nz) {
+            const size_t i = gidx(g, x, y, zz);
+            v = first ? z[i] : z[i] + beta * pold[i];
+        }
+        dst[h] = v;
+    }
+}
+
+// (A u) at haloed index h
+template <int EX, typename T>
+__device__ __forceinline__ T apply_stencil(const T* U, const T* K, int h) {
+    constexpr int HX = TileT<EX>::HX, HXY = TileT<EX>::HXY;
+    const T uc = U[h], kc = K[h];
+    T a = harm(kc, K[h - 1]) * (uc - U[h - 1]);
+    a += harm(kc, K[h + 1]) * (uc - U[h + 1]);
+    a += harm(kc, K[h - HX]) * (uc - U[h - HX]);
+    a += harm(kc, K[h + HX]) * (uc - U[h + HX]);
+    a += harm(kc, K[h - HXY]) * (uc - U[h - HXY]);
+    a += harm(kc, K[h + HXY]) * (uc - U[h + HXY]);
+    return a;
+}
+
+template <int EX>
+__device__ __forceinline__ int hidx(int x, int y, int z) {
+    return (x + 1) + TileT<EX>::HX * ((y + 1) + 10 * (z + 1));
+}
+
+// Forward and backward IC(0) substitution on the element of this wavefront.
+// Y (tile layout, no halo): in t, out (D+L^T)^{-1} D (D+L)^{-1} t.
+// ID: inverse pivots (tile layout).  K: kappa~ in tile layout (HALO = 0) or
+// haloed layout (HALO = 1).  a_ij = -T_ij off the diagonal.
+template <int EX, int HALO, typename T>
+__device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* K) {
+    constexpr int TX = TileT<EX>::TX;
+    constexpr int KX = HALO ? TileT<EX>::HX : TX;
+    constexpr int KXY = HALO ? TileT<EX>::HXY : TX * 8;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    for (int s = 0; s < kPlanes; ++s) {
+        const int o = kPT.off[s];
+        const int cnt = kPT.off[s + 1] - o;
+        if (lane < cnt) {
+            const int c = kPT.cell[o + lane];
+            const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+            const int ti = 8 * w + i + TX * (j + 8 * k);
+            const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
+            const T kc = K[ki];
+            T acc = Y[ti];
+            if (i > 0) acc += harm(kc, K[ki - 1]) * Y[ti - 1];
+            if (j > 0) acc += harm(kc, K[ki - KX]) * Y[ti - TX];
+            if (k > 0) acc += harm(kc, K[ki - KXY]) * Y[ti - 8 * TX];
+            Y[ti] = acc * ID[ti];
+        }
+        __syncthreads();
+    }
+    for (int s = kPlanes - 1; s >= 0; --s) {
+        const int o = kPT.off[s];
+        const int cnt = kPT.off[s + 1] - o;
+        if (lane < cnt) {
+            const int c = kPT.cell[o + lane];
+            const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+            const int ti = 8 * w + i + TX * (j + 8 * k);
+            const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
+            const T kc = K[ki];
+            T acc = T(0);
+            if (i < 7) acc += harm(kc, K[ki + 1]) * Y[ti + 1];
+            if (j < 7) acc += harm(kc, K[ki + KX]) * Y[ti + TX];
+            if (k < 7) acc += harm(kc, K[ki + KXY]) * Y[ti + 8 * TX];
+            Y[ti] = Y[ti] + ID[ti] * acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pre-smoothing: (optionally r -= alpha q with ||r||^2) then u = M^{-1} r
+// mode bit0: update r and reduce ||r||^2 (sets the converged flag)
+// mode bit1: return at once when the solve is finished
+template <int EX, typename T>
+__global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __restrict__ kt,
+                                                        const T* __restrict__ invd, double* r,
+                                                        const double* __restrict__ q, T* __restrict__ u,
+                                                        Scalars* sc, RedBuf rb, int mode) {
+    using TT = TileT<EX>;
+    if ((mode & 2) && sc->done) return;
+    __shared__ T sK[TT::NC];
+    __shared__ T sY[TT::NC];
+    __shared__ T sD[TT::NC];
+    __shared__ double sred[EX];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    const double alpha = (mode & 1) ? sc->alpha : 0.0;
+    double rr = 0.0;
+    for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
+        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
+        const size_t gi = gidx(g, x0 + x, y0 + y, z0 + z);
+        double rv = r[gi];
+        if (mode & 1) {
+            rv -= alpha * q[gi];
+            r[gi] = rv;
+            rr += rv * rv;
+        }
+        sY[c] = (T)rv;
+        sK[c] = kt[gi];
+        sD[c] = invd[gi];
+    }
+    if (mode & 1) {
+        double v[1] = {block_sum(rr, sred)};
+        double out[1];
+        if (grid_reduce<1>(v, rb, RS_RR, out)) {
+            if (threadIdx.x == 0) {
+                sc->rr = out[0];
+                if (!(out[0] <= sc->thresh2)) {
+                    if (!isfinite(out[0])) sc->done = 2;
+                } else {
+                    sc->done = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    ic_sweep<EX, 0, T>(sY, sD, sK);
+    for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
+        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
+        u[gidx(g, x0 + x, y0 + y, z0 + z)] = sY[c];
+    }
+}
+
+// s = r - A u, then r2[e][j] = sum_c phi[e][j][c] s_c for every element
+template <int EX, typename T>
+__global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
+                                                            const T* __restrict__ u,
+                                                            const double* __restrict__ r,
+                                                            const T* __restrict__ phi,
+                                                            const int* __restrict__ nkeep, int L,
+                                                            T* __restrict__ r2, const Scalars* sc,
+                                                            int check_done) {
+    using TT = TileT<EX>;
+    if (check_done && sc->done) return;
+    __shared__ T sU[TT::NH];
+    __shared__ T sK[TT::NH];
+    __shared__ T sS[TT::NC];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_halo<EX>(g, u, sU, x0, y0, z0);
+    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    __syncthreads();
+    {
+        const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+        for (int z = 0; z < 8; ++z) {
+            const int h = hidx<EX>(tx, ty, z);
+            const T s = (T)r[gidx(g, x0 + tx, y0 + ty, z0 + z)] - apply_stencil<EX, T>(sU, sK, h);
+            sS[tx + TT::TX * (ty + 8 * z)] = s;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = (x0 >> 3) + w + g.mx * ((y0 >> 3) + g.my * (z0 >> 3));
+    T sv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int c = lane + 64 * i;
+        sv[i] = sS[8 * w + (c & 7) + TT::TX * (c >> 3)];
+    }
+    const int nk = nkeep[e];
+    const T* ph = phi + (size_t)e * L * kSub3;
+    for (int jj = 0; jj < L; ++jj) {
+        T acc = T(0);
+        if (jj < nk) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc += ph[(size_t)jj * kSub3 + lane + 64 * i] * sv[i];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) r2[(size_t)e * L + jj] = acc;
+    }
+}
+
+// u += phi e2 on every element (prolongation, Algorithm 1 step 8)
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const T* __restrict__ phi,
+                                                  const int* __restrict__ nkeep, int L,
+                                                  const T* __restrict__ e2, const Scalars* sc,
+                                                  int check_done) {
+    if (check_done && sc->done) return;
+    const int e = blockIdx.x;
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    const int nk = nkeep[e];
+    const T* ph = phi + (size_t)e * L * kSub3;
+    const T* ee = e2 + (size_t)e * L;
+    for (int c = threadIdx.x; c < kSub3; c += 256) {
+        T acc = T(0);
+        for (int jj = 0; jj < nk; ++jj) acc += ph[(size_t)jj * kSub3 + c] * ee[jj];
+        const size_t gi = gidx(g, ex * 8 + (c & 7), ey * 8 + ((c >> 3) & 7), ez * 8 + (c >> 6));
+        u[gi] += acc;
+    }
+}
+
+// post-smoothing: t = r - A u;  z = u + M^{-1} t  (Algorithm 1 step 9)
+// mode bit0: reduce r.z (and z.q when flexible) and update the CG beta
+// mode bit1: return at once when the solve is finished
+template <int EX, typename T>
+__global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __restrict__ kt,
+                                                         const T* __restrict__ invd,
+                                                         const T* __restrict__ u,
+                                                         const double* __restrict__ r,
+                                                         const double* __restrict__ q,
+                                                         double* __restrict__ z, Scalars* sc, RedBuf rb,
+                                                         int mode) {
+    using TT = TileT<EX>;
+    if ((mode & 2) && sc->done) return;
+    __shared__ T sU[TT::NH];
+    __shared__ T sK[TT::NH];
+    __shared__ T sY[TT::NC];
+    __shared__ T sD[TT::NC];
+    __shared__ double sred[EX];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_halo<EX>(g, u, sU, x0, y0, z0);
+    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    __syncthreads();
+    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+    for (int zz = 0; zz < 8; ++zz) {
+        const int h = hidx<EX>(tx, ty, zz);
+        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
+        const int ti = tx + TT::TX * (ty + 8 * zz);
+        sY[ti] = (T)r[gi] - apply_stencil<EX, T>(sU, sK, h);
+        sD[ti] = invd[gi];
+    }
+    __syncthreads();
+    ic_sweep<EX, 1, T>(sY, sD, sK);
+    double rz = 0.0, zq = 0.0;
+    const int flex = (mode & 1) ? sc->flexible : 0;
+    for (int zz = 0; zz < 8; ++zz) {
+        const int h = hidx<EX>(tx, ty, zz);
+        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
+        const double zv = (double)sU[h] + (double)sY[tx + TT::TX * (ty + 8 * zz)];
+        z[gi] = zv;
+        if (mode & 1) {
+            rz += r[gi] * zv;
+            if (flex) zq += zv * q[gi];
+        }
+    }
+    if (mode & 1) {
+        double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
+        double out[2];
+        if (grid_reduce<2>(v, rb, RS_RZ, out)) {
+            if (threadIdx.x == 0) {
+                const double old = sc->rz;
+                double beta = 0.0;
+                if (old != 0.0) beta = flex ? (-sc->alpha * out[1] / old) : (out[0] / old);
+                sc->beta = beta;
+                sc->rz_new = out[0];
+                sc->zq = out[1];
+                sc->rz = out[0];
+            }
+        }
+    }
+}
+
+// p = z + beta pold (or p = z), x += alpha_x pold, q = A p, alpha = rz / p.q
+template <int EX>
+__global__ __launch_bounds__(64 * EX) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
+                                                      const double* __restrict__ zv,
+                                                      const double* __restrict__ pold,
+                                                      double* __restrict__ pnew, double* x,
+                                                      double* __restrict__ q, Scalars* sc, RedBuf rb,
+                                                      int first, int pbuf) {
+    using TT = TileT<EX>;
+    if (sc->done) return;
+    __shared__ double sP[TT::NH];
+    __shared__ double sK[TT::NH];
+    __shared__ double sred[EX];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    const double beta = sc->beta;
+    const double ax = first ? 0.0 : sc->alpha_x;
+    load_halo_p<EX>(g, zv, pold, beta, first, sP, x0, y0, z0);
+    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    __syncthreads();
+    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+    double pq = 0.0;
+    for (int zz = 0; zz < 8; ++zz) {
+        const int h = hidx<EX>(tx, ty, zz);
+        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
+        const double p = sP[h];
+        const double qq = apply_stencil<EX, double>(sP, sK, h);
+        if (!first && ax != 0.0) x[gi] += ax * pold[gi];
+        pnew[gi] = p;
+        q[gi] = qq;
+        pq += p * qq;
+    }
+    double v[1] = {block_sum(pq, sred)};
+    double out[1];
+    if (grid_reduce<1>(v, rb, RS_PQ, out)) {
+        if (threadIdx.x == 0) {
+            sc->pq = out[0];
+            sc->iter += 1;
+            sc->pbuf = pbuf;
+            if (!(out[0] > 0.0) || !isfinite(out[0])) {
+                sc->done = 2;
+                sc->alpha = 0.0;
+                sc->alpha_x = 0.0;
+            } else {
+                sc->alpha = sc->rz / out[0];
+                sc->alpha_x = sc->alpha;
+            }
+        }
+    }
+}
+
+// y = A x  (resid = 0)   or   y = b - A x  (resid = 1)
+template <int EX>
+__global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* __restrict__ kt,
+                                                     const double* __restrict__ xv,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ y, int resid) {
+    using TT = TileT<EX>;
+    __shared__ double sX[TT::NH];
+    __shared__ double sK[TT::NH];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_halo<EX>(g, xv, sX, x0, y0, z0);
+    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    __syncthreads();
+    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+    for (int zz = 0; zz < 8; ++zz) {
+        const int h = hidx<EX>(tx, ty, zz);
+        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
+        const double a = apply_stencil<EX, double>(sX, sK, h);
+        y[gi] = resid ? b[gi] - a : a;
+    }
+}
+
+// IC(0) pivots of every 8^3 block: d_i = a_ii - sum_{j<i} a_ij^2 / d_j, with
+// a_ii summing all six faces (faces leaving the block included).
+template <int EX>
+__global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* __restrict__ kt,
+                                                      double* __restrict__ invd, float* invd32,
+                                                      int* bad) {
+    using TT = TileT<EX>;
+    __shared__ double sK[TT::NH];
+    __shared__ double sDg[TT::NC];
+    int x0, y0, z0;
+    tile_origin(g, x0, y0, z0);
+    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    __syncthreads();
+    constexpr int HX = TT::HX, HXY = TT::HXY, TX = TT::TX;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int s = 0; s < kPlanes; ++s) {
+        const int o = kPT.off[s];
+        const int cnt = kPT.off[s + 1] - o;
+        if (lane < cnt) {
+            const int c = kPT.cell[o + lane];
+            const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
+            const int ti = 8 * w + i + TX * (j + 8 * k);
+            const int h = hidx<EX>(8 * w + i, j, k);
+            const double kc = sK[h];
+            double diag = harm(kc, sK[h - 1]) + harm(kc, sK[h + 1]) + harm(kc, sK[h - HX]) +
+                          harm(kc, sK[h + HX]) + harm(kc, sK[h - HXY]) + harm(kc, sK[h + HXY]);
+            if (i > 0) {
+                const double t = harm(kc, sK[h - 1]);
+                diag -= t * t / sDg[ti - 1];
+            }
+            if (j > 0) {
+                const double t = harm(kc, sK[h - HX]);
+                diag -= t * t / sDg[ti - TX];
+            }
+            if (k > 0) {
+                const double t = harm(kc, sK[h - HXY]);
+                diag -= t * t / sDg[ti - 8 * TX];
+            }
+            sDg[ti] = diag;
+            if (!(diag > 0.0)) atomicOr(bad, 1);
+        }
+        __syncthreads();
+    }
+    for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
+        const int x = c % TX, y = (c / TX) & 7, z = c / (TX * 8);
+        const size_t gi = gidx(g, x0 + x, y0 + y, z0 + z);
+        const double v = 1.0 / sDg[c];
+        invd[gi] = v;
+        if (invd32) invd32[gi] = (float)v;
+    }
+}
+
+__global__ void k_perm_to_kt(const double* __restrict__ perm, double* __restrict__ kt, float* kt32,
+                             double scale, int64_t n, int* bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double p = perm[i];
+        if (!(p > 0.0) || !isfinite(p)) atomicOr(bad, 1);
+        const double v = p * scale;
+        kt[i] = v;
+        if (kt32) kt32[i] = (float)v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// vector utilities
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
+                                              int64_t n, double* out, RedBuf rb, int site) {
+    __shared__ double sred[4];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        s += a[i] * b[i];
+    double v[1] = {block_sum(s, sred)};
+    double o[1];
+    if (grid_reduce<1>(v, rb, site, o)) {
+        if (threadIdx.x == 0) *out = o[0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, int64_t n, double* out_sum,
+                                                  double* out_abs, RedBuf rb) {
+    __shared__ double sred[4];
+    double s = 0.0, t = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        s += a[i];
+        t += fabs(a[i]);
+    }
+    double v[2] = {block_sum(s, sred), block_sum(t, sred)};
+    double o[2];
+    if (grid_reduce<2>(v, rb, RS_GEN2, o)) {
+        if (threadIdx.x == 0) {
+            *out_sum = o[0];
+            *out_abs = o[1];
+        }
+    }
+}
+
+__global__ void k_axpy_x(double* x, const double* __restrict__ p0, const double* __restrict__ p1,
+                         Scalars* sc, int64_t n) {
+    const double a = sc->alpha_x;
+    const double* p = sc->pbuf ? p1 : p0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += a * p[i];
+}
+
+__global__ void k_clear_alpha_x(Scalars* sc) { sc->alpha_x = 0.0; }
+
+__global__ void k_sub_mean(double* x, int64_t n, const double* sum) {
+    const double m = *sum / (double)n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] -= m;
+}
+
+__global__ void k_fill(double* d, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = v;
+}
+
+__global__ void k_copy(double* d, const double* __restrict__ s, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
+}
+
+__global__ void k_pcg_init(Scalars* sc, double thresh2, int flexible) {
+    sc->rz = 0.0;
+    sc->rz_new = 0.0;
+    sc->pq = 0.0;
+    sc->alpha = 0.0;
+    sc->alpha_x = 0.0;
+    sc->beta = 0.0;
+    sc->rr = 0.0;
+    sc->thresh2 = thresh2;
+    sc->zq = 0.0;
+    sc->sum = 0.0;
+    sc->sum2 = 0.0;
+    sc->done = 0;
+    sc->iter = 0;
+    sc->flexible = flexible;
+    sc->pbuf = 0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+static inline int grid_1d(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+#define SPECMG_EX_DISPATCH(EXV, ...)          \
+    switch (EXV) {                            \
+        case 4: {                             \
+            constexpr int EX = 4;             \
+            __VA_ARGS__;                      \
+        } break;                              \
+        case 2: {                             \
+            constexpr int EX = 2;             \
+            __VA_ARGS__;                      \
+        } break;                              \
+        default: {                            \
+            constexpr int EX = 1;             \
+            __VA_ARGS__;                      \
+        } break;                              \
+    }
+
+template <typename T>
+void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q, T* u,
+                       Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_pre_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0, s,
+                                                g, kt, invd, r, q, u, sc, rb, mode));
+}
+
+template <typename T>
+void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
+                           const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s) {
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_resid_restrict<EX, T>), dim3(g.ntiles), dim3(64 * EX),
+                                                0, s, g, kt, u, r, phi, nkeep, L, r2, sc, check_done));
+}
+
+template <typename T>
+void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
+                    Scalars* sc, int check_done, hipStream_t s) {
+    hipLaunchKernelGGL((k_prolong<T>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
+                       sc, check_done);
+}
+
+template <typename T>
+void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
+                        const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
+                                                s, g, kt, invd, u, r, q, z, sc, rb, mode));
+}
+
+void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
+                     double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first, hipStream_t s) {
+    // pnew is buffer index 0 or 1 as chosen by the caller; recorded for the
+    // final x update
+    const int pbuf = first & 2 ? 1 : 0;
+    const int f = first & 1;
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_spmv_pcg<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
+                                                kt, z, pold, pnew, x, q, sc, rb, f, pbuf));
+}
+
+void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
+                    int resid, hipStream_t s) {
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_apply_A<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
+                                                kt, x, b, y, resid));
+}
+
+void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* invd32, int* bad,
+                     hipStream_t s) {
+    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_ic_setup<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
+                                                kt, invd, invd32, bad));
+}
+
+void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n, int* bad,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_to_kt, dim3(grid_1d(n)), dim3(256), 0, s, perm, kt, kt32, scale, n, bad);
+}
+
+void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_dot, dim3(grid_1d(n)), dim3(256), 0, s, a, b, n, out, rb, site);
+}
+
+void launch_sum_abs(const double* a, int64_t n, double* out_sum, double* out_abs, RedBuf rb,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_abs, dim3(grid_1d(n)), dim3(256), 0, s, a, n, out_sum, out_abs, rb);
+}
+
+void launch_axpy_x(double* x, const double* p0, const double* p1, Scalars* sc, int64_t n,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_x, dim3(grid_1d(n)), dim3(256), 0, s, x, p0, p1, sc, n);
+    hipLaunchKernelGGL(k_clear_alpha_x, dim3(1), dim3(1), 0, s, sc);
+}
+
+void launch_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_mean, dim3(grid_1d(n)), dim3(256), 0, s, x, n, sum);
+}
+
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n);
+}
+
+void launch_fill(double* dst, double v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_1d(n)), dim3(256), 0, s, dst, v, n);
+}
+
+void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1), 0, s, sc, thresh2, flexible);
+}
+
+template void launch_pre_smooth<double>(const FineGeom&, const double*, const double*, double*,
+                                        const double*, double*, Scalars*, RedBuf, int, hipStream_t);
+template void launch_pre_smooth<float>(const FineGeom&, const float*, const float*, double*,
+                                       const double*, float*, Scalars*, RedBuf, int, hipStream_t);
+template void launch_resid_restrict<double>(const FineGeom&, const double*, const double*, const double*,
+                                            const double*, const int*, int, double*, Scalars*, int,
+                                            hipStream_t);
+template void launch_resid_restrict<float>(const FineGeom&, const float*, const float*, const double*,
+                                           const float*, const int*, int, float*, Scalars*, int,
+                                           hipStream_t);
+template void launch_prolong<double>(const FineGeom&, double*, const double*, const int*, int,
+                                     const double*, Scalars*, int, hipStream_t);
+template void launch_prolong<float>(const FineGeom&, float*, const float*, const int*, int, const float*,
+                                    Scalars*, int, hipStream_t);
+template void launch_post_smooth<double>(const FineGeom&, const double*, const double*, const double*,
+                                         const double*, const double*, double*, Scalars*, RedBuf, int,
+                                         hipStream_t);
+template void launch_post_smooth<float>(const FineGeom&, const float*, const float*, const float*,
+                                        const double*, const double*, double*, Scalars*, RedBuf, int,
+                                        hipStream_t);
+
+}  // namespace specmg

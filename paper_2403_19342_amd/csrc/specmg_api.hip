@@ -1,0 +1,655 @@
+// C-ABI of the specmg library: context, set-up orchestration, the V-cycle
+// recursion and the preconditioned CG driver.  Every numerical step runs in
+// the kernels of k_fine / k_coarse / k_eig / k_dense; this file only sizes
+// buffers, sequences launches and moves a few scalars.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "../../include/specmg.h"
+
+using namespace specmg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                                  \
+    do {                                                           \
+        hipError_t _e = (x);                                       \
+        if (_e != hipSuccess) throw HipError{_e, #x};              \
+    } while (0)
+
+struct Level {
+    int l = 0;             // level index (2 = first coarse level)
+    CoarseGeom g{};        // element grid; parents filled unless coarsest
+    int L = 0;             // padded width
+    int rows = 0;          // basis rows per element: 512 (level 2) or agg^3 L_prev
+    std::vector<int> nkeep_h;
+    int dim = 0;
+    int* nkeep = nullptr;
+    int* status = nullptr;
+    double* lam = nullptr;
+    double* basis = nullptr;   // level 2: phi; level >= 3: V
+    double* Aint = nullptr;
+    double* D = nullptr;
+    double* Aoff = nullptr;
+    double* Ad = nullptr;
+    double* Dinv = nullptr;
+    double* z = nullptr;
+    float* basis32 = nullptr;
+    float* Aoff32 = nullptr;
+    float* Ad32 = nullptr;
+    float* Dinv32 = nullptr;
+    double *r = nullptr, *u = nullptr, *e = nullptr;
+    float *r32 = nullptr, *u32 = nullptr, *e32 = nullptr;
+};
+
+}  // namespace
+
+struct specmg_ctx {
+    specmg_grid grid{};
+    specmg_opts opts{};
+    int levels = 0, target = 0, L = 0, nvec = 0;
+    int fp32 = 0;
+    int64_t n = 0;
+    FineGeom fg{};
+    std::vector<void*> allocs;
+    double* kt = nullptr;
+    float* kt32 = nullptr;
+    double* invd = nullptr;
+    float* invd32 = nullptr;
+    std::vector<Level> lev;    // lev[0] = level 2
+    int nL = 0, npL = 0;
+    double* Pinv = nullptr;
+    int* cmap = nullptr;
+    // CG state
+    double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *u1 = nullptr;
+    float* u1_32 = nullptr;
+    double* dtmp = nullptr;     // scratch scalars
+    int* dflag = nullptr;       // error flags
+    Scalars* sc = nullptr;
+    Scalars* sc_host = nullptr; // pinned
+    RedBuf rb{};
+    specmg_solve_info setup_info{};
+
+    template <typename T>
+    T* alloc(size_t count) {
+        void* ptr = nullptr;
+        if (count == 0) count = 1;
+        HIPCHK(hipMalloc(&ptr, count * sizeof(T)));
+        allocs.push_back(ptr);
+        return (T*)ptr;
+    }
+    ~specmg_ctx() {
+        for (void* a : allocs) (void)hipFree(a);
+        if (sc_host) (void)hipHostFree(sc_host);
+    }
+};
+
+namespace {
+
+template <typename T>
+struct VArgs;
+
+// pointers of one precision variant of the V-cycle
+struct VPtrs {
+    const void* kt;
+    const void* invd;
+    void* u1;
+};
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+T* pick(double* d, float* f);
+template <>
+double* pick<double>(double* d, float*) { return d; }
+template <>
+float* pick<float>(double*, float* f) { return f; }
+
+// coarse levels from level index li (lev[li] holds r, receives e)
+template <typename T>
+void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
+    Level& lv = c->lev[li];
+    T* r = pick<T>(lv.r, lv.r32);
+    T* e = pick<T>(lv.e, lv.e32);
+    if (li + 1 == c->lev.size()) {
+        launch_coarsest<T>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->sc, check, s);
+        return;
+    }
+    Level& up = c->lev[li + 1];
+    T* u = pick<T>(lv.u, lv.u32);
+    const T* Ad = pick<T>(lv.Ad, lv.Ad32);
+    const T* Aoff = pick<T>(lv.Aoff, lv.Aoff32);
+    const T* Dinv = pick<T>(lv.Dinv, lv.Dinv32);
+    const T* V = pick<T>(up.basis, up.basis32);
+    launch_coarse_smooth<T>(lv.g, Dinv, Aoff, r, u, c->sc, check, s);
+    launch_coarse_resid_restrict<T>(lv.g, Ad, Aoff, r, u, V, up.nkeep, up.L, pick<T>(up.r, up.r32), c->sc, check, s);
+    coarse_cycle<T>(c, li + 1, check, s);
+    launch_coarse_prolong<T>(lv.g, u, V, up.nkeep, up.L, pick<T>(up.e, up.e32), c->sc, check, s);
+    launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, r, u, e, c->sc, check, s);
+}
+
+// z = P^{-1} r (fine level + recursion).  pre_mode / post_mode are the mode
+// bits of the fine smoother kernels; check: return early when solve is done.
+template <typename T>
+void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
+            hipStream_t s) {
+    const T* kt = pick<T>(c->kt, c->kt32);
+    const T* invd = pick<T>(c->invd, c->invd32);
+    T* u1 = pick<T>(c->u1, c->u1_32);
+    Level& l2 = c->lev[0];
+    const T* phi = pick<T>(l2.basis, l2.basis32);
+    launch_pre_smooth<T>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
+    launch_resid_restrict<T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
+    coarse_cycle<T>(c, 0, check, s);
+    launch_prolong<T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
+    launch_post_smooth<T>(c->fg, kt, invd, u1, r, q, z, c->sc, c->rb, post_mode, s);
+}
+
+void run_vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
+                hipStream_t s) {
+    if (c->fp32) vcycle<float>(c, r, z, q, pre_mode, post_mode, check, s);
+    else vcycle<double>(c, r, z, q, pre_mode, post_mode, check, s);
+}
+
+int nvec_for(int target) {
+    // block size: eigenvalues through index target+3 are needed by the
+    // cluster rule, plus two guard vectors; even sizes 10/12/14 are built
+    int m = target + 6;
+    if (m % 2) ++m;
+    if (m < 10) m = 10;
+    return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+extern "C" const char* specmg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" void specmg_destroy(specmg_ctx* ctx) { delete ctx; }
+
+static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
+    const double t0 = now_ms();
+    const specmg_grid& G = c->grid;
+    const int levels = c->levels;
+    c->n = (int64_t)G.nx * G.ny * G.nz;
+    FineGeom& fg = c->fg;
+    fg.nx = G.nx;
+    fg.ny = G.ny;
+    fg.nz = G.nz;
+    fg.mx = G.nx / 8;
+    fg.my = G.ny / 8;
+    fg.mz = G.nz / 8;
+    fg.ex = (fg.mx % 4 == 0) ? 4 : ((fg.mx % 2 == 0) ? 2 : 1);
+    if (fg.ex == 4) fg.ex = 2;   // 2 elements per tile: 16x8x8 cells, 128-byte rows
+    fg.ntx = fg.mx / fg.ex;
+    fg.nty = fg.my;
+    fg.ntz = fg.mz;
+    fg.ntiles = fg.ntx * fg.nty * fg.ntz;
+    fg.xcd_remap = (fg.ntiles % 8 == 0) ? 1 : 0;
+    if (fg.ntiles > kMaxRedBlocks) return fail(SPECMG_EINVAL, "grid too large for the reduction buffer");
+
+    c->dflag = c->alloc<int>(8);
+    HIPCHK(hipMemsetAsync(c->dflag, 0, 8 * sizeof(int), s));
+    c->kt = c->alloc<double>(c->n);
+    c->invd = c->alloc<double>(c->n);
+    if (c->fp32) {
+        c->kt32 = c->alloc<float>(c->n);
+        c->invd32 = c->alloc<float>(c->n);
+    }
+    const double h = G.hx;
+    launch_perm_to_kt(perm, c->kt, c->kt32, 1.0 / (h * h), c->n, c->dflag, s);
+    int flags[8];
+    HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flags[0]) return fail(SPECMG_EINVAL_PERM, "permeability must be positive and finite");
+    launch_ic_setup(fg, c->kt, c->invd, c->invd32, c->dflag + 1, s);
+
+    const int L = c->L;
+    const double tol = c->opts.eig_tol > 0 ? c->opts.eig_tol : 1e-12;
+    const double crtol = c->opts.cluster_rtol > 0 ? c->opts.cluster_rtol : 1e-6;
+    c->lev.resize(levels - 1);
+    // ---- level 2
+    {
+        Level& lv = c->lev[0];
+        lv.l = 2;
+        lv.L = L;
+        lv.rows = 512;
+        lv.g.mx = fg.mx;
+        lv.g.my = fg.my;
+        lv.g.mz = fg.mz;
+        lv.g.m = fg.mx * fg.my * fg.mz;
+        lv.g.L = L;
+        const int m = lv.g.m;
+        lv.nkeep = c->alloc<int>(m);
+        lv.status = c->alloc<int>(m);
+        lv.lam = c->alloc<double>((size_t)m * L);
+        lv.basis = c->alloc<double>((size_t)m * L * 512);
+        lv.Aint = c->alloc<double>((size_t)m * L * L);
+        lv.D = c->alloc<double>((size_t)m * 6 * L * L);
+        lv.Aoff = c->alloc<double>((size_t)m * 3 * L * L);
+        lv.Ad = c->alloc<double>((size_t)m * L * L);
+        lv.z = c->alloc<double>((size_t)m * L);
+        launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint, lv.status,
+                    lv.z, s);
+        launch_galerkin2(fg, c->kt, lv.basis, lv.nkeep, L, lv.D, lv.Aoff, s);
+        launch_assemble_diag(lv.g, lv.Aint, lv.D, lv.Ad, s);
+    }
+    // ---- levels 3..levels
+    for (int li = 1; li < levels - 1; ++li) {
+        Level& lo = c->lev[li - 1];
+        Level& up = c->lev[li];
+        const int agg = G.agg;
+        up.l = li + 2;
+        up.L = L;
+        up.g.mx = lo.g.mx / agg;
+        up.g.my = lo.g.my / agg;
+        up.g.mz = lo.g.mz / agg;
+        up.g.m = up.g.mx * up.g.my * up.g.mz;
+        up.g.L = L;
+        up.rows = agg * agg * agg * lo.L;
+        lo.g.agg = agg;
+        lo.g.px = up.g.mx;
+        lo.g.py = up.g.my;
+        lo.g.pz = up.g.mz;
+        lo.g.M = up.g.m;
+        const int m = up.g.m;
+        up.nkeep = c->alloc<int>(m);
+        up.status = c->alloc<int>(m);
+        up.lam = c->alloc<double>((size_t)m * L);
+        up.basis = c->alloc<double>((size_t)m * L * up.rows);
+        up.Aint = c->alloc<double>((size_t)m * L * L);
+        up.D = c->alloc<double>((size_t)m * 6 * L * L);
+        up.Aoff = c->alloc<double>((size_t)m * 3 * L * L);
+        up.Ad = c->alloc<double>((size_t)m * L * L);
+        up.z = c->alloc<double>((size_t)m * L);
+        double* hd = c->alloc<double>((size_t)lo.g.m * L * L);
+        launch_eig_up(lo.g, up.g, lo.Aint, lo.D, lo.Aoff, lo.nkeep, lo.z, hd, c->target, c->nvec, tol, crtol,
+                      up.basis, up.lam, up.nkeep, up.Aint, up.z, up.status, s);
+        launch_galerkin_up(lo.g, up.g, lo.D, lo.Aoff, up.basis, up.nkeep, up.D, up.Aoff, s);
+        launch_assemble_diag(up.g, up.Aint, up.D, up.Ad, s);
+    }
+    // ---- smoothers of the non-coarsest coarse levels
+    for (int li = 0; li < levels - 2; ++li) {
+        Level& lv = c->lev[li];
+        lv.Dinv = c->alloc<double>((size_t)lv.g.m * L * L);
+        launch_blockic_setup(lv.g, lv.Ad, lv.Aoff, lv.nkeep, lv.Dinv, c->dflag + 2, s);
+    }
+    // ---- host copies of the kept counts, unconverged eigensolves
+    int unconv = 0;
+    for (auto& lv : c->lev) {
+        lv.nkeep_h.resize(lv.g.m);
+        std::vector<int> st(lv.g.m);
+        HIPCHK(hipMemcpyAsync(lv.nkeep_h.data(), lv.nkeep, lv.g.m * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(st.data(), lv.status, lv.g.m * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        lv.dim = 0;
+        for (int k : lv.nkeep_h) lv.dim += k;
+        for (int v : st) unconv += (v < 0);
+    }
+    // ---- coarsest: A_L^+ = (A_L + alpha z z^T)^{-1} - z z^T / alpha
+    {
+        Level& top = c->lev.back();
+        const int m = top.g.m;
+        std::vector<int> cmap, cinv((size_t)m * L, -1);
+        for (int e = 0; e < m; ++e)
+            for (int a = 0; a < top.nkeep_h[e]; ++a) {
+                cinv[(size_t)e * L + a] = (int)cmap.size();
+                cmap.push_back(e * L + a);
+            }
+        const int nL = (int)cmap.size();
+        const int np = ((nL + 31) / 32) * 32;
+        c->nL = nL;
+        c->npL = np;
+        c->cmap = c->alloc<int>(nL);
+        int* dcinv = c->alloc<int>(cinv.size());
+        HIPCHK(hipMemcpyAsync(c->cmap, cmap.data(), nL * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(dcinv, cinv.data(), cinv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        c->Pinv = c->alloc<double>((size_t)np * np);
+        double* work = (double*)nullptr;
+        HIPCHK(hipMalloc((void**)&work, (size_t)np * np * sizeof(double)));
+        HIPCHK(hipMemsetAsync(c->Pinv, 0, (size_t)np * np * sizeof(double), s));
+        launch_build_coarsest(top.g, top.Ad, top.Aoff, dcinv, np, c->Pinv, s);
+        launch_pad_identity(c->Pinv, np, nL, s);
+        // z (constant function) and alpha = trace / n on the host
+        std::vector<double> zp((size_t)m * L), ad((size_t)m * L * L);
+        HIPCHK(hipMemcpyAsync(zp.data(), top.z, zp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ad.data(), top.Ad, ad.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<double> zc(nL);
+        double zn = 0.0, tr = 0.0;
+        for (int i = 0; i < nL; ++i) {
+            zc[i] = zp[cmap[i]];
+            zn += zc[i] * zc[i];
+            const int e = cmap[i] / L, a = cmap[i] % L;
+            tr += ad[((size_t)e * L + a) * L + a];
+        }
+        zn = std::sqrt(zn);
+        if (!(zn > 0.0)) {
+            (void)hipFree(work);
+            return fail(SPECMG_EFACT, "constant function not found in the coarsest space");
+        }
+        for (double& v : zc) v /= zn;
+        const double alpha = tr / nL;
+        double* dz = c->alloc<double>(nL);
+        HIPCHK(hipMemcpyAsync(dz, zc.data(), nL * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_add_rank1(c->Pinv, np, nL, dz, alpha, s);
+        dense_spd_inverse(c->Pinv, np, work, c->dflag + 3, s);
+        launch_pinv_finish(c->Pinv, np, nL, dz, alpha, s);
+        HIPCHK(hipStreamSynchronize(s));
+        (void)hipFree(work);
+    }
+    // ---- float32 copies for the mixed-precision V-cycle
+    if (c->fp32) {
+        for (size_t li = 0; li < c->lev.size(); ++li) {
+            Level& lv = c->lev[li];
+            const size_t LL = (size_t)L * L;
+            const size_t nb = (size_t)lv.g.m * L * lv.rows;
+            lv.basis32 = c->alloc<float>(nb);
+            launch_convert<double, float>(lv.basis, lv.basis32, (int64_t)nb, s);
+            lv.Ad32 = c->alloc<float>(lv.g.m * LL);
+            launch_convert<double, float>(lv.Ad, lv.Ad32, (int64_t)(lv.g.m * LL), s);
+            lv.Aoff32 = c->alloc<float>(lv.g.m * 3 * LL);
+            launch_convert<double, float>(lv.Aoff, lv.Aoff32, (int64_t)(lv.g.m * 3 * LL), s);
+            if (lv.Dinv) {
+                lv.Dinv32 = c->alloc<float>(lv.g.m * LL);
+                launch_convert<double, float>(lv.Dinv, lv.Dinv32, (int64_t)(lv.g.m * LL), s);
+            }
+        }
+    }
+    // ---- vectors
+    for (auto& lv : c->lev) {
+        const size_t nv = (size_t)lv.g.m * L;
+        lv.r = c->alloc<double>(nv);
+        lv.u = c->alloc<double>(nv);
+        lv.e = c->alloc<double>(nv);
+        HIPCHK(hipMemsetAsync(lv.r, 0, nv * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(lv.u, 0, nv * sizeof(double), s));
+        HIPCHK(hipMemsetAsync(lv.e, 0, nv * sizeof(double), s));
+        if (c->fp32) {
+            lv.r32 = c->alloc<float>(nv);
+            lv.u32 = c->alloc<float>(nv);
+            lv.e32 = c->alloc<float>(nv);
+            HIPCHK(hipMemsetAsync(lv.r32, 0, nv * sizeof(float), s));
+            HIPCHK(hipMemsetAsync(lv.u32, 0, nv * sizeof(float), s));
+            HIPCHK(hipMemsetAsync(lv.e32, 0, nv * sizeof(float), s));
+        }
+    }
+    c->r = c->alloc<double>(c->n);
+    c->z = c->alloc<double>(c->n);
+    c->p[0] = c->alloc<double>(c->n);
+    c->p[1] = c->alloc<double>(c->n);
+    c->q = c->alloc<double>(c->n);
+    c->u1 = c->alloc<double>(c->n);
+    if (c->fp32) c->u1_32 = c->alloc<float>(c->n);
+    c->dtmp = c->alloc<double>(8);
+    c->sc = c->alloc<Scalars>(1);
+    HIPCHK(hipHostMalloc((void**)&c->sc_host, sizeof(Scalars), hipHostMallocDefault));
+    c->rb.partial = c->alloc<double>((size_t)2 * kMaxRedBlocks);
+    c->rb.counter = c->alloc<unsigned>(16);
+    HIPCHK(hipMemsetAsync(c->rb.counter, 0, 16 * sizeof(unsigned), s));
+    launch_pcg_init(c->sc, 0.0, 0, s);
+    HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+
+    specmg_solve_info& si = c->setup_info;
+    memset(&si, 0, sizeof(si));
+    si.n_levels = levels;
+    si.dims[0] = (int)c->n;
+    for (size_t li = 0; li < c->lev.size() && li + 1 < 8; ++li) si.dims[li + 1] = c->lev[li].dim;
+    si.eig_unconverged = unconv;
+    si.setup_ms = now_ms() - t0;
+    if (flags[1]) return fail(SPECMG_EFACT, "fine IC(0) pivot not positive");
+    if (flags[2]) return fail(SPECMG_EFACT, "coarse block IC(0) pivot not positive definite");
+    if (flags[3]) return fail(SPECMG_EFACT, "coarsest factor not positive definite");
+    if (unconv) return fail(SPECMG_EEIG, std::to_string(unconv) + " local eigensolves did not converge");
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
+                            const specmg_opts* opts, void* stream, specmg_ctx** out) {
+    g_last_error.clear();
+    if (!out || !grid || !opts || !perm_dev) return fail(SPECMG_EINVAL, "null argument");
+    *out = nullptr;
+    if (perm_components != 1) return fail(SPECMG_EINVAL, "only isotropic permeability (1 component) is supported");
+    const specmg_grid& G = *grid;
+    if (G.sub != 8) return fail(SPECMG_EINVAL, "sub must be 8");
+    if (G.agg != 2 && G.agg != 4) return fail(SPECMG_EINVAL, "agg must be 2 or 4");
+    if (!(G.hx > 0) || G.hx != G.hy || G.hx != G.hz) return fail(SPECMG_EINVAL, "equal positive spacings required");
+    if (opts->levels < 2 || opts->levels > 8) return fail(SPECMG_EINVAL, "levels must be in [2, 8]");
+    if (opts->eigs_per_subdomain < 1 || opts->eigs_per_subdomain > 8)
+        return fail(SPECMG_EINVAL, "eigs_per_subdomain must be in [1, 8]");
+    if (opts->nu != 1) return fail(SPECMG_EINVAL, "only nu = 1 is supported");
+    if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE)
+        return fail(SPECMG_EINVAL, "unknown precision");
+    if (opts->warm_start != SPECMG_WS_NONE) return fail(SPECMG_EINVAL, "warm_start not available in this build");
+    long div = 8;
+    for (int l = 2; l < opts->levels; ++l) div *= G.agg;
+    if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.nx % div || G.ny % div || G.nz % div)
+        return fail(SPECMG_EINVAL, "nx, ny, nz must be positive multiples of 8*agg^(levels-2)");
+    if ((long)G.nx * G.ny * G.nz / 512 < 2) return fail(SPECMG_EINVAL, "need at least two 8^3 elements");
+    specmg_ctx* c = new specmg_ctx();
+    c->grid = G;
+    c->opts = *opts;
+    c->levels = opts->levels;
+    c->target = opts->eigs_per_subdomain;
+    c->L = c->target + 3;
+    c->nvec = nvec_for(c->target);
+    c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
+    int rc;
+    try {
+        rc = do_setup(c, perm_dev, (hipStream_t)stream);
+    } catch (const HipError& e) {
+        rc = fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    if (rc == SPECMG_OK || rc == SPECMG_EEIG) {
+        *out = c;
+    } else {
+        delete c;
+    }
+    return rc;
+}
+
+extern "C" int specmg_apply_operator(specmg_ctx* c, const double* x, double* y, void* stream) {
+    if (!c || !x || !y) return fail(SPECMG_EINVAL, "null argument");
+    try {
+        launch_apply_A(c->fg, c->kt, x, nullptr, y, 0, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_apply_precond(specmg_ctx* c, const double* r, double* z, void* stream) {
+    if (!c || !r || !z) return fail(SPECMG_EINVAL, "null argument");
+    if (r == z) return fail(SPECMG_EINVAL, "r and z must not alias");
+    try {
+        run_vcycle(c, const_cast<double*>(r), z, nullptr, 0, 0, 0, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return SPECMG_OK;
+}
+
+static void read_scalars(specmg_ctx* c, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+static double dev_dot(specmg_ctx* c, const double* a, const double* b, hipStream_t s) {
+    launch_dot(a, b, c->n, c->dtmp, c->rb, RS_GEN, s);
+    double v = 0.0;
+    HIPCHK(hipMemcpyAsync(&v, c->dtmp, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return v;
+}
+
+__global__ void k_reset_done(Scalars* sc) { sc->done = 0; }
+
+static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, double tol, int max_iter,
+                    specmg_solve_info* info, hipStream_t s) {
+    const double t0 = now_ms();
+    const int64_t n = c->n;
+    specmg_solve_info si = c->setup_info;
+    si.iters = 0;
+    si.converged = 0;
+    si.replacements = 0;
+    // compatibility of the source: |sum f| <= 1e-12 sum |f|
+    launch_sum_abs(b, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    double sa[2];
+    HIPCHK(hipMemcpyAsync(sa, c->dtmp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (std::fabs(sa[0]) > 1e-12 * sa[1]) return fail(SPECMG_ERHS, "source does not sum to zero");
+    const double nb = std::sqrt(dev_dot(c, b, b, s));
+    if (nb == 0.0) {
+        launch_fill(x, 0.0, n, s);
+        si.converged = 1;
+        si.solve_ms = now_ms() - t0;
+        if (info) *info = si;
+        return SPECMG_OK;
+    }
+    if (use_x0) launch_apply_A(c->fg, c->kt, x, b, c->r, 1, s);
+    else {
+        launch_fill(x, 0.0, n, s);
+        launch_copy(c->r, b, n, s);
+    }
+    const double thresh2 = (tol * nb) * (tol * nb);
+    const int flexible = c->fp32;
+    launch_pcg_init(c->sc, thresh2, flexible, s);
+    int rc = SPECMG_OK;
+    double r0 = std::sqrt(dev_dot(c, c->r, c->r, s));
+    bool converged = r0 <= tol * nb;
+    int k = 0;   // CG iterations issued so far (= device iteration counter after a sync)
+    bool restart = true;
+    while (!converged) {
+        if (restart) {
+            // z = P^{-1} r, r.z and beta (first call: beta unused)
+            run_vcycle(c, c->r, c->z, c->q, 0, 1, 0, s);
+            restart = false;
+        }
+        const int chunk = 4;
+        for (int i = 0; i < chunk && k < max_iter; ++i, ++k) {
+            const int first = (k == 0) ? 1 : 0;
+            const int pb = k & 1;
+            launch_spmv_pcg(c->fg, c->kt, c->z, c->p[pb ^ 1], c->p[pb], x, c->q, c->sc, c->rb, first | (pb << 1), s);
+            run_vcycle(c, c->r, c->z, c->q, 1 | 2, 1 | 2, 1, s);
+        }
+        read_scalars(c, s);
+        const Scalars& h = *c->sc_host;
+        k = h.iter;
+        if (h.done == 2) {
+            launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
+            rc = fail(SPECMG_EBREAKDOWN, "breakdown: p^T A p not positive");
+            break;
+        }
+        if (h.done == 1) {
+            // confirm on the true residual; replace it when the check fails
+            launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
+            launch_apply_A(c->fg, c->kt, x, b, c->r, 1, s);
+            const double rt = dev_dot(c, c->r, c->r, s);
+            if (rt <= thresh2) {
+                converged = true;
+                break;
+            }
+            si.replacements += 1;
+            hipLaunchKernelGGL(k_reset_done, dim3(1), dim3(1), 0, s, c->sc);
+            restart = true;
+            // the next spmv continues the direction update p = z + beta p
+            if (k >= max_iter) break;
+            continue;
+        }
+        if (k >= max_iter) {
+            launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
+            break;
+        }
+    }
+    read_scalars(c, s);
+    si.iters = c->sc_host->iter;
+    si.rel_resid = std::sqrt(c->sc_host->rr) / nb;
+    // zero-mean solution
+    launch_sum_abs(x, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    launch_sub_mean(x, n, c->dtmp, s);
+    launch_apply_A(c->fg, c->kt, x, b, c->q, 1, s);
+    si.rel_resid_true = std::sqrt(dev_dot(c, c->q, c->q, s)) / nb;
+    si.converged = converged ? 1 : 0;
+    HIPCHK(hipStreamSynchronize(s));
+    si.solve_ms = now_ms() - t0;
+    if (info) *info = si;
+    if (rc != SPECMG_OK) return rc;
+    if (!converged) return fail(SPECMG_ENOCONV, "maximum number of iterations reached");
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_pcg_solve(specmg_ctx* c, const double* rhs, double* x, int32_t use_x0, double tol,
+                                int32_t max_iter, specmg_solve_info* info, void* stream) {
+    g_last_error.clear();
+    if (!c || !rhs || !x) return fail(SPECMG_EINVAL, "null argument");
+    if (!(tol > 0) || max_iter < 1) return fail(SPECMG_EINVAL, "tol must be > 0 and max_iter >= 1");
+    try {
+        return do_solve(c, rhs, x, use_x0, tol, max_iter, info, (hipStream_t)stream);
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+}
+
+extern "C" int specmg_get_info(specmg_ctx* c, int32_t* levels, int32_t* dims, int32_t* elems, int32_t* lmax,
+                               specmg_solve_info* setup_info) {
+    if (!c) return fail(SPECMG_EINVAL, "null context");
+    if (levels) *levels = c->levels;
+    if (lmax) *lmax = c->L;
+    if (dims) {
+        for (int i = 0; i < 8; ++i) dims[i] = 0;
+        dims[0] = (int)c->n;
+        for (size_t li = 0; li < c->lev.size() && li + 1 < 8; ++li) dims[li + 1] = c->lev[li].dim;
+    }
+    if (elems) {
+        for (int i = 0; i < 8; ++i) elems[i] = 0;
+        elems[0] = (int)c->n;
+        for (size_t li = 0; li < c->lev.size() && li + 1 < 8; ++li) elems[li + 1] = c->lev[li].g.m;
+    }
+    if (setup_info) *setup_info = c->setup_info;
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_copy_level(specmg_ctx* c, int32_t level, int32_t which, void* dst, size_t bytes) {
+    if (!c || !dst) return fail(SPECMG_EINVAL, "null argument");
+    if (level < 2 || level > c->levels) return fail(SPECMG_EINVAL, "level out of range");
+    Level& lv = c->lev[level - 2];
+    const size_t m = lv.g.m, L = lv.L;
+    const void* src = nullptr;
+    size_t need = 0;
+    switch (which) {
+        case 0: src = lv.nkeep; need = m * sizeof(int); break;
+        case 1: src = lv.lam; need = m * L * sizeof(double); break;
+        case 2: src = lv.basis; need = m * L * lv.rows * sizeof(double); break;
+        case 3: src = lv.Ad; need = m * L * L * sizeof(double); break;
+        case 4: src = lv.Aoff; need = m * 3 * L * L * sizeof(double); break;
+        default: return fail(SPECMG_EINVAL, "unknown array");
+    }
+    if (bytes != need) return fail(SPECMG_EINVAL, "size mismatch: expected " + std::to_string(need));
+    if (hipMemcpy(dst, src, need, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(SPECMG_EDEVICE, "copy failed");
+    return SPECMG_OK;
+}

@@ -1,0 +1,203 @@
+"""ctypes binding of libspecmg (the C-ABI declared in include/specmg.h).
+
+Argument marshalling only: device buffers are torch tensors on the current
+device (float64, contiguous, x fastest), streams are torch streams.  Every
+numerical step runs in the library's HIP kernels; loading fails loudly when
+the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspecmg.so")
+
+OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FP64, FP32_VCYCLE = 0, 1
+WS_NONE, WS_CNN = 0, 1
+
+EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_apply_operator",
+            "specmg_get_info", "specmg_copy_level", "specmg_destroy", "specmg_last_error"]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("hz", ctypes.c_double),
+                ("sub", ctypes.c_int32), ("agg", ctypes.c_int32)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("eigs_per_subdomain", ctypes.c_int32),
+                ("nu", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("cnn_weights", ctypes.c_void_p),
+                ("eig_tol", ctypes.c_double), ("cluster_rtol", ctypes.c_double),
+                ("ws_resid_tol", ctypes.c_double)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_resid", ctypes.c_double), ("rel_resid_true", ctypes.c_double),
+                ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("n_levels", ctypes.c_int32), ("dims", ctypes.c_int32 * 8),
+                ("eig_unconverged", ctypes.c_int32), ("ws_fallbacks", ctypes.c_int32),
+                ("replacements", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "converged": bool(self.converged), "rel_resid": self.rel_resid,
+                "rel_resid_true": self.rel_resid_true, "setup_ms": self.setup_ms,
+                "solve_ms": self.solve_ms, "n_levels": self.n_levels,
+                "dims": list(self.dims)[: self.n_levels], "eig_unconverged": self.eig_unconverged,
+                "ws_fallbacks": self.ws_fallbacks, "replacements": self.replacements}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libspecmg.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2403_19342_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.specmg_setup.argtypes = [vp, i32, ctypes.POINTER(Grid), ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
+    lib.specmg_setup.restype = ctypes.c_int
+    lib.specmg_apply_precond.argtypes = [vp, vp, vp, vp]
+    lib.specmg_apply_precond.restype = ctypes.c_int
+    lib.specmg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolveInfo), vp]
+    lib.specmg_pcg_solve.restype = ctypes.c_int
+    lib.specmg_apply_operator.argtypes = [vp, vp, vp, vp]
+    lib.specmg_apply_operator.restype = ctypes.c_int
+    lib.specmg_get_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32 * 8), ctypes.POINTER(i32 * 8),
+                                    ctypes.POINTER(i32), ctypes.POINTER(SolveInfo)]
+    lib.specmg_get_info.restype = ctypes.c_int
+    lib.specmg_copy_level.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
+    lib.specmg_copy_level.restype = ctypes.c_int
+    lib.specmg_destroy.argtypes = [vp]
+    lib.specmg_destroy.restype = None
+    lib.specmg_last_error.argtypes = []
+    lib.specmg_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class SpecMGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"specmg error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != OK:
+        raise SpecMGError(code, _lib.specmg_last_error().decode())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class LevelArrays:
+    nkeep: np.ndarray
+    lam: np.ndarray
+    basis: np.ndarray
+    Ad: np.ndarray
+    Aoff: np.ndarray
+
+
+class SpecMG:
+    """Set-up context of the multiscale spectral multigrid preconditioner."""
+
+    def __init__(self, perm, levels: int, eigs_per_subdomain: int, h: float | None = None,
+                 agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
+                 allow_unconverged: bool = False):
+        lib = load_library()
+        import torch
+        if perm.dim() != 3:
+            raise ValueError("perm must have shape (nz, ny, nx)")
+        nz, ny, nx = perm.shape
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        if h is None:
+            h = 1.0 / nx
+        self.grid = Grid(nx, ny, nz, h, h, h, 8, agg)
+        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, WS_NONE, None, eig_tol, cluster_rtol, 1e-3)
+        ctx = ctypes.c_void_p()
+        perm = perm.contiguous()
+        rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
+                              ctypes.byref(ctx))
+        if rc == EEIG and allow_unconverged:
+            pass
+        elif rc != OK:
+            _check(rc)
+        self._ctx = ctx
+        self.levels = levels
+        torch.cuda.synchronize()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.specmg_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply_precond(self, r, z):
+        _check(_lib.specmg_apply_precond(self._ctx, _dev_ptr(r), _dev_ptr(z), _stream()))
+
+    def apply_operator(self, x, y):
+        _check(_lib.specmg_apply_operator(self._ctx, _dev_ptr(x), _dev_ptr(y), _stream()))
+
+    def pcg_solve(self, rhs, x, tol: float = 1e-6, max_iter: int = 1000, use_x0: bool = False,
+                  raise_on_error: bool = True):
+        info = SolveInfo()
+        rc = _lib.specmg_pcg_solve(self._ctx, _dev_ptr(rhs), _dev_ptr(x), int(use_x0), tol, max_iter,
+                                   ctypes.byref(info), _stream())
+        if rc != OK and raise_on_error:
+            _check(rc)
+        return rc, info
+
+    def info(self):
+        lv = ctypes.c_int32()
+        dims = (ctypes.c_int32 * 8)()
+        elems = (ctypes.c_int32 * 8)()
+        lmax = ctypes.c_int32()
+        si = SolveInfo()
+        _check(_lib.specmg_get_info(self._ctx, ctypes.byref(lv), ctypes.byref(dims), ctypes.byref(elems),
+                                    ctypes.byref(lmax), ctypes.byref(si)))
+        return {"levels": lv.value, "dims": list(dims)[: lv.value], "elems": list(elems)[: lv.value],
+                "lmax": lmax.value, "setup": si.as_dict()}
+
+    def level_arrays(self, level: int) -> LevelArrays:
+        inf = self.info()
+        m = inf["elems"][level - 1]
+        L = inf["lmax"]
+        if level == 2:
+            rows = 512
+        else:
+            rows = self.grid.agg ** 3 * L
+        out = {}
+        for which, name, dtype, shape in ((0, "nkeep", np.int32, (m,)), (1, "lam", np.float64, (m, L)),
+                                          (2, "basis", np.float64, (m, L, rows)),
+                                          (3, "Ad", np.float64, (m, L, L)), (4, "Aoff", np.float64, (m, 3, L, L))):
+            arr = np.empty(shape, dtype=dtype)
+            _check(_lib.specmg_copy_level(self._ctx, level, which, arr.ctypes.data_as(ctypes.c_void_p), arr.nbytes))
+            out[name] = arr
+        return LevelArrays(**out)
