@@ -141,8 +141,25 @@ int specmg_get_info(specmg_ctx* ctx, int32_t* levels, int32_t* dims, int32_t* el
  *             S-normalised; level >= 3: [m][Lmax][agg^3*Lmax] columns of R^T
  *   3 Adiag   float64 [m][Lmax][Lmax] diagonal blocks of A_l
  *   4 Aoff    float64 [m][3][Lmax][Lmax] blocks A_l(e, e + x|y|z)
+ *   5 status  int32  [m]  Chebyshev cycles used by the local eigensolve, -1 if
+ *             it stopped at the cycle cap
  * `bytes` must equal the array size; returns SPECMG_EINVAL otherwise. */
 int specmg_copy_level(specmg_ctx* ctx, int32_t level, int32_t which, void* host_dst, size_t bytes);
+
+/* Per-kernel timing of later specmg_pcg_solve calls (on != 0) or off.
+ * Each fine-level kernel of the CG iteration, and the coarse part of the
+ * V-cycle as a whole, is bracketed by HIP events on the solve's stream;
+ * turning it on resets the accumulated totals. */
+int specmg_set_profiling(specmg_ctx* ctx, int32_t on);
+
+/* Accumulated event times (ms) and launch counts per kernel class since
+ * profiling was turned on, and the algorithmic bytes one launch of the class
+ * moves (compulsory HBM traffic of its inputs and outputs).  Classes:
+ * 0 CG operator (p update, A p, p.Ap)   1 pre-smoothing (r update, IC(0))
+ * 2 residual + restriction             3 prolongation
+ * 4 residual + post-smoothing          5 coarse levels 2..L-1 (all kernels)
+ * 6 coarsest solve (two-level set-ups) 7 unused.  Arrays hold 8 entries. */
+int specmg_get_profile(specmg_ctx* ctx, double* ms, int32_t* launches, double* bytes);
 
 /* Releases every device and host resource of the context (NULL is a no-op). */
 void specmg_destroy(specmg_ctx* ctx);

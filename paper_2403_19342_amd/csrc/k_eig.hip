@@ -20,7 +20,7 @@
 namespace specmg {
 
 constexpr int kDeg = 20;          // Chebyshev degree per cycle
-constexpr int kMaxCycles = 120;
+constexpr int kMaxCycles = 300;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -559,9 +559,12 @@ __device__ void rayleigh_ritz(const OP& op, const double* Y, int ld, int n, doub
 // Full CheFSI loop.  X holds the start block on entry and the Ritz vectors
 // on exit, AX = A X.  Returns the number of cycles, or -1 when the residual
 // tolerance (relative to bnd) was not met within kMaxCycles.
+// Convergence: vectors that the cluster rule keeps need residual <= tol*bnd;
+// the remaining ones up to index need-1 only feed the cluster decision
+// through their eigenvalues (error <= residual^2 / gap), so sqrt(tol)*bnd.
 template <int M, int R, class OP>
 __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M], double (&AX)[R][M],
-                      double bnd, int need, double tol, EigShared<M>& sh) {
+                      double bnd, int need, double tol, int target, double crtol, EigShared<M>& sh) {
     store_block<M, R>(Y, ld, n, X);
     __syncthreads();
     orthonormalise<M, R>(Y, ld, n, sh);
@@ -575,9 +578,10 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
                 for (int j = 0; j < M; ++j) Rs[r][j] = AX[r][j] - sh.th[j] * X[r][j];
             colnorm2<M, R>(Rs, sh.nrm, sh.red);
         }
-        double worst = 0.0;
-        for (int j = 0; j < need; ++j) worst = fmax(worst, sqrt(sh.nrm[j]));
-        if (worst <= tol * bnd) return cyc;
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        bool ok = true;
+        for (int j = 0; j < need; ++j) ok = ok && (sqrt(sh.nrm[j]) <= (j < nk ? tol : sqrt(tol)) * bnd);
+        if (ok) return cyc;
         if (cyc >= kMaxCycles) return -1;
         const double a = fmin(sh.th[M - 1], 0.5 * bnd);
         const double a0 = fmin(sh.th[0], 0.0) - 1e-3 * bnd;
@@ -673,7 +677,7 @@ __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restri
         X[0][jj] = sq * (md + 0.05 * hash_noise((unsigned)e, (unsigned)jj, (unsigned)c));
     }
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
-    const int cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, sh);
+    const int cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, sh);
 
     if (threadIdx.x == 0) {
         const int nk = cluster_cut_dev(sh.th, M, target, crtol);
@@ -804,7 +808,7 @@ __global__ __launch_bounds__(512) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     }
     const double bnd = block_max(rb, sh.misc);
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
-    const int cyc = chefsi<M, R>(op, dyn, ld, n, X, AX, bnd, need, tol, sh);
+    const int cyc = chefsi<M, R>(op, dyn, ld, n, X, AX, bnd, need, tol, target, crtol, sh);
     if (threadIdx.x == 0) {
         const int nk = cluster_cut_dev(sh.th, M, target, crtol);
         sh.flag = nk;

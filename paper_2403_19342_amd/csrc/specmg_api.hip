@@ -86,6 +86,15 @@ struct specmg_ctx {
     Scalars* sc_host = nullptr; // pinned
     RedBuf rb{};
     specmg_solve_info setup_info{};
+    // per-kernel-class event timing of pcg_solve (see specmg_set_profiling)
+    int prof_on = 0;
+    int cur_iter = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec { int cls, iter; size_t e0, e1; };
+    std::vector<Rec> recs;
+    double prof_ms[8] = {0};
+    int prof_count[8] = {0};
 
     template <typename T>
     T* alloc(size_t count) {
@@ -96,6 +105,7 @@ struct specmg_ctx {
         return (T*)ptr;
     }
     ~specmg_ctx() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* a : allocs) (void)hipFree(a);
         if (sc_host) (void)hipHostFree(sc_host);
     }
@@ -115,6 +125,31 @@ struct VPtrs {
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// event bracket around one launch (no-op unless profiling is on)
+enum ProfClass { PC_SPMV = 0, PC_PRE = 1, PC_RESTRICT = 2, PC_PROLONG = 3, PC_POST = 4, PC_COARSE = 5,
+                 PC_COARSEST = 6 };
+
+size_t prof_begin(specmg_ctx* c, hipStream_t s) {
+    if (!c->prof_on) return (size_t)-1;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+        for (int i = 0; i < 256; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->ev_pool.push_back(e);
+        }
+    }
+    const size_t i = c->ev_used;
+    c->ev_used += 2;
+    HIPCHK(hipEventRecord(c->ev_pool[i], s));
+    return i;
+}
+
+void prof_end(specmg_ctx* c, size_t i, int cls, hipStream_t s) {
+    if (i == (size_t)-1) return;
+    HIPCHK(hipEventRecord(c->ev_pool[i + 1], s));
+    c->recs.push_back({cls, c->cur_iter, i, i + 1});
 }
 
 template <typename T>
@@ -157,11 +192,21 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     T* u1 = pick<T>(c->u1, c->u1_32);
     Level& l2 = c->lev[0];
     const T* phi = pick<T>(l2.basis, l2.basis32);
+    size_t ev = prof_begin(c, s);
     launch_pre_smooth<T>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
+    prof_end(c, ev, PC_PRE, s);
+    ev = prof_begin(c, s);
     launch_resid_restrict<T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
+    prof_end(c, ev, PC_RESTRICT, s);
+    ev = prof_begin(c, s);
     coarse_cycle<T>(c, 0, check, s);
+    prof_end(c, ev, c->lev.size() == 1 ? PC_COARSEST : PC_COARSE, s);
+    ev = prof_begin(c, s);
     launch_prolong<T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
+    prof_end(c, ev, PC_PROLONG, s);
+    ev = prof_begin(c, s);
     launch_post_smooth<T>(c->fg, kt, invd, u1, r, q, z, c->sc, c->rb, post_mode, s);
+    prof_end(c, ev, PC_POST, s);
 }
 
 void run_vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
@@ -513,6 +558,9 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
     const double t0 = now_ms();
     const int64_t n = c->n;
     specmg_solve_info si = c->setup_info;
+    c->ev_used = 0;
+    c->recs.clear();
+    c->cur_iter = 0;
     si.iters = 0;
     si.converged = 0;
     si.replacements = 0;
@@ -553,7 +601,10 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
         for (int i = 0; i < chunk && k < max_iter; ++i, ++k) {
             const int first = (k == 0) ? 1 : 0;
             const int pb = k & 1;
+            c->cur_iter = k + 1;
+            const size_t ev = prof_begin(c, s);
             launch_spmv_pcg(c->fg, c->kt, c->z, c->p[pb ^ 1], c->p[pb], x, c->q, c->sc, c->rb, first | (pb << 1), s);
+            prof_end(c, ev, PC_SPMV, s);
             run_vcycle(c, c->r, c->z, c->q, 1 | 2, 1 | 2, 1, s);
         }
         read_scalars(c, s);
@@ -596,6 +647,17 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
     si.converged = converged ? 1 : 0;
     HIPCHK(hipStreamSynchronize(s));
     si.solve_ms = now_ms() - t0;
+    if (c->prof_on) {
+        // launches of iterations past the last executed one returned at once
+        for (const auto& rcd : c->recs) {
+            if (rcd.iter > si.iters) continue;
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev_pool[rcd.e0], c->ev_pool[rcd.e1]));
+            c->prof_ms[rcd.cls] += ms;
+            c->prof_count[rcd.cls] += 1;
+        }
+        c->recs.clear();
+    }
     if (info) *info = si;
     if (rc != SPECMG_OK) return rc;
     if (!converged) return fail(SPECMG_ENOCONV, "maximum number of iterations reached");
@@ -646,10 +708,40 @@ extern "C" int specmg_copy_level(specmg_ctx* c, int32_t level, int32_t which, vo
         case 2: src = lv.basis; need = m * L * lv.rows * sizeof(double); break;
         case 3: src = lv.Ad; need = m * L * L * sizeof(double); break;
         case 4: src = lv.Aoff; need = m * 3 * L * L * sizeof(double); break;
+        case 5: src = lv.status; need = m * sizeof(int); break;
         default: return fail(SPECMG_EINVAL, "unknown array");
     }
     if (bytes != need) return fail(SPECMG_EINVAL, "size mismatch: expected " + std::to_string(need));
     if (hipMemcpy(dst, src, need, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(SPECMG_EDEVICE, "copy failed");
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_set_profiling(specmg_ctx* c, int32_t on) {
+    if (!c) return fail(SPECMG_EINVAL, "null context");
+    c->prof_on = on ? 1 : 0;
+    for (int i = 0; i < 8; ++i) {
+        c->prof_ms[i] = 0.0;
+        c->prof_count[i] = 0;
+    }
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, double* bytes) {
+    if (!c) return fail(SPECMG_EINVAL, "null context");
+    const double n = (double)c->n;
+    const double w = c->fp32 ? 4.0 : 8.0;          // V-cycle word size
+    const double phi_cells = 512.0 * c->lev[0].dim; // sum over elements of 512 * nkeep
+    double b[8] = {0};
+    b[PC_SPMV] = n * 8.0 * 7.0;                      // z, p_old, x, kappa~ in; p, q, x out
+    b[PC_PRE] = n * (8.0 * 3.0 + 2.0 * w + w);       // r, q in, r out; kappa~, 1/d in; u out
+    b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * w;   // u, kappa~, r; phi
+    b[PC_PROLONG] = n * 2.0 * w + phi_cells * w;             // u in/out; phi
+    b[PC_POST] = n * (3.0 * w + 8.0 * 2.0 + (c->fp32 ? 8.0 : 0.0));  // u, kappa~, 1/d, r in; z out (q)
+    for (int i = 0; i < 8; ++i) {
+        if (ms) ms[i] = c->prof_ms[i];
+        if (launches) launches[i] = c->prof_count[i];
+        if (bytes) bytes[i] = b[i];
+    }
     return SPECMG_OK;
 }

@@ -21,7 +21,10 @@ FP64, FP32_VCYCLE = 0, 1
 WS_NONE, WS_CNN = 0, 1
 
 EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_apply_operator",
-            "specmg_get_info", "specmg_copy_level", "specmg_destroy", "specmg_last_error"]
+            "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
+            "specmg_destroy", "specmg_last_error"]
+PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_levels",
+                   "coarsest", "unused"]
 
 
 class Grid(ctypes.Structure):
@@ -79,6 +82,10 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_get_info.restype = ctypes.c_int
     lib.specmg_copy_level.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
     lib.specmg_copy_level.restype = ctypes.c_int
+    lib.specmg_set_profiling.argtypes = [vp, i32]
+    lib.specmg_set_profiling.restype = ctypes.c_int
+    lib.specmg_get_profile.argtypes = [vp, ctypes.POINTER(dbl * 8), ctypes.POINTER(i32 * 8), ctypes.POINTER(dbl * 8)]
+    lib.specmg_get_profile.restype = ctypes.c_int
     lib.specmg_destroy.argtypes = [vp]
     lib.specmg_destroy.restype = None
     lib.specmg_last_error.argtypes = []
@@ -117,6 +124,7 @@ class LevelArrays:
     basis: np.ndarray
     Ad: np.ndarray
     Aoff: np.ndarray
+    status: np.ndarray
 
 
 class SpecMG:
@@ -174,6 +182,17 @@ class SpecMG:
             _check(rc)
         return rc, info
 
+    def set_profiling(self, on: bool = True):
+        _check(_lib.specmg_set_profiling(self._ctx, int(on)))
+
+    def profile(self):
+        """{class: (total_ms, launches, algorithmic_bytes_per_launch)}"""
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int32 * 8)()
+        by = (ctypes.c_double * 8)()
+        _check(_lib.specmg_get_profile(self._ctx, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)))
+        return {PROFILE_CLASSES[i]: (ms[i], cnt[i], by[i]) for i in range(7)}
+
     def info(self):
         lv = ctypes.c_int32()
         dims = (ctypes.c_int32 * 8)()
@@ -196,7 +215,8 @@ class SpecMG:
         out = {}
         for which, name, dtype, shape in ((0, "nkeep", np.int32, (m,)), (1, "lam", np.float64, (m, L)),
                                           (2, "basis", np.float64, (m, L, rows)),
-                                          (3, "Ad", np.float64, (m, L, L)), (4, "Aoff", np.float64, (m, 3, L, L))):
+                                          (3, "Ad", np.float64, (m, L, L)), (4, "Aoff", np.float64, (m, 3, L, L)),
+                                          (5, "status", np.int32, (m,))):
             arr = np.empty(shape, dtype=dtype)
             _check(_lib.specmg_copy_level(self._ctx, level, which, arr.ctypes.data_as(ctypes.c_void_p), arr.nbytes))
             out[name] = arr

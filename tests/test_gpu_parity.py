@@ -7,7 +7,11 @@ Tolerances:
   local spans               sin(angle) <= 1e-9 (residual over the gap to the
                             first dropped eigenvalue, gaps >= 1e-2 here)
   Galerkin blocks           1e-9 relative after aligning the bases
-  P^{-1} r                  1e-9 relative (spans enter P^{-1} linearly)
+  P^{-1} r                  max(1e-10, 1e-15 / lambda_min+(A_L)) relative: the coarse
+                            problems are posed in dimensionless O(1) units, so their
+                            entries carry ~1e-16 absolute rounding on either side,
+                            which the coarsest pseudo-inverse amplifies by
+                            1 / lambda_min+(A_L) (1.4e-8 for contrast 1e6, 3 levels)
   PCG solution              1e-8 relative L2, iterations within +-1
 """
 import numpy as np
@@ -86,6 +90,27 @@ def test_level2_spectral(name, n, shape, kind, seed, levels, eigs, agg):
     assert worst_a < 1e-9
 
 
+@pytest.mark.parametrize("name,n,shape,kind,seed,levels,eigs,agg", [c for c in CASES if c[5] >= 3])
+def test_coarse_level_spectral(name, n, shape, kind, seed, levels, eigs, agg):
+    perm = _field(n, shape, kind, seed)
+    nz, ny, nx = perm.shape
+    g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / nx, 1.0 / nx)
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
+    ctx = _setup(perm, levels, eigs, agg=agg)
+    for l in range(3, levels + 1):
+        lv = ctx.level_arrays(l)
+        ref = hier.level(l)
+        assert np.array_equal(lv.nkeep, ref.nkeep)
+        worst = 0.0
+        for e in range(ref.m):
+            k = ref.nkeep[e]
+            worst = max(worst, np.max(np.abs(lv.lam[e, :k] - ref.lam[e][:k])))
+            print(f"{name} level {l} elem {e}: gpu {np.array2string(lv.lam[e, :k + 1], precision=10)}")
+            print(f"{name} level {l} elem {e}: ref {np.array2string(ref.lam[e][:k + 1], precision=10)}")
+        print(f"{name}: level {l} eig err {worst:.2e}")
+        assert worst < 1e-11
+
+
 def _aligned_blocks(ctx, hier, level):
     """GPU and oracle coarse operators expressed in the oracle's basis."""
     lv = ctx.level_arrays(level)
@@ -148,6 +173,8 @@ def test_apply_precond(name, n, shape, kind, seed, levels, eigs, agg):
     ctx = _setup(perm, levels, eigs, agg=agg)
     for l in range(2, levels + 1):
         assert np.array_equal(ctx.level_arrays(l).nkeep, hier.level(l).nkeep), f"nkeep differs at level {l}"
+    wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
+    tol = max(1e-10, 1e-15 / wL[1])
     for s in range(2):
         r = random_zero_mean(perm.shape, 100 + s).reshape(-1)
         z = torch.empty(g.n, dtype=torch.float64, device="cuda")
@@ -158,8 +185,8 @@ def test_apply_precond(name, n, shape, kind, seed, levels, eigs, agg):
         zg -= zg.mean()
         zo -= zo.mean()
         err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
-        print(f"{name}: P^-1 r rel err {err:.2e}")
-        assert err < 1e-9
+        print(f"{name}: P^-1 r rel err {err:.2e} (tol {tol:.1e})")
+        assert err < tol
 
 
 @pytest.mark.parametrize("name,n,shape,kind,seed,levels,eigs,agg", CASES)
