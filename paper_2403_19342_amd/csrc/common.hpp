@@ -36,10 +36,13 @@ struct Scalars {
 // one arrival counter per reduction site.
 struct RedBuf {
     double* partial;      // [kMaxRedBlocks * 2]
-    unsigned* counter;    // [16]
 };
 
-enum RedSite { RS_PQ = 0, RS_RR = 1, RS_RZ = 2, RS_GEN = 3, RS_GEN2 = 4, RS_EIG = 5 };
+void launch_finalize(int site, int nblocks, Scalars* sc, RedBuf rb, double* out, int check_done,
+                     hipStream_t s);
+
+// what the finalize kernel does with the totals
+enum RedSite { RS_PQ = 0, RS_RR = 1, RS_RZ = 2, RS_GEN = 3, RS_GEN2 = 4 };
 
 // ---------------------------------------------------------------------------
 // wavefront / block reductions (wave64); fixed combination order, so results
@@ -74,41 +77,16 @@ __device__ __forceinline__ double atomic_load_relaxed(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid-wide reduction of NV values per block (blockDim.x <= 256).  Every
-// block calls it once with its block sums (valid in thread 0).  Returns true
-// in exactly one block, the last to arrive; there thread 0's out[] holds the
-// totals, summed in a fixed order (strided per thread, then by thread).
+// Grid-wide reductions: every block writes its NV block sums to
+// partial[k * kMaxRedBlocks + block] (no atomics: a shared arrival counter
+// serialises thousands of same-address atomics); a one-block finalize kernel
+// launched right after sums them in block order, so results are reproducible.
 template <int NV>
-__device__ bool grid_reduce(const double (&v)[NV], RedBuf rb, int site, double (&out)[NV]) {
-    __shared__ int s_last;
-    __shared__ double sh[NV][256];
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
+__device__ __forceinline__ void write_partials(const double (&v)[NV], RedBuf rb) {
     if (threadIdx.x == 0) {
         const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
         for (int k = 0; k < NV; ++k) rb.partial[(size_t)k * kMaxRedBlocks + b] = v[k];
-        __threadfence();
-        const unsigned t = atomicAdd(&rb.counter[site], 1u);
-        s_last = (t == (unsigned)(nb - 1));
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
-    for (int k = 0; k < NV; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nb; i += blockDim.x)
-            s += atomic_load_relaxed(&rb.partial[(size_t)k * kMaxRedBlocks + i]);
-        sh[k][threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 0; k < NV; ++k) {
-            double t = 0.0;
-            for (int i = 0; i < (int)blockDim.x; ++i) t += sh[k][i];
-            out[k] = t;
-        }
-        rb.counter[site] = 0u;
-    }
-    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -169,7 +147,7 @@ void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s);
 
 // coarse levels (k_coarse.hip)
 template <typename T>
-void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* Aoff, const T* r, T* u,
+void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const T* r, T* u,
                           const Scalars* sc, int check_done, hipStream_t s);
 template <typename T>
 void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r,
@@ -180,8 +158,8 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
                            const T* eup, const Scalars* sc, int check_done, hipStream_t s);
 template <typename T>
 void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff,
-                                const T* r, const T* u, T* e, const Scalars* sc, int check_done,
-                                hipStream_t s);
+                                const T* G, const T* r, const T* u, T* e, const Scalars* sc,
+                                int check_done, hipStream_t s);
 template <typename T>
 void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e,
                      const Scalars* sc, int check_done, hipStream_t s);
@@ -195,7 +173,7 @@ void launch_galerkin_up(const CoarseGeom& lo, const CoarseGeom& up, const double
 void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double* D, double* Ad,
                           hipStream_t s);
 void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
-                          double* Dinv, int* bad, hipStream_t s);
+                          double* Dinv, double* G, int* bad, hipStream_t s);
 void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* Aoff,
                            const int* cmap_inv, int np, double* dense, hipStream_t s);
 template <typename S, typename T>

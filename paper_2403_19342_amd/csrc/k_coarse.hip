@@ -11,186 +11,252 @@
 // children in lexicographic order (Section 5): pivots
 //   D_c = Ad_c - sum_{lower neighbour c'} A(c, c') D_c'^{-1} A(c', c),
 // stored inverted in Dinv.  Padded slots carry an identity pivot and zero
-// couplings, so they stay zero.
+// couplings, so they stay zero.  For the substitutions the set-up also forms
+//   G[c][2 ax]     = D_c^{-1} A(c, c - e_ax)   (lower neighbour, same parent)
+//   G[c][2 ax + 1] = D_c^{-1} A(c, c + e_ax)   (upper neighbour, same parent)
+// so that every hyperplane step is a single product:
+//   forward   y_c = D_c^{-1} r_c - sum_lower G y_c'
+//   backward  z_c = y_c - sum_upper G z_c''.
 #include "common.hpp"
 
 namespace specmg {
 
+__device__ __forceinline__ int log2_agg(int agg) { return agg == 4 ? 2 : 1; }
+
+// level-l index of the child at position p (lexicographic in the parent) of
+// parent E; agg is 2 or 4, so positions decode with shifts
 __device__ __forceinline__ int child_of(const CoarseGeom& g, int E, int p) {
-    const int a = g.agg;
+    const int a = g.agg, sh = log2_agg(a);
     const int Ex = E % g.px, Ey = (E / g.px) % g.py, Ez = E / (g.px * g.py);
-    const int qx = p % a, qy = (p / a) % a, qz = p / (a * a);
+    const int qx = p & (a - 1), qy = (p >> sh) & (a - 1), qz = p >> (2 * sh);
     return (Ex * a + qx) + g.mx * ((Ey * a + qy) + g.my * (Ez * a + qz));
 }
 
-// positions of the agg^3 children sorted by qx+qy+qz, built in LDS
-__device__ void build_planes(int agg, int* pos, int* off) {
-    if (threadIdx.x == 0) {
-        int k = 0;
-        for (int s = 0; s <= 3 * (agg - 1); ++s) {
-            off[s] = k;
-            for (int p = 0; p < agg * agg * agg; ++p) {
-                const int q = p % agg + (p / agg) % agg + p / (agg * agg);
-                if (q == s) pos[k++] = p;
-            }
-        }
-        off[3 * (agg - 1) + 1] = k;
+// children positions sorted by qx+qy+qz for agg = 2 and agg = 4
+struct ChildPlanes {
+    unsigned char pos2[8], off2[5];
+    unsigned char pos4[64], off4[11];
+};
+
+constexpr ChildPlanes make_child_planes() {
+    ChildPlanes t{};
+    int k = 0;
+    for (int s = 0; s <= 3; ++s) {
+        t.off2[s] = (unsigned char)k;
+        for (int p = 0; p < 8; ++p)
+            if ((p & 1) + ((p >> 1) & 1) + (p >> 2) == s) t.pos2[k++] = (unsigned char)p;
     }
+    t.off2[4] = (unsigned char)k;
+    k = 0;
+    for (int s = 0; s <= 9; ++s) {
+        t.off4[s] = (unsigned char)k;
+        for (int p = 0; p < 64; ++p)
+            if ((p & 3) + ((p >> 2) & 3) + (p >> 4) == s) t.pos4[k++] = (unsigned char)p;
+    }
+    t.off4[10] = (unsigned char)k;
+    return t;
+}
+
+__constant__ ChildPlanes kCP = make_child_planes();
+
+// positions of the agg^3 children sorted by qx+qy+qz, copied into LDS
+__device__ void build_planes(int agg, int* pos, int* off) {
+    const int nc = agg * agg * agg, np = 3 * (agg - 1) + 2;
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) pos[t] = agg == 4 ? kCP.pos4[t] : kCP.pos2[t];
+    for (int t = threadIdx.x; t < np; t += blockDim.x) off[t] = agg == 4 ? kCP.off4[t] : kCP.off2[t];
     __syncthreads();
 }
 
-// y_c = (A_l u)_c for row a of child element c (neighbours read from global)
+constexpr int kMaxLc = 12;   // padded widths up to target 8 + 3
+
+// y_c = (A_l u)_c for row a of child element c; all block-row loads of the
+// thread are issued before the products
 template <typename T>
 __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __restrict__ Ad,
                                              const T* __restrict__ Aoff, const T* __restrict__ u, int c,
                                              int a) {
     const int L = g.L;
     const int cx = c % g.mx, cy = (c / g.mx) % g.my, cz = c / (g.mx * g.my);
-    T s = T(0);
-    const T* ad = Ad + ((size_t)c * L + a) * L;
-    const T* uc = u + (size_t)c * L;
-    for (int b = 0; b < L; ++b) s += ad[b] * uc[b];
     const int cc[3] = {cx, cy, cz};
     const int ext[3] = {g.mx, g.my, g.mz};
     const int stride[3] = {1, g.mx, g.mx * g.my};
+    T acc = T(0);
+    {
+        const T* ad = Ad + ((size_t)c * L + a) * L;
+        const T* uc = u + (size_t)c * L;
+#pragma unroll
+        for (int b = 0; b < kMaxLc; ++b) {
+            const int bb = b < L ? b : L - 1;
+            acc += (b < L ? ad[bb] : T(0)) * uc[bb];
+        }
+    }
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         if (cc[ax] + 1 < ext[ax]) {
             const int cn = c + stride[ax];
             const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
             const T* un = u + (size_t)cn * L;
-            for (int b = 0; b < L; ++b) s += o[b] * un[b];
+#pragma unroll
+            for (int b = 0; b < kMaxLc; ++b) {
+                const int bb = b < L ? b : L - 1;
+                acc += (b < L ? o[bb] : T(0)) * un[bb];
+            }
         }
         if (cc[ax] > 0) {
             const int cn = c - stride[ax];
             const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
             const T* un = u + (size_t)cn * L;
-            for (int b = 0; b < L; ++b) s += o[b * L + a] * un[b];
-        }
-    }
-    return s;
-}
-
-// Block IC(0) forward/backward substitution over the children of parent E.
-// sY[p*L + a] holds the right-hand side on entry and the result on exit.
-template <typename T>
-__device__ void block_ic_sweep(const CoarseGeom& g, int E, const T* __restrict__ Dinv,
-                               const T* __restrict__ Aoff, T* sY, T* tmp, const int* pos, const int* off) {
-    const int L = g.L, agg = g.agg;
-    const int nplanes = 3 * (agg - 1) + 1;
-    const int k = threadIdx.x / L, a = threadIdx.x % L;
-    for (int s = 0; s < nplanes; ++s) {
-        const int cnt = off[s + 1] - off[s];
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
-            const int c = child_of(g, E, p);
-            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
-            const int pstep[3] = {1, agg, agg * agg};
-            const int cstep[3] = {1, g.mx, g.mx * g.my};
-            T acc = sY[p * L + a];
-            for (int ax = 0; ax < 3; ++ax) {
-                if (q[ax] > 0) {
-                    // A(c, c') = Aoff[c'][ax]^T with c' = c - e_ax
-                    const int cn = c - cstep[ax], pn = p - pstep[ax];
-                    const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
-                    for (int b = 0; b < L; ++b) acc -= o[b * L + a] * sY[pn * L + b];
-                }
+#pragma unroll
+            for (int b = 0; b < kMaxLc; ++b) {
+                const int bb = b < L ? b : L - 1;
+                acc += (b < L ? o[bb * L + a] : T(0)) * un[bb];
             }
-            tmp[k * L + a] = acc;
         }
-        __syncthreads();
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
-            const int c = child_of(g, E, p);
-            const T* di = Dinv + ((size_t)c * L + a) * L;
-            T y = T(0);
-            for (int b = 0; b < L; ++b) y += di[b] * tmp[k * L + b];
-            sY[p * L + a] = y;
-        }
-        __syncthreads();
     }
-    for (int s = nplanes - 1; s >= 0; --s) {
-        const int cnt = off[s + 1] - off[s];
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
-            const int c = child_of(g, E, p);
-            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
-            const int pstep[3] = {1, agg, agg * agg};
-            T acc = T(0);
-            for (int ax = 0; ax < 3; ++ax) {
-                if (q[ax] < agg - 1) {
-                    const int pn = p + pstep[ax];
-                    const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
-                    for (int b = 0; b < L; ++b) acc += o[b] * sY[pn * L + b];
-                }
-            }
-            tmp[k * L + a] = acc;
-        }
-        __syncthreads();
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
-            const int c = child_of(g, E, p);
-            const T* di = Dinv + ((size_t)c * L + a) * L;
-            T z = T(0);
-            for (int b = 0; b < L; ++b) z += di[b] * tmp[k * L + b];
-            sY[p * L + a] -= z;
-        }
-        __syncthreads();
-    }
+    return acc;
 }
 
 constexpr int kCoarseThreads = 256;
 constexpr int kMaxChildren = 64;   // agg <= 4
 constexpr int kMaxL = 16;
 
-// u = M_l^{-1} r
+// Staged copy of the coupling blocks of one sweep direction for all
+// children of E: sG[(p * 3 + ax) * LL + e] = G[child(p)][2 ax + upper][e].
+// Loads are issued 16 per thread before their LDS stores.
 template <typename T>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_smooth(CoarseGeom g, const T* __restrict__ Dinv,
-                                                                 const T* __restrict__ Aoff,
-                                                                 const T* __restrict__ r, T* __restrict__ u,
-                                                                 const Scalars* sc, int check_done) {
-    if (check_done && sc->done) return;
-    __shared__ T sY[kMaxChildren * kMaxL];
-    __shared__ T tmp[12 * kMaxL];
-    __shared__ int pos[kMaxChildren], off[12];
-    const int E = blockIdx.x;
-    const int L = g.L, nc = g.agg * g.agg * g.agg;
-    build_planes(g.agg, pos, off);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        sY[t] = r[(size_t)child_of(g, E, p) * L + a];
-    }
-    __syncthreads();
-    block_ic_sweep<T>(g, E, Dinv, Aoff, sY, tmp, pos, off);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        u[(size_t)child_of(g, E, p) * L + a] = sY[t];
+__device__ void stage_couplings(const CoarseGeom& g, int E, const T* __restrict__ G, int upper, T* sG) {
+    const int LL = g.L * g.L, nc = g.agg * g.agg * g.agg;
+    const int total = nc * 3 * LL;
+    for (int base = 0; base < total; base += 16 * blockDim.x) {
+        T v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = base + u * blockDim.x + threadIdx.x;
+            v[u] = T(0);
+            if (t < total) {
+                const int p = t / (3 * LL), ax = (t / LL) % 3, e = t % LL;
+                v[u] = G[((size_t)child_of(g, E, p) * 6 + 2 * ax + upper) * LL + e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = base + u * blockDim.x + threadIdx.x;
+            if (t < total) sG[t] = v[u];
+        }
     }
 }
 
-// e = u + M_l^{-1} (r - A_l u)
+// One hyperplane-ordered half of the block IC(0) substitution over the
+// children of E, in place on sY.  forward: y_c = sW_c - sum_lower G y;
+// backward: z_c = y_c - sum_upper G z.  Couplings from LDS (sG, staged) or
+// global memory.
 template <typename T>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_smooth(
-    CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Dinv, const T* __restrict__ Aoff,
-    const T* __restrict__ r, const T* __restrict__ u, T* __restrict__ e, const Scalars* sc, int check_done) {
+__device__ void ic_half_sweep(const CoarseGeom& g, int E, int upper, const T* __restrict__ G, const T* sG,
+                              T* sY, const T* sW, const int* pos, const int* off) {
+    const int L = g.L, agg = g.agg, LL = L * L;
+    const int nplanes = 3 * (agg - 1) + 1;
+    const int k = threadIdx.x / L, a = threadIdx.x % L;
+    const int pstep[3] = {1, agg, agg * agg};
+    for (int ss = 0; ss < nplanes; ++ss) {
+        const int s = upper ? nplanes - 1 - ss : ss;
+        const int cnt = off[s + 1] - off[s];
+        if (k < cnt) {
+            const int p = pos[off[s] + k];
+            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
+            T acc = upper ? sY[p * L + a] : sW[p * L + a];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const bool has = upper ? (q[ax] < agg - 1) : (q[ax] > 0);
+                if (!has) continue;
+                const int pn = upper ? p + pstep[ax] : p - pstep[ax];
+                const T* gr = sG ? sG + ((size_t)(p * 3 + ax) * L + a) * L
+                                 : G + (((size_t)child_of(g, E, p) * 6 + 2 * ax + upper) * L + a) * L;
+#pragma unroll
+                for (int b = 0; b < kMaxLc; ++b) {
+                    const int bb = b < L ? b : L - 1;
+                    acc -= (b < L ? gr[bb] : T(0)) * sY[pn * L + bb];
+                }
+            }
+            sY[p * L + a] = acc;
+        }
+        __syncthreads();
+    }
+    (void)LL;
+}
+
+constexpr int kSweepThreads = 512;
+
+// forward half of the level-l smoother on parent E:
+//   t = r (mode 0) or t = r - A_l u (mode 1);  y = (D + L)^{-1} t, written to yout
+template <typename T>
+__global__ __launch_bounds__(kSweepThreads) void k_coarse_fwd(CoarseGeom g, int mode, const T* __restrict__ Ad,
+                                                              const T* __restrict__ Aoff,
+                                                              const T* __restrict__ Dinv, const T* __restrict__ G,
+                                                              const T* __restrict__ r, const T* __restrict__ u,
+                                                              T* __restrict__ yout, const Scalars* sc, int check_done,
+                                                              int staged) {
     if (check_done && sc->done) return;
-    __shared__ T sY[kMaxChildren * kMaxL];
-    __shared__ T tmp[12 * kMaxL];
+    extern __shared__ double dyn_coarse[];
     __shared__ int pos[kMaxChildren], off[12];
     const int E = blockIdx.x;
-    const int L = g.L, nc = g.agg * g.agg * g.agg;
+    const int L = g.L, nc = g.agg * g.agg * g.agg, LL = L * L;
+    T* sG = staged ? (T*)dyn_coarse : nullptr;
+    T* sY = (T*)dyn_coarse + (staged ? nc * 3 * LL : 0);
+    T* sW = sY + nc * L;
     build_planes(g.agg, pos, off);
+    if (staged) stage_couplings<T>(g, E, G, 0, sG);
     for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
         const int p = t / L, a = t % L;
         const int c = child_of(g, E, p);
-        sY[t] = r[(size_t)c * L + a] - block_row_apply<T>(g, Ad, Aoff, u, c, a);
+        T tv = r[(size_t)c * L + a];
+        if (mode) tv -= block_row_apply<T>(g, Ad, Aoff, u, c, a);
+        sY[t] = tv;
     }
     __syncthreads();
-    block_ic_sweep<T>(g, E, Dinv, Aoff, sY, tmp, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        const T* di = Dinv + ((size_t)child_of(g, E, p) * L + a) * L;
+        T acc = T(0);
+#pragma unroll
+        for (int b = 0; b < kMaxLc; ++b) {
+            const int bb = b < L ? b : L - 1;
+            acc += (b < L ? di[bb] : T(0)) * sY[p * L + bb];
+        }
+        sW[t] = acc;
+    }
+    __syncthreads();
+    ic_half_sweep<T>(g, E, 0, G, sG, sY, sW, pos, off);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        yout[(size_t)child_of(g, E, p) * L + a] = sY[t];
+    }
+}
+
+// backward half on parent E: z = y - (D)^{-1} L^T z by hyperplanes;
+// mode 0: out = z;  mode 1: out = u + z.  y and out may alias.
+template <typename T>
+__global__ __launch_bounds__(kSweepThreads) void k_coarse_bwd(CoarseGeom g, int mode, const T* __restrict__ G,
+                                                              const T* y, const T* __restrict__ u, T* out,
+                                                              const Scalars* sc, int check_done, int staged) {
+    if (check_done && sc->done) return;
+    extern __shared__ double dyn_coarse[];
+    __shared__ int pos[kMaxChildren], off[12];
+    const int E = blockIdx.x;
+    const int L = g.L, nc = g.agg * g.agg * g.agg, LL = L * L;
+    T* sG = staged ? (T*)dyn_coarse : nullptr;
+    T* sY = (T*)dyn_coarse + (staged ? nc * 3 * LL : 0);
+    build_planes(g.agg, pos, off);
+    if (staged) stage_couplings<T>(g, E, G, 1, sG);
+    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+        const int p = t / L, a = t % L;
+        sY[t] = y[(size_t)child_of(g, E, p) * L + a];
+    }
+    __syncthreads();
+    ic_half_sweep<T>(g, E, 1, G, sG, sY, nullptr, pos, off);
     for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
         const int p = t / L, a = t % L;
         const size_t i = (size_t)child_of(g, E, p) * L + a;
-        e[i] = u[i] + sY[t];
+        out[i] = mode ? u[i] + sY[t] : sY[t];
     }
 }
 
@@ -212,15 +278,31 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     }
     __syncthreads();
     const int nk = nkeep_up[E];
-    for (int j = 0; j < Lup; ++j) {
-        double v = 0.0;
-        if (j < nk) {
-            const T* vj = V + ((size_t)E * Lup + j) * n;
-            for (int t = threadIdx.x; t < n; t += blockDim.x) v += (double)vj[t] * (double)sS[t];
+    double acc[kMaxLc];
+#pragma unroll
+    for (int j = 0; j < kMaxLc; ++j) acc[j] = 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double sv = (double)sS[t];
+#pragma unroll
+        for (int j = 0; j < kMaxLc; ++j) {
+            const int jj = j < nk ? j : nk - 1;
+            acc[j] += (j < nk ? (double)V[((size_t)E * Lup + jj) * n + t] : 0.0) * sv;
         }
-        const double s = block_sum(v, sred);
-        if (threadIdx.x == 0) rup[(size_t)E * Lup + j] = (T)s;
     }
+    __shared__ double sacc[kCoarseThreads / 64][kMaxLc];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kMaxLc; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) sacc[w][j] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < Lup) {
+        double t = 0.0;
+        for (int ww = 0; ww < kCoarseThreads / 64; ++ww) t += sacc[ww][threadIdx.x];
+        rup[(size_t)E * Lup + threadIdx.x] = (int)threadIdx.x < nk ? (T)t : T(0);
+    }
+    (void)sred;
 }
 
 // u += V_E e_up[E] on the children of E
@@ -238,7 +320,11 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int p = t / L, a = t % L;
         T acc = T(0);
-        for (int j = 0; j < nk; ++j) acc += V[((size_t)E * Lup + j) * n + t] * ee[j];
+#pragma unroll
+        for (int j = 0; j < kMaxLc; ++j) {
+            const int jj = j < nk ? j : nk - 1;
+            acc += (j < nk ? V[((size_t)E * Lup + jj) * n + t] : T(0)) * ee[jj];
+        }
         u[(size_t)child_of(g, E, p) * L + a] += acc;
     }
 }
@@ -520,6 +606,33 @@ __global__ __launch_bounds__(64) void k_blockic_setup(CoarseGeom g, const double
     }
 }
 
+// G[c][2ax] = Dinv_c A(c, c - e_ax), G[c][2ax+1] = Dinv_c A(c, c + e_ax) for
+// neighbours inside the same parent (zero otherwise)
+__global__ __launch_bounds__(256) void k_blockic_couple(CoarseGeom g, const double* __restrict__ Aoff,
+                                                         const double* __restrict__ Dinv, double* __restrict__ G) {
+    const int c = blockIdx.x;
+    const int L = g.L, LL = L * L, agg = g.agg;
+    const int cx = c % g.mx, cy = (c / g.mx) % g.my, cz = c / (g.mx * g.my);
+    const int q[3] = {cx % agg, cy % agg, cz % agg};
+    const int stride[3] = {1, g.mx, g.mx * g.my};
+    const double* Di = Dinv + (size_t)c * LL;
+    for (int t = threadIdx.x; t < 6 * LL; t += blockDim.x) {
+        const int d = t / LL, a = (t % LL) / L, b = t % L;
+        const int ax = d >> 1;
+        const bool upper = d & 1;
+        double v = 0.0;
+        if (upper ? (q[ax] < agg - 1) : (q[ax] > 0)) {
+            for (int k = 0; k < L; ++k) {
+                // A(c, c - e) = Aoff[c - e][ax]^T ; A(c, c + e) = Aoff[c][ax]
+                const double A = upper ? Aoff[(((size_t)c * 3 + ax) * L + k) * L + b]
+                                       : Aoff[(((size_t)(c - stride[ax]) * 3 + ax) * L + b) * L + k];
+                v += Di[a * L + k] * A;
+            }
+        }
+        G[((size_t)c * 6 + d) * LL + a * L + b] = v;
+    }
+}
+
 // coarsest dense matrix over the compact unknowns (cinv: padded -> compact
 // or -1); the matrix must be zeroed beforehand
 __global__ void k_build_coarsest(CoarseGeom g, const double* __restrict__ Ad, const double* __restrict__ Aoff,
@@ -559,13 +672,6 @@ __global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_
 // launchers
 
 template <typename T>
-void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* Aoff, const T* r, T* u, const Scalars* sc,
-                          int check_done, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_smooth<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Dinv, Aoff, r, u, sc,
-                       check_done);
-}
-
-template <typename T>
 void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
                                   const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
                                   int check_done, hipStream_t s) {
@@ -580,11 +686,42 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
                        sc, check_done);
 }
 
+// dynamic LDS of the sweep kernels; couplings are staged when they fit
 template <typename T>
-void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* r,
-                                const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_resid_smooth<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Ad, Dinv, Aoff, r, u,
-                       e, sc, check_done);
+static size_t sweep_lds(const CoarseGeom& g, int& staged) {
+    const size_t nc = (size_t)g.agg * g.agg * g.agg, LL = (size_t)g.L * g.L;
+    const size_t vec = 2 * nc * g.L * sizeof(T);
+    const size_t all = nc * 3 * LL * sizeof(T) + vec;
+    staged = all <= 150 * 1024;
+    return staged ? all : vec;
+}
+
+// u = M_l^{-1} r
+template <typename T>
+void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const T* r, T* u, const Scalars* sc,
+                          int check_done, hipStream_t s) {
+    int staged;
+    const size_t lds = sweep_lds<T>(g, staged);
+    hipFuncSetAttribute((const void*)k_coarse_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void*)k_coarse_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_coarse_fwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, (const T*)nullptr,
+                       (const T*)nullptr, Dinv, G, r, (const T*)nullptr, u, sc, check_done, staged);
+    hipLaunchKernelGGL((k_coarse_bwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, G, (const T*)u,
+                       (const T*)nullptr, u, sc, check_done, staged);
+}
+
+// e = u + M_l^{-1} (r - A_l u)
+template <typename T>
+void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* G,
+                                const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
+    int staged;
+    const size_t lds = sweep_lds<T>(g, staged);
+    hipFuncSetAttribute((const void*)k_coarse_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute((const void*)k_coarse_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_coarse_fwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, Ad, Aoff, Dinv, G, r, u, e,
+                       sc, check_done, staged);
+    hipLaunchKernelGGL((k_coarse_bwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, G, (const T*)e, u, e, sc,
+                       check_done, staged);
 }
 
 template <typename T>
@@ -610,8 +747,9 @@ void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double*
 }
 
 void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
-                          double* Dinv, int* bad, hipStream_t s) {
+                          double* Dinv, double* G, int* bad, hipStream_t s) {
     hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64), 0, s, g, Ad, Aoff, nkeep, Dinv, bad);
+    hipLaunchKernelGGL(k_blockic_couple, dim3(g.m), dim3(256), 0, s, g, Aoff, Dinv, G);
 }
 
 void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* cinv, int np,
@@ -642,11 +780,11 @@ template void launch_coarse_prolong<double>(const CoarseGeom&, double*, const do
 template void launch_coarse_prolong<float>(const CoarseGeom&, float*, const float*, const int*, int, const float*,
                                            const Scalars*, int, hipStream_t);
 template void launch_coarse_resid_smooth<double>(const CoarseGeom&, const double*, const double*, const double*,
-                                                 const double*, const double*, double*, const Scalars*, int,
-                                                 hipStream_t);
+                                                 const double*, const double*, const double*, double*,
+                                                 const Scalars*, int, hipStream_t);
 template void launch_coarse_resid_smooth<float>(const CoarseGeom&, const float*, const float*, const float*,
-                                                const float*, const float*, float*, const Scalars*, int,
-                                                hipStream_t);
+                                                const float*, const float*, const float*, float*, const Scalars*,
+                                                int, hipStream_t);
 template void launch_coarsest<double>(int, int, const double*, const int*, const double*, double*, const Scalars*,
                                       int, hipStream_t);
 template void launch_coarsest<float>(int, int, const double*, const int*, const float*, float*, const Scalars*, int,

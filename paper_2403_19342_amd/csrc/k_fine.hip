@@ -37,6 +37,8 @@ constexpr PlaneTable make_planes() {
 
 __constant__ PlaneTable kPT = make_planes();
 
+constexpr int kMaxCols = 12;   // padded basis width (target <= 8, plus 3)
+
 template <typename T>
 __device__ __forceinline__ T harm(T a, T b) {
     // harmonic mean 2ab/(a+b); zero when a neighbour is outside the domain
@@ -71,37 +73,66 @@ __device__ __forceinline__ size_t gidx(const FineGeom& g, int x, int y, int z) {
     return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
 }
 
-// tile (with one-cell halo) of a global cell array into LDS, zero outside Omega
-template <int EX, typename S, typename D>
-__device__ __forceinline__ void load_halo(const FineGeom& g, const S* __restrict__ src, D* dst, int x0,
-                                          int y0, int z0) {
+// Tiles (with a one-cell halo) of global cell arrays into LDS, zero outside
+// Omega.  All loads of a thread are issued before any LDS store, so each
+// wavefront keeps its whole share of the tile in flight.
+template <int EX>
+__device__ __forceinline__ bool halo_cell(const FineGeom& g, int h, int x0, int y0, int z0, size_t& gi) {
     using TT = TileT<EX>;
-    for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
-        const int hx = h % TT::HX;
-        const int r = h / TT::HX;
-        const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, z = z0 + (r / 10) - 1;
-        D v = D(0);
-        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz) v = (D)src[gidx(g, x, y, z)];
-        dst[h] = v;
+    const int hx = h % TT::HX;
+    const int r = h / TT::HX;
+    const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, z = z0 + (r / 10) - 1;
+    gi = gidx(g, x, y, z);
+    return h < TT::NH && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+}
+
+template <int EX, typename S1, typename D1, typename S2, typename D2>
+__device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restrict__ a, D1* da,
+                                           const S2* __restrict__ b, D2* db, int x0, int y0, int z0) {
+    using TT = TileT<EX>;
+    constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
+    D1 va[IT];
+    D2 vb[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        size_t gi;
+        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi);
+        va[it] = in ? (D1)a[gi] : D1(0);
+        vb[it] = in ? (D2)b[gi] : D2(0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int h = threadIdx.x + it * TT::NT;
+        if (h < TT::NH) {
+            da[h] = va[it];
+            db[h] = vb[it];
+        }
     }
 }
 
-// p = z + beta * pold on the haloed tile
+// p = z + beta * pold on the haloed tile, together with kappa~
 template <int EX>
 __device__ __forceinline__ void load_halo_p(const FineGeom& g, const double* __restrict__ z,
                                             const double* __restrict__ pold, double beta, int first,
-                                            double* dst, int x0, int y0, int z0) {
+                                            double* dst, const double* __restrict__ kt, double* dk, int x0,
+                                            int y0, int z0) {
     using TT = TileT<EX>;
-    for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
-        const int hx = h % TT::HX;
-        const int r = h / TT::HX;
-        const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, zz = z0 + (r / 10) - 1;
-        double v = 0.0;
-        if (x >= 0 && x < g.nx && y >= 0 && y < g.ny && zz >= 0 && zz < g.nz) {
-            const size_t i = gidx(g, x, y, zz);
-            v = first ? z[i] : z[i] + beta * pold[i];
+    constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
+    double vp[IT], vk[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        size_t gi;
+        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi);
+        vp[it] = in ? (first ? z[gi] : z[gi] + beta * pold[gi]) : 0.0;
+        vk[it] = in ? kt[gi] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int h = threadIdx.x + it * TT::NT;
+        if (h < TT::NH) {
+            dst[h] = vp[it];
+            dk[h] = vk[it];
         }
-        dst[h] = v;
     }
 }
 
@@ -135,11 +166,18 @@ __device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* K) {
     constexpr int KXY = HALO ? TileT<EX>::HXY : TX * 8;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
+    // this lane's cell on every hyperplane (-1: idle), fetched once
+    int myc[kPlanes];
+#pragma unroll
     for (int s = 0; s < kPlanes; ++s) {
         const int o = kPT.off[s];
         const int cnt = kPT.off[s + 1] - o;
-        if (lane < cnt) {
-            const int c = kPT.cell[o + lane];
+        myc[s] = lane < cnt ? (int)kPT.cell[o + lane] : -1;
+    }
+#pragma unroll
+    for (int s = 0; s < kPlanes; ++s) {
+        const int c = myc[s];
+        if (c >= 0) {
             const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
             const int ti = 8 * w + i + TX * (j + 8 * k);
             const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
@@ -152,11 +190,10 @@ __device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* K) {
         }
         __syncthreads();
     }
+#pragma unroll
     for (int s = kPlanes - 1; s >= 0; --s) {
-        const int o = kPT.off[s];
-        const int cnt = kPT.off[s + 1] - o;
-        if (lane < cnt) {
-            const int c = kPT.cell[o + lane];
+        const int c = myc[s];
+        if (c >= 0) {
             const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
             const int ti = 8 * w + i + TX * (j + 8 * k);
             const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
@@ -190,32 +227,36 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     tile_origin(g, x0, y0, z0);
     const double alpha = (mode & 1) ? sc->alpha : 0.0;
     double rr = 0.0;
-    for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
+    constexpr int IT = TT::NC / TT::NT;
+    double vr[IT], vq[IT];
+    T vk[IT], vd[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int c = threadIdx.x + it * TT::NT;
         const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
         const size_t gi = gidx(g, x0 + x, y0 + y, z0 + z);
-        double rv = r[gi];
+        vr[it] = r[gi];
+        vq[it] = (mode & 1) ? q[gi] : 0.0;
+        vk[it] = kt[gi];
+        vd[it] = invd[gi];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int c = threadIdx.x + it * TT::NT;
+        double rv = vr[it];
         if (mode & 1) {
-            rv -= alpha * q[gi];
-            r[gi] = rv;
+            const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
+            rv -= alpha * vq[it];
+            r[gidx(g, x0 + x, y0 + y, z0 + z)] = rv;
             rr += rv * rv;
         }
         sY[c] = (T)rv;
-        sK[c] = kt[gi];
-        sD[c] = invd[gi];
+        sK[c] = vk[it];
+        sD[c] = vd[it];
     }
     if (mode & 1) {
         double v[1] = {block_sum(rr, sred)};
-        double out[1];
-        if (grid_reduce<1>(v, rb, RS_RR, out)) {
-            if (threadIdx.x == 0) {
-                sc->rr = out[0];
-                if (!(out[0] <= sc->thresh2)) {
-                    if (!isfinite(out[0])) sc->done = 2;
-                } else {
-                    sc->done = 1;
-                }
-            }
-        }
+        write_partials<1>(v, rb);
     }
     __syncthreads();
     ic_sweep<EX, 0, T>(sY, sD, sK);
@@ -241,8 +282,7 @@ __global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T*
     __shared__ T sS[TT::NC];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
-    load_halo<EX>(g, u, sU, x0, y0, z0);
-    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
     __syncthreads();
     {
         const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
@@ -263,14 +303,20 @@ __global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T*
     }
     const int nk = nkeep[e];
     const T* ph = phi + (size_t)e * L * kSub3;
-    for (int jj = 0; jj < L; ++jj) {
-        T acc = T(0);
-        if (jj < nk) {
+    // all basis loads of the lane first, then one wave reduction per column
+    T acc[kMaxCols];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) acc += ph[(size_t)jj * kSub3 + lane + 64 * i] * sv[i];
-        }
-        acc = wave_sum(acc);
-        if (lane == 0) r2[(size_t)e * L + jj] = acc;
+    for (int jj = 0; jj < kMaxCols; ++jj) {
+        const int jc = jj < nk ? jj : nk - 1;
+        T a = T(0);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) a += ph[(size_t)jc * kSub3 + lane + 64 * i] * sv[i];
+        acc[jj] = jj < nk ? a : T(0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < kMaxCols; ++jj) {
+        const T v = wave_sum(acc[jj]);
+        if (lane == 0 && jj < L) r2[(size_t)e * L + jj] = v;
     }
 }
 
@@ -288,7 +334,11 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const T* __re
     const T* ee = e2 + (size_t)e * L;
     for (int c = threadIdx.x; c < kSub3; c += 256) {
         T acc = T(0);
-        for (int jj = 0; jj < nk; ++jj) acc += ph[(size_t)jj * kSub3 + c] * ee[jj];
+#pragma unroll
+        for (int jj = 0; jj < kMaxCols; ++jj) {
+            const int jc = jj < nk ? jj : nk - 1;
+            acc += (jj < nk ? ph[(size_t)jc * kSub3 + c] : T(0)) * ee[jc];
+        }
         const size_t gi = gidx(g, ex * 8 + (c & 7), ey * 8 + ((c >> 3) & 7), ez * 8 + (c >> 6));
         u[gi] += acc;
     }
@@ -314,8 +364,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
-    load_halo<EX>(g, u, sU, x0, y0, z0);
-    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
     __syncthreads();
     const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
     for (int zz = 0; zz < 8; ++zz) {
@@ -341,18 +390,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     }
     if (mode & 1) {
         double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
-        double out[2];
-        if (grid_reduce<2>(v, rb, RS_RZ, out)) {
-            if (threadIdx.x == 0) {
-                const double old = sc->rz;
-                double beta = 0.0;
-                if (old != 0.0) beta = flex ? (-sc->alpha * out[1] / old) : (out[0] / old);
-                sc->beta = beta;
-                sc->rz_new = out[0];
-                sc->zq = out[1];
-                sc->rz = out[0];
-            }
-        }
+        write_partials<2>(v, rb);
     }
 }
 
@@ -373,8 +411,7 @@ __global__ __launch_bounds__(64 * EX) void k_spmv_pcg(FineGeom g, const double* 
     tile_origin(g, x0, y0, z0);
     const double beta = sc->beta;
     const double ax = first ? 0.0 : sc->alpha_x;
-    load_halo_p<EX>(g, zv, pold, beta, first, sP, x0, y0, z0);
-    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    load_halo_p<EX>(g, zv, pold, beta, first, sP, kt, sK, x0, y0, z0);
     __syncthreads();
     const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
     double pq = 0.0;
@@ -389,22 +426,8 @@ __global__ __launch_bounds__(64 * EX) void k_spmv_pcg(FineGeom g, const double* 
         pq += p * qq;
     }
     double v[1] = {block_sum(pq, sred)};
-    double out[1];
-    if (grid_reduce<1>(v, rb, RS_PQ, out)) {
-        if (threadIdx.x == 0) {
-            sc->pq = out[0];
-            sc->iter += 1;
-            sc->pbuf = pbuf;
-            if (!(out[0] > 0.0) || !isfinite(out[0])) {
-                sc->done = 2;
-                sc->alpha = 0.0;
-                sc->alpha_x = 0.0;
-            } else {
-                sc->alpha = sc->rz / out[0];
-                sc->alpha_x = sc->alpha;
-            }
-        }
-    }
+    write_partials<1>(v, rb);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
 }
 
 // y = A x  (resid = 0)   or   y = b - A x  (resid = 1)
@@ -418,8 +441,7 @@ __global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* _
     __shared__ double sK[TT::NH];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
-    load_halo<EX>(g, xv, sX, x0, y0, z0);
-    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    load_halo2<EX>(g, xv, sX, kt, sK, x0, y0, z0);
     __syncthreads();
     const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
     for (int zz = 0; zz < 8; ++zz) {
@@ -441,7 +463,10 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
     __shared__ double sDg[TT::NC];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
-    load_halo<EX>(g, kt, sK, x0, y0, z0);
+    for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
+        size_t gi;
+        sK[h] = halo_cell<EX>(g, h, x0, y0, z0, gi) ? kt[gi] : 0.0;
+    }
     __syncthreads();
     constexpr int HX = TT::HX, HXY = TT::HXY, TX = TT::TX;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -497,20 +522,16 @@ __global__ void k_perm_to_kt(const double* __restrict__ perm, double* __restrict
 // ---------------------------------------------------------------------------
 // vector utilities
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
-                                              int64_t n, double* out, RedBuf rb, int site) {
+                                              int64_t n, RedBuf rb) {
     __shared__ double sred[4];
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         s += a[i] * b[i];
     double v[1] = {block_sum(s, sred)};
-    double o[1];
-    if (grid_reduce<1>(v, rb, site, o)) {
-        if (threadIdx.x == 0) *out = o[0];
-    }
+    write_partials<1>(v, rb);
 }
 
-__global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, int64_t n, double* out_sum,
-                                                  double* out_abs, RedBuf rb) {
+__global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, int64_t n, RedBuf rb) {
     __shared__ double sred[4];
     double s = 0.0, t = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -518,13 +539,67 @@ __global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, i
         t += fabs(a[i]);
     }
     double v[2] = {block_sum(s, sred), block_sum(t, sred)};
-    double o[2];
-    if (grid_reduce<2>(v, rb, RS_GEN2, o)) {
-        if (threadIdx.x == 0) {
-            *out_sum = o[0];
-            *out_abs = o[1];
+    write_partials<2>(v, rb);
+}
+
+// Sums the block partials of one reduction in block order and applies the
+// CG scalar update of the reduction site.
+__global__ __launch_bounds__(256) void k_finalize(int site, int nb, Scalars* sc, RedBuf rb, double* out,
+                                                   int check_done) {
+    if (check_done && sc->done) return;
+    __shared__ double sh[2][4];
+    const int nv = (site == RS_RZ || site == RS_GEN2) ? 2 : 1;
+    double t[2] = {0.0, 0.0};
+    for (int k = 0; k < nv; ++k) {
+        const double* pk = rb.partial + (size_t)k * kMaxRedBlocks;
+        double a[8];
+        for (int base = 0; base < nb; base += 256 * 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = base + u * 256 + threadIdx.x;
+                a[u] = i < nb ? pk[i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t[k] += a[u];
         }
+        t[k] = wave_sum(t[k]);
+        if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = t[k];
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < nv; ++k) t[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+    if (site == RS_PQ) {
+        sc->pq = t[0];
+        sc->iter += 1;
+        if (!(t[0] > 0.0) || !isfinite(t[0])) {
+            sc->done = 2;
+            sc->alpha = 0.0;
+            sc->alpha_x = 0.0;
+        } else {
+            sc->alpha = sc->rz / t[0];
+            sc->alpha_x = sc->alpha;
+        }
+    } else if (site == RS_RR) {
+        sc->rr = t[0];
+        if (t[0] <= sc->thresh2) sc->done = 1;
+        else if (!isfinite(t[0])) sc->done = 2;
+    } else if (site == RS_RZ) {
+        const double old = sc->rz;
+        double beta = 0.0;
+        if (old != 0.0) beta = sc->flexible ? (-sc->alpha * t[1] / old) : (t[0] / old);
+        sc->beta = beta;
+        sc->rz_new = t[0];
+        sc->zq = t[1];
+        sc->rz = t[0];
+    } else {
+        out[0] = t[0];
+        if (nv == 2) out[1] = t[1];
+    }
+}
+
+void launch_finalize(int site, int nblocks, Scalars* sc, RedBuf rb, double* out, int check_done,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, nblocks, sc, rb, out, check_done);
 }
 
 __global__ void k_axpy_x(double* x, const double* __restrict__ p0, const double* __restrict__ p1,
@@ -606,6 +681,7 @@ void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r,
                        Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
     SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_pre_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0, s,
                                                 g, kt, invd, r, q, u, sc, rb, mode));
+    if (mode & 1) launch_finalize(RS_RR, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
 template <typename T>
@@ -627,6 +703,7 @@ void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* 
                         const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
     SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
                                                 s, g, kt, invd, u, r, q, z, sc, rb, mode));
+    if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
 void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
@@ -637,6 +714,7 @@ void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const
     const int f = first & 1;
     SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_spmv_pcg<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
                                                 kt, z, pold, pnew, x, q, sc, rb, f, pbuf));
+    launch_finalize(RS_PQ, g.ntiles, sc, rb, nullptr, 1, s);
 }
 
 void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
@@ -658,12 +736,19 @@ void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale
 
 void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,
                 hipStream_t s) {
-    hipLaunchKernelGGL(k_dot, dim3(grid_1d(n)), dim3(256), 0, s, a, b, n, out, rb, site);
+    (void)site;
+    const int nb = grid_1d(n);
+    hipLaunchKernelGGL(k_dot, dim3(nb), dim3(256), 0, s, a, b, n, rb);
+    launch_finalize(RS_GEN, nb, nullptr, rb, out, 0, s);
 }
 
 void launch_sum_abs(const double* a, int64_t n, double* out_sum, double* out_abs, RedBuf rb,
                     hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_abs, dim3(grid_1d(n)), dim3(256), 0, s, a, n, out_sum, out_abs, rb);
+    const int nb = grid_1d(n);
+    hipLaunchKernelGGL(k_sum_abs, dim3(nb), dim3(256), 0, s, a, n, rb);
+    // the two totals land in out_sum[0], out_sum[1]; callers pass out_abs = out_sum + 1
+    (void)out_abs;
+    launch_finalize(RS_GEN2, nb, nullptr, rb, out_sum, 0, s);
 }
 
 void launch_axpy_x(double* x, const double* p0, const double* p1, Scalars* sc, int64_t n,

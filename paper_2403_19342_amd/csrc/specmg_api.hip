@@ -50,11 +50,13 @@ struct Level {
     double* Aoff = nullptr;
     double* Ad = nullptr;
     double* Dinv = nullptr;
+    double* G = nullptr;       // D_c^{-1} A(c, neighbour) for the smoother
     double* z = nullptr;
     float* basis32 = nullptr;
     float* Aoff32 = nullptr;
     float* Ad32 = nullptr;
     float* Dinv32 = nullptr;
+    float* G32 = nullptr;
     double *r = nullptr, *u = nullptr, *e = nullptr;
     float *r32 = nullptr, *u32 = nullptr, *e32 = nullptr;
 };
@@ -174,12 +176,13 @@ void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
     const T* Ad = pick<T>(lv.Ad, lv.Ad32);
     const T* Aoff = pick<T>(lv.Aoff, lv.Aoff32);
     const T* Dinv = pick<T>(lv.Dinv, lv.Dinv32);
+    const T* G = pick<T>(lv.G, lv.G32);
     const T* V = pick<T>(up.basis, up.basis32);
-    launch_coarse_smooth<T>(lv.g, Dinv, Aoff, r, u, c->sc, check, s);
+    launch_coarse_smooth<T>(lv.g, Dinv, G, r, u, c->sc, check, s);
     launch_coarse_resid_restrict<T>(lv.g, Ad, Aoff, r, u, V, up.nkeep, up.L, pick<T>(up.r, up.r32), c->sc, check, s);
     coarse_cycle<T>(c, li + 1, check, s);
     launch_coarse_prolong<T>(lv.g, u, V, up.nkeep, up.L, pick<T>(up.e, up.e32), c->sc, check, s);
-    launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, r, u, e, c->sc, check, s);
+    launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
 }
 
 // z = P^{-1} r (fine level + recursion).  pre_mode / post_mode are the mode
@@ -337,7 +340,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     for (int li = 0; li < levels - 2; ++li) {
         Level& lv = c->lev[li];
         lv.Dinv = c->alloc<double>((size_t)lv.g.m * L * L);
-        launch_blockic_setup(lv.g, lv.Ad, lv.Aoff, lv.nkeep, lv.Dinv, c->dflag + 2, s);
+        lv.G = c->alloc<double>((size_t)lv.g.m * 6 * L * L);
+        launch_blockic_setup(lv.g, lv.Ad, lv.Aoff, lv.nkeep, lv.Dinv, lv.G, c->dflag + 2, s);
     }
     // ---- host copies of the kept counts, unconverged eigensolves
     int unconv = 0;
@@ -418,6 +422,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
             if (lv.Dinv) {
                 lv.Dinv32 = c->alloc<float>(lv.g.m * LL);
                 launch_convert<double, float>(lv.Dinv, lv.Dinv32, (int64_t)(lv.g.m * LL), s);
+                lv.G32 = c->alloc<float>(lv.g.m * 6 * LL);
+                launch_convert<double, float>(lv.G, lv.G32, (int64_t)(lv.g.m * 6 * LL), s);
             }
         }
     }
@@ -450,8 +456,6 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->sc = c->alloc<Scalars>(1);
     HIPCHK(hipHostMalloc((void**)&c->sc_host, sizeof(Scalars), hipHostMallocDefault));
     c->rb.partial = c->alloc<double>((size_t)2 * kMaxRedBlocks);
-    c->rb.counter = c->alloc<unsigned>(16);
-    HIPCHK(hipMemsetAsync(c->rb.counter, 0, 16 * sizeof(unsigned), s));
     launch_pcg_init(c->sc, 0.0, 0, s);
     HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
