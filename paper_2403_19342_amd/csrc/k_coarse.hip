@@ -186,15 +186,18 @@ __device__ void ic_half_sweep(const CoarseGeom& g, int E, int upper, const T* __
 
 constexpr int kSweepThreads = 512;
 
-// forward half of the level-l smoother on parent E:
-//   t = r (mode 0) or t = r - A_l u (mode 1);  y = (D + L)^{-1} t, written to yout
+// Level-l smoother on parent E (both substitutions in one kernel):
+//   t = r (mode 0) or t = r - A_l u (mode 1)
+//   y = forward substitution of t, z = backward substitution of y
+//   out = z (mode 0) or out = u + z (mode 1)
+// The couplings of each direction are staged in LDS in turn when they fit.
 template <typename T>
-__global__ __launch_bounds__(kSweepThreads) void k_coarse_fwd(CoarseGeom g, int mode, const T* __restrict__ Ad,
-                                                              const T* __restrict__ Aoff,
-                                                              const T* __restrict__ Dinv, const T* __restrict__ G,
-                                                              const T* __restrict__ r, const T* __restrict__ u,
-                                                              T* __restrict__ yout, const Scalars* sc, int check_done,
-                                                              int staged) {
+__global__ __launch_bounds__(kSweepThreads) void k_coarse_sweep(CoarseGeom g, int mode, const T* __restrict__ Ad,
+                                                                const T* __restrict__ Aoff,
+                                                                const T* __restrict__ Dinv,
+                                                                const T* __restrict__ G, const T* __restrict__ r,
+                                                                const T* u, T* out, const Scalars* sc,
+                                                                int check_done, int staged) {
     if (check_done && sc->done) return;
     extern __shared__ double dyn_coarse[];
     __shared__ int pos[kMaxChildren], off[12];
@@ -226,32 +229,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_coarse_fwd(CoarseGeom g, int 
     }
     __syncthreads();
     ic_half_sweep<T>(g, E, 0, G, sG, sY, sW, pos, off);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        yout[(size_t)child_of(g, E, p) * L + a] = sY[t];
+    if (staged) {
+        stage_couplings<T>(g, E, G, 1, sG);
+        __syncthreads();
     }
-}
-
-// backward half on parent E: z = y - (D)^{-1} L^T z by hyperplanes;
-// mode 0: out = z;  mode 1: out = u + z.  y and out may alias.
-template <typename T>
-__global__ __launch_bounds__(kSweepThreads) void k_coarse_bwd(CoarseGeom g, int mode, const T* __restrict__ G,
-                                                              const T* y, const T* __restrict__ u, T* out,
-                                                              const Scalars* sc, int check_done, int staged) {
-    if (check_done && sc->done) return;
-    extern __shared__ double dyn_coarse[];
-    __shared__ int pos[kMaxChildren], off[12];
-    const int E = blockIdx.x;
-    const int L = g.L, nc = g.agg * g.agg * g.agg, LL = L * L;
-    T* sG = staged ? (T*)dyn_coarse : nullptr;
-    T* sY = (T*)dyn_coarse + (staged ? nc * 3 * LL : 0);
-    build_planes(g.agg, pos, off);
-    if (staged) stage_couplings<T>(g, E, G, 1, sG);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        sY[t] = y[(size_t)child_of(g, E, p) * L + a];
-    }
-    __syncthreads();
     ic_half_sweep<T>(g, E, 1, G, sG, sY, nullptr, pos, off);
     for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
         const int p = t / L, a = t % L;
@@ -702,12 +683,9 @@ void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const 
                           int check_done, hipStream_t s) {
     int staged;
     const size_t lds = sweep_lds<T>(g, staged);
-    hipFuncSetAttribute((const void*)k_coarse_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute((const void*)k_coarse_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_coarse_fwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, (const T*)nullptr,
+    hipFuncSetAttribute((const void*)k_coarse_sweep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_coarse_sweep<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, (const T*)nullptr,
                        (const T*)nullptr, Dinv, G, r, (const T*)nullptr, u, sc, check_done, staged);
-    hipLaunchKernelGGL((k_coarse_bwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, G, (const T*)u,
-                       (const T*)nullptr, u, sc, check_done, staged);
 }
 
 // e = u + M_l^{-1} (r - A_l u)
@@ -716,12 +694,9 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
                                 const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
     int staged;
     const size_t lds = sweep_lds<T>(g, staged);
-    hipFuncSetAttribute((const void*)k_coarse_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipFuncSetAttribute((const void*)k_coarse_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_coarse_fwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, Ad, Aoff, Dinv, G, r, u, e,
+    hipFuncSetAttribute((const void*)k_coarse_sweep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_coarse_sweep<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, Ad, Aoff, Dinv, G, r, u, e,
                        sc, check_done, staged);
-    hipLaunchKernelGGL((k_coarse_bwd<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, G, (const T*)e, u, e, sc,
-                       check_done, staged);
 }
 
 template <typename T>

@@ -46,15 +46,35 @@ __device__ __forceinline__ T harm(T a, T b) {
     return s > T(0) ? (T(2) * a * b) / s : T(0);
 }
 
+// LDS layouts use odd row pitches so that cells of one hyperplane spread
+// over the banks: tile arrays x + PX (y + 8 z), haloed arrays
+// (x+1) + HX ((y+1) + 10 (z+1)).
 template <int EX>
 struct TileT {
     static constexpr int TX = 8 * EX;
     static constexpr int NT = 64 * EX;
-    static constexpr int HX = TX + 2;
+    static constexpr int LX = TX + 2;          // haloed row length (logical)
+    static constexpr int NH = LX * 100;        // haloed cells (logical)
+    static constexpr int HX = TX + 3;          // haloed row pitch (odd)
     static constexpr int HXY = HX * 10;
-    static constexpr int NH = HX * 100;
-    static constexpr int NC = TX * 64;
+    static constexpr int NHP = HX * 100;       // haloed array size
+    static constexpr int NC = TX * 64;         // tile cells
+    static constexpr int PX = TX + 1;          // tile row pitch (odd)
+    static constexpr int NCP = PX * 64;        // tile array size
 };
+
+template <int EX>
+__device__ __forceinline__ int tidx(int x, int y, int z) {
+    return x + TileT<EX>::PX * (y + 8 * z);
+}
+
+// a wavefront's LDS writes are visible to its later LDS reads; keeps the
+// compiler from moving LDS accesses across the point
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ void tile_origin(const FineGeom& g, int& x0, int& y0, int& z0) {
     int t = blockIdx.x;
@@ -77,12 +97,14 @@ __device__ __forceinline__ size_t gidx(const FineGeom& g, int x, int y, int z) {
 // Omega.  All loads of a thread are issued before any LDS store, so each
 // wavefront keeps its whole share of the tile in flight.
 template <int EX>
-__device__ __forceinline__ bool halo_cell(const FineGeom& g, int h, int x0, int y0, int z0, size_t& gi) {
+__device__ __forceinline__ bool halo_cell(const FineGeom& g, int h, int x0, int y0, int z0, size_t& gi,
+                                          int& ph) {
     using TT = TileT<EX>;
-    const int hx = h % TT::HX;
-    const int r = h / TT::HX;
+    const int hx = h % TT::LX;
+    const int r = h / TT::LX;
     const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, z = z0 + (r / 10) - 1;
     gi = gidx(g, x, y, z);
+    ph = hx + TT::HX * r;
     return h < TT::NH && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
 }
 
@@ -93,10 +115,11 @@ __device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restri
     constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
     D1 va[IT];
     D2 vb[IT];
+    int pp[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         size_t gi;
-        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi);
+        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi, pp[it]);
         va[it] = in ? (D1)a[gi] : D1(0);
         vb[it] = in ? (D2)b[gi] : D2(0);
     }
@@ -104,8 +127,8 @@ __device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restri
     for (int it = 0; it < IT; ++it) {
         const int h = threadIdx.x + it * TT::NT;
         if (h < TT::NH) {
-            da[h] = va[it];
-            db[h] = vb[it];
+            da[pp[it]] = va[it];
+            db[pp[it]] = vb[it];
         }
     }
 }
@@ -119,10 +142,11 @@ __device__ __forceinline__ void load_halo_p(const FineGeom& g, const double* __r
     using TT = TileT<EX>;
     constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
     double vp[IT], vk[IT];
+    int pp[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         size_t gi;
-        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi);
+        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi, pp[it]);
         vp[it] = in ? (first ? z[gi] : z[gi] + beta * pold[gi]) : 0.0;
         vk[it] = in ? kt[gi] : 0.0;
     }
@@ -130,8 +154,8 @@ __device__ __forceinline__ void load_halo_p(const FineGeom& g, const double* __r
     for (int it = 0; it < IT; ++it) {
         const int h = threadIdx.x + it * TT::NT;
         if (h < TT::NH) {
-            dst[h] = vp[it];
-            dk[h] = vk[it];
+            dst[pp[it]] = vp[it];
+            dk[pp[it]] = vk[it];
         }
     }
 }
@@ -159,53 +183,70 @@ __device__ __forceinline__ int hidx(int x, int y, int z) {
 // Y (tile layout, no halo): in t, out (D+L^T)^{-1} D (D+L)^{-1} t.
 // ID: inverse pivots (tile layout).  K: kappa~ in tile layout (HALO = 0) or
 // haloed layout (HALO = 1).  a_ij = -T_ij off the diagonal.
-template <int EX, int HALO, typename T>
-__device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* K) {
-    constexpr int TX = TileT<EX>::TX;
-    constexpr int KX = HALO ? TileT<EX>::HX : TX;
-    constexpr int KXY = HALO ? TileT<EX>::HXY : TX * 8;
+// Forward and backward IC(0) substitution on the element of each
+// wavefront.  Y (tile layout): in t, out (D+L^T)^{-1} D (D+L)^{-1} t.
+// ID: inverse pivots; Tx, Ty, Tz: transmissibility of the +x, +y, +z face of
+// each cell (a_ij = -T off the diagonal).  Branch-free: neighbour indices are
+// clamped and the products masked, so each hyperplane step is one round of
+// LDS loads followed by fused multiply-adds.
+template <int EX, typename T>
+__device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* Tx, const T* Ty, const T* Tz) {
+    constexpr int PX = TileT<EX>::PX;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     // this lane's cell on every hyperplane (-1: idle), fetched once
-    int myc[kPlanes];
+    // (cells packed two per register; 0xFFFF marks an idle lane)
+    unsigned myc[(kPlanes + 1) / 2];
 #pragma unroll
-    for (int s = 0; s < kPlanes; ++s) {
-        const int o = kPT.off[s];
-        const int cnt = kPT.off[s + 1] - o;
-        myc[s] = lane < cnt ? (int)kPT.cell[o + lane] : -1;
-    }
+    for (int s = 0; s < kPlanes; s += 2) {
+        unsigned v = 0;
 #pragma unroll
-    for (int s = 0; s < kPlanes; ++s) {
-        const int c = myc[s];
-        if (c >= 0) {
-            const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
-            const int ti = 8 * w + i + TX * (j + 8 * k);
-            const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
-            const T kc = K[ki];
-            T acc = Y[ti];
-            if (i > 0) acc += harm(kc, K[ki - 1]) * Y[ti - 1];
-            if (j > 0) acc += harm(kc, K[ki - KX]) * Y[ti - TX];
-            if (k > 0) acc += harm(kc, K[ki - KXY]) * Y[ti - 8 * TX];
-            Y[ti] = acc * ID[ti];
+        for (int h = 0; h < 2; ++h) {
+            const int o = kPT.off[s + h];
+            const int cnt = kPT.off[s + h + 1] - o;
+            const unsigned cell = lane < cnt ? (unsigned)kPT.cell[o + lane] : 0xFFFFu;
+            v |= cell << (16 * h);
         }
-        __syncthreads();
+        myc[s / 2] = v;
+    }
+    // each wavefront sweeps its own element: only wavefront-level ordering
+    // of the LDS accesses is needed between hyperplanes
+#pragma unroll
+    for (int s = 0; s < kPlanes; ++s) {
+        const unsigned cw = (myc[s / 2] >> (16 * (s & 1))) & 0xFFFFu;
+        const int c = cw == 0xFFFFu ? -1 : (int)cw;
+        const int cc = c < 0 ? 0 : c;
+        const int i = cc & 7, j = (cc >> 3) & 7, k = cc >> 6;
+        const int ti = tidx<EX>(8 * w + i, j, k);
+        const int xi = i > 0 ? ti - 1 : ti, yi = j > 0 ? ti - PX : ti, zi = k > 0 ? ti - 8 * PX : ti;
+        const T tx = Tx[xi], ty = Ty[yi], tz = Tz[zi];
+        const T yx = Y[xi], yy = Y[yi], yz = Y[zi];
+        const T y0 = Y[ti], d = ID[ti];
+        T acc = y0;
+        acc += (i > 0 ? tx : T(0)) * yx;
+        acc += (j > 0 ? ty : T(0)) * yy;
+        acc += (k > 0 ? tz : T(0)) * yz;
+        if (c >= 0) Y[ti] = acc * d;
+        wave_lds_sync();
     }
 #pragma unroll
     for (int s = kPlanes - 1; s >= 0; --s) {
-        const int c = myc[s];
-        if (c >= 0) {
-            const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
-            const int ti = 8 * w + i + TX * (j + 8 * k);
-            const int ki = HALO ? hidx<EX>(8 * w + i, j, k) : ti;
-            const T kc = K[ki];
-            T acc = T(0);
-            if (i < 7) acc += harm(kc, K[ki + 1]) * Y[ti + 1];
-            if (j < 7) acc += harm(kc, K[ki + KX]) * Y[ti + TX];
-            if (k < 7) acc += harm(kc, K[ki + KXY]) * Y[ti + 8 * TX];
-            Y[ti] = Y[ti] + ID[ti] * acc;
-        }
-        __syncthreads();
+        const unsigned cw = (myc[s / 2] >> (16 * (s & 1))) & 0xFFFFu;
+        const int c = cw == 0xFFFFu ? -1 : (int)cw;
+        const int cc = c < 0 ? 0 : c;
+        const int i = cc & 7, j = (cc >> 3) & 7, k = cc >> 6;
+        const int ti = tidx<EX>(8 * w + i, j, k);
+        const int xi = i < 7 ? ti + 1 : ti, yi = j < 7 ? ti + PX : ti, zi = k < 7 ? ti + 8 * PX : ti;
+        const T tx = Tx[ti], ty = Ty[ti], tz = Tz[ti];
+        const T yx = Y[xi], yy = Y[yi], yz = Y[zi];
+        const T y0 = Y[ti], d = ID[ti];
+        T acc = (i < 7 ? tx : T(0)) * yx;
+        acc += (j < 7 ? ty : T(0)) * yy;
+        acc += (k < 7 ? tz : T(0)) * yz;
+        if (c >= 0) Y[ti] = y0 + d * acc;
+        wave_lds_sync();
     }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -219,9 +260,14 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
                                                         Scalars* sc, RedBuf rb, int mode) {
     using TT = TileT<EX>;
     if ((mode & 2) && sc->done) return;
-    __shared__ T sK[TT::NC];
-    __shared__ T sY[TT::NC];
-    __shared__ T sD[TT::NC];
+    // region 1: kappa~ tile, then the three face-transmissibility tiles
+    __shared__ T smem[5 * TT::NCP];
+    T* sK = smem;
+    T* sTx = smem;
+    T* sTy = smem + TT::NCP;
+    T* sTz = smem + 2 * TT::NCP;
+    T* sY = smem + 3 * TT::NCP;
+    T* sD = smem + 4 * TT::NCP;
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
@@ -243,26 +289,50 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int c = threadIdx.x + it * TT::NT;
+        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
         double rv = vr[it];
         if (mode & 1) {
-            const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
             rv -= alpha * vq[it];
             r[gidx(g, x0 + x, y0 + y, z0 + z)] = rv;
             rr += rv * rv;
         }
-        sY[c] = (T)rv;
-        sK[c] = vk[it];
-        sD[c] = vd[it];
+        const int pc = tidx<EX>(x, y, z);
+        sY[pc] = (T)rv;
+        sK[pc] = vk[it];
+        sD[pc] = vd[it];
     }
     if (mode & 1) {
         double v[1] = {block_sum(rr, sred)};
         write_partials<1>(v, rb);
     }
     __syncthreads();
-    ic_sweep<EX, 0, T>(sY, sD, sK);
+    // face transmissibilities inside the tile (faces on the tile boundary are
+    // never used by the block solves)
+    T tx[IT], ty[IT], tz[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int c = threadIdx.x + it * TT::NT;
+        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
+        const int pc = tidx<EX>(x, y, z);
+        const T kc = sK[pc];
+        tx[it] = x + 1 < TT::TX ? harm(kc, sK[pc + 1]) : T(0);
+        ty[it] = y + 1 < 8 ? harm(kc, sK[pc + TT::PX]) : T(0);
+        tz[it] = z + 1 < 8 ? harm(kc, sK[pc + 8 * TT::PX]) : T(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int c = threadIdx.x + it * TT::NT;
+        const int pc = tidx<EX>(c % TT::TX, (c / TT::TX) & 7, c / (TT::TX * 8));
+        sTx[pc] = tx[it];
+        sTy[pc] = ty[it];
+        sTz[pc] = tz[it];
+    }
+    __syncthreads();
+    ic_sweep<EX, T>(sY, sD, sTx, sTy, sTz);
     for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
         const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
-        u[gidx(g, x0 + x, y0 + y, z0 + z)] = sY[c];
+        u[gidx(g, x0 + x, y0 + y, z0 + z)] = sY[tidx<EX>(x, y, z)];
     }
 }
 
@@ -277,9 +347,9 @@ __global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T*
                                                             int check_done) {
     using TT = TileT<EX>;
     if (check_done && sc->done) return;
-    __shared__ T sU[TT::NH];
-    __shared__ T sK[TT::NH];
-    __shared__ T sS[TT::NC];
+    __shared__ T sU[TT::NHP];
+    __shared__ T sK[TT::NHP];
+    __shared__ T sS[TT::NCP];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
@@ -289,7 +359,7 @@ __global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T*
         for (int z = 0; z < 8; ++z) {
             const int h = hidx<EX>(tx, ty, z);
             const T s = (T)r[gidx(g, x0 + tx, y0 + ty, z0 + z)] - apply_stencil<EX, T>(sU, sK, h);
-            sS[tx + TT::TX * (ty + 8 * z)] = s;
+            sS[tidx<EX>(tx, ty, z)] = s;
         }
     }
     __syncthreads();
@@ -299,7 +369,7 @@ __global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T*
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const int c = lane + 64 * i;
-        sv[i] = sS[8 * w + (c & 7) + TT::TX * (c >> 3)];
+        sv[i] = sS[tidx<EX>(8 * w + (c & 7), (c >> 3) & 7, c >> 6)];
     }
     const int nk = nkeep[e];
     const T* ph = phi + (size_t)e * L * kSub3;
@@ -357,31 +427,60 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
                                                          int mode) {
     using TT = TileT<EX>;
     if ((mode & 2) && sc->done) return;
-    __shared__ T sU[TT::NH];
-    __shared__ T sK[TT::NH];
-    __shared__ T sY[TT::NC];
-    __shared__ T sD[TT::NC];
+    // region 1 holds the haloed u and kappa~ tiles, later the three face
+    // transmissibility tiles
+    constexpr int R1 = (2 * TT::NHP > 3 * TT::NCP) ? 2 * TT::NHP : 3 * TT::NCP;
+    __shared__ T smem[R1 + 2 * TT::NCP];
+    T* sU = smem;
+    T* sK = smem + TT::NHP;
+    T* sTx = smem;
+    T* sTy = smem + TT::NCP;
+    T* sTz = smem + 2 * TT::NCP;
+    T* sY = smem + R1;
+    T* sD = smem + R1 + TT::NCP;
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
-    __syncthreads();
     const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+    double rv[8];
+    T dv[8];
+#pragma unroll
     for (int zz = 0; zz < 8; ++zz) {
-        const int h = hidx<EX>(tx, ty, zz);
         const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const int ti = tx + TT::TX * (ty + 8 * zz);
-        sY[ti] = (T)r[gi] - apply_stencil<EX, T>(sU, sK, h);
-        sD[ti] = invd[gi];
+        rv[zz] = r[gi];
+        dv[zz] = invd[gi];
     }
     __syncthreads();
-    ic_sweep<EX, 1, T>(sY, sD, sK);
-    double rz = 0.0, zq = 0.0;
-    const int flex = (mode & 1) ? sc->flexible : 0;
+    T uo[8], fx[8], fy[8], fz[8];
+#pragma unroll
     for (int zz = 0; zz < 8; ++zz) {
         const int h = hidx<EX>(tx, ty, zz);
+        const int ti = tidx<EX>(tx, ty, zz);
+        uo[zz] = sU[h];
+        sY[ti] = (T)rv[zz] - apply_stencil<EX, T>(sU, sK, h);
+        sD[ti] = dv[zz];
+        const T kc = sK[h];
+        fx[zz] = harm(kc, sK[h + 1]);
+        fy[zz] = harm(kc, sK[h + TT::HX]);
+        fz[zz] = harm(kc, sK[h + TT::HXY]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int zz = 0; zz < 8; ++zz) {
+        const int ti = tidx<EX>(tx, ty, zz);
+        sTx[ti] = fx[zz];
+        sTy[ti] = fy[zz];
+        sTz[ti] = fz[zz];
+    }
+    __syncthreads();
+    ic_sweep<EX, T>(sY, sD, sTx, sTy, sTz);
+    double rz = 0.0, zq = 0.0;
+    const int flex = (mode & 1) ? sc->flexible : 0;
+#pragma unroll
+    for (int zz = 0; zz < 8; ++zz) {
         const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const double zv = (double)sU[h] + (double)sY[tx + TT::TX * (ty + 8 * zz)];
+        const double zv = (double)uo[zz] + (double)sY[tidx<EX>(tx, ty, zz)];
         z[gi] = zv;
         if (mode & 1) {
             rz += r[gi] * zv;
@@ -404,8 +503,8 @@ __global__ __launch_bounds__(64 * EX) void k_spmv_pcg(FineGeom g, const double* 
                                                       int first, int pbuf) {
     using TT = TileT<EX>;
     if (sc->done) return;
-    __shared__ double sP[TT::NH];
-    __shared__ double sK[TT::NH];
+    __shared__ double sP[TT::NHP];
+    __shared__ double sK[TT::NHP];
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
@@ -437,8 +536,8 @@ __global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* _
                                                      const double* __restrict__ b,
                                                      double* __restrict__ y, int resid) {
     using TT = TileT<EX>;
-    __shared__ double sX[TT::NH];
-    __shared__ double sK[TT::NH];
+    __shared__ double sX[TT::NHP];
+    __shared__ double sK[TT::NHP];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     load_halo2<EX>(g, xv, sX, kt, sK, x0, y0, z0);
@@ -459,13 +558,15 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
                                                       double* __restrict__ invd, float* invd32,
                                                       int* bad) {
     using TT = TileT<EX>;
-    __shared__ double sK[TT::NH];
-    __shared__ double sDg[TT::NC];
+    __shared__ double sK[TT::NHP];
+    __shared__ double sDg[TT::NCP];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
         size_t gi;
-        sK[h] = halo_cell<EX>(g, h, x0, y0, z0, gi) ? kt[gi] : 0.0;
+        int ph;
+        const bool in = halo_cell<EX>(g, h, x0, y0, z0, gi, ph);
+        sK[ph] = in ? kt[gi] : 0.0;
     }
     __syncthreads();
     constexpr int HX = TT::HX, HXY = TT::HXY, TX = TT::TX;
