@@ -6,6 +6,13 @@
 
 namespace specmg {
 
+// failure of a HIP call or of a launch precondition inside a launcher;
+// caught at the C-ABI boundary and returned as SPECMG_EDEVICE
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
 constexpr int kSub = 8;             // level-2 element edge in cells
 constexpr int kSub3 = 512;          // cells per level-2 element
 constexpr int kPlanes = 22;         // hyperplanes i+j+k = s in an 8^3 block
@@ -47,16 +54,53 @@ enum RedSite { RS_PQ = 0, RS_RR = 1, RS_RZ = 2, RS_GEN = 3, RS_GEN2 = 4 };
 // ---------------------------------------------------------------------------
 // wavefront / block reductions (wave64); fixed combination order, so results
 // are reproducible run to run.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+// Reductions over the 64 lanes of a wavefront (every lane active; every
+// lane receives the result).  Exchanges inside each 16-lane row use DPP
+// (quad permutations, half-row and row mirrors); the four row results are
+// combined through readlane.  Every lane of a row forms the same sums in
+// the same order, so the result is identical in all lanes.  The DPP and
+// readlane builtins move 32-bit integers, so values travel as their bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | (unsigned long long)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int lane) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);   // row_half_mirror
+    v += dpp_move<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
+
+// every source lane of the four patterns lies in the same row, so no
+// lane falls back to the identity
+__device__ __forceinline__ double wave_max(double v) {
+    v = fmax(v, dpp_move<0xB1>(v));
+    v = fmax(v, dpp_move<0x4E>(v));
+    v = fmax(v, dpp_move<0x141>(v));
+    v = fmax(v, dpp_move<0x140>(v));
+    return fmax(fmax(read_lane(v, 0), read_lane(v, 16)), fmax(read_lane(v, 32), read_lane(v, 48)));
 }
 
 // Sum over the block; every thread receives the result.  `sh` holds at

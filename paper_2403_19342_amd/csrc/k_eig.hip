@@ -21,6 +21,7 @@ namespace specmg {
 
 constexpr int kDeg = 20;          // Chebyshev degree per cycle
 constexpr int kMaxCycles = 300;
+constexpr int kMaxEigWaves = 12;   // workgroups of at most 768 threads
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -51,163 +52,171 @@ __device__ __forceinline__ T harm_e(T a, T b) {
 // ---------------------------------------------------------------------------
 // small dense helpers on LDS, run by one thread or one wavefront
 
-// Round-robin tournament: player at position k in round r (M players).
-__device__ __forceinline__ int rr_player(int k, int r, int M) {
-    return k == 0 ? 0 : 1 + ((k - 1 + r) % (M - 1));
+// Circle-method round robin on M players (M even): in round r player M-1
+// meets player r and every other pair (i, j) has i + j = 2r modulo M-1.
+template <int M>
+__device__ __forceinline__ int jac_partner(int i, int r) {
+    constexpr int K = M - 1;
+    if (i == K) return r;
+    if (i == r) return K;
+    int j = 2 * r - i;
+    j = j < 0 ? j + K : (j >= K ? j - K : j);
+    return j;
+}
+
+// Rotation (c, s) that annihilates H[p][q] (p < q): the rotated rows are
+// p' = c p - s q and q' = s p + c q.
+__device__ __forceinline__ void jac_rot(const double* H, int M, int p, int q, double& c, double& s) {
+    const double hpp = H[p * M + p], hqq = H[q * M + q], hpq = H[p * M + q];
+    c = 1.0;
+    s = 0.0;
+    if (hpq != 0.0) {
+        const double tt = (hqq - hpp) / (2.0 * hpq);
+        const double t = (tt >= 0.0 ? 1.0 : -1.0) / (fabs(tt) + sqrt(tt * tt + 1.0));
+        c = 1.0 / sqrt(t * t + 1.0);
+        s = t * c;
+    }
 }
 
 // Symmetric eigendecomposition H = Q diag(th) Q^T, eigenvalues ascending,
-// by parallel cyclic Jacobi in wavefront 0.  H (M*M) is destroyed; Q (M*M)
+// by parallel cyclic Jacobi in wavefront 0: each round applies M/2 disjoint
+// rotations at once; every lane derives the rotations of the rows and
+// columns of its own elements, so a round costs one read phase and one
+// write phase.  Stops when the largest off-diagonal entry is below
+// 1e-15 times the largest diagonal entry.  H (M*M) is destroyed; Q (M*M)
 // receives the eigenvectors as columns.  Must be called by all threads.
 template <int M>
 __device__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
     static_assert(M % 2 == 0 && M <= 16, "Jacobi block size");
     constexpr int MM = M * M;
     constexpr int PER = (MM + 63) / 64;
+    (void)scr;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        double* cs = scr;          // [M] cosine per index
-        double* sn = scr + M;      // [M] sine per index
-        int* lo = iscr;            // [M] smaller index of the pair
-        int* hi = iscr + M;        // [M] larger index of the pair
-        for (int t = lane; t < MM; t += 64) Q[t] = (t / M == t % M) ? 1.0 : 0.0;
+        int ei[PER], ej[PER];
+        bool ev[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = lane + 64 * u;
+            ev[u] = t < MM;
+            ei[u] = ev[u] ? t / M : 0;
+            ej[u] = ev[u] ? t % M : 0;
+            if (ev[u]) Q[t] = (ei[u] == ej[u]) ? 1.0 : 0.0;
+        }
         wave_sync();
 #pragma unroll 1
-        for (int sweep = 0; sweep < 24; ++sweep) {
+        for (int sweep = 0; sweep < 30; ++sweep) {
             double off = 0.0, dg = 0.0;
-            for (int t = lane; t < MM; t += 64) {
-                const int i = t / M, j = t % M;
-                if (i != j) off = fmax(off, fabs(H[t]));
-                else dg = fmax(dg, fabs(H[t]));
-            }
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                off = fmax(off, __shfl_xor(off, o, 64));
-                dg = fmax(dg, __shfl_xor(dg, o, 64));
+            for (int u = 0; u < PER; ++u) {
+                const double h = ev[u] ? fabs(H[ei[u] * M + ej[u]]) : 0.0;
+                if (ei[u] != ej[u]) off = fmax(off, h);
+                else dg = fmax(dg, h);
             }
-            if (off <= 1e-18 * dg || off == 0.0) break;
+            off = wave_max(off);
+            dg = wave_max(dg);
+            if (off <= 1e-15 * dg || off == 0.0) break;
 #pragma unroll 1
             for (int r = 0; r < M - 1; ++r) {
-                if (lane < M / 2) {
-                    int p = rr_player(lane, r, M), q = rr_player(M - 1 - lane, r, M);
-                    if (p > q) {
-                        const int t = p;
-                        p = q;
-                        q = t;
-                    }
-                    const double hpp = H[p * M + p], hqq = H[q * M + q], hpq = H[p * M + q];
-                    double c = 1.0, s = 0.0;
-                    if (hpq != 0.0) {
-                        const double tt = (hqq - hpp) / (2.0 * hpq);
-                        const double t = (tt >= 0.0 ? 1.0 : -1.0) / (fabs(tt) + sqrt(tt * tt + 1.0));
-                        c = 1.0 / sqrt(t * t + 1.0);
-                        s = t * c;
-                    }
-                    cs[p] = c;
-                    cs[q] = c;
-                    sn[p] = s;
-                    sn[q] = s;
-                    lo[p] = p;
-                    lo[q] = p;
-                    hi[p] = q;
-                    hi[q] = q;
-                }
-                wave_sync();
                 double nh[PER], nq[PER];
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
-                    const int t = lane + 64 * u;
-                    nh[u] = 0.0;
-                    nq[u] = 0.0;
-                    if (t < MM) {
-                        const int i = t / M, j = t % M;
-                        const int ai = lo[i], bi = hi[i], aj = lo[j], bj = hi[j];
-                        const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
-                        const double wra = (i == ai) ? ci : si, wrb = (i == ai) ? -si : ci;
-                        const double wca = (j == aj) ? cj : sj, wcb = (j == aj) ? -sj : cj;
-                        nh[u] = wra * (wca * H[ai * M + aj] + wcb * H[ai * M + bj]) +
-                                wrb * (wca * H[bi * M + aj] + wcb * H[bi * M + bj]);
-                        nq[u] = wca * Q[i * M + aj] + wcb * Q[i * M + bj];
-                    }
+                    const int i = ei[u], j = ej[u];
+                    const int pi = jac_partner<M>(i, r), pj = jac_partner<M>(j, r);
+                    const int ai = i < pi ? i : pi, bi = i < pi ? pi : i;
+                    const int aj = j < pj ? j : pj, bj = j < pj ? pj : j;
+                    double ci, si, cj, sj;
+                    jac_rot(H, M, ai, bi, ci, si);
+                    jac_rot(H, M, aj, bj, cj, sj);
+                    const double wra = (i == ai) ? ci : si, wrb = (i == ai) ? -si : ci;
+                    const double wca = (j == aj) ? cj : sj, wcb = (j == aj) ? -sj : cj;
+                    nh[u] = wra * (wca * H[ai * M + aj] + wcb * H[ai * M + bj]) +
+                            wrb * (wca * H[bi * M + aj] + wcb * H[bi * M + bj]);
+                    // the annihilated entry of a rotated pair is zero exactly
+                    if (ai == aj && bi == bj && i != j) nh[u] = 0.0;
+                    nq[u] = wca * Q[i * M + aj] + wcb * Q[i * M + bj];
                 }
                 wave_sync();
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
-                    const int t = lane + 64 * u;
-                    if (t < MM) {
-                        H[t] = nh[u];
-                        Q[t] = nq[u];
+                    if (ev[u]) {
+                        H[ei[u] * M + ej[u]] = nh[u];
+                        Q[ei[u] * M + ej[u]] = nq[u];
                     }
                 }
                 wave_sync();
             }
         }
-        // sort ascending (selection sort by lane 0), permute the columns of Q
-        if (lane == 0) {
-            int* perm = iscr;
-            for (int k = 0; k < M; ++k) perm[k] = k;
-            for (int k = 0; k < M; ++k) {
-                int best = k;
-                for (int l = k + 1; l < M; ++l)
-                    if (H[perm[l] * M + perm[l]] < H[perm[best] * M + perm[best]]) best = l;
-                const int t = perm[k];
-                perm[k] = perm[best];
-                perm[best] = t;
+        // ascending order: lane k < M finds the rank of H[k][k]
+        if (lane < M) {
+            const double hk = H[lane * M + lane];
+            int rank = 0;
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                const double hl = H[l * M + l];
+                rank += (hl < hk || (hl == hk && l < lane)) ? 1 : 0;
             }
-            for (int k = 0; k < M; ++k) th[k] = H[perm[k] * M + perm[k]];
+            iscr[rank] = lane;
+            th[rank] = hk;
         }
         wave_sync();
         double nq[PER];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int t = lane + 64 * u;
-            if (t < MM) nq[u] = Q[(t / M) * M + iscr[t % M]];
-        }
+        for (int u = 0; u < PER; ++u) nq[u] = ev[u] ? Q[ei[u] * M + iscr[ej[u]]] : 0.0;
         wave_sync();
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int t = lane + 64 * u;
-            if (t < MM) Q[t] = nq[u];
-        }
+        for (int u = 0; u < PER; ++u)
+            if (ev[u]) Q[ei[u] * M + ej[u]] = nq[u];
     }
     __syncthreads();
 }
 
-// Cholesky of the SPD M x M matrix G (upper factor R, G = R^T R) and the
-// inverse of R, by thread 0.  Returns false (in every thread) when G is not
-// numerically positive definite.
+// Cholesky G = R^T R of the SPD M x M matrix G (R upper triangular, stored
+// in Rm; dinv[j] = 1 / R[j][j]) by wavefront 0, one column per step with a
+// lane-parallel trailing update.  G is left intact.  Returns false (in every
+// thread) when G is not numerically positive definite.
 template <int M>
-__device__ bool chol_inv_upper(const double* G, double* Rinv, double* scr, int* flag) {
-    if (threadIdx.x == 0) {
-        double* R = scr;   // M*M
+__device__ bool chol_wave(const double* G, double* Rm, double* dinv, int* flag) {
+    constexpr int MM = M * M;
+    constexpr int PER = (MM + 63) / 64;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int ei[PER], ej[PER];
+        bool ev[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = lane + 64 * u;
+            ev[u] = t < MM;
+            ei[u] = ev[u] ? t / M : 0;
+            ej[u] = ev[u] ? t % M : 0;
+            if (ev[u]) Rm[t] = ei[u] <= ej[u] ? G[t] : 0.0;
+        }
+        wave_sync();
         int ok = 1;
-        for (int i = 0; i < M * M; ++i) R[i] = 0.0;
+#pragma unroll 1
         for (int j = 0; j < M; ++j) {
-            double d = G[j * M + j];
-            for (int k = 0; k < j; ++k) d -= R[k * M + j] * R[k * M + j];
+            double d = Rm[j * M + j];
             if (!(d > 0.0)) {
                 ok = 0;
                 d = 1.0;
             }
-            const double rjj = sqrt(d);
-            R[j * M + j] = rjj;
-            for (int i = j + 1; i < M; ++i) {
-                double v = G[j * M + i];
-                for (int k = 0; k < j; ++k) v -= R[k * M + j] * R[k * M + i];
-                R[j * M + i] = v / rjj;
+            const double inv_d = 1.0 / d;
+            // trailing update of the upper triangle with the unscaled row j
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int i = ei[u], l = ej[u];
+                if (ev[u] && i > j && l >= i) Rm[i * M + l] -= Rm[j * M + i] * Rm[j * M + l] * inv_d;
             }
-        }
-        // Rinv upper triangular: R Rinv = I
-        for (int i = 0; i < M * M; ++i) Rinv[i] = 0.0;
-        for (int j = 0; j < M; ++j) {
-            Rinv[j * M + j] = 1.0 / R[j * M + j];
-            for (int i = j - 1; i >= 0; --i) {
-                double v = 0.0;
-                for (int k = i + 1; k <= j; ++k) v += R[i * M + k] * Rinv[k * M + j];
-                Rinv[i * M + j] = -v / R[i * M + i];
+            wave_sync();
+            const double rjj = sqrt(d), ir = 1.0 / rjj;
+            if (lane > j && lane < M) Rm[j * M + lane] *= ir;
+            if (lane == j) {
+                Rm[j * M + j] = rjj;
+                dinv[j] = ir;
             }
+            wave_sync();
         }
-        *flag = ok;
+        if (lane == 0) *flag = ok;
     }
     __syncthreads();
     const bool ok = *flag != 0;
@@ -239,48 +248,24 @@ __device__ int cluster_cut_dev(const double* th, int n, int target, double rtol)
 
 template <int M>
 struct EigShared {
-    double red[8 * M * M];
+    double red[kMaxEigWaves * M * M];
     double G[M * M];
     double Q[M * M];
-    double Rinv[M * M];
+    double Rm[M * M];
     double scr[M * M];
+    double dinv[M];
     double th[M];
     double nrm[M];
-    double misc[8];
+    double misc[kMaxEigWaves];
     int iscr[2 * M];
     int flag;
 };
 
-// G = Y^T Y from LDS (symmetric)
-template <int M>
-__device__ void gram_lds(const double* Y, int ld, int n, double* G, double* red) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll 1
-    for (int i = 0; i < M; ++i) {
-#pragma unroll 1
-        for (int j = i; j < M; ++j) {
-            double v = 0.0;
-            for (int row = threadIdx.x; row < n; row += blockDim.x) v += Y[i * ld + row] * Y[j * ld + row];
-            v = wave_sum(v);
-            if (lane == 0) red[w * M * M + i * M + j] = v;
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
-        const int i = t / M, j = t % M;
-        if (i <= j) {
-            double s = 0.0;
-            for (int ww = 0; ww < nw; ++ww) s += red[ww * M * M + t];
-            G[t] = s;
-            G[j * M + i] = s;
-        }
-    }
-    __syncthreads();
-}
-
-// G = sym(Y^T Z): Y in LDS, Z in registers (rows of this thread)
+// G = sym(Y^T B) over all block rows: Y in LDS, B this thread's rows in
+// registers.  With B = the thread's own rows of Y this is the Gram matrix.
+// One wave reduction per entry; the M reductions of a row of G overlap.
 template <int M, int R>
-__device__ void gram_lds_reg(const double* Y, int ld, int n, const double (&Z)[R][M], double* G,
+__device__ void gram_lds_reg(const double* Y, int ld, int n, const double (&B)[R][M], double* G,
                              double* red) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll 1
@@ -295,7 +280,7 @@ __device__ void gram_lds_reg(const double* Y, int ld, int n, const double (&Z)[R
         for (int j = 0; j < M; ++j) {
             double v = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v += yi[r] * Z[r][j];
+            for (int r = 0; r < R; ++r) v += yi[r] * B[r][j];
             v = wave_sum(v);
             if (lane == 0) red[w * M * M + i * M + j] = v;
         }
@@ -304,14 +289,14 @@ __device__ void gram_lds_reg(const double* Y, int ld, int n, const double (&Z)[R
     for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
         const int i = t / M, j = t % M;
         if (i <= j) {
-            double a = 0.0, b = 0.0;
+            double x = 0.0, y = 0.0;
             for (int ww = 0; ww < nw; ++ww) {
-                a += red[ww * M * M + i * M + j];
-                b += red[ww * M * M + j * M + i];
+                x += red[ww * M * M + i * M + j];
+                y += red[ww * M * M + j * M + i];
             }
-            const double s = 0.5 * (a + b);
-            G[i * M + j] = s;
-            G[j * M + i] = s;
+            const double v = 0.5 * (x + y);
+            G[i * M + j] = v;
+            G[j * M + i] = v;
         }
     }
     __syncthreads();
@@ -338,7 +323,9 @@ __device__ void colnorm2(const double (&A)[R][M], double* out, double* red) {
     __syncthreads();
 }
 
-// registers A <- A C (C: M*M in LDS)
+// registers A <- A C (C: M*M in LDS, read by every lane at the same address);
+// the row loop stays rolled and picks A[r][i] by selects, so no register
+// array is indexed dynamically
 template <int M, int R>
 __device__ __forceinline__ void rmul(double (&A)[R][M], const double* C) {
 #pragma unroll
@@ -357,36 +344,6 @@ __device__ __forceinline__ void rmul(double (&A)[R][M], const double* C) {
 #pragma unroll
         for (int j = 0; j < M; ++j) A[r][j] = t[j];
     }
-}
-
-// LDS block Y <- Y C (rows of this thread), C: M*M in LDS
-template <int M, int R>
-__device__ void lds_rmul(double* Y, int ld, int n, const double* C) {
-    double t[R][M];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = threadIdx.x + r * blockDim.x;
-#pragma unroll
-        for (int j = 0; j < M; ++j) t[r][j] = 0.0;
-        if (row < n) {
-#pragma unroll 1
-            for (int i = 0; i < M; ++i) {
-                const double y = Y[i * ld + row];
-#pragma unroll
-                for (int j = 0; j < M; ++j) t[r][j] += y * C[i * M + j];
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = threadIdx.x + r * blockDim.x;
-        if (row < n) {
-#pragma unroll
-            for (int j = 0; j < M; ++j) Y[j * ld + row] = t[r][j];
-        }
-    }
-    __syncthreads();
 }
 
 template <int M, int R>
@@ -411,22 +368,49 @@ __device__ __forceinline__ void load_block(const double* Y, int ld, int n, doubl
     }
 }
 
-// Orthonormalise the LDS block (Cholesky-QR, twice).
+// Inverse of the upper triangular factor (Rm, dinv from chol_wave) into
+// Ri, by wavefront 0: rows from the bottom up, lane l owning column l.
+template <int M>
+__device__ void trtri_wave(const double* Rm, const double* dinv, double* Ri) {
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+#pragma unroll 1
+        for (int i = M - 1; i >= 0; --i) {
+            if (l < M) {
+                double v = (l == i) ? 1.0 : 0.0;
+                for (int k = i + 1; k <= l; ++k) v -= Rm[i * M + k] * Ri[k * M + l];
+                Ri[i * M + l] = l >= i ? v * dinv[i] : 0.0;
+            }
+            wave_sync();
+        }
+    }
+    __syncthreads();
+}
+
+// Orthonormalise the LDS block (Cholesky-QR, twice): Y <- Y R^-1 with
+// Y^T Y = R^T R.
 template <int M, int R>
 __device__ void orthonormalise(double* Y, int ld, int n, EigShared<M>& sh) {
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
-        gram_lds<M>(Y, ld, n, sh.G, sh.red);
-        if (!chol_inv_upper<M>(sh.G, sh.Rinv, sh.scr, &sh.flag)) {
+        double A[R][M];
+        load_block<M, R>(Y, ld, n, A);
+        gram_lds_reg<M, R>(Y, ld, n, A, sh.G, sh.red);
+        if (!chol_wave<M>(sh.G, sh.Rm, sh.dinv, &sh.flag)) {
+            // rank-deficient block: a tiny diagonal shift keeps the factor
+            // finite; the next Chebyshev cycle restores the lost directions
             if (threadIdx.x == 0) {
                 double mx = 0.0;
                 for (int i = 0; i < M; ++i) mx = fmax(mx, sh.G[i * M + i]);
                 for (int i = 0; i < M; ++i) sh.G[i * M + i] += 1e-12 * mx + 1e-300;
             }
             __syncthreads();
-            chol_inv_upper<M>(sh.G, sh.Rinv, sh.scr, &sh.flag);
+            chol_wave<M>(sh.G, sh.Rm, sh.dinv, &sh.flag);
         }
-        lds_rmul<M, R>(Y, ld, n, sh.Rinv);
+        trtri_wave<M>(sh.Rm, sh.dinv, sh.scr);
+        rmul<M, R>(A, sh.scr);
+        store_block<M, R>(Y, ld, n, A);
+        __syncthreads();
     }
 }
 
@@ -451,52 +435,51 @@ struct Op2 {
     }
 };
 
-// Levels >= 3: block 7-point H_E on the agg^3 children of E; row
-// r = p * Lp + a (child position p, slot a).
-template <int R>
+// Levels >= 3: block 7-point H_E on the agg^3 children of E, LP slots per
+// child; row = p * LP + a (child position p, slot a), one row per thread.
+// The row's own diagonal block stays in registers; the coupling rows of the
+// six directions are re-read (from L2) on every apply, the LP loads of a
+// direction issued together; a missing neighbour reads its own child with
+// weight zero.
+template <int LP>
 struct OpUp {
-    const double* Hd;     // [m_lo][Lp][Lp] child diagonal blocks (interior to E)
-    const double* Aoff;   // [m_lo][3][Lp][Lp]
-    int Lp, agg;
-    int row_child[R];     // child element of each row (-1: padded row)
-    int row_slot[R];
-    int row_pos[R];
-    int nbc[R][6];        // neighbour child inside E per direction (-1: none)
+    const double* Aoff;   // [m_lo][3][LP][LP]
+    double hd[LP];        // H_d[c][a][0..LP-1]
+    int c, a, p;          // child element, slot, child position in E
+    int q[3];             // child coordinates inside E
+    int cstep[3];         // element-index steps of the lower grid
+    int agg;
+    bool valid;           // kept slot of an existing child row
     template <int M>
-    __device__ __forceinline__ void apply(const double* Y, int ld, double (&out)[R][M]) const {
+    __device__ __forceinline__ void apply(const double* Y, int ld, double (&out)[1][M]) const {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int j = 0; j < M; ++j) out[0][j] = 0.0;
+        if (!valid) return;
 #pragma unroll
-            for (int j = 0; j < M; ++j) out[r][j] = 0.0;
-            const int c = row_child[r];
-            if (c < 0) continue;
-            const int a = row_slot[r], p = row_pos[r];
-            const double* hd = Hd + ((size_t)c * Lp + a) * Lp;
+        for (int b = 0; b < LP; ++b) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * LP + b];
+        }
 #pragma unroll 1
-            for (int b = 0; b < Lp; ++b) {
-                const double h = hd[b];
-                if (h != 0.0) {
+        for (int d = 0; d < 6; ++d) {
+            const int ax = d >> 1;
+            const int qa = ax == 0 ? q[0] : (ax == 1 ? q[1] : q[2]);
+            const int cs = ax == 0 ? cstep[0] : (ax == 1 ? cstep[1] : cstep[2]);
+            const int ps = ax == 0 ? 1 : (ax == 1 ? agg : agg * agg);
+            const bool in = (d & 1) ? (qa < agg - 1) : (qa > 0);
+            const int cn = in ? ((d & 1) ? c + cs : c - cs) : c;
+            const int pn = in ? ((d & 1) ? p + ps : p - ps) : p;
+            const double msk = in ? 1.0 : 0.0;
+            // + direction: A(c, cn)[a][b] = Aoff[c][ax][a][b]; - direction: Aoff[cn][ax][b][a]
+            const size_t base = (d & 1) ? (((size_t)c * 3 + ax) * LP + a) * LP : (((size_t)cn * 3 + ax) * LP) * LP + a;
+            const int st = (d & 1) ? 1 : LP;
+            double h[LP];
 #pragma unroll
-                    for (int j = 0; j < M; ++j) out[r][j] += h * Y[j * ld + p * Lp + b];
-                }
-            }
+            for (int b = 0; b < LP; ++b) h[b] = Aoff[base + (size_t)b * st] * msk;
 #pragma unroll
-            for (int d = 0; d < 6; ++d) {
-                const int cn = nbc[r][d];
-                if (cn < 0) continue;
-                const int ax = d >> 1;
-                const int step = (ax == 0) ? 1 : (ax == 1 ? agg : agg * agg);
-                const int pn = (d & 1) ? p + step : p - step;
-#pragma unroll 1
-                for (int b = 0; b < Lp; ++b) {
-                    // + direction: A(c, cn) = Aoff[c][ax]; - direction: Aoff[cn][ax]^T
-                    const double h = (d & 1) ? Aoff[(((size_t)c * 3 + ax) * Lp + a) * Lp + b]
-                                             : Aoff[(((size_t)cn * 3 + ax) * Lp + b) * Lp + a];
-                    if (h != 0.0) {
+            for (int b = 0; b < LP; ++b) {
 #pragma unroll
-                        for (int j = 0; j < M; ++j) out[r][j] += h * Y[j * ld + pn * Lp + b];
-                    }
-                }
+                for (int j = 0; j < M; ++j) out[0][j] += h[b] * Y[j * ld + pn * LP + b];
             }
         }
     }
@@ -543,17 +526,24 @@ __device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, 
     }
 }
 
-// Rayleigh-Ritz on the orthonormal LDS block Y: X = Y Q, AX = A X,
-// sh.th ascending.
+// Rayleigh-Ritz on the orthonormal LDS block Y: X = Y Q (also left in
+// LDS), AX = A X, sh.th ascending.  A Y is dead while the small
+// eigenproblem runs; A X is formed afresh from X.
 template <int M, int R, class OP>
-__device__ void rayleigh_ritz(const OP& op, const double* Y, int ld, int n, double (&X)[R][M],
+__device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
                               double (&AX)[R][M], EigShared<M>& sh) {
-    op.template apply<M>(Y, ld, AX);
-    gram_lds_reg<M, R>(Y, ld, n, AX, sh.G, sh.red);
+    {
+        double AY[R][M];
+        op.template apply<M>(Y, ld, AY);
+        gram_lds_reg<M, R>(Y, ld, n, AY, sh.G, sh.red);
+    }
     jacobi_eig<M>(sh.G, sh.Q, sh.th, sh.scr, sh.iscr);
     load_block<M, R>(Y, ld, n, X);
     rmul<M, R>(X, sh.Q);
-    rmul<M, R>(AX, sh.Q);
+    __syncthreads();
+    store_block<M, R>(Y, ld, n, X);
+    __syncthreads();
+    op.template apply<M>(Y, ld, AX);
 }
 
 // Full CheFSI loop.  X holds the start block on entry and the Ritz vectors
@@ -593,8 +583,7 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
 
 __device__ __forceinline__ double block_max(double v, double* sh) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    v = wave_max(v);
     __syncthreads();
     if (lane == 0) sh[w] = v;
     __syncthreads();
@@ -727,9 +716,10 @@ __global__ void k_build_hd(CoarseGeom lo, const double* __restrict__ Aint, const
     }
 }
 
-// level >= 3 kernel: one 512-thread workgroup per parent element E
-template <int M, int R>
-__global__ __launch_bounds__(512) void k_eig_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Hd,
+// level >= 3 kernel: one workgroup per parent element E, one thread per row
+// of H_E (blockDim = agg^3 * LP rounded up to whole wavefronts, <= 768)
+template <int M, int LP>
+__global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Hd,
                                                 const double* __restrict__ Aoff,
                                                 const int* __restrict__ nkeep_lo,
                                                 const double* __restrict__ zlo, int target, double tol,
@@ -740,105 +730,89 @@ __global__ __launch_bounds__(512) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     extern __shared__ double dyn[];
     __shared__ EigShared<M> sh;
     const int E = blockIdx.x;
-    const int agg = lo.agg, Lp = lo.L, Lu = up.L;
-    const int n = agg * agg * agg * Lp;
+    const int agg = lo.agg, Lu = up.L;
+    const int n = agg * agg * agg * LP;
     const int ld = n | 1;
     const int Ex = E % up.mx, Ey = (E / up.mx) % up.my, Ez = E / (up.mx * up.my);
-    OpUp<R> op;
-    op.Hd = Hd;
+    const int row = threadIdx.x;
+    OpUp<LP> op;
     op.Aoff = Aoff;
-    op.Lp = Lp;
+    const int rr = row < n ? row : n - 1;
+    const int p = rr / LP, a = rr % LP;
+    const int qx = p % agg, qy = (p / agg) % agg, qz = p / (agg * agg);
+    const int c = (Ex * agg + qx) + lo.mx * ((Ey * agg + qy) + lo.my * (Ez * agg + qz));
+    op.c = c;
+    op.a = a;
+    op.p = p;
+    op.q[0] = qx;
+    op.q[1] = qy;
+    op.q[2] = qz;
+    op.cstep[0] = 1;
+    op.cstep[1] = lo.mx;
+    op.cstep[2] = lo.mx * lo.my;
     op.agg = agg;
-    double rb = 0.0;
-    double X[R][M], AX[R][M];
-    double zr[R];
-    const double pa = 3.14159265358979323846 / agg;
+    op.valid = row < n && a < nkeep_lo[c];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = threadIdx.x + r * blockDim.x;
-        op.row_child[r] = -1;
-        op.row_slot[r] = 0;
-        op.row_pos[r] = 0;
-        zr[r] = 0.0;
+    for (int b = 0; b < LP; ++b) op.hd[b] = Hd[((size_t)c * LP + a) * LP + b];
+    // Gershgorin bound: absolute row sum of H_E
+    double rs = 0.0;
+    if (op.valid) {
 #pragma unroll
-        for (int d = 0; d < 6; ++d) op.nbc[r][d] = -1;
-#pragma unroll
-        for (int j = 0; j < M; ++j) X[r][j] = 0.0;
-        if (row >= n) continue;
-        const int p = row / Lp, a = row % Lp;
-        const int qx = p % agg, qy = (p / agg) % agg, qz = p / (agg * agg);
-        const int c = (Ex * agg + qx) + lo.mx * ((Ey * agg + qy) + lo.my * (Ez * agg + qz));
-        if (a >= nkeep_lo[c]) continue;
-        op.row_child[r] = c;
-        op.row_slot[r] = a;
-        op.row_pos[r] = p;
-#pragma unroll
+        for (int b = 0; b < LP; ++b) rs += fabs(op.hd[b]);
         for (int d = 0; d < 6; ++d) {
             const int ax = d >> 1;
-            const int q = ax == 0 ? qx : (ax == 1 ? qy : qz);
-            const int stride = ax == 0 ? 1 : (ax == 1 ? lo.mx : lo.mx * lo.my);
-            const bool in = (d & 1) ? (q < agg - 1) : (q > 0);
-            if (in) op.nbc[r][d] = (d & 1) ? c + stride : c - stride;
-        }
-        double s = 0.0;
-        for (int b = 0; b < Lp; ++b) s += fabs(Hd[((size_t)c * Lp + a) * Lp + b]);
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            const int cn = op.nbc[r][d];
-            if (cn < 0) continue;
-            const int ax = d >> 1;
-            for (int b = 0; b < Lp; ++b)
-                s += fabs((d & 1) ? Aoff[(((size_t)c * 3 + ax) * Lp + a) * Lp + b]
-                                  : Aoff[(((size_t)cn * 3 + ax) * Lp + b) * Lp + a]);
-        }
-        rb = fmax(rb, s);
-        zr[r] = zlo[(size_t)c * Lp + a];
-        // start block: the constant function, smooth weights of the
-        // children's constant modes, and noise on every kept slot
-        const double az = fabs(zr[r]) + 1e-300;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
-            if (j == 0) v = zr[r];
-            else if (a == 0)
-                v += zr[r] * cos(pa * kModes[j & 15][0] * (qx + 0.5)) * cos(pa * kModes[j & 15][1] * (qy + 0.5)) *
-                     cos(pa * kModes[j & 15][2] * (qz + 0.5));
-            X[r][j] = v;
+            const int qa = op.q[ax];
+            const bool in = (d & 1) ? (qa < agg - 1) : (qa > 0);
+            if (!in) continue;
+            const int cn = (d & 1) ? c + op.cstep[ax] : c - op.cstep[ax];
+            for (int b = 0; b < LP; ++b)
+                rs += fabs((d & 1) ? Aoff[(((size_t)c * 3 + ax) * LP + a) * LP + b]
+                                   : Aoff[(((size_t)cn * 3 + ax) * LP + b) * LP + a]);
         }
     }
-    const double bnd = block_max(rb, sh.misc);
+    const double bnd = block_max(rs, sh.misc);
+    // start block: the constant function, smooth weights of the children's
+    // constant modes, and noise on every kept slot
+    const double zr = op.valid ? zlo[(size_t)c * LP + a] : 0.0;
+    double X[1][M], AX[1][M];
+    const double pa = 3.14159265358979323846 / agg;
+    const double az = fabs(zr) + 1e-300;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
+        if (j == 0) v = zr;
+        else if (a == 0)
+            v += zr * cos(pa * kModes[j & 15][0] * (qx + 0.5)) * cos(pa * kModes[j & 15][1] * (qy + 0.5)) *
+                 cos(pa * kModes[j & 15][2] * (qz + 0.5));
+        X[0][j] = op.valid ? v : 0.0;
+    }
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
-    const int cyc = chefsi<M, R>(op, dyn, ld, n, X, AX, bnd, need, tol, target, crtol, sh);
+    const int cyc = chefsi<M, 1>(op, dyn, ld, n, X, AX, bnd, need, tol, target, crtol, sh);
     if (threadIdx.x == 0) {
         const int nk = cluster_cut_dev(sh.th, M, target, crtol);
         sh.flag = nk;
         nkeep[E] = nk;
         status[E] = cyc;
-        for (int a = 0; a < Lu; ++a) lam[(size_t)E * Lu + a] = sh.th[a];
+        for (int b = 0; b < Lu; ++b) lam[(size_t)E * Lu + b] = sh.th[b];
     }
     __syncthreads();
     const int nk = sh.flag;
     __syncthreads();
-    store_block<M, R>(dyn, ld, n, X);
+    store_block<M, 1>(dyn, ld, n, X);
     __syncthreads();
-    gram_lds_reg<M, R>(dyn, ld, n, AX, sh.G, sh.red);
+    gram_lds_reg<M, 1>(dyn, ld, n, AX, sh.G, sh.red);
     for (int t = threadIdx.x; t < Lu * Lu; t += blockDim.x) {
-        const int a = t / Lu, b = t % Lu;
-        Aint[(size_t)E * Lu * Lu + t] = (a < nk && b < nk) ? sh.G[a * M + b] : 0.0;
+        const int i = t / Lu, j = t % Lu;
+        Aint[(size_t)E * Lu * Lu + t] = (i < nk && j < nk) ? sh.G[i * M + j] : 0.0;
     }
-    double zv[R][M];
+    double zv[1][M];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int jj = 0; jj < M; ++jj) zv[r][jj] = X[r][jj] * zr[r];
-    column_sums<M, R>(zv, zup + (size_t)E * Lu, Lu, nk, sh.red);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int row = threadIdx.x + r * blockDim.x;
-        if (row >= n) continue;
+    for (int jj = 0; jj < M; ++jj) zv[0][jj] = X[0][jj] * zr;
+    column_sums<M, 1>(zv, zup + (size_t)E * Lu, Lu, nk, sh.red);
+    if (row < n) {
 #pragma unroll
         for (int jj = 0; jj < M; ++jj)
-            if (jj < Lu) V[((size_t)E * Lu + jj) * n + row] = (jj < nk) ? X[r][jj] : 0.0;
+            if (jj < Lu) V[((size_t)E * Lu + jj) * n + row] = (jj < nk) ? X[0][jj] : 0.0;
     }
 }
 
@@ -869,26 +843,34 @@ void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, doub
                                                crtol, phi, lam, nkeep, Aint, zc, status));
 }
 
+// block size M and slot width LP = target + 3 are compile-time per target
+#define SPECMG_T_DISPATCH(TV, ...)                                        \
+    switch (TV) {                                                         \
+        case 1: { constexpr int M = 10, LP = 4; __VA_ARGS__; } break;    \
+        case 2: { constexpr int M = 10, LP = 5; __VA_ARGS__; } break;    \
+        case 3: { constexpr int M = 10, LP = 6; __VA_ARGS__; } break;    \
+        case 4: { constexpr int M = 10, LP = 7; __VA_ARGS__; } break;    \
+        case 5: { constexpr int M = 12, LP = 8; __VA_ARGS__; } break;    \
+        case 6: { constexpr int M = 12, LP = 9; __VA_ARGS__; } break;    \
+        case 7: { constexpr int M = 14, LP = 10; __VA_ARGS__; } break;   \
+        default: { constexpr int M = 14, LP = 11; __VA_ARGS__; } break;  \
+    }
+
 void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
                    const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
                    int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,
                    double* Aint, double* zup, int* status, hipStream_t s) {
     hipLaunchKernelGGL(k_build_hd, dim3(lo.m), dim3(128), 0, s, lo, Aint_lo, Dlo, Hd_work);
     const int n = lo.agg * lo.agg * lo.agg * lo.L;
+    const int threads = (n + 63) / 64 * 64;
+    if (lo.L != target + 3 || threads > 768 || target < 1 || target > 8) throw HipError{hipErrorInvalidValue, "eig_up shape"};
     const size_t shmem = (size_t)nvec * (n | 1) * sizeof(double);
-    if (n <= 512) {
-        SPECMG_M_DISPATCH(nvec, hipFuncSetAttribute((const void*)k_eig_up<M, 1>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-                          hipLaunchKernelGGL((k_eig_up<M, 1>), dim3(up.m), dim3(512), shmem, s, lo, up, Hd_work,
-                                             Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint,
-                                             zup, status));
-    } else {
-        SPECMG_M_DISPATCH(nvec, hipFuncSetAttribute((const void*)k_eig_up<M, 2>,
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-                          hipLaunchKernelGGL((k_eig_up<M, 2>), dim3(up.m), dim3(512), shmem, s, lo, up, Hd_work,
-                                             Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint,
-                                             zup, status));
-    }
+    SPECMG_T_DISPATCH(target, if (nvec != M) throw HipError{hipErrorInvalidValue, "eig_up block size"};
+                      hipFuncSetAttribute((const void*)k_eig_up<M, LP>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+                      hipLaunchKernelGGL((k_eig_up<M, LP>), dim3(up.m), dim3(threads), shmem, s, lo, up, Hd_work,
+                                         Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint, zup,
+                                         status));
 }
 
 }  // namespace specmg

@@ -23,11 +23,6 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
-struct HipError {
-    hipError_t e;
-    const char* what;
-};
-
 #define HIPCHK(x)                                                  \
     do {                                                           \
         hipError_t _e = (x);                                       \
