@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 from synth.fields import WORKLOADS, make_field, make_source  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20
 
 
 def parse():
@@ -36,12 +37,15 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_vcycle"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="edge of the field crop timed on the CPU oracle")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run three plain device copies of COPY_BYTES each (counter calibration)")
     return ap.parse_args()
 
 
 def cpu_baseline(perm, wl, edge):
     """The FP64 oracle on a bounded sample: an edge^3 corner crop of the same
     field, same levels / eigenvector count / source kind, full set-up and PCG."""
+    from threadpoolctl import threadpool_limits
     from oracle import Grid, build_hierarchy, Preconditioner, pcg
     crop = np.ascontiguousarray(perm[:edge, :edge, :edge])
     g = Grid.unit_cube(edge)
@@ -52,15 +56,17 @@ def cpu_baseline(perm, wl, edge):
     pre = Preconditioner(hier)
     t1 = time.perf_counter()
     b = make_source(wl.source, crop.shape).reshape(-1)
-    res = pcg(hier.A, b, pre.apply, tol=1e-6)
+    ts = time.perf_counter()
+    with threadpool_limits(limits=1):
+        res = pcg(hier.A, b, pre.apply, tol=1e-6)
     t2 = time.perf_counter()
     return {
-        "value": g.n / (t2 - t1),
+        "value": g.n / (t2 - ts),
         "unit": "DoF/s",
         "cores": 1,
         "kind": "oracle",
         "sample": (f"{edge}^3 corner crop of the {wl.name} field, {wl.levels} levels, {wl.eigs} eigs, "
-                   f"agg {agg}; solve {t2 - t1:.2f} s ({res.iters} iters, single-threaded numpy/scipy); "
+                   f"agg {agg}; solve {t2 - ts:.2f} s ({res.iters} iters, numpy/scipy limited to one thread); "
                    f"set-up {t1 - t0:.2f} s on {workers} worker processes"),
     }
 
@@ -85,6 +91,14 @@ def main():
     x = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
     agg = 4
     precision = FP32_VCYCLE if prec == "fp32_vcycle" else FP64
+
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(profile):
         ctx = SpecMG(perm, levels=wl.levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision)
@@ -121,6 +135,8 @@ def main():
     fine = [k for k in tot if k in ("cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth")]
     dom = max(fine, key=lambda k: tot[k][0])
     ms, cnt, by = tot[dom]
+    from paper_2403_19342_amd.profile_summary import read_traffic
+    measured = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{wl.name}.md"))
     avg_ms = ms / max(cnt, 1)
     achieved = by / (avg_ms * 1e-3) / 1e9
     kernels = {k: {"avg_us": 1e3 * v[0] / max(v[1], 1), "launches": v[1],
@@ -149,7 +165,7 @@ def main():
         "dims": list(infos[-1].dims)[: wl.levels],
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured.get(dom),
                      "bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3},
     }
     if not args.no_cpu_baseline:

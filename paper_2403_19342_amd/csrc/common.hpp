@@ -2,9 +2,30 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace specmg {
+
+// Event pair for the next timed kernel launch: hipExtLaunchKernelGGL stamps
+// the dispatch's own start and end into them, so the interval is the
+// kernel alone (no launch gaps, no neighbouring kernels).  Set by the
+// context's profiling code on the calling thread, consumed by one launch.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local KernelEvents g_kev;
+
+#define SPECMG_TIMED_LAUNCH(K, GRID, BLOCK, SHM, S, ...)                                \
+    do {                                                                                \
+        if (::specmg::g_kev.start) {                                                    \
+            const hipEvent_t ev0_ = ::specmg::g_kev.start, ev1_ = ::specmg::g_kev.stop;  \
+            ::specmg::g_kev = ::specmg::KernelEvents{};                                 \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHM, S, ev0_, ev1_, 0, __VA_ARGS__);   \
+        } else {                                                                        \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHM, S, __VA_ARGS__);                    \
+        }                                                                               \
+    } while (0)
 
 // failure of a HIP call or of a launch precondition inside a launcher;
 // caught at the C-ABI boundary and returned as SPECMG_EDEVICE

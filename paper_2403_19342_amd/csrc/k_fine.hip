@@ -13,6 +13,9 @@
 
 namespace specmg {
 
+thread_local KernelEvents g_kev;
+
+
 // ---------------------------------------------------------------------------
 // hyperplane table of an 8^3 block: cells sorted by i+j+k
 struct PlaneTable {
@@ -780,7 +783,7 @@ static inline int grid_1d(int64_t n) {
 template <typename T>
 void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q, T* u,
                        Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_pre_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0, s,
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_pre_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0, s,
                                                 g, kt, invd, r, q, u, sc, rb, mode));
     if (mode & 1) launch_finalize(RS_RR, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
@@ -788,21 +791,21 @@ void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r,
 template <typename T>
 void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
                            const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_resid_restrict<EX, T>), dim3(g.ntiles), dim3(64 * EX),
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_resid_restrict<EX, T>), dim3(g.ntiles), dim3(64 * EX),
                                                 0, s, g, kt, u, r, phi, nkeep, L, r2, sc, check_done));
 }
 
 template <typename T>
 void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
                     Scalars* sc, int check_done, hipStream_t s) {
-    hipLaunchKernelGGL((k_prolong<T>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
+    SPECMG_TIMED_LAUNCH((k_prolong<T>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
                        sc, check_done);
 }
 
 template <typename T>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
                         const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
                                                 s, g, kt, invd, u, r, q, z, sc, rb, mode));
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
@@ -813,7 +816,7 @@ void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const
     // final x update
     const int pbuf = first & 2 ? 1 : 0;
     const int f = first & 1;
-    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_spmv_pcg<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_spmv_pcg<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
                                                 kt, z, pold, pnew, x, q, sc, rb, f, pbuf));
     launch_finalize(RS_PQ, g.ntiles, sc, rb, nullptr, 1, s);
 }

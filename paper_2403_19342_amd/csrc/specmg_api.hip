@@ -124,12 +124,14 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// event bracket around one launch (no-op unless profiling is on)
+// Kernel timing (no-op unless profiling is on).  prof_begin hands an event
+// pair to the next timed launch (the fine-level kernels stamp their own
+// dispatch); prof_begin_range / prof_end record plain events around a group
+// of launches (the coarse levels).
 enum ProfClass { PC_SPMV = 0, PC_PRE = 1, PC_RESTRICT = 2, PC_PROLONG = 3, PC_POST = 4, PC_COARSE = 5,
                  PC_COARSEST = 6 };
 
-size_t prof_begin(specmg_ctx* c, hipStream_t s) {
-    if (!c->prof_on) return (size_t)-1;
+static size_t prof_events(specmg_ctx* c) {
     if (c->ev_used + 2 > c->ev_pool.size()) {
         for (int i = 0; i < 256; ++i) {
             hipEvent_t e;
@@ -139,13 +141,33 @@ size_t prof_begin(specmg_ctx* c, hipStream_t s) {
     }
     const size_t i = c->ev_used;
     c->ev_used += 2;
-    HIPCHK(hipEventRecord(c->ev_pool[i], s));
     return i;
+}
+
+size_t prof_begin(specmg_ctx* c, hipStream_t) {
+    if (!c->prof_on) return (size_t)-1;
+    const size_t i = prof_events(c);
+    g_kev.start = c->ev_pool[i];
+    g_kev.stop = c->ev_pool[i + 1];
+    return i;
+}
+
+size_t prof_begin_range(specmg_ctx* c, hipStream_t s) {
+    if (!c->prof_on) return (size_t)-1;
+    const size_t i = prof_events(c);
+    HIPCHK(hipEventRecord(c->ev_pool[i], s));
+    return i | ((size_t)1 << 62);
 }
 
 void prof_end(specmg_ctx* c, size_t i, int cls, hipStream_t s) {
     if (i == (size_t)-1) return;
-    HIPCHK(hipEventRecord(c->ev_pool[i + 1], s));
+    if (i & ((size_t)1 << 62)) {
+        i &= ~((size_t)1 << 62);
+        HIPCHK(hipEventRecord(c->ev_pool[i + 1], s));
+    } else if (g_kev.start) {
+        g_kev = KernelEvents{};   // no timed launch consumed the pair
+        return;
+    }
     c->recs.push_back({cls, c->cur_iter, i, i + 1});
 }
 
@@ -196,7 +218,7 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     ev = prof_begin(c, s);
     launch_resid_restrict<T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
     prof_end(c, ev, PC_RESTRICT, s);
-    ev = prof_begin(c, s);
+    ev = prof_begin_range(c, s);
     coarse_cycle<T>(c, 0, check, s);
     prof_end(c, ev, c->lev.size() == 1 ? PC_COARSEST : PC_COARSE, s);
     ev = prof_begin(c, s);

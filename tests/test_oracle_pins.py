@@ -398,3 +398,32 @@ def test_pcg_iteration_counts_bounded_across_contrast():
         assert res.converged and not res.breakdown
         its.append(res.iters)
     assert max(its) < 60
+
+
+def _golden(name):
+    out = {}
+    path = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", name)
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = [int(t) for t in v.split()]
+    return out
+
+
+def test_paper_ladder_on_homogeneous_element():
+    # The oracle's level-2 spectrum of a homogeneous 8^3 element reproduces the
+    # ladder printed in Section 5.2: equal labels <=> equal eigenvalues, and the
+    # clean cuts it names are exactly where the cluster rule keeps the target.
+    gold = _golden("homogeneous_ladder.txt")
+    lad, cuts = gold["ladder"], gold["clean_cuts"]
+    g = Grid.unit_cube(8)
+    h = build_hierarchy(np.ones(g.shape), g, 2, len(lad), sub=8, workers=1)
+    lam = h.level(2).lam[0][: len(lad)]
+    for i in range(1, len(lad)):
+        same = abs(lam[i] - lam[i - 1]) <= 1e-9 * max(lam[i], 1e-12)
+        assert same == (lad[i] == lad[i - 1]), (i, lam[i - 1], lam[i])
+    clean = [i for i in range(1, len(lad)) if lad[i] != lad[i - 1]]
+    for c in cuts:
+        assert c in clean
+        assert cluster_cut(np.asarray(lam), c) == c
