@@ -17,6 +17,9 @@ with plain NumPy/SciPy building blocks and no blocking or fusion:
   vcycle     Algorithm 1 (three-grid iteration) applied recursively, with the
              pseudo-inverse at the coarsest level.
   pcg        Preconditioned conjugate gradients around the V-cycle.
+  cnn        Extension, not in the paper: the 3D CNN that predicts start
+             blocks for the level-2 eigenproblems, its subspace loss and
+             gradients (forward and backward written out in float64).
   dense      Brute-force dense references for tiny grids.
 """
 from .assembly import Grid, transmissibilities, assemble, weight_diag, neumann_local
