@@ -76,11 +76,16 @@ typedef struct {
     int32_t nu;
     int32_t precision;       /* SPECMG_FP64 or SPECMG_FP32_VCYCLE */
     int32_t warm_start;      /* SPECMG_WS_NONE or SPECMG_WS_CNN   */
-    const void* cnn_weights; /* device pointer to the CNN parameter blob (WS_CNN only) */
+    const void* cnn_weights; /* WS_CNN only: device pointer to the network's bf16
+                                parameter vector for k = eigs_per_subdomain (layout
+                                below, specmg_cnn_param_count(k) values); read
+                                during specmg_setup only */
     double eig_tol;          /* default 1e-12 when <= 0 */
     double cluster_rtol;     /* default 1e-6 when <= 0  */
-    double ws_resid_tol;     /* default 1e-3 when <= 0: warm starts with a larger
-                                Rayleigh-quotient residual fall back to the cold solve */
+    double ws_resid_tol;     /* default 1e-3 when <= 0: an element whose predicted
+                                start block, after Rayleigh-Ritz, leaves a residual
+                                above ws_resid_tol times the spectral bound of the
+                                local pencil falls back to the cold start */
 } specmg_opts;
 
 /* Outcome of a solve.  iters counts products A p (one per CG iteration). */
@@ -166,6 +171,79 @@ void specmg_destroy(specmg_ctx* ctx);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* specmg_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension of the method; not in the paper).  A
+ * 3-layer 3D CNN maps each level-2 element's log-permeability patch to k
+ * cell vectors that start the element's eigensolve (Section 3, eq. spepb).
+ *
+ *   patch: log kappa on the 8^3 cells and a one-cell halo (10^3 values, x
+ *          fastest; outside the domain the nearest boundary cell repeats),
+ *          standardised by its own mean and standard deviation (population,
+ *          1e-6 added under the root).
+ *   a1 = relu(conv(patch, W1) + b1)   1 -> 32 channels, no padding (-> 8^3)
+ *   a2 = relu(conv(a1, W2) + b2)      32 -> 32 channels, zero padding 1
+ *   X  = conv(a2, W3) + b3            32 -> k channels, zero padding 1
+ * conv(x, W)[o][p] = sum_c sum_{t in {0,1,2}^3} W[o][c][t] x[c][p + t - pad].
+ * Parameter vector, in this order: W1[32][1][27], b1[32], W2[32][32][27],
+ * b2[32], W3[k][32][27], b3[k]; taps t = 9 dz + 3 dy + dx.  Weights are used
+ * as bfloat16 values and every product is accumulated in float32.
+ *
+ * Network outputs are float32 [count][kp][512] with kp = k rounded up to an
+ * even number (channel k of an odd k is zero), cell order x fastest.
+ *
+ * Training loss of one element: with S its weight diagonal (tr K~, any
+ * positive scale; normalised to mean 1 inside) and Phi its first k
+ * eigenvectors (Phi^T S Phi = I up to the same scale), the S-distance of
+ * Phi from span(X): || Phi - X^T C* ||_S^2, C* = (X S X^T)^-1 X S Phi.  The
+ * batch loss is the mean over elements.
+ * ---------------------------------------------------------------------- */
+
+typedef struct specmg_cnn specmg_cnn;   /* network workspace, owned by the library */
+
+/* Length of the parameter vector for k outputs (k in [1, 8]), -1 otherwise. */
+int64_t specmg_cnn_param_count(int32_t k);
+
+/* Workspace for batches of at most max_batch elements (activations and
+ * gradients: about 256 KiB per element).  EINVAL for k outside [1, 8]. */
+int specmg_cnn_create(int32_t k, int32_t max_batch, specmg_cnn** out);
+void specmg_cnn_destroy(specmg_cnn* net);
+
+/* Load parameters: exactly one of theta32 (float32 master values, rounded
+ * to bf16 here) and theta16 (bf16 values) is non-NULL; device pointers of
+ * specmg_cnn_param_count(k) values, read before the call returns on the
+ * stream's timeline. */
+int specmg_cnn_load(specmg_cnn* net, const float* theta32, const uint16_t* theta16, void* stream);
+
+/* Patches of level-2 elements e0 .. e0+count-1 (x-fastest element order of
+ * the 8^3 tiling of `grid`, whose nx, ny, nz must be multiples of 8, hx > 0):
+ * patches_dev receives count*1000 floats; s_dev (optional) receives the
+ * elements' weight diagonals tr K~ = 3 kappa / hx^2, count*512 doubles (the
+ * normalisation of the set-up's level-2 basis, Section 3).  EINVAL for a
+ * bad grid or range. */
+int specmg_cnn_patches(const double* perm_dev, const specmg_grid* grid, int32_t e0, int32_t count,
+                       float* patches_dev, double* s_dev, void* stream);
+
+/* X_dev = network(patches_dev), 1 <= count <= max_batch.  Keeps the hidden
+ * activations for a following specmg_cnn_loss_backward on the same batch. */
+int specmg_cnn_forward(specmg_cnn* net, const float* patches_dev, int32_t count, float* X_dev, void* stream);
+
+/* Loss of the batch (mean over elements) and its gradient w.r.t. the
+ * parameter vector (grad_dev: specmg_cnn_param_count(k) floats,
+ * overwritten).  X_dev is the output of the preceding forward call with the
+ * same patches_dev and count (EINVAL otherwise); phi_dev holds the target
+ * vectors [count][ldphi][512] (the first k rows are used); s_dev the
+ * weights [count][512].  loss (host, optional) is written after the call
+ * synchronises the stream. */
+int specmg_cnn_loss_backward(specmg_cnn* net, const float* patches_dev, const float* X_dev, const double* phi_dev,
+                             int32_t ldphi, const double* s_dev, int32_t count, double* loss, float* grad_dev,
+                             void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on n float32 parameters with
+ * moment buffers m1, m2 (zero before step 1); theta16_dev (optional)
+ * receives the updated values rounded to bf16. */
+int specmg_cnn_adam(float* theta_dev, const float* grad_dev, float* m1_dev, float* m2_dev, int64_t n, double lr,
+                    double beta1, double beta2, double eps, int32_t step, uint16_t* theta16_dev, void* stream);
 
 #ifdef __cplusplus
 }

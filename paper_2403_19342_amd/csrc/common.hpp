@@ -246,8 +246,24 @@ void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s);
 
 // local eigensolves (k_eig.hip)
 void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
-                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc,
-                 hipStream_t s);
+                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, int e0, int count,
+                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, hipStream_t s);
+
+// learned warm start (k_cnn.hip)
+int64_t cnn_param_count(int k);
+size_t cnn_pack_words(int kp);
+void launch_cnn_patches(const FineGeom& g, const double* perm, int e0, int count, double s_scale, float* out,
+                        double* s_out, hipStream_t s);
+void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void* packs, hipStream_t s);
+void launch_cnn_forward(const void* packs, int kp, const float* patches, int count, float* a1, float* a2, float* X,
+                        hipStream_t s);
+void launch_cnn_loss(const float* X, const double* phi, int ldphi, const double* sdiag, int k, int kp, int count,
+                     double inv_m, double* loss_part, float* gX, hipStream_t s);
+void launch_cnn_backward(const void* packs, int k, int kp, const float* patches, const float* a1, const float* a2,
+                         const float* gX, int count, float* g2, float* g1, float* part, int nblk, float* grad,
+                         hipStream_t s);
+void launch_cnn_adam(float* theta, const float* grad, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
+                     float eps, float c1, float c2, uint16_t* theta16, hipStream_t s);
 void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
                    const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
                    int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,

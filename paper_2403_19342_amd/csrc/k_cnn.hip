@@ -1,0 +1,542 @@
+// Learned warm start for the level-2 eigenproblems (an extension of the
+// method, not in the paper): a 3-layer 3D CNN maps the standardised
+// log-permeability patch of each 8^3 element (with a one-cell halo) to k
+// cell vectors that start the element's eigensolve.
+//
+//   a1 = relu(conv(patch, W1) + b1)    1 -> 32 channels, 10^3 -> 8^3 (no padding)
+//   a2 = relu(conv(a1, W2) + b2)       32 -> 32 channels, zero padding 1
+//   X  = conv(a2, W3) + b3             32 -> k channels, zero padding 1
+//
+// conv is the 3x3x3 cross-correlation y[o][p] = sum_c sum_t W[o][c][t]
+// x[c][p + t] with t = (dz, dy, dx) in {0,1,2}^3.  Weights are bfloat16
+// values, every product is accumulated in float32; activations are float32.
+//
+// Parameter vector (flat, this order): W1[32][1][27], b1[32], W2[32][32][27],
+// b2[32], W3[k][32][27], b3[k].
+//
+// Training loss of one element (S: weight diagonal tr K~ of the element's
+// cells normalised to mean 1; Phi: the first k eigenvectors, scaled so that
+// Phi^T S Phi = I): loss = || Phi - X^T C* ||_S^2 with
+// C* = (X S X^T)^-1 X S Phi, the S-distance of Phi from span(X).  Its
+// gradient is dloss/dX = -2 C* (S R)^T with R = Phi - X^T C* (C* minimises
+// the inner problem).  The batch loss is the mean over elements.
+#include "common.hpp"
+
+namespace specmg {
+
+constexpr int kCnnC = 32;         // hidden channels
+constexpr int kCnnIn = 1000;      // 10^3 input patch
+constexpr int kCnnTile = 1000;    // LDS tile per input channel (10^3, zero halo for padded layers)
+
+__device__ __forceinline__ float bf_lo(uint32_t u) { return __builtin_bit_cast(float, u << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t u) { return __builtin_bit_cast(float, u & 0xFFFF0000u); }
+
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// patches: log kappa on the element and its halo (the nearest boundary cell
+// repeated outside the domain), standardised by the patch's own mean and
+// standard deviation (population, 1e-6 under the root).  Optionally also the
+// element's weight diagonal tr K~ = s_scale * kappa (s_scale = 3 / h^2), cell
+// order x fastest.
+__global__ __launch_bounds__(256) void k_cnn_patches(FineGeom g, const double* __restrict__ perm, int e0,
+                                                     double s_scale, float* __restrict__ out,
+                                                     double* __restrict__ s_out) {
+    __shared__ double sv[kCnnIn];
+    __shared__ double sred[4];
+    const int e = e0 + blockIdx.x;
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    double s1 = 0.0;
+    for (int t = threadIdx.x; t < kCnnIn; t += blockDim.x) {
+        const int x = t % 10, y = (t / 10) % 10, z = t / 100;
+        int gx = ex * 8 + x - 1, gy = ey * 8 + y - 1, gz = ez * 8 + z - 1;
+        gx = gx < 0 ? 0 : (gx >= g.nx ? g.nx - 1 : gx);
+        gy = gy < 0 ? 0 : (gy >= g.ny ? g.ny - 1 : gy);
+        gz = gz < 0 ? 0 : (gz >= g.nz ? g.nz - 1 : gz);
+        const double v = log(perm[(size_t)gx + (size_t)g.nx * ((size_t)gy + (size_t)g.ny * gz)]);
+        sv[t] = v;
+        s1 += v;
+    }
+    const double mu = block_sum(s1, sred) / kCnnIn;
+    double s2 = 0.0;
+    for (int t = threadIdx.x; t < kCnnIn; t += blockDim.x) s2 += (sv[t] - mu) * (sv[t] - mu);
+    const double inv = 1.0 / sqrt(block_sum(s2, sred) / kCnnIn + 1e-6);
+    for (int t = threadIdx.x; t < kCnnIn; t += blockDim.x)
+        out[(size_t)blockIdx.x * kCnnIn + t] = (float)((sv[t] - mu) * inv);
+    if (s_out) {
+        for (int c = threadIdx.x; c < 512; c += blockDim.x) {
+            const int x = ex * 8 + (c & 7), y = ey * 8 + ((c >> 3) & 7), z = ez * 8 + (c >> 6);
+            s_out[(size_t)blockIdx.x * 512 + c] =
+                s_scale * perm[(size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z)];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3x3 convolution over one element per workgroup, one output position per
+// thread, all COUT outputs in registers.  Input channels are staged in LDS
+// eight at a time as 10^3 tiles (PAD = 1: 8^3 input with a zero halo;
+// PAD = 0: the 10^3 patch).  Wp[(c*27 + t)*(COUT/2) + o/2] holds the bf16
+// pair of outputs (o, o+1), even o in the low half; the address is the same
+// in every lane, so the pairs come through scalar loads.
+// ACT: 0 none, 1 relu, 2 keep only where mask > 0 (relu derivative).
+template <int CIN, int COUT, int PAD, int ACT>
+__global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const uint32_t* __restrict__ Wp,
+                                              const float* __restrict__ bias, const float* __restrict__ mask,
+                                              float* __restrict__ y) {
+    static_assert(COUT % 2 == 0, "output channels come in pairs");
+    constexpr int CH = CIN < 8 ? CIN : 8;
+    constexpr int INSZ = PAD ? 512 : kCnnIn;
+    __shared__ float tile[CH * kCnnTile];
+    const int e = blockIdx.x;
+    const int p = threadIdx.x;
+    const int base = (p >> 6) * 100 + ((p >> 3) & 7) * 10 + (p & 7);
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = bias ? bias[o] : 0.0f;
+    const float* xe = x + (size_t)e * CIN * INSZ;
+#pragma unroll 1
+    for (int c0 = 0; c0 < CIN; c0 += CH) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x) {
+            const int cl = t / kCnnTile, r = t % kCnnTile;
+            float v;
+            if (PAD) {
+                const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
+                const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
+                v = in ? xe[(size_t)(c0 + cl) * 512 + X + 8 * Y + 64 * Z] : 0.0f;
+            } else {
+                v = xe[(size_t)(c0 + cl) * kCnnIn + r];
+            }
+            tile[t] = v;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int cl = 0; cl < CH; ++cl) {
+            const uint32_t* wc = Wp + (size_t)(c0 + cl) * 27 * (COUT / 2);
+            const float* tc = tile + cl * kCnnTile + base;
+#pragma unroll
+            for (int t = 0; t < 27; ++t) {
+                const float v = tc[(t / 9) * 100 + ((t / 3) % 3) * 10 + (t % 3)];
+#pragma unroll
+                for (int o = 0; o < COUT / 2; ++o) {
+                    const uint32_t u = wc[t * (COUT / 2) + o];
+                    acc[2 * o] += bf_lo(u) * v;
+                    acc[2 * o + 1] += bf_hi(u) * v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) {
+        const size_t i = ((size_t)e * COUT + o) * 512 + p;
+        float v = acc[o];
+        if (ACT == 1) v = fmaxf(v, 0.0f);
+        if (ACT == 2) v = mask[i] > 0.0f ? v : 0.0f;
+        y[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients: part[b][(o*CIN + c)*27 + t] = sum over the elements of
+// block column b of sum_p gy[e][o][p] x[e][c][p + t] (padded coordinates),
+// and part[b][COUT*CIN*27 + o] = sum_p gy[e][o][p].  Thread = (c, o) pair of
+// an eight-channel slice (blockIdx.y), 27 tap accumulators in registers;
+// the slice's input and all of gy are staged in LDS per element.
+template <int CIN, int COUT, int PAD>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x, const float* __restrict__ gy,
+                                                    int count, int per_block, float* __restrict__ part,
+                                                    int pstride) {
+    constexpr int CH = CIN < 8 ? CIN : 8;
+    constexpr int INSZ = PAD ? 512 : kCnnIn;
+    constexpr int GLD = 513;   // odd row pitch: lanes with different o hit different banks
+    __shared__ float tile[CH * kCnnTile];
+    __shared__ float sg[COUT * GLD];
+    const int c0 = blockIdx.y * CH;
+    const int q = threadIdx.x;
+    const bool act = q < CH * COUT;
+    const int cl = act ? q / COUT : 0, o = act ? q % COUT : 0;
+    float acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
+    float accb = 0.0f;
+    const int e_beg = blockIdx.x * per_block;
+    const int e_end = min(count, e_beg + per_block);
+#pragma unroll 1
+    for (int e = e_beg; e < e_end; ++e) {
+        __syncthreads();
+        const float* xe = x + (size_t)e * CIN * INSZ;
+        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x) {
+            const int c = t / kCnnTile, r = t % kCnnTile;
+            float v;
+            if (PAD) {
+                const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
+                const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
+                v = in ? xe[(size_t)(c0 + c) * 512 + X + 8 * Y + 64 * Z] : 0.0f;
+            } else {
+                v = xe[(size_t)(c0 + c) * kCnnIn + r];
+            }
+            tile[t] = v;
+        }
+        const float* ge = gy + (size_t)e * COUT * 512;
+        for (int t = threadIdx.x; t < COUT * 512; t += blockDim.x) sg[(t >> 9) * GLD + (t & 511)] = ge[t];
+        __syncthreads();
+        if (act) {
+            const float* tc = tile + cl * kCnnTile;
+            const float* gr = sg + o * GLD;
+#pragma unroll 1
+            for (int zy = 0; zy < 64; ++zy) {
+                const int z = zy >> 3, yy = zy & 7;
+                float gv[8];
+#pragma unroll
+                for (int px = 0; px < 8; ++px) {
+                    gv[px] = gr[zy * 8 + px];
+                    accb += gv[px];
+                }
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz) {
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) {
+                        float row[10];
+                        const float* rp = tc + (z + dz) * 100 + (yy + dy) * 10;
+#pragma unroll
+                        for (int i = 0; i < 10; ++i) row[i] = rp[i];
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) {
+                            float s = 0.0f;
+#pragma unroll
+                            for (int px = 0; px < 8; ++px) s += gv[px] * row[px + dx];
+                            acc[dz * 9 + dy * 3 + dx] += s;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (act) {
+        float* pb = part + (size_t)blockIdx.x * pstride;
+#pragma unroll
+        for (int t = 0; t < 27; ++t) pb[((size_t)o * CIN + c0 + cl) * 27 + t] = acc[t];
+        if (c0 + cl == 0) pb[(size_t)COUT * CIN * 27 + o] = accb;
+    }
+}
+
+// grad[i] = sum_b part[b][src(i)] for the layer's k-row weights and biases
+// (rows o >= k of a padded layer are dropped); fixed summation order.
+__global__ void k_cnn_reduce(const float* __restrict__ part, int nblk, int pstride, int nw, int bias_src, int nb,
+                             float* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw + nb) return;
+    const int src = i < nw ? i : bias_src + (i - nw);
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * pstride + src];
+    grad[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Subspace loss and its gradient w.r.t. X, one element per workgroup, one
+// cell per thread; the small k x k systems in float64.
+template <int KP>
+__global__ __launch_bounds__(512) void k_cnn_loss(const float* __restrict__ X, const double* __restrict__ phi,
+                                                  int ldphi, const double* __restrict__ s, int k, double inv_m,
+                                                  double* __restrict__ loss_part, float* __restrict__ gX) {
+    __shared__ double red[8][2 * KP * KP];
+    __shared__ double sG[KP * KP], sB[KP * KP], sC[KP * KP];
+    __shared__ double sred[8];
+    const int e = blockIdx.x, c = threadIdx.x;
+    const int lane = c & 63, w = c >> 6;
+    const double sc = s[(size_t)e * 512 + c];
+    const double mean_s = block_sum(sc, sred) / 512.0;
+    const double sb = sc / mean_s, root = sqrt(mean_s);
+    double xv[KP], pv[KP];
+#pragma unroll
+    for (int o = 0; o < KP; ++o) {
+        xv[o] = o < k ? (double)X[((size_t)e * KP + o) * 512 + c] : 0.0;
+        pv[o] = o < k ? phi[((size_t)e * ldphi + o) * 512 + c] * root : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < KP; ++o) {
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const double gv = wave_sum(sb * xv[o] * xv[q]);
+            const double bv = wave_sum(sb * xv[o] * pv[q]);
+            if (lane == 0) {
+                red[w][o * KP + q] = gv;
+                red[w][KP * KP + o * KP + q] = bv;
+            }
+        }
+    }
+    __syncthreads();
+    if (c < 2 * KP * KP) {
+        double t = 0.0;
+        for (int ww = 0; ww < 8; ++ww) t += red[ww][c];
+        if (c < KP * KP) sG[c] = t;
+        else sB[c - KP * KP] = t;
+    }
+    __syncthreads();
+    if (c == 0) {
+        // C = G^-1 B by Cholesky of G (k x k), a tiny ridge keeps it definite
+        double Lm[KP * KP];
+        double tr = 0.0;
+        for (int i = 0; i < k; ++i) tr += sG[i * KP + i];
+        const double ridge = 1e-12 * tr / k + 1e-300;
+        for (int i = 0; i < KP * KP; ++i) Lm[i] = 0.0;
+        for (int j = 0; j < k; ++j) {
+            double d = sG[j * KP + j] + ridge;
+            for (int l = 0; l < j; ++l) d -= Lm[j * KP + l] * Lm[j * KP + l];
+            d = sqrt(fmax(d, 1e-300));
+            Lm[j * KP + j] = d;
+            for (int i = j + 1; i < k; ++i) {
+                double v = sG[i * KP + j];
+                for (int l = 0; l < j; ++l) v -= Lm[i * KP + l] * Lm[j * KP + l];
+                Lm[i * KP + j] = v / d;
+            }
+        }
+        for (int col = 0; col < KP; ++col) {
+            double yv[KP];
+            for (int i = 0; i < k; ++i) {
+                double v = sB[i * KP + col];
+                for (int l = 0; l < i; ++l) v -= Lm[i * KP + l] * yv[l];
+                yv[i] = v / Lm[i * KP + i];
+            }
+            for (int i = k - 1; i >= 0; --i) {
+                double v = yv[i];
+                for (int l = i + 1; l < k; ++l) v -= Lm[l * KP + i] * sC[l * KP + col];
+                sC[i * KP + col] = v / Lm[i * KP + i];
+            }
+            for (int i = k; i < KP; ++i) sC[i * KP + col] = 0.0;
+        }
+    }
+    __syncthreads();
+    double r[KP];
+    double l2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        double v = pv[j];
+#pragma unroll
+        for (int o = 0; o < KP; ++o) v -= xv[o] * sC[o * KP + j];
+        r[j] = j < k ? v : 0.0;
+        l2 += sb * r[j] * r[j];
+    }
+#pragma unroll
+    for (int o = 0; o < KP; ++o) {
+        double gsum = 0.0;
+#pragma unroll
+        for (int j = 0; j < KP; ++j) gsum += sC[o * KP + j] * r[j];
+        gX[((size_t)e * KP + o) * 512 + c] = o < k ? (float)(-2.0 * inv_m * sb * gsum) : 0.0f;
+    }
+    const double loss = block_sum(l2, sred);
+    if (c == 0) loss_part[e] = loss * inv_m;
+}
+
+// ---------------------------------------------------------------------------
+// Parameter packing for the convolution kernels.  Values come from the bf16
+// vector or, rounded to bf16, from the float32 master vector.
+//   fwd1[t][16], fwd2[c][t][16], fwd3[c][t][KP/2]          (pairs of outputs)
+//   bwd2[o][t][16], bwd3[o][t][16] with flipped taps       (pairs of inputs)
+struct CnnPacks {
+    uint32_t* fwd1;
+    uint32_t* fwd2;
+    uint32_t* fwd3;
+    uint32_t* bwd2;
+    uint32_t* bwd3;
+    float* b1;
+    float* b2;
+    float* b3;
+};
+
+__device__ __forceinline__ float cnn_param(const float* t32, const uint16_t* t16, size_t i) {
+    return t16 ? bf2f(t16[i]) : bf2f(f2bf(t32[i]));
+}
+
+__global__ void k_cnn_pack(const float* __restrict__ t32, const uint16_t* __restrict__ t16, int k, int kp,
+                           CnnPacks pk) {
+    const size_t oW1 = 0, ob1 = 32 * 27, oW2 = ob1 + 32, ob2 = oW2 + 32 * 32 * 27, oW3 = ob2 + 32,
+                 ob3 = oW3 + (size_t)k * 32 * 27;
+    auto W1 = [&](int o, int t) { return cnn_param(t32, t16, oW1 + (size_t)o * 27 + t); };
+    auto W2 = [&](int o, int c, int t) { return cnn_param(t32, t16, oW2 + ((size_t)o * 32 + c) * 27 + t); };
+    auto W3 = [&](int o, int c, int t) {
+        return o < k ? cnn_param(t32, t16, oW3 + ((size_t)o * 32 + c) * 27 + t) : 0.0f;
+    };
+    auto pack = [](float lo, float hi) {
+        return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
+    };
+    const int n1 = 27 * 16, n2 = 32 * 27 * 16, n3 = 32 * 27 * (kp / 2), nb2 = 32 * 27 * 16, nb3 = kp * 27 * 16;
+    const int total = n1 + n2 + n3 + nb2 + nb3 + 32 + 32 + kp;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        int j = i;
+        if (j < n1) {
+            const int t = j / 16, op = j % 16;
+            pk.fwd1[j] = pack(W1(2 * op, t), W1(2 * op + 1, t));
+            continue;
+        }
+        j -= n1;
+        if (j < n2) {
+            const int c = j / (27 * 16), t = (j / 16) % 27, op = j % 16;
+            pk.fwd2[j] = pack(W2(2 * op, c, t), W2(2 * op + 1, c, t));
+            continue;
+        }
+        j -= n2;
+        if (j < n3) {
+            const int h = kp / 2;
+            const int c = j / (27 * h), t = (j / h) % 27, op = j % h;
+            pk.fwd3[j] = pack(W3(2 * op, c, t), W3(2 * op + 1, c, t));
+            continue;
+        }
+        j -= n3;
+        if (j < nb2) {
+            // transposed layer 2: inputs o (32), outputs c (pairs), taps flipped
+            const int o = j / (27 * 16), t = (j / 16) % 27, cp = j % 16;
+            pk.bwd2[j] = pack(W2(o, 2 * cp, 26 - t), W2(o, 2 * cp + 1, 26 - t));
+            continue;
+        }
+        j -= nb2;
+        if (j < nb3) {
+            const int o = j / (27 * 16), t = (j / 16) % 27, cp = j % 16;
+            pk.bwd3[j] = pack(W3(o, 2 * cp, 26 - t), W3(o, 2 * cp + 1, 26 - t));
+            continue;
+        }
+        j -= nb3;
+        if (j < 32) {
+            pk.b1[j] = cnn_param(t32, t16, ob1 + j);
+            continue;
+        }
+        j -= 32;
+        if (j < 32) {
+            pk.b2[j] = cnn_param(t32, t16, ob2 + j);
+            continue;
+        }
+        j -= 32;
+        pk.b3[j] = j < k ? cnn_param(t32, t16, ob3 + j) : 0.0f;
+    }
+}
+
+// Adam on the float32 master parameters; the bf16 copy used by inference
+// is refreshed in the same pass.
+__global__ void k_cnn_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m1,
+                           float* __restrict__ m2, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                           float c2, uint16_t* __restrict__ theta16) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float g = grad[i];
+        const float a = b1 * m1[i] + (1.0f - b1) * g;
+        const float b = b2 * m2[i] + (1.0f - b2) * g * g;
+        m1[i] = a;
+        m2[i] = b;
+        const float v = theta[i] - lr * (a * c1) / (sqrtf(b * c2) + eps);
+        theta[i] = v;
+        if (theta16) theta16[i] = f2bf(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+int64_t cnn_param_count(int k) { return 32 * 27 + 32 + 32 * 32 * 27 + 32 + (int64_t)k * 32 * 27 + k; }
+
+size_t cnn_pack_words(int kp) {
+    return 27 * 16 + 32 * 27 * 16 + 32 * 27 * (kp / 2) + 32 * 27 * 16 + (size_t)kp * 27 * 16 + 32 + 32 + kp;
+}
+
+CnnPacks cnn_pack_view(void* base, int kp) {
+    CnnPacks p;
+    uint32_t* u = (uint32_t*)base;
+    p.fwd1 = u;
+    p.fwd2 = p.fwd1 + 27 * 16;
+    p.fwd3 = p.fwd2 + 32 * 27 * 16;
+    p.bwd2 = p.fwd3 + 32 * 27 * (kp / 2);
+    p.bwd3 = p.bwd2 + 32 * 27 * 16;
+    p.b1 = (float*)(p.bwd3 + (size_t)kp * 27 * 16);
+    p.b2 = p.b1 + 32;
+    p.b3 = p.b2 + 32;
+    return p;
+}
+
+void launch_cnn_patches(const FineGeom& g, const double* perm, int e0, int count, double s_scale, float* out,
+                        double* s_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cnn_patches, dim3(count), dim3(256), 0, s, g, perm, e0, s_scale, out, s_out);
+}
+
+void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void* packs, hipStream_t s) {
+    hipLaunchKernelGGL(k_cnn_pack, dim3(64), dim3(256), 0, s, t32, t16, k, kp, cnn_pack_view(packs, kp));
+}
+
+#define SPECMG_KP_DISPATCH(KPV, ...)                             \
+    switch (KPV) {                                               \
+        case 2: { constexpr int KP = 2; __VA_ARGS__; } break;    \
+        case 4: { constexpr int KP = 4; __VA_ARGS__; } break;    \
+        case 6: { constexpr int KP = 6; __VA_ARGS__; } break;    \
+        default: { constexpr int KP = 8; __VA_ARGS__; } break;   \
+    }
+
+// X = network(patches) for `count` elements; a1, a2 receive the hidden
+// activations (kept for the backward pass)
+void launch_cnn_forward(const void* packs, int kp, const float* patches, int count, float* a1, float* a2, float* X,
+                        hipStream_t s) {
+    const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
+    hipLaunchKernelGGL((k_conv<1, 32, 0, 1>), dim3(count), dim3(512), 0, s, patches, p.fwd1, p.b1, nullptr, a1);
+    hipLaunchKernelGGL((k_conv<32, 32, 1, 1>), dim3(count), dim3(512), 0, s, a1, p.fwd2, p.b2, nullptr, a2);
+    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<32, KP, 1, 0>), dim3(count), dim3(512), 0, s, a2, p.fwd3,
+                                              p.b3, nullptr, X));
+}
+
+void launch_cnn_loss(const float* X, const double* phi, int ldphi, const double* sdiag, int k, int kp, int count,
+                     double inv_m, double* loss_part, float* gX, hipStream_t s) {
+    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_cnn_loss<KP>), dim3(count), dim3(512), 0, s, X, phi, ldphi,
+                                              sdiag, k, inv_m, loss_part, gX));
+}
+
+// parameter gradient (flat, float32) from dL/dX; g2, g1: scratch of the
+// activation size; part: scratch of nblk * (32*32*27 + 32) floats
+void launch_cnn_backward(const void* packs, int k, int kp, const float* patches, const float* a1, const float* a2,
+                         const float* gX, int count, float* g2, float* g1, float* part, int nblk, float* grad,
+                         hipStream_t s) {
+    const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
+    const int per = (count + nblk - 1) / nblk;
+    const int nb = (count + per - 1) / per;
+    const int64_t oW3 = 32 * 27 + 32 + 32 * 32 * 27 + 32, oW2 = 32 * 27 + 32;
+    // layer 3: weight gradient, then data gradient through the relu of a2
+    {
+        const int pstride = kp * 32 * 27 + kp;
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_wgrad<32, KP, 1>), dim3(nb, 4), dim3(256), 0, s, a2, gX,
+                                                  count, per, part, pstride));
+        const int nw = k * 32 * 27;
+        hipLaunchKernelGGL(k_cnn_reduce, dim3((nw + k + 255) / 256), dim3(256), 0, s, part, nb, pstride, nw,
+                           kp * 32 * 27, k, grad + oW3);
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<KP, 32, 1, 2>), dim3(count), dim3(512), 0, s, gX, p.bwd3,
+                                                  nullptr, a2, g2));
+    }
+    // layer 2
+    {
+        const int pstride = 32 * 32 * 27 + 32;
+        hipLaunchKernelGGL((k_conv_wgrad<32, 32, 1>), dim3(nb, 4), dim3(256), 0, s, a1, g2, count, per, part,
+                           pstride);
+        const int nw = 32 * 32 * 27;
+        hipLaunchKernelGGL(k_cnn_reduce, dim3((nw + 32 + 255) / 256), dim3(256), 0, s, part, nb, pstride, nw, nw,
+                           32, grad + oW2);
+        hipLaunchKernelGGL((k_conv<32, 32, 1, 2>), dim3(count), dim3(512), 0, s, g2, p.bwd2, nullptr, a1, g1);
+    }
+    // layer 1 (the input patch needs no gradient)
+    {
+        const int pstride = 32 * 27 + 32;
+        hipLaunchKernelGGL((k_conv_wgrad<1, 32, 0>), dim3(nb, 1), dim3(256), 0, s, patches, g1, count, per, part,
+                           pstride);
+        const int nw = 32 * 27;
+        hipLaunchKernelGGL(k_cnn_reduce, dim3((nw + 32 + 255) / 256), dim3(256), 0, s, part, nb, pstride, nw, nw,
+                           32, grad);
+    }
+}
+
+void launch_cnn_adam(float* theta, const float* grad, float* m1, float* m2, int64_t n, float lr, float b1, float b2,
+                     float eps, float c1, float c2, uint16_t* theta16, hipStream_t s) {
+    hipLaunchKernelGGL(k_cnn_adam, dim3(64), dim3(256), 0, s, theta, grad, m1, m2, n, lr, b1, b2, eps, c1, c2,
+                       theta16);
+}
+
+}  // namespace specmg

@@ -617,16 +617,23 @@ __device__ void column_sums(const double (&A)[R][M], double* dst, int cnt, int n
 
 // ---------------------------------------------------------------------------
 // level 2 kernel: one 512-thread workgroup per 8^3 element
+// Warm start (warm != null): the first kw columns of the start block are
+// the predicted cell vectors warm[blockIdx.x][0..kw-1][512] (row pitch kp),
+// the rest the next cosine modes.  The block is S-orthonormalised and
+// Rayleigh-Ritz'd; when the largest residual of the `target` lowest Ritz
+// pairs exceeds ws_tol times the Gershgorin bound, the element falls back to
+// the cold start (ws_fb[e] = 1).
 template <int M>
 __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restrict__ kt, int target, int L,
                                               double tol, double crtol, double* __restrict__ phi,
                                               double* __restrict__ lam, int* __restrict__ nkeep,
                                               double* __restrict__ Aint, double* __restrict__ zc,
-                                              int* __restrict__ status) {
+                                              int* __restrict__ status, int e0, const float* __restrict__ warm,
+                                              int kp, int kw, double ws_tol, int* __restrict__ ws_fb) {
     constexpr int LD = 513;
     __shared__ double sY[M * LD];
     __shared__ EigShared<M> sh;
-    const int e = blockIdx.x;
+    const int e = e0 + blockIdx.x;
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int c = threadIdx.x;
     const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
@@ -659,11 +666,38 @@ __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restri
 
     double X[1][M], AX[1][M];
     const double pi8 = 3.14159265358979323846 / 8.0;
+    const int nw = warm ? kw : 0;
 #pragma unroll
     for (int jj = 0; jj < M; ++jj) {
         const double md = cos(pi8 * kModes[jj][0] * (i + 0.5)) * cos(pi8 * kModes[jj][1] * (j + 0.5)) *
                           cos(pi8 * kModes[jj][2] * (k + 0.5));
-        X[0][jj] = sq * (md + 0.05 * hash_noise((unsigned)e, (unsigned)jj, (unsigned)c));
+        const double cold = sq * (md + 0.05 * hash_noise((unsigned)e, (unsigned)jj, (unsigned)c));
+        X[0][jj] = jj < nw ? sq * (double)warm[((size_t)blockIdx.x * kp + jj) * 512 + c] : cold;
+    }
+    if (warm) {
+        store_block<M, 1>(sY, LD, 512, X);
+        __syncthreads();
+        orthonormalise<M, 1>(sY, LD, 512, sh);
+        rayleigh_ritz<M, 1>(op, sY, LD, 512, X, AX, sh);
+        {
+            double Rs[1][M];
+#pragma unroll
+            for (int jj = 0; jj < M; ++jj) Rs[0][jj] = AX[0][jj] - sh.th[jj] * X[0][jj];
+            colnorm2<M, 1>(Rs, sh.nrm, sh.red);
+        }
+        double rho = 0.0;
+        for (int jj = 0; jj < target; ++jj) rho = fmax(rho, sqrt(sh.nrm[jj]));
+        const bool fb = !(rho <= ws_tol * bnd);
+        if (fb) {
+#pragma unroll
+            for (int jj = 0; jj < M; ++jj) {
+                const double md = cos(pi8 * kModes[jj][0] * (i + 0.5)) * cos(pi8 * kModes[jj][1] * (j + 0.5)) *
+                                  cos(pi8 * kModes[jj][2] * (k + 0.5));
+                X[0][jj] = sq * (md + 0.05 * hash_noise((unsigned)e, (unsigned)jj, (unsigned)c));
+            }
+        }
+        if (c == 0) ws_fb[e] = fb ? 1 : 0;
+        __syncthreads();
     }
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
     const int cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, sh);
@@ -836,11 +870,12 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     }
 
 void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
-                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, hipStream_t s) {
-    const int m = g.mx * g.my * g.mz;
+                 double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, int e0, int count,
+                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, hipStream_t s) {
     const int L = target + 3;
-    SPECMG_M_DISPATCH(nvec, hipLaunchKernelGGL((k_eig2<M>), dim3(m), dim3(512), 0, s, g, kt, target, L, tol,
-                                               crtol, phi, lam, nkeep, Aint, zc, status));
+    SPECMG_M_DISPATCH(nvec, hipLaunchKernelGGL((k_eig2<M>), dim3(count), dim3(512), 0, s, g, kt, target, L, tol,
+                                               crtol, phi, lam, nkeep, Aint, zc, status, e0, warm, kp, kw, ws_tol,
+                                               ws_fb));
 }
 
 // block size M and slot width LP = target + 3 are compile-time per target

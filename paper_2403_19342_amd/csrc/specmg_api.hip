@@ -23,6 +23,14 @@ int fail(int code, const std::string& msg) {
     return code;
 }
 
+}  // namespace
+
+namespace specmg {
+int fail_message(int code, const char* msg) { return fail(code, msg); }
+}  // namespace specmg
+
+namespace {
+
 #define HIPCHK(x)                                                  \
     do {                                                           \
         hipError_t _e = (x);                                       \
@@ -58,6 +66,17 @@ struct Level {
 
 }  // namespace
 
+// device buffer released at scope exit (transient set-up workspaces)
+struct DevBuf {
+    void* p = nullptr;
+    explicit DevBuf(size_t bytes) { HIPCHK(hipMalloc(&p, bytes ? bytes : 1)); }
+    ~DevBuf() { (void)hipFree(p); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+};
+
+constexpr int kCnnSetupBatch = 8192;   // level-2 elements per network batch in set-up
+
 struct specmg_ctx {
     specmg_grid grid{};
     specmg_opts opts{};
@@ -81,6 +100,7 @@ struct specmg_ctx {
     int* dflag = nullptr;       // error flags
     Scalars* sc = nullptr;
     Scalars* sc_host = nullptr; // pinned
+    int* ws_fb = nullptr;       // per level-2 element: 1 if the predicted start fell back
     RedBuf rb{};
     specmg_solve_info setup_info{};
     // per-kernel-class event timing of pcg_solve (see specmg_set_profiling)
@@ -314,8 +334,30 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         lv.Aoff = c->alloc<double>((size_t)m * 3 * L * L);
         lv.Ad = c->alloc<double>((size_t)m * L * L);
         lv.z = c->alloc<double>((size_t)m * L);
-        launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint, lv.status,
-                    lv.z, s);
+        if (c->opts.warm_start == SPECMG_WS_CNN) {
+            // predicted start blocks, batch by batch, each batch's network
+            // output consumed by the eigensolves of the same batch
+            const int k = c->target, kp = k + (k & 1);
+            const int batch = m < kCnnSetupBatch ? m : kCnnSetupBatch;
+            DevBuf packs(cnn_pack_words(kp) * sizeof(uint32_t)), patches((size_t)batch * 1000 * sizeof(float)),
+                a1((size_t)batch * 32 * 512 * sizeof(float)), a2((size_t)batch * 32 * 512 * sizeof(float)),
+                xw((size_t)batch * kp * 512 * sizeof(float));
+            c->ws_fb = c->alloc<int>(m);
+            const double wtol = c->opts.ws_resid_tol > 0 ? c->opts.ws_resid_tol : 1e-3;
+            launch_cnn_pack(nullptr, (const uint16_t*)c->opts.cnn_weights, k, kp, packs.p, s);
+            for (int e0 = 0; e0 < m; e0 += batch) {
+                const int cnt = m - e0 < batch ? m - e0 : batch;
+                launch_cnn_patches(fg, perm, e0, cnt, 0.0, (float*)patches.p, nullptr, s);
+                launch_cnn_forward(packs.p, kp, (const float*)patches.p, cnt, (float*)a1.p, (float*)a2.p,
+                                   (float*)xw.p, s);
+                launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint,
+                            lv.status, lv.z, e0, cnt, (const float*)xw.p, kp, k, wtol, c->ws_fb, s);
+            }
+            HIPCHK(hipStreamSynchronize(s));
+        } else {
+            launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint, lv.status,
+                        lv.z, 0, m, nullptr, 0, 0, 0.0, nullptr, s);
+        }
         launch_galerkin2(fg, c->kt, lv.basis, lv.nkeep, L, lv.D, lv.Aoff, s);
         launch_assemble_diag(lv.g, lv.Aint, lv.D, lv.Ad, s);
     }
@@ -484,6 +526,11 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     si.dims[0] = (int)c->n;
     for (size_t li = 0; li < c->lev.size() && li + 1 < 8; ++li) si.dims[li + 1] = c->lev[li].dim;
     si.eig_unconverged = unconv;
+    if (c->ws_fb) {
+        std::vector<int> fb(c->lev[0].g.m);
+        HIPCHK(hipMemcpy(fb.data(), c->ws_fb, fb.size() * sizeof(int), hipMemcpyDeviceToHost));
+        for (int v : fb) si.ws_fallbacks += v;
+    }
     si.setup_ms = now_ms() - t0;
     if (flags[1]) return fail(SPECMG_EFACT, "fine IC(0) pivot not positive");
     if (flags[2]) return fail(SPECMG_EFACT, "coarse block IC(0) pivot not positive definite");
@@ -508,7 +555,10 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     if (opts->nu != 1) return fail(SPECMG_EINVAL, "only nu = 1 is supported");
     if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE)
         return fail(SPECMG_EINVAL, "unknown precision");
-    if (opts->warm_start != SPECMG_WS_NONE) return fail(SPECMG_EINVAL, "warm_start not available in this build");
+    if (opts->warm_start != SPECMG_WS_NONE && opts->warm_start != SPECMG_WS_CNN)
+        return fail(SPECMG_EINVAL, "unknown warm_start");
+    if (opts->warm_start == SPECMG_WS_CNN && !opts->cnn_weights)
+        return fail(SPECMG_EINVAL, "warm_start CNN needs cnn_weights");
     long div = 8;
     for (int l = 2; l < opts->levels; ++l) div *= G.agg;
     if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.nx % div || G.ny % div || G.nz % div)

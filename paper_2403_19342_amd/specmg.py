@@ -22,7 +22,9 @@ WS_NONE, WS_CNN = 0, 1
 
 EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_apply_operator",
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
-            "specmg_destroy", "specmg_last_error"]
+            "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
+            "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
+            "specmg_cnn_loss_backward", "specmg_cnn_adam"]
 PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_levels",
                    "coarsest", "unused"]
 
@@ -90,6 +92,23 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_destroy.restype = None
     lib.specmg_last_error.argtypes = []
     lib.specmg_last_error.restype = ctypes.c_char_p
+    i64 = ctypes.c_int64
+    lib.specmg_cnn_param_count.argtypes = [i32]
+    lib.specmg_cnn_param_count.restype = i64
+    lib.specmg_cnn_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
+    lib.specmg_cnn_create.restype = ctypes.c_int
+    lib.specmg_cnn_destroy.argtypes = [vp]
+    lib.specmg_cnn_destroy.restype = None
+    lib.specmg_cnn_load.argtypes = [vp, vp, vp, vp]
+    lib.specmg_cnn_load.restype = ctypes.c_int
+    lib.specmg_cnn_patches.argtypes = [vp, ctypes.POINTER(Grid), i32, i32, vp, vp, vp]
+    lib.specmg_cnn_patches.restype = ctypes.c_int
+    lib.specmg_cnn_forward.argtypes = [vp, vp, i32, vp, vp]
+    lib.specmg_cnn_forward.restype = ctypes.c_int
+    lib.specmg_cnn_loss_backward.argtypes = [vp, vp, vp, vp, i32, vp, i32, ctypes.POINTER(dbl), vp, vp]
+    lib.specmg_cnn_loss_backward.restype = ctypes.c_int
+    lib.specmg_cnn_adam.argtypes = [vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, i32, vp, vp]
+    lib.specmg_cnn_adam.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -110,10 +129,11 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev_ptr(t):
+def _dev_ptr(t, dtype=None):
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise ValueError("expected a contiguous float64 CUDA tensor")
+    dtype = dtype or torch.float64
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -132,7 +152,7 @@ class SpecMG:
 
     def __init__(self, perm, levels: int, eigs_per_subdomain: int, h: float | None = None,
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
-                 allow_unconverged: bool = False):
+                 allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3):
         lib = load_library()
         import torch
         if perm.dim() != 3:
@@ -143,7 +163,15 @@ class SpecMG:
         if h is None:
             h = 1.0 / nx
         self.grid = Grid(nx, ny, nz, h, h, h, 8, agg)
-        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, WS_NONE, None, eig_tol, cluster_rtol, 1e-3)
+        ws, wp = WS_NONE, None
+        if cnn_weights is not None:
+            # bf16 parameter vector, stored as int16 bits in a torch tensor
+            if not (cnn_weights.is_cuda and cnn_weights.dtype == torch.int16 and cnn_weights.is_contiguous()):
+                raise ValueError("cnn_weights must be a contiguous int16 (bf16 bits) CUDA tensor")
+            if cnn_weights.numel() != lib.specmg_cnn_param_count(eigs_per_subdomain):
+                raise ValueError("cnn_weights has the wrong length for eigs_per_subdomain")
+            ws, wp = WS_CNN, ctypes.c_void_p(cnn_weights.data_ptr())
+        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol)
         ctx = ctypes.c_void_p()
         perm = perm.contiguous()
         rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
@@ -221,3 +249,69 @@ class SpecMG:
             _check(_lib.specmg_copy_level(self._ctx, level, which, arr.ctypes.data_as(ctypes.c_void_p), arr.nbytes))
             out[name] = arr
         return LevelArrays(**out)
+
+
+class CNN:
+    """Workspace of the warm-start network (k outputs, batches of at most
+    max_batch level-2 elements).  Parameters are float32 CUDA tensors (the
+    master copy) or int16 tensors holding bf16 bits."""
+
+    def __init__(self, k: int, max_batch: int):
+        lib = load_library()
+        self.k = k
+        self.kp = k + (k & 1)
+        self.max_batch = max_batch
+        self.n_params = int(lib.specmg_cnn_param_count(k))
+        h = ctypes.c_void_p()
+        _check(lib.specmg_cnn_create(k, max_batch, ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.specmg_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, theta):
+        import torch
+        if theta.dtype == torch.float32:
+            _check(_lib.specmg_cnn_load(self._h, _dev_ptr(theta, torch.float32), None, _stream()))
+        else:
+            _check(_lib.specmg_cnn_load(self._h, None, _dev_ptr(theta, torch.int16), _stream()))
+
+    @staticmethod
+    def patches(perm, e0: int, count: int, patches, s=None):
+        import torch
+        load_library()
+        nz, ny, nx = perm.shape
+        g = Grid(nx, ny, nz, 1.0 / nx, 1.0 / nx, 1.0 / nx, 8, 2)
+        _check(_lib.specmg_cnn_patches(_dev_ptr(perm), ctypes.byref(g), e0, count,
+                                       _dev_ptr(patches, torch.float32),
+                                       None if s is None else _dev_ptr(s), _stream()))
+
+    def forward(self, patches, count: int, X):
+        import torch
+        _check(_lib.specmg_cnn_forward(self._h, _dev_ptr(patches, torch.float32), count,
+                                       _dev_ptr(X, torch.float32), _stream()))
+
+    def loss_backward(self, patches, X, phi, ldphi: int, s, count: int, grad) -> float:
+        import torch
+        loss = ctypes.c_double()
+        _check(_lib.specmg_cnn_loss_backward(self._h, _dev_ptr(patches, torch.float32), _dev_ptr(X, torch.float32),
+                                             _dev_ptr(phi), ldphi, _dev_ptr(s), count, ctypes.byref(loss),
+                                             _dev_ptr(grad, torch.float32), _stream()))
+        return loss.value
+
+    @staticmethod
+    def adam(theta, grad, m1, m2, lr: float, step: int, theta16=None, beta1=0.9, beta2=0.999, eps=1e-8):
+        import torch
+        load_library()
+        _check(_lib.specmg_cnn_adam(_dev_ptr(theta, torch.float32), _dev_ptr(grad, torch.float32),
+                                    _dev_ptr(m1, torch.float32), _dev_ptr(m2, torch.float32), theta.numel(),
+                                    lr, beta1, beta2, eps, step,
+                                    None if theta16 is None else _dev_ptr(theta16, torch.int16), _stream()))
