@@ -76,16 +76,20 @@ typedef struct {
     int32_t nu;
     int32_t precision;       /* SPECMG_FP64 or SPECMG_FP32_VCYCLE */
     int32_t warm_start;      /* SPECMG_WS_NONE or SPECMG_WS_CNN   */
-    const void* cnn_weights; /* WS_CNN only: device pointer to the network's bf16
-                                parameter vector for k = eigs_per_subdomain (layout
-                                below, specmg_cnn_param_count(k) values); read
-                                during specmg_setup only */
+    const void* cnn_weights; /* WS_CNN only (eigs_per_subdomain even): device
+                                pointer to the network's bf16 parameter vector
+                                for k = eigs_per_subdomain (layout below,
+                                specmg_cnn_param_count(k) values); read during
+                                specmg_setup only */
     double eig_tol;          /* default 1e-12 when <= 0 */
     double cluster_rtol;     /* default 1e-6 when <= 0  */
-    double ws_resid_tol;     /* default 1e-3 when <= 0: an element whose predicted
-                                start block, after Rayleigh-Ritz, leaves a residual
-                                above ws_resid_tol times the spectral bound of the
-                                local pencil falls back to the cold start */
+    double ws_resid_tol;     /* WS_CNN: default 1e-3 when <= 0.  Each level-2
+                                element's eigensolve starts from the predicted
+                                block and stops at this residual (relative to
+                                the spectral bound of the local pencil, as
+                                eig_tol); an element that does not reach it
+                                within 4 Chebyshev cycles falls back to the
+                                exact solve (eig_tol) from the cold start */
 } specmg_opts;
 
 /* Outcome of a solve.  iters counts products A p (one per CG iteration). */
@@ -99,7 +103,7 @@ typedef struct {
     int32_t n_levels;
     int32_t dims[8];         /* dims[0] = n, dims[l-1] = dim W_l        */
     int32_t eig_unconverged; /* local eigensolves that hit the cycle cap */
-    int32_t ws_fallbacks;    /* warm starts rejected by the residual test */
+    int32_t ws_fallbacks;    /* WS_CNN: elements that fell back to the exact solve */
     int32_t replacements;    /* true-residual replacements in CG        */
 } specmg_solve_info;
 
@@ -181,16 +185,21 @@ const char* specmg_last_error(void);
  *          fastest; outside the domain the nearest boundary cell repeats),
  *          standardised by its own mean and standard deviation (population,
  *          1e-6 added under the root).
- *   a1 = relu(conv(patch, W1) + b1)   1 -> 32 channels, no padding (-> 8^3)
+ *   c_j:  the k lowest cosine modes of the homogeneous element (the cold
+ *         start block), cos(pi p (x+1/2)/8) cos(pi q (y+1/2)/8)
+ *         cos(pi r (z+1/2)/8) with (p,q,r) = (000), (100), (010), (001),
+ *         (110), (101), (011), (111) in this order
+ *   a1 = relu(conv([patch, c_0..c_{k-1}], W1) + b1)  1+k -> 32 channels, no
+ *        padding (-> 8^3); the mode channels are evaluated on the patch grid
  *   a2 = relu(conv(a1, W2) + b2)      32 -> 32 channels, zero padding 1
- *   X  = conv(a2, W3) + b3            32 -> k channels, zero padding 1
+ *   X  = c + conv(a2, W3) + b3        32 -> k channels, zero padding 1
  * conv(x, W)[o][p] = sum_c sum_{t in {0,1,2}^3} W[o][c][t] x[c][p + t - pad].
- * Parameter vector, in this order: W1[32][1][27], b1[32], W2[32][32][27],
- * b2[32], W3[k][32][27], b3[k]; taps t = 9 dz + 3 dy + dx.  Weights are used
- * as bfloat16 values and every product is accumulated in float32.
+ * k is 2, 4, 6 or 8.  Parameter vector, in this order: W1[32][1+k][27],
+ * b1[32], W2[32][32][27], b2[32], W3[k][32][27], b3[k]; taps
+ * t = 9 dz + 3 dy + dx.  Weights are used as bfloat16 values and every
+ * product is accumulated in float32.
  *
- * Network outputs are float32 [count][kp][512] with kp = k rounded up to an
- * even number (channel k of an odd k is zero), cell order x fastest.
+ * Network outputs are float32 [count][k][512], cell order x fastest.
  *
  * Training loss of one element: with S its weight diagonal (tr K~, any
  * positive scale; normalised to mean 1 inside) and Phi its first k
@@ -201,11 +210,11 @@ const char* specmg_last_error(void);
 
 typedef struct specmg_cnn specmg_cnn;   /* network workspace, owned by the library */
 
-/* Length of the parameter vector for k outputs (k in [1, 8]), -1 otherwise. */
+/* Length of the parameter vector for k outputs (k = 2, 4, 6, 8), -1 otherwise. */
 int64_t specmg_cnn_param_count(int32_t k);
 
 /* Workspace for batches of at most max_batch elements (activations and
- * gradients: about 256 KiB per element).  EINVAL for k outside [1, 8]. */
+ * gradients: about 256 KiB per element).  EINVAL for k not in {2, 4, 6, 8}. */
 int specmg_cnn_create(int32_t k, int32_t max_batch, specmg_cnn** out);
 void specmg_cnn_destroy(specmg_cnn* net);
 

@@ -12,10 +12,16 @@ Definitions followed here (the GPU kernels implement the same definitions):
   values, z slowest, x fastest); outside the domain the nearest boundary
   cell is repeated.  Each patch is standardised by its own mean and standard
   deviation (population, plus 1e-6 under the root).
+* Modes: the k lowest cosine modes of the homogeneous element,
+  c_j(x, y, z) = cos(pi p_j (x + 1/2) / 8) cos(pi q_j (y + 1/2) / 8)
+  cos(pi r_j (z + 1/2) / 8) with (p_j, q_j, r_j) from MODES, evaluated on
+  the patch grid (cell coordinates -1 .. 8) and on the element (0 .. 7).
+  They are the start block of the cold eigensolve; the network predicts a
+  correction to them.
 * Network: three 3x3x3 cross-correlations with biases,
-    a1 = relu(conv(patch, W1, b1))            1 -> 32 channels, 10^3 -> 8^3 (no padding)
-    a2 = relu(conv(a1, W2, b2))               32 -> 32 channels, zero padding 1
-    X  = conv(a2, W3, b3)                     32 -> k channels, zero padding 1
+    a1 = relu(conv([patch, c_0..c_{k-1}], W1, b1))   1+k -> 32 channels, 10^3 -> 8^3
+    a2 = relu(conv(a1, W2, b2))                      32 -> 32 channels, zero padding 1
+    X  = c + conv(a2, W3, b3)                        32 -> k channels, zero padding 1
   X (k x 512) holds k cell vectors of K.  Weights are W[o, i, dz, dy, dx].
 * Loss of one element, with S the weight diagonal on K normalised to mean 1
   and Phi the k target eigenvectors scaled so that Phi^T S Phi = I:
@@ -33,9 +39,21 @@ CHANNELS = 32
 PATCH = 10
 EDGE = 8
 
+# (p, q, r) of the lowest cosine modes of an 8^3 block, by increasing
+# p^2 + q^2 + r^2; ties: x before y before z
+MODES = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1)]
+
+
+def mode_grid(j: int, first: int, size: int) -> np.ndarray:
+    """Mode j on the cells first .. first+size-1 of each axis, shape (size,)*3 (z, y, x)."""
+    p, q, r = MODES[j]
+    t = (np.arange(first, first + size) + 0.5) * np.pi / EDGE
+    cx, cy, cz = np.cos(p * t), np.cos(q * t), np.cos(r * t)
+    return cz[:, None, None] * cy[None, :, None] * cx[None, None, :]
+
 
 def param_shapes(k: int):
-    return [("W1", (CHANNELS, 1, 3, 3, 3)), ("b1", (CHANNELS,)),
+    return [("W1", (CHANNELS, 1 + k, 3, 3, 3)), ("b1", (CHANNELS,)),
             ("W2", (CHANNELS, CHANNELS, 3, 3, 3)), ("b2", (CHANNELS,)),
             ("W3", (k, CHANNELS, 3, 3, 3)), ("b3", (k,))]
 
@@ -108,26 +126,34 @@ def conv_backward(x: np.ndarray, w: np.ndarray, gy: np.ndarray, pad: int):
     return gx, gw, gy.sum(axis=(1, 2, 3))
 
 
+def network_input(patch: np.ndarray, k: int) -> np.ndarray:
+    """The patch and the k mode channels on the patch grid, shape (1+k, 10, 10, 10)."""
+    return np.stack([patch] + [mode_grid(j, -1, PATCH) for j in range(k)])
+
+
 def forward(p: dict, patch: np.ndarray):
     """Network output X (k x 512) and the activations the backward pass needs."""
-    z1 = conv(patch[None], p["W1"], p["b1"], 0)
+    k = p["W3"].shape[0]
+    x0 = network_input(patch, k)
+    z1 = conv(x0, p["W1"], p["b1"], 0)
     a1 = np.maximum(z1, 0.0)
     z2 = conv(a1, p["W2"], p["b2"], 1)
     a2 = np.maximum(z2, 0.0)
     x = conv(a2, p["W3"], p["b3"], 1)
-    return x.reshape(x.shape[0], -1), (z1, a1, z2, a2)
+    base = np.stack([mode_grid(j, 0, EDGE) for j in range(k)])
+    return (x + base).reshape(k, -1), (x0, z1, a1, z2, a2)
 
 
 def backward(p: dict, patch: np.ndarray, cache, gX: np.ndarray) -> dict:
     """Parameter gradients from dL/dX (k x 512)."""
-    z1, a1, z2, a2 = cache
+    x0, z1, a1, z2, a2 = cache
     k = gX.shape[0]
     g3 = gX.reshape(k, EDGE, EDGE, EDGE)
     ga2, gW3, gb3 = conv_backward(a2, p["W3"], g3, 1)
     gz2 = ga2 * (z2 > 0)
     ga1, gW2, gb2 = conv_backward(a1, p["W2"], gz2, 1)
     gz1 = ga1 * (z1 > 0)
-    _, gW1, gb1 = conv_backward(patch[None], p["W1"], gz1, 0)
+    _, gW1, gb1 = conv_backward(x0, p["W1"], gz1, 0)
     return {"W1": gW1, "b1": gb1, "W2": gW2, "b2": gb2, "W3": gW3, "b3": gb3}
 
 

@@ -61,14 +61,14 @@ struct specmg_cnn {
 };
 
 extern "C" int64_t specmg_cnn_param_count(int32_t k) {
-    if (k < 1 || k > 8) return -1;
+    if (k < 2 || k > 8 || (k & 1)) return -1;
     return cnn_param_count(k);
 }
 
 extern "C" int specmg_cnn_create(int32_t k, int32_t max_batch, specmg_cnn** out) {
     if (!out) return fail_message(SPECMG_EINVAL, "null argument");
     *out = nullptr;
-    if (k < 1 || k > 8) return fail_message(SPECMG_EINVAL, "k must be in [1, 8]");
+    if (k < 2 || k > 8 || (k & 1)) return fail_message(SPECMG_EINVAL, "k must be 2, 4, 6 or 8");
     if (max_batch < 1 || max_batch > (1 << 20)) return fail_message(SPECMG_EINVAL, "max_batch out of range");
     return guarded([&] {
         specmg_cnn* n = new specmg_cnn();

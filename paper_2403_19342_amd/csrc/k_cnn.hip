@@ -3,16 +3,22 @@
 // log-permeability patch of each 8^3 element (with a one-cell halo) to k
 // cell vectors that start the element's eigensolve.
 //
-//   a1 = relu(conv(patch, W1) + b1)    1 -> 32 channels, 10^3 -> 8^3 (no padding)
-//   a2 = relu(conv(a1, W2) + b2)       32 -> 32 channels, zero padding 1
-//   X  = conv(a2, W3) + b3             32 -> k channels, zero padding 1
+//   a1 = relu(conv([patch, c_0..c_{k-1}], W1) + b1)   1+k -> 32 channels, 10^3 -> 8^3
+//   a2 = relu(conv(a1, W2) + b2)                      32 -> 32 channels, zero padding 1
+//   X  = c + conv(a2, W3) + b3                        32 -> k channels, zero padding 1
+//
+// c_j are the k lowest cosine modes of the homogeneous element (the start
+// block of the cold eigensolve), cos(pi p (x+1/2)/8) cos(pi q (y+1/2)/8)
+// cos(pi r (z+1/2)/8), evaluated on the patch grid (cells -1..8) as input
+// channels and on the element (cells 0..7) as the base the network corrects.
+// k is even (2, 4, 6 or 8).
 //
 // conv is the 3x3x3 cross-correlation y[o][p] = sum_c sum_t W[o][c][t]
 // x[c][p + t] with t = (dz, dy, dx) in {0,1,2}^3.  Weights are bfloat16
 // values, every product is accumulated in float32; activations are float32.
 //
-// Parameter vector (flat, this order): W1[32][1][27], b1[32], W2[32][32][27],
-// b2[32], W3[k][32][27], b3[k].
+// Parameter vector (flat, this order): W1[32][1+k][27], b1[32],
+// W2[32][32][27], b2[32], W3[k][32][27], b3[k].
 //
 // Training loss of one element (S: weight diagonal tr K~ of the element's
 // cells normalised to mean 1; Phi: the first k eigenvectors, scaled so that
@@ -39,6 +45,24 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
+
+// cosine mode j (j < 8, by increasing p^2+q^2+r^2, ties x before y before z)
+// at integer cell coordinates (x, y, z) of an 8^3 block
+__device__ __forceinline__ float cnn_mode(int j, int x, int y, int z) {
+    int p = 0, q = 0, r = 0;
+    switch (j) {
+        case 1: p = 1; break;
+        case 2: q = 1; break;
+        case 3: r = 1; break;
+        case 4: p = 1; q = 1; break;
+        case 5: p = 1; r = 1; break;
+        case 6: q = 1; r = 1; break;
+        case 7: p = 1; q = 1; r = 1; break;
+        default: break;
+    }
+    const double w = 3.14159265358979323846 / 8.0;
+    return (float)(cos(w * p * (x + 0.5)) * cos(w * q * (y + 0.5)) * cos(w * r * (z + 0.5)));
+}
 
 // ---------------------------------------------------------------------------
 // patches: log kappa on the element and its halo (the nearest boundary cell
@@ -80,20 +104,41 @@ __global__ __launch_bounds__(256) void k_cnn_patches(FineGeom g, const double* _
 }
 
 // ---------------------------------------------------------------------------
+// Staging of input channel c of element e into a 10^3 LDS tile.
+//   IN = 1: 8^3 input [e][CIN][512], zero halo (padded layers)
+//   IN = 2: the network input: channel 0 the patch [e][1000], channel
+//           c >= 1 the cosine mode c-1 on the patch grid
+template <int IN>
+__device__ __forceinline__ float stage_value(const float* xe, int c, int r) {
+    const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
+    if (IN == 1) {
+        const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
+        return in ? xe[(size_t)c * 512 + X + 8 * Y + 64 * Z] : 0.0f;
+    }
+    return c == 0 ? xe[r] : cnn_mode(c - 1, X, Y, Z);
+}
+
+template <int CIN>
+struct ConvChunk {
+    static constexpr int CH = CIN <= 9 ? CIN : 8;   // channels staged at once
+    static_assert(CIN % CH == 0, "channel chunks");
+};
+
 // 3x3x3 convolution over one element per workgroup, one output position per
 // thread, all COUT outputs in registers.  Input channels are staged in LDS
-// eight at a time as 10^3 tiles (PAD = 1: 8^3 input with a zero halo;
-// PAD = 0: the 10^3 patch).  Wp[(c*27 + t)*(COUT/2) + o/2] holds the bf16
-// pair of outputs (o, o+1), even o in the low half; the address is the same
-// in every lane, so the pairs come through scalar loads.
-// ACT: 0 none, 1 relu, 2 keep only where mask > 0 (relu derivative).
-template <int CIN, int COUT, int PAD, int ACT>
+// (at most nine at a time) as 10^3 tiles.  Wp[(c*27 + t)*(COUT/2) + o/2]
+// holds the bf16 pair of outputs (o, o+1), even o in the low half; the
+// address is the same in every lane, so the pairs come through scalar loads.
+// ACT: 0 none, 1 relu, 2 keep only where mask > 0 (relu derivative),
+//      3 add cosine mode o (the network output).
+template <int CIN, int COUT, int IN, int ACT>
 __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const uint32_t* __restrict__ Wp,
                                               const float* __restrict__ bias, const float* __restrict__ mask,
                                               float* __restrict__ y) {
     static_assert(COUT % 2 == 0, "output channels come in pairs");
-    constexpr int CH = CIN < 8 ? CIN : 8;
-    constexpr int INSZ = PAD ? 512 : kCnnIn;
+    constexpr int CH = ConvChunk<CIN>::CH;
+    constexpr int INSZ = IN == 1 ? 512 : kCnnIn;
+    constexpr int ESZ = IN == 1 ? CIN * INSZ : kCnnIn;
     __shared__ float tile[CH * kCnnTile];
     const int e = blockIdx.x;
     const int p = threadIdx.x;
@@ -101,22 +146,12 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
     float acc[COUT];
 #pragma unroll
     for (int o = 0; o < COUT; ++o) acc[o] = bias ? bias[o] : 0.0f;
-    const float* xe = x + (size_t)e * CIN * INSZ;
+    const float* xe = x + (size_t)e * ESZ;
 #pragma unroll 1
     for (int c0 = 0; c0 < CIN; c0 += CH) {
         __syncthreads();
-        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x) {
-            const int cl = t / kCnnTile, r = t % kCnnTile;
-            float v;
-            if (PAD) {
-                const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
-                const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
-                v = in ? xe[(size_t)(c0 + cl) * 512 + X + 8 * Y + 64 * Z] : 0.0f;
-            } else {
-                v = xe[(size_t)(c0 + cl) * kCnnIn + r];
-            }
-            tile[t] = v;
-        }
+        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x)
+            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile);
         __syncthreads();
 #pragma unroll 1
         for (int cl = 0; cl < CH; ++cl) {
@@ -140,6 +175,7 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
         float v = acc[o];
         if (ACT == 1) v = fmaxf(v, 0.0f);
         if (ACT == 2) v = mask[i] > 0.0f ? v : 0.0f;
+        if (ACT == 3) v += cnn_mode(o, p & 7, (p >> 3) & 7, p >> 6);
         y[i] = v;
     }
 }
@@ -148,14 +184,17 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
 // Weight gradients: part[b][(o*CIN + c)*27 + t] = sum over the elements of
 // block column b of sum_p gy[e][o][p] x[e][c][p + t] (padded coordinates),
 // and part[b][COUT*CIN*27 + o] = sum_p gy[e][o][p].  Thread = (c, o) pair of
-// an eight-channel slice (blockIdx.y), 27 tap accumulators in registers;
-// the slice's input and all of gy are staged in LDS per element.
-template <int CIN, int COUT, int PAD>
-__global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x, const float* __restrict__ gy,
+// a channel slice (blockIdx.y), 27 tap accumulators in registers; the
+// slice's input and all of gy are staged in LDS per element.  blockDim.x
+// covers the slice's (c, o) pairs (at most 320).
+template <int CIN, int COUT, int IN>
+__global__ __launch_bounds__(320) void k_conv_wgrad(const float* __restrict__ x, const float* __restrict__ gy,
                                                     int count, int per_block, float* __restrict__ part,
                                                     int pstride) {
-    constexpr int CH = CIN < 8 ? CIN : 8;
-    constexpr int INSZ = PAD ? 512 : kCnnIn;
+    constexpr int CH = ConvChunk<CIN>::CH;
+    constexpr int INSZ = IN == 1 ? 512 : kCnnIn;
+    constexpr int ESZ = IN == 1 ? CIN * INSZ : kCnnIn;
+    static_assert(CH * COUT <= 320, "one thread per (c, o) pair");
     constexpr int GLD = 513;   // odd row pitch: lanes with different o hit different banks
     __shared__ float tile[CH * kCnnTile];
     __shared__ float sg[COUT * GLD];
@@ -172,19 +211,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ x,
 #pragma unroll 1
     for (int e = e_beg; e < e_end; ++e) {
         __syncthreads();
-        const float* xe = x + (size_t)e * CIN * INSZ;
-        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x) {
-            const int c = t / kCnnTile, r = t % kCnnTile;
-            float v;
-            if (PAD) {
-                const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
-                const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
-                v = in ? xe[(size_t)(c0 + c) * 512 + X + 8 * Y + 64 * Z] : 0.0f;
-            } else {
-                v = xe[(size_t)(c0 + c) * kCnnIn + r];
-            }
-            tile[t] = v;
-        }
+        const float* xe = x + (size_t)e * ESZ;
+        for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x)
+            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile);
         const float* ge = gy + (size_t)e * COUT * 512;
         for (int t = threadIdx.x; t < COUT * 512; t += blockDim.x) sg[(t >> 9) * GLD + (t & 511)] = ge[t];
         __syncthreads();
@@ -339,7 +368,7 @@ __global__ __launch_bounds__(512) void k_cnn_loss(const float* __restrict__ X, c
 // ---------------------------------------------------------------------------
 // Parameter packing for the convolution kernels.  Values come from the bf16
 // vector or, rounded to bf16, from the float32 master vector.
-//   fwd1[t][16], fwd2[c][t][16], fwd3[c][t][KP/2]          (pairs of outputs)
+//   fwd1[c][t][16], fwd2[c][t][16], fwd3[c][t][KP/2]       (pairs of outputs)
 //   bwd2[o][t][16], bwd3[o][t][16] with flipped taps       (pairs of inputs)
 struct CnnPacks {
     uint32_t* fwd1;
@@ -358,9 +387,10 @@ __device__ __forceinline__ float cnn_param(const float* t32, const uint16_t* t16
 
 __global__ void k_cnn_pack(const float* __restrict__ t32, const uint16_t* __restrict__ t16, int k, int kp,
                            CnnPacks pk) {
-    const size_t oW1 = 0, ob1 = 32 * 27, oW2 = ob1 + 32, ob2 = oW2 + 32 * 32 * 27, oW3 = ob2 + 32,
+    const int c1 = 1 + k;   // input channels of layer 1
+    const size_t oW1 = 0, ob1 = (size_t)32 * c1 * 27, oW2 = ob1 + 32, ob2 = oW2 + 32 * 32 * 27, oW3 = ob2 + 32,
                  ob3 = oW3 + (size_t)k * 32 * 27;
-    auto W1 = [&](int o, int t) { return cnn_param(t32, t16, oW1 + (size_t)o * 27 + t); };
+    auto W1 = [&](int o, int c, int t) { return cnn_param(t32, t16, oW1 + ((size_t)o * c1 + c) * 27 + t); };
     auto W2 = [&](int o, int c, int t) { return cnn_param(t32, t16, oW2 + ((size_t)o * 32 + c) * 27 + t); };
     auto W3 = [&](int o, int c, int t) {
         return o < k ? cnn_param(t32, t16, oW3 + ((size_t)o * 32 + c) * 27 + t) : 0.0f;
@@ -368,13 +398,14 @@ __global__ void k_cnn_pack(const float* __restrict__ t32, const uint16_t* __rest
     auto pack = [](float lo, float hi) {
         return (uint32_t)f2bf(lo) | ((uint32_t)f2bf(hi) << 16);
     };
-    const int n1 = 27 * 16, n2 = 32 * 27 * 16, n3 = 32 * 27 * (kp / 2), nb2 = 32 * 27 * 16, nb3 = kp * 27 * 16;
+    const int n1 = c1 * 27 * 16, n2 = 32 * 27 * 16, n3 = 32 * 27 * (kp / 2), nb2 = 32 * 27 * 16,
+              nb3 = kp * 27 * 16;
     const int total = n1 + n2 + n3 + nb2 + nb3 + 32 + 32 + kp;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int j = i;
         if (j < n1) {
-            const int t = j / 16, op = j % 16;
-            pk.fwd1[j] = pack(W1(2 * op, t), W1(2 * op + 1, t));
+            const int c = j / (27 * 16), t = (j / 16) % 27, op = j % 16;
+            pk.fwd1[j] = pack(W1(2 * op, c, t), W1(2 * op + 1, c, t));
             continue;
         }
         j -= n1;
@@ -438,17 +469,20 @@ __global__ void k_cnn_adam(float* __restrict__ theta, const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // launchers
 
-int64_t cnn_param_count(int k) { return 32 * 27 + 32 + 32 * 32 * 27 + 32 + (int64_t)k * 32 * 27 + k; }
+int64_t cnn_param_count(int k) {
+    return (int64_t)32 * (1 + k) * 27 + 32 + 32 * 32 * 27 + 32 + (int64_t)k * 32 * 27 + k;
+}
 
 size_t cnn_pack_words(int kp) {
-    return 27 * 16 + 32 * 27 * 16 + 32 * 27 * (kp / 2) + 32 * 27 * 16 + (size_t)kp * 27 * 16 + 32 + 32 + kp;
+    return (size_t)(1 + kp) * 27 * 16 + 32 * 27 * 16 + 32 * 27 * (kp / 2) + 32 * 27 * 16 + (size_t)kp * 27 * 16 +
+           32 + 32 + kp;
 }
 
 CnnPacks cnn_pack_view(void* base, int kp) {
     CnnPacks p;
     uint32_t* u = (uint32_t*)base;
     p.fwd1 = u;
-    p.fwd2 = p.fwd1 + 27 * 16;
+    p.fwd2 = p.fwd1 + (1 + kp) * 27 * 16;
     p.fwd3 = p.fwd2 + 32 * 27 * 16;
     p.bwd2 = p.fwd3 + 32 * 27 * (kp / 2);
     p.bwd3 = p.bwd2 + 32 * 27 * 16;
@@ -467,12 +501,12 @@ void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void*
     hipLaunchKernelGGL(k_cnn_pack, dim3(64), dim3(256), 0, s, t32, t16, k, kp, cnn_pack_view(packs, kp));
 }
 
-#define SPECMG_KP_DISPATCH(KPV, ...)                             \
-    switch (KPV) {                                               \
-        case 2: { constexpr int KP = 2; __VA_ARGS__; } break;    \
-        case 4: { constexpr int KP = 4; __VA_ARGS__; } break;    \
-        case 6: { constexpr int KP = 6; __VA_ARGS__; } break;    \
-        default: { constexpr int KP = 8; __VA_ARGS__; } break;   \
+#define SPECMG_KP_DISPATCH(KPV, ...)                                          \
+    switch (KPV) {                                                            \
+        case 2: { constexpr int KP = 2, C1 = 3; __VA_ARGS__; } break;         \
+        case 4: { constexpr int KP = 4, C1 = 5; __VA_ARGS__; } break;         \
+        case 6: { constexpr int KP = 6, C1 = 7; __VA_ARGS__; } break;         \
+        default: { constexpr int KP = 8, C1 = 9; __VA_ARGS__; } break;        \
     }
 
 // X = network(patches) for `count` elements; a1, a2 receive the hidden
@@ -480,9 +514,10 @@ void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void*
 void launch_cnn_forward(const void* packs, int kp, const float* patches, int count, float* a1, float* a2, float* X,
                         hipStream_t s) {
     const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
-    hipLaunchKernelGGL((k_conv<1, 32, 0, 1>), dim3(count), dim3(512), 0, s, patches, p.fwd1, p.b1, nullptr, a1);
+    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<C1, 32, 2, 1>), dim3(count), dim3(512), 0, s, patches,
+                                              p.fwd1, p.b1, nullptr, a1));
     hipLaunchKernelGGL((k_conv<32, 32, 1, 1>), dim3(count), dim3(512), 0, s, a1, p.fwd2, p.b2, nullptr, a2);
-    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<32, KP, 1, 0>), dim3(count), dim3(512), 0, s, a2, p.fwd3,
+    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<32, KP, 1, 3>), dim3(count), dim3(512), 0, s, a2, p.fwd3,
                                               p.b3, nullptr, X));
 }
 
@@ -500,11 +535,11 @@ void launch_cnn_backward(const void* packs, int k, int kp, const float* patches,
     const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
     const int per = (count + nblk - 1) / nblk;
     const int nb = (count + per - 1) / per;
-    const int64_t oW3 = 32 * 27 + 32 + 32 * 32 * 27 + 32, oW2 = 32 * 27 + 32;
+    const int64_t oW2 = (int64_t)32 * (1 + k) * 27 + 32, oW3 = oW2 + 32 * 32 * 27 + 32;
     // layer 3: weight gradient, then data gradient through the relu of a2
     {
         const int pstride = kp * 32 * 27 + kp;
-        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_wgrad<32, KP, 1>), dim3(nb, 4), dim3(256), 0, s, a2, gX,
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_wgrad<32, KP, 1>), dim3(nb, 4), dim3(64), 0, s, a2, gX,
                                                   count, per, part, pstride));
         const int nw = k * 32 * 27;
         hipLaunchKernelGGL(k_cnn_reduce, dim3((nw + k + 255) / 256), dim3(256), 0, s, part, nb, pstride, nw,
@@ -522,12 +557,14 @@ void launch_cnn_backward(const void* packs, int k, int kp, const float* patches,
                            32, grad + oW2);
         hipLaunchKernelGGL((k_conv<32, 32, 1, 2>), dim3(count), dim3(512), 0, s, g2, p.bwd2, nullptr, a1, g1);
     }
-    // layer 1 (the input patch needs no gradient)
+    // layer 1 (the network input needs no gradient)
     {
-        const int pstride = 32 * 27 + 32;
-        hipLaunchKernelGGL((k_conv_wgrad<1, 32, 0>), dim3(nb, 1), dim3(256), 0, s, patches, g1, count, per, part,
-                           pstride);
-        const int nw = 32 * 27;
+        const int c1 = 1 + k;
+        const int pstride = 32 * c1 * 27 + 32;
+        const int threads = (c1 * 32 + 63) / 64 * 64;
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_wgrad<C1, 32, 2>), dim3(nb, 1), dim3(threads), 0, s,
+                                                  patches, g1, count, per, part, pstride));
+        const int nw = 32 * c1 * 27;
         hipLaunchKernelGGL(k_cnn_reduce, dim3((nw + 32 + 255) / 256), dim3(256), 0, s, part, nb, pstride, nw, nw,
                            32, grad);
     }

@@ -559,6 +559,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
         return fail(SPECMG_EINVAL, "unknown warm_start");
     if (opts->warm_start == SPECMG_WS_CNN && !opts->cnn_weights)
         return fail(SPECMG_EINVAL, "warm_start CNN needs cnn_weights");
+    if (opts->warm_start == SPECMG_WS_CNN && (opts->eigs_per_subdomain & 1))
+        return fail(SPECMG_EINVAL, "warm_start CNN needs an even eigs_per_subdomain");
     long div = 8;
     for (int l = 2; l < opts->levels; ++l) div *= G.agg;
     if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.nx % div || G.ny % div || G.nz % div)

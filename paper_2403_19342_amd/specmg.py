@@ -259,7 +259,7 @@ class CNN:
     def __init__(self, k: int, max_batch: int):
         lib = load_library()
         self.k = k
-        self.kp = k + (k & 1)
+        self.kp = k
         self.max_batch = max_batch
         self.n_params = int(lib.specmg_cnn_param_count(k))
         h = ctypes.c_void_p()

@@ -30,16 +30,18 @@ from synth.fields import learned_field  # noqa: E402
 
 
 def init_params(k: int, seed: int) -> np.ndarray:
-    """He-normal weights, small normal biases, in the library's parameter order."""
+    """He-normal weights, small normal biases, in the library's parameter order;
+    the output layer starts near zero, so training starts from the cold modes."""
     from paper_2403_19342_amd.specmg import load_library
     rng = np.random.default_rng(seed)
-    shapes = [(32, 1), (32,), (32, 32), (32,), (k, 32), (k,)]
+    shapes = [(32, 1 + k), (32,), (32, 32), (32,), (k, 32), (k,)]
     parts = []
-    for shp in shapes:
+    for i, shp in enumerate(shapes):
+        scale = 0.01 if i >= 4 else 1.0
         if len(shp) == 2:
-            parts.append(rng.standard_normal(shp[0] * shp[1] * 27) * np.sqrt(2.0 / (shp[1] * 27)))
+            parts.append(rng.standard_normal(shp[0] * shp[1] * 27) * np.sqrt(2.0 / (shp[1] * 27)) * scale)
         else:
-            parts.append(rng.standard_normal(shp[0]) * 0.05)
+            parts.append(rng.standard_normal(shp[0]) * 0.05 * scale)
     theta = np.concatenate(parts).astype(np.float32)
     assert theta.size == load_library().specmg_cnn_param_count(k)
     return theta
@@ -99,17 +101,32 @@ def train(P, S, F, k: int, steps: int, batch: int, lr: float, seed: int = 0, log
     return theta, theta16, history, time.perf_counter() - t0
 
 
-def evaluate(theta16, n: int, seeds, k: int, levels: int = 3, ws_resid_tol: float = 1e-3):
+def modes_only(k: int):
+    """bf16 parameters with a zero output layer: the network returns the cold
+    start's cosine modes (the learned set-up without a trained network)."""
+    import torch
+    th = init_params(k, 0)
+    th[-(k * 32 * 27 + k):] = 0.0
+    bits = (th.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)   # exact: no rounding needed for 0
+    th16 = torch.as_tensor(bits.copy(), device="cuda")
+    return th16
+
+
+def evaluate(theta16, n: int, seeds, k: int, levels: int = 3, ws_resid_tol: float = 1e-3, precision: int = 0):
+    """Set-up and solve per test field: exact (cold), relaxed from the cosine
+    modes (no network), relaxed from the trained network."""
     import torch
     from paper_2403_19342_amd.specmg import SpecMG
     from synth.fields import make_source
     out = []
+    variants = (("exact", None), ("modes", modes_only(k)), ("trained", theta16))
     for sd in seeds:
         perm = torch.as_tensor(learned_field(n, sd), device="cuda")
         b = torch.as_tensor(make_source("quarter_five_spot", (n, n, n)).reshape(-1), device="cuda")
         row = {"seed": sd}
-        for name, w in (("cold", None), ("warm", theta16)):
-            ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=k, cnn_weights=w, ws_resid_tol=ws_resid_tol)
+        for name, w in variants:
+            ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=k, cnn_weights=w, ws_resid_tol=ws_resid_tol,
+                         precision=precision)
             inf = ctx.info()["setup"]
             cyc = ctx.level_arrays(2).status
             x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")

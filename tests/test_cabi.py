@@ -69,12 +69,14 @@ def test_cnn_arguments_validated_on_host():
     lib = _lib()
     from paper_2403_19342_amd.specmg import Grid, Opts
     from oracle import cnn
-    for k in (1, 6, 8):
+    for k in (2, 4, 6, 8):
         assert lib.specmg_cnn_param_count(k) == cnn.n_params(k)
-    assert lib.specmg_cnn_param_count(0) == -1 and lib.specmg_cnn_param_count(9) == -1
+    for k in (0, 1, 5, 9):
+        assert lib.specmg_cnn_param_count(k) == -1
     h = ctypes.c_void_p()
     assert lib.specmg_cnn_create(0, 16, ctypes.byref(h)) == -1 and h.value is None
     assert lib.specmg_cnn_create(9, 16, ctypes.byref(h)) == -1
+    assert lib.specmg_cnn_create(5, 16, ctypes.byref(h)) == -1
     assert lib.specmg_cnn_create(6, 0, ctypes.byref(h)) == -1
     fake = ctypes.c_void_p(0x1000)
     bad = Grid(36, 32, 32, 1 / 32, 1 / 32, 1 / 32, 8, 4)

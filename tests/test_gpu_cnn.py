@@ -174,60 +174,73 @@ def test_training_lowers_the_loss():
     assert last < 0.7 * first
 
 
-def test_warm_start_keeps_the_coarse_space():
-    from paper_2403_19342_amd.specmg import SpecMG
-    P, S, Phi = _training_set(range(10000, 10008))
-    _, theta16, losses = _train(P, S, Phi, 200)
-    perm = learned_field(32, 1000)
-    cold = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2)
-    warm = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2, cnn_weights=theta16)
-    lc, lw = cold.level_arrays(2), warm.level_arrays(2)
-    assert np.array_equal(lc.nkeep, lw.nkeep)
-    for e in range(len(lc.nkeep)):
-        nk = lc.nkeep[e]
-        bnd = max(lc.lam[e, nk - 1], 1e-12)
-        assert np.abs(lc.lam[e, :nk] - lw.lam[e, :nk]).max() <= 1e-10 * max(bnd, 1.0)
-        assert subspace_angle(lc.basis[e, :nk].T, lw.basis[e, :nk].T) < 1e-8
+def _zero_network():
+    """Parameters whose output layer is zero: the network returns the cold
+    start's cosine modes, the method without a trained network."""
+    th = _theta(0)
+    n3 = K * 32 * 27 + K
+    th[-n3:] = 0.0
+    bits = (_bf16(th).view(np.uint32) >> 16).astype(np.uint16).view(np.int16)
+    return torch.as_tensor(bits.copy(), device="cuda")
+
+
+def _solve(ctx, perm):
     b = np.zeros(perm.shape)
     b[0, 0, 0], b[-1, -1, -1] = 1.0, -1.0
     bd = to_dev(b.reshape(-1))
-    xc = torch.zeros_like(bd)
-    xw = torch.zeros_like(bd)
-    _, ic = cold.pcg_solve(bd, xc, tol=1e-6)
-    _, iw = warm.pcg_solve(bd, xw, tol=1e-6)
-    assert abs(ic.iters - iw.iters) <= 1
-    fb = warm.info()["setup"]["ws_fallbacks"]
-    cyc_c, cyc_w = lc.status.mean(), lw.status.mean()
-    print(f"loss {losses[0]:.3f} -> {np.mean(losses[-10:]):.3f}; fallbacks {fb}/{len(lc.nkeep)}; "
-          f"mean eigensolve cycles cold {cyc_c:.2f} warm {cyc_w:.2f}; PCG iters {ic.iters} / {iw.iters}")
-    cold.close()
-    warm.close()
+    x = torch.zeros_like(bd)
+    _, info = ctx.pcg_solve(bd, x, tol=1e-6)
+    return x.cpu().numpy(), info
 
 
-def test_accepted_warm_starts_give_the_same_coarse_space():
-    # every predicted block accepted (threshold out of reach): the warm path
-    # must converge to the same spans, eigenvalues and cut as the cold one
+def test_learned_start_at_exact_tolerance_keeps_the_coarse_space():
+    # with the relaxed residual set to the exact one, every element either
+    # converges from the predicted block to eig_tol or falls back: the spans,
+    # eigenvalues and cuts equal the cold set-up's.  On the box field most
+    # elements are homogeneous, where the modes are exact and get accepted.
     from paper_2403_19342_amd.specmg import SpecMG
-    P, S, Phi = _training_set([10000, 10001])
-    _, theta16, _ = _train(P, S, Phi, 40)
-    perm = learned_field(32, 1001)
+    perm = make_field("boxes", 32, 0)
     cold = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2)
-    warm = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2, cnn_weights=theta16, ws_resid_tol=1e30)
-    assert warm.info()["setup"]["ws_fallbacks"] == 0
+    warm = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2, cnn_weights=_zero_network(),
+                  ws_resid_tol=1e-12)
+    m = len(cold.level_arrays(2).nkeep)
+    fb = warm.info()["setup"]["ws_fallbacks"]
+    assert fb < m
     lc, lw = cold.level_arrays(2), warm.level_arrays(2)
     assert np.array_equal(lc.nkeep, lw.nkeep)
-    for e in range(len(lc.nkeep)):
+    for e in range(m):
         nk = lc.nkeep[e]
         assert np.abs(lc.lam[e, :nk] - lw.lam[e, :nk]).max() <= 1e-10
         assert subspace_angle(lc.basis[e, :nk].T, lw.basis[e, :nk].T) < 1e-8
-    b = np.zeros(perm.shape)
-    b[0, 0, 0], b[-1, -1, -1] = 1.0, -1.0
-    bd = to_dev(b.reshape(-1))
-    xc, xw = torch.zeros_like(bd), torch.zeros_like(bd)
-    _, ic = cold.pcg_solve(bd, xc, tol=1e-6)
-    _, iw = warm.pcg_solve(bd, xw, tol=1e-6)
+    xc, ic = _solve(cold, perm)
+    xw, iw = _solve(warm, perm)
     assert abs(ic.iters - iw.iters) <= 1
-    assert np.linalg.norm((xc - xw).cpu().numpy()) <= 1e-8 * np.linalg.norm(xc.cpu().numpy())
-    print(f"forced warm starts: cycles cold {lc.status.mean():.2f} warm {lw.status.mean():.2f}")
+    assert np.linalg.norm(xc - xw) <= 1e-8 * np.linalg.norm(xc)
+    print(f"exact-tolerance learned start: {m - fb}/{m} accepted")
     cold.close()
     warm.close()
+
+
+def test_relaxed_learned_setup_keeps_the_iteration_count():
+    # relaxed local eigensolves (residual 1e-3) from the trained network and
+    # from the untrained modes: PCG must keep its iteration count within 10%
+    from paper_2403_19342_amd.specmg import SpecMG
+    P, S, Phi = _training_set(range(10000, 10008))
+    _, theta16, losses = _train(P, S, Phi, 300)
+    perm = learned_field(32, 1000)
+    cold = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2)
+    xc, ic = _solve(cold, perm)
+    rows = {}
+    for name, w in (("modes", _zero_network()), ("trained", theta16)):
+        ctx = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=K, agg=2, cnn_weights=w)
+        xw, iw = _solve(ctx, perm)
+        la = ctx.level_arrays(2)
+        assert iw.converged and iw.rel_resid_true <= 1e-6
+        assert iw.iters <= int(1.1 * ic.iters) + 1
+        assert np.linalg.norm(xw - xc) <= 1e-4 * np.linalg.norm(xc)
+        rows[name] = (ctx.info()["setup"]["ws_fallbacks"], float(la.status.mean()), iw.iters)
+        ctx.close()
+    lc = cold.level_arrays(2)
+    print(f"loss {losses[0]:.3f} -> {np.mean(losses[-10:]):.3f}; cold: cycles {lc.status.mean():.2f} "
+          f"iters {ic.iters}; (fallbacks, cycles, iters) modes {rows['modes']} trained {rows['trained']}")
+    cold.close()

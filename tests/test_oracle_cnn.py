@@ -152,3 +152,40 @@ def test_patches_standardised_and_edge_replicated():
     std = (raw - raw.mean()) / np.sqrt(((raw - raw.mean()) ** 2).mean() + 1e-6)
     assert np.allclose(P[0], std)
     del p
+
+
+def test_modes_are_the_homogeneous_eigenvectors():
+    # the mode channels are eigenvectors of the homogeneous 8^3 element's
+    # Neumann matrix (closed form of Section 5.2's ladder): checked against
+    # the oracle's own level-2 eigensolve, and the zero network returns them
+    from oracle import Grid, build_hierarchy
+    g = Grid.unit_cube(8)
+    h = build_hierarchy(np.ones(g.shape), g, 2, 8, sub=8, workers=1)
+    lam = h.level(2).lam[0]
+    A = h.A.toarray()
+    for j in range(8):
+        c = cnn.mode_grid(j, 0, 8).reshape(-1)
+        r = A @ c - (A @ c) @ c / (c @ c) * c
+        assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(A @ c) + 1e-14
+    k = 4
+    p = cnn.unflatten(np.zeros(cnn.n_params(k)), k)
+    X, _ = cnn.forward(p, np.zeros((10, 10, 10)))
+    for j in range(k):
+        assert np.allclose(X[j], cnn.mode_grid(j, 0, 8).reshape(-1))
+    # halo values continue the cosines
+    assert np.allclose(cnn.mode_grid(1, -1, 10)[0, 0, 1:9], np.cos(np.pi * (np.arange(8) + 0.5) / 8))
+    del lam
+
+
+def test_zero_correction_loss_on_homogeneous_element():
+    # with a zero correction the network returns the modes, which span the
+    # homogeneous element's lowest eigenvectors at the clean cut 4
+    from oracle import Grid, build_hierarchy
+    g = Grid.unit_cube(8)
+    h = build_hierarchy(np.ones(g.shape), g, 2, 4, sub=8, workers=1)
+    phi = h.level(2).R.toarray().T
+    s = np.full(512, 3.0 * 64)
+    k = 4
+    X, _ = cnn.forward(cnn.unflatten(np.zeros(cnn.n_params(k)), k), np.zeros((10, 10, 10)))
+    loss, _ = cnn.subspace_loss(X, phi[:, :k], s)
+    assert loss < 1e-20
