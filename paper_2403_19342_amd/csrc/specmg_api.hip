@@ -76,6 +76,7 @@ struct DevBuf {
 };
 
 constexpr int kCnnSetupBatch = 8192;   // level-2 elements per network batch in set-up
+constexpr int kReplacePeriod = 25;     // FP32 V-cycle: iterations between residual replacements
 
 struct specmg_ctx {
     specmg_grid grid{};
@@ -663,6 +664,7 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
     double r0 = std::sqrt(dev_dot(c, c->r, c->r, s));
     bool converged = r0 <= tol * nb;
     int k = 0;   // CG iterations issued so far (= device iteration counter after a sync)
+    int last_replace = 0;
     bool restart = true;
     while (!converged) {
         if (restart) {
@@ -707,6 +709,16 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
         if (k >= max_iter) {
             launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
             break;
+        }
+        if (flexible && k - last_replace >= kReplacePeriod) {
+            // FP32 V-cycle: replace the recursive residual by the true FP64
+            // one, r = b - A x, and restart the V-cycle from it; the next
+            // direction update continues p = z + beta p
+            launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
+            launch_apply_A(c->fg, c->kt, x, b, c->r, 1, s);
+            si.replacements += 1;
+            last_replace = k;
+            restart = true;
         }
     }
     read_scalars(c, s);

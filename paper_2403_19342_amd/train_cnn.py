@@ -112,31 +112,53 @@ def modes_only(k: int):
     return th16
 
 
-def evaluate(theta16, n: int, seeds, k: int, levels: int = 3, ws_resid_tol: float = 1e-3, precision: int = 0):
-    """Set-up and solve per test field: exact (cold), relaxed from the cosine
-    modes (no network), relaxed from the trained network."""
+def evaluate(theta16, n: int, seeds, k: int, levels: int = 3, ws_resid_tol: float = 1e-3):
+    """Set-up and solve per test field for four forms: the plain FP64 method
+    (exact local eigensolves), the FP32 V-cycle alone, and the FP32 V-cycle
+    with the learned set-up started from the cosine modes (no network) and
+    from the trained network.  Solutions are compared with the plain one."""
     import torch
-    from paper_2403_19342_amd.specmg import SpecMG
+    from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE
     from synth.fields import make_source
     out = []
-    variants = (("exact", None), ("modes", modes_only(k)), ("trained", theta16))
+    variants = (("fp64_exact", None, FP64), ("fp32_exact", None, FP32_VCYCLE),
+                ("fp32_modes", modes_only(k), FP32_VCYCLE), ("fp32_trained", theta16, FP32_VCYCLE))
     for sd in seeds:
         perm = torch.as_tensor(learned_field(n, sd), device="cuda")
         b = torch.as_tensor(make_source("quarter_five_spot", (n, n, n)).reshape(-1), device="cuda")
         row = {"seed": sd}
-        for name, w in variants:
+        x_ref = None
+        for name, w, prec in variants:
             ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=k, cnn_weights=w, ws_resid_tol=ws_resid_tol,
-                         precision=precision)
+                         precision=prec)
             inf = ctx.info()["setup"]
             cyc = ctx.level_arrays(2).status
             x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
             _, si = ctx.pcg_solve(b, x, tol=1e-6)
-            row[name] = {"setup_ms": inf["setup_ms"], "fallbacks": inf["ws_fallbacks"],
-                         "mean_cycles": float(cyc.mean()), "max_cycles": int(cyc.max()), "iters": si.iters}
+            if x_ref is None:
+                x_ref = x
+            diff = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
+            row[name] = {"setup_ms": inf["setup_ms"], "solve_ms": si.solve_ms,
+                         "total_ms": inf["setup_ms"] + si.solve_ms, "iters": si.iters,
+                         "rel_resid_true": si.rel_resid_true, "rel_diff_vs_fp64": diff,
+                         "fallbacks": inf["ws_fallbacks"], "mean_cycles": float(cyc.mean()),
+                         "max_cycles": int(cyc.max())}
             ctx.close()
         out.append(row)
         print(json.dumps(row), flush=True)
     return out
+
+
+def summarize(rows):
+    """Means over test fields of each form's set-up, solve and iterations."""
+    names = [k for k in rows[0] if k != "seed"]
+    summ = {}
+    for nm in names:
+        summ[nm] = {f: float(np.mean([r[nm][f] for r in rows]))
+                    for f in ("setup_ms", "solve_ms", "total_ms", "iters", "mean_cycles", "fallbacks",
+                              "rel_diff_vs_fp64")}
+        summ[nm]["max_iter_ratio"] = float(max(r[nm]["iters"] / r[names[0]]["iters"] for r in rows))
+    return summ
 
 
 def main(argv=None):
@@ -160,7 +182,8 @@ def main(argv=None):
                       "seconds": secs, "loss_first": float(np.mean(hist[:20])),
                       "loss_last": float(np.mean(hist[-20:]))}), flush=True)
     if a.eval:
-        evaluate(theta16, a.n, range(1000, 1000 + a.eval), a.k, ws_resid_tol=a.ws_resid_tol)
+        rows = evaluate(theta16, a.n, range(1000, 1000 + a.eval), a.k, ws_resid_tol=a.ws_resid_tol)
+        print(json.dumps({"summary": summarize(rows), "fields": len(rows)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,87 @@
+"""FP32 V-cycle inside FP64 CG (the mixed-precision extension) against the
+FP64 oracle.
+
+There is no exactness pin: the V-cycle rounds to float32 while CG, its dot
+products, the residual replacement and the coarsest pseudo-inverse stay in
+float64.  Each result is reported as its error against the FP64 oracle and
+must satisfy:
+  P^{-1} r   max(1e-4, 1e-6 / lambda_min+(A_L)) relative (mean-projected):
+             float32 rounding (6e-8) of the smoother and of the coarse
+             right-hand sides, amplified by the FP64 coarsest pseudo-inverse
+             as in the FP64 bound, with a factor 10 of headroom
+  PCG        true FP64 residual <= 1e-6, iterations at most 10% (+1) above
+             the FP64 oracle's, and ||x - x_oracle|| <= (||r|| + ||r_oracle||)
+             / lambda_min+(A): both solutions are zero-mean, so their
+             difference is bounded by the difference of their residuals
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import Grid, build_hierarchy, Preconditioner, pcg
+from synth.fields import make_field, make_source, random_zero_mean
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("boxes32_l2", 32, "boxes", 0, 2, 4, 4),
+    ("gauss32_l3", 32, "gauss", 1, 3, 6, 2),
+    ("incl32_l3", 32, "inclusions", 3, 3, 6, 4),
+]
+
+
+def _ctx(perm, levels, eigs, agg):
+    from paper_2403_19342_amd.specmg import SpecMG, FP32_VCYCLE
+    return SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, precision=FP32_VCYCLE)
+
+
+@pytest.mark.parametrize("name,n,kind,seed,levels,eigs,agg", CASES)
+def test_fp32_apply_precond(name, n, kind, seed, levels, eigs, agg):
+    import torch
+    perm = make_field(kind, n, seed)
+    g = Grid.unit_cube(n)
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
+    pre = Preconditioner(hier)
+    ctx = _ctx(perm, levels, eigs, agg)
+    wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
+    tol = max(1e-4, 1e-6 / wL[1])
+    for s in range(2):
+        r = random_zero_mean(perm.shape, 200 + s).reshape(-1)
+        z = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(to_dev(r), z)
+        torch.cuda.synchronize()
+        zg, zo = to_host(z), pre.apply(r)
+        zg -= zg.mean()
+        zo -= zo.mean()
+        err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+        print(f"{name}: FP32 V-cycle P^-1 r error vs FP64 oracle {err:.2e} (bound {tol:.1e})")
+        assert err < tol
+
+
+@pytest.mark.parametrize("name,n,kind,seed,levels,eigs,agg", CASES)
+def test_fp32_pcg(name, n, kind, seed, levels, eigs, agg):
+    import torch
+    perm = make_field(kind, n, seed)
+    g = Grid.unit_cube(n)
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
+    b = make_source("corner", perm.shape).reshape(-1)
+    ref = pcg(hier.A, b, Preconditioner(hier).apply, tol=1e-6)
+    ctx = _ctx(perm, levels, eigs, agg)
+    x = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    rc, info = ctx.pcg_solve(to_dev(b), x, tol=1e-6)
+    xg = to_host(x)
+    # lambda_min+(A): the two eigenvalues nearest -1 are 0 (constants) and lambda_min+
+    w = np.sort(spla.eigsh(hier.A.tocsc(), k=2, sigma=-1.0, which="LM", return_eigenvectors=False))
+    nb = np.linalg.norm(b)
+    bound = (info.rel_resid_true + ref.rel_resid_true) * nb / w[1] / np.linalg.norm(ref.x)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"{name}: FP32 V-cycle iters {info.iters} (FP64 oracle {ref.iters}), error vs FP64 oracle "
+          f"{err:.2e} (bound {bound:.1e}), true resid {info.rel_resid_true:.2e}, "
+          f"replacements {info.replacements}")
+    assert rc == 0 and info.converged
+    assert info.rel_resid_true <= 1e-6
+    assert info.iters <= int(1.1 * ref.iters) + 1
+    assert err <= bound
+    if info.iters > 25:
+        assert info.replacements >= 1
