@@ -34,8 +34,8 @@ __device__ __forceinline__ int child_of(const CoarseGeom& g, int E, int p) {
 
 // children positions sorted by qx+qy+qz for agg = 2 and agg = 4
 struct ChildPlanes {
-    unsigned char pos2[8], off2[5];
-    unsigned char pos4[64], off4[11];
+    unsigned char pos2[8], off2[5], rank2[8];
+    unsigned char pos4[64], off4[11], rank4[64];
 };
 
 constexpr ChildPlanes make_child_planes() {
@@ -54,6 +54,8 @@ constexpr ChildPlanes make_child_planes() {
             if ((p & 3) + ((p >> 2) & 3) + (p >> 4) == s) t.pos4[k++] = (unsigned char)p;
     }
     t.off4[10] = (unsigned char)k;
+    for (int i = 0; i < 8; ++i) t.rank2[t.pos2[i]] = (unsigned char)i;
+    for (int i = 0; i < 64; ++i) t.rank4[t.pos4[i]] = (unsigned char)i;
     return t;
 }
 
@@ -120,125 +122,131 @@ constexpr int kCoarseThreads = 256;
 constexpr int kMaxChildren = 64;   // agg <= 4
 constexpr int kMaxL = 16;
 
-// Staged copy of the coupling blocks of one sweep direction for all
-// children of E: sG[(p * 3 + ax) * LL + e] = G[child(p)][2 ax + upper][e].
-// Loads are issued 16 per thread before their LDS stores.
-template <typename T>
-__device__ void stage_couplings(const CoarseGeom& g, int E, const T* __restrict__ G, int upper, T* sG) {
-    const int LL = g.L * g.L, nc = g.agg * g.agg * g.agg;
-    const int total = nc * 3 * LL;
-    for (int base = 0; base < total; base += 16 * blockDim.x) {
-        T v[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int t = base + u * blockDim.x + threadIdx.x;
-            v[u] = T(0);
-            if (t < total) {
-                const int p = t / (3 * LL), ax = (t / LL) % 3, e = t % LL;
-                v[u] = G[((size_t)child_of(g, E, p) * 6 + 2 * ax + upper) * LL + e];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int t = base + u * blockDim.x + threadIdx.x;
-            if (t < total) sG[t] = v[u];
-        }
-    }
-}
-
-// One hyperplane-ordered half of the block IC(0) substitution over the
-// children of E, in place on sY.  forward: y_c = sW_c - sum_lower G y;
-// backward: z_c = y_c - sum_upper G z.  Couplings from LDS (sG, staged) or
-// global memory.
-template <typename T>
-__device__ void ic_half_sweep(const CoarseGeom& g, int E, int upper, const T* __restrict__ G, const T* sG,
-                              T* sY, const T* sW, const int* pos, const int* off) {
-    const int L = g.L, agg = g.agg, LL = L * L;
-    const int nplanes = 3 * (agg - 1) + 1;
-    const int k = threadIdx.x / L, a = threadIdx.x % L;
-    const int pstep[3] = {1, agg, agg * agg};
-    for (int ss = 0; ss < nplanes; ++ss) {
-        const int s = upper ? nplanes - 1 - ss : ss;
-        const int cnt = off[s + 1] - off[s];
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
-            const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
-            T acc = upper ? sY[p * L + a] : sW[p * L + a];
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const bool has = upper ? (q[ax] < agg - 1) : (q[ax] > 0);
-                if (!has) continue;
-                const int pn = upper ? p + pstep[ax] : p - pstep[ax];
-                const T* gr = sG ? sG + ((size_t)(p * 3 + ax) * L + a) * L
-                                 : G + (((size_t)child_of(g, E, p) * 6 + 2 * ax + upper) * L + a) * L;
-#pragma unroll
-                for (int b = 0; b < kMaxLc; ++b) {
-                    const int bb = b < L ? b : L - 1;
-                    acc -= (b < L ? gr[bb] : T(0)) * sY[pn * L + bb];
-                }
-            }
-            sY[p * L + a] = acc;
-        }
-        __syncthreads();
-    }
-    (void)LL;
-}
-
-constexpr int kSweepThreads = 512;
-
-// Level-l smoother on parent E (both substitutions in one kernel):
+// Level-l smoother on parent E, both substitutions in one kernel:
 //   t = r (mode 0) or t = r - A_l u (mode 1)
-//   y = forward substitution of t, z = backward substitution of y
+//   w = D^-1 t per child; y = forward substitution, z = backward substitution
 //   out = z (mode 0) or out = u + z (mode 1)
-// The couplings of each direction are staged in LDS in turn when they fit.
-template <typename T>
-__global__ __launch_bounds__(kSweepThreads) void k_coarse_sweep(CoarseGeom g, int mode, const T* __restrict__ Ad,
-                                                                const T* __restrict__ Aoff,
-                                                                const T* __restrict__ Dinv,
-                                                                const T* __restrict__ G, const T* __restrict__ r,
-                                                                const T* u, T* out, const Scalars* sc,
-                                                                int check_done, int staged) {
+// One thread per row (child, slot) with the children in hyperplane order, so
+// the rows of plane s are threads [off[s] LP, off[s+1] LP).  Each thread keeps
+// the rows of its lower and upper couplings G in registers; only y lives in
+// LDS.  A plane step is one LDS read per coupling entry, the products, a store
+// and a barrier.  Missing neighbours read the thread's own child with weight 0.
+template <typename T, int LP>
+__global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, const T* __restrict__ Ad,
+                                                      const T* __restrict__ Aoff, const T* __restrict__ Dinv,
+                                                      const T* __restrict__ G, const T* __restrict__ r,
+                                                      const T* u, T* out, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
-    extern __shared__ double dyn_coarse[];
-    __shared__ int pos[kMaxChildren], off[12];
+    __shared__ T sY[kMaxChildren * LP];
     const int E = blockIdx.x;
-    const int L = g.L, nc = g.agg * g.agg * g.agg, LL = L * L;
-    T* sG = staged ? (T*)dyn_coarse : nullptr;
-    T* sY = (T*)dyn_coarse + (staged ? nc * 3 * LL : 0);
-    T* sW = sY + nc * L;
-    build_planes(g.agg, pos, off);
-    if (staged) stage_couplings<T>(g, E, G, 0, sG);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        const int c = child_of(g, E, p);
-        T tv = r[(size_t)c * L + a];
-        if (mode) tv -= block_row_apply<T>(g, Ad, Aoff, u, c, a);
-        sY[t] = tv;
+    const int agg = g.agg, nc = agg * agg * agg, sh = log2_agg(agg);
+    const int nplanes = 3 * (agg - 1) + 1;
+    const int t = threadIdx.x;
+    const bool row_ok = t < nc * LP;
+    const int k = row_ok ? t / LP : 0, a = t % LP;
+    const int p = agg == 4 ? kCP.pos4[k] : kCP.pos2[k];
+    const int q[3] = {p & (agg - 1), (p >> sh) & (agg - 1), p >> (2 * sh)};
+    const int plane = q[0] + q[1] + q[2];
+    const int c = child_of(g, E, p);
+    // neighbour rows in LDS and weights per direction (lower: 2 ax, upper: 2 ax + 1)
+    int nb[6];
+    T wgt[6];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const int ax = d >> 1;
+        const bool in = (d & 1) ? (q[ax] < agg - 1) : (q[ax] > 0);
+        const int step = 1 << (sh * ax);
+        const int pn = in ? ((d & 1) ? p + step : p - step) : p;
+        nb[d] = (agg == 4 ? kCP.rank4[pn] : kCP.rank2[pn]) * LP;
+        wgt[d] = in ? T(1) : T(0);
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        const T* di = Dinv + ((size_t)child_of(g, E, p) * L + a) * L;
+    // right-hand side t = r (- A_l u): all loads of the row first
+    const size_t row = (size_t)c * LP + a;
+    T tv = r[row];
+    if (mode) {
+        const int cx = c % g.mx, cy = (c / g.mx) % g.my, cz = c / (g.mx * g.my);
         T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < kMaxLc; ++b) {
-            const int bb = b < L ? b : L - 1;
-            acc += (b < L ? di[bb] : T(0)) * sY[p * L + bb];
+        for (int b = 0; b < LP; ++b) acc += Ad[row * LP + b] * u[(size_t)c * LP + b];
+        // one direction at a time keeps the loads in flight to 4 LP values
+#pragma unroll 1
+        for (int ax = 0; ax < 3; ++ax) {
+            const int cca = ax == 0 ? cx : (ax == 1 ? cy : cz);
+            const int exa = ax == 0 ? g.mx : (ax == 1 ? g.my : g.mz);
+            const int sta = ax == 0 ? 1 : (ax == 1 ? g.mx : g.mx * g.my);
+            const bool hp = cca + 1 < exa, hm = cca > 0;
+            const int cp = hp ? c + sta : c, cm = hm ? c - sta : c;
+            const T wp = hp ? T(1) : T(0), wm = hm ? T(1) : T(0);
+            T sp = T(0), sm = T(0);
+#pragma unroll
+            for (int b = 0; b < LP; ++b) {
+                // A(c, c+e) = Aoff[c][ax]; A(c, c-e) = Aoff[c-e][ax]^T
+                sp += Aoff[(((size_t)c * 3 + ax) * LP + a) * LP + b] * u[(size_t)cp * LP + b];
+                sm += Aoff[(((size_t)cm * 3 + ax) * LP + b) * LP + a] * u[(size_t)cm * LP + b];
+            }
+            acc += wp * sp + wm * sm;
         }
-        sW[t] = acc;
+        tv -= acc;
+    }
+    if (row_ok) sY[t] = tv;
+    // lower coupling rows G[c][2 ax][a][0..LP-1], loaded while the block
+    // synchronises; the upper ones follow the forward sweep, so the two
+    // sets are never live together
+    T gl[3][LP];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+        for (int b = 0; b < LP; ++b) gl[ax][b] = G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] * wgt[2 * ax];
     }
     __syncthreads();
-    ic_half_sweep<T>(g, E, 0, G, sG, sY, sW, pos, off);
-    if (staged) {
-        stage_couplings<T>(g, E, G, 1, sG);
+    T w = T(0);
+    {
+        const T* di = Dinv + row * LP;
+        const T* ty = sY + k * LP;
+#pragma unroll
+        for (int b = 0; b < LP; ++b) w += di[b] * ty[b];
+    }
+    __syncthreads();
+    // forward: y = w - sum_lower G y
+    T y = T(0);
+    for (int s = 0; s < nplanes; ++s) {
+        if (row_ok && plane == s) {
+            T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+            for (int b = 0; b < LP; ++b) {
+                s0 += gl[0][b] * sY[nb[0] + b];
+                s1 += gl[1][b] * sY[nb[2] + b];
+                s2 += gl[2][b] * sY[nb[4] + b];
+            }
+            y = w - (s0 + s1 + s2);
+            sY[t] = y;
+        }
         __syncthreads();
     }
-    ic_half_sweep<T>(g, E, 1, G, sG, sY, nullptr, pos, off);
-    for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
-        const int p = t / L, a = t % L;
-        const size_t i = (size_t)child_of(g, E, p) * L + a;
-        out[i] = mode ? u[i] + sY[t] : sY[t];
+    // backward: z = y - sum_upper G z
+    T gu[3][LP];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+        for (int b = 0; b < LP; ++b)
+            gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
     }
+    T z = T(0);
+    for (int s = nplanes - 1; s >= 0; --s) {
+        if (row_ok && plane == s) {
+            T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+            for (int b = 0; b < LP; ++b) {
+                s0 += gu[0][b] * sY[nb[1] + b];
+                s1 += gu[1][b] * sY[nb[3] + b];
+                s2 += gu[2][b] * sY[nb[5] + b];
+            }
+            z = y - (s0 + s1 + s2);
+            sY[t] = z;
+        }
+        __syncthreads();
+    }
+    if (row_ok) out[row] = mode ? u[row] + z : z;
 }
 
 // s = r - A_l u on the children of E, then r_up[E] = V_E^T s
@@ -668,35 +676,40 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
 }
 
 // dynamic LDS of the sweep kernels; couplings are staged when they fit
-template <typename T>
-static size_t sweep_lds(const CoarseGeom& g, int& staged) {
-    const size_t nc = (size_t)g.agg * g.agg * g.agg, LL = (size_t)g.L * g.L;
-    const size_t vec = 2 * nc * g.L * sizeof(T);
-    const size_t all = nc * 3 * LL * sizeof(T) + vec;
-    staged = all <= 150 * 1024;
-    return staged ? all : vec;
+#define SPECMG_LP_DISPATCH(LV, ...)                           \
+    switch (LV) {                                             \
+        case 4: { constexpr int LP = 4; __VA_ARGS__; } break;     \
+        case 5: { constexpr int LP = 5; __VA_ARGS__; } break;     \
+        case 6: { constexpr int LP = 6; __VA_ARGS__; } break;     \
+        case 7: { constexpr int LP = 7; __VA_ARGS__; } break;     \
+        case 8: { constexpr int LP = 8; __VA_ARGS__; } break;     \
+        case 9: { constexpr int LP = 9; __VA_ARGS__; } break;     \
+        case 10: { constexpr int LP = 10; __VA_ARGS__; } break;   \
+        default: { constexpr int LP = 11; __VA_ARGS__; } break;   \
+    }
+
+static int sweep_threads(const CoarseGeom& g) {
+    const int rows = g.agg * g.agg * g.agg * g.L;
+    return (rows + 63) / 64 * 64;
 }
 
 // u = M_l^{-1} r
 template <typename T>
 void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const T* r, T* u, const Scalars* sc,
                           int check_done, hipStream_t s) {
-    int staged;
-    const size_t lds = sweep_lds<T>(g, staged);
-    hipFuncSetAttribute((const void*)k_coarse_sweep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_coarse_sweep<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 0, (const T*)nullptr,
-                       (const T*)nullptr, Dinv, G, r, (const T*)nullptr, u, sc, check_done, staged);
+    if (g.L < 4 || g.L > 11 || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
+    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
+                                               0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
+                                               (const T*)nullptr, u, sc, check_done));
 }
 
 // e = u + M_l^{-1} (r - A_l u)
 template <typename T>
 void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* G,
                                 const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
-    int staged;
-    const size_t lds = sweep_lds<T>(g, staged);
-    hipFuncSetAttribute((const void*)k_coarse_sweep<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_coarse_sweep<T>), dim3(g.M), dim3(kSweepThreads), lds, s, g, 1, Ad, Aoff, Dinv, G, r, u, e,
-                       sc, check_done, staged);
+    if (g.L < 4 || g.L > 11 || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
+    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
+                                               1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
 }
 
 template <typename T>
