@@ -132,7 +132,8 @@ def main():
             a = tot.setdefault(k, [0.0, 0, by])
             a[0] += ms
             a[1] += cnt
-    fine = [k for k in tot if k in ("cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth")]
+    fine = [k for k in tot if k in ("cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth",
+                                    "post_residual")]
     dom = max(fine, key=lambda k: tot[k][0])
     ms, cnt, by = tot[dom]
     from paper_2403_19342_amd.profile_summary import read_traffic

@@ -166,8 +166,9 @@ int specmg_set_profiling(specmg_ctx* ctx, int32_t on);
  * moves (compulsory HBM traffic of its inputs and outputs).  Classes:
  * 0 CG operator (p update, A p, p.Ap)   1 pre-smoothing (r update, IC(0))
  * 2 residual + restriction             3 prolongation
- * 4 residual + post-smoothing          5 coarse levels 2..L-1 (all kernels)
- * 6 coarsest solve (two-level set-ups) 7 unused.  Arrays hold 8 entries. */
+ * 4 post-smoothing (IC(0), r.z)       5 coarse levels 2..L-1 (all kernels)
+ * 6 coarsest solve (two-level set-ups) 7 residual before post-smoothing.
+ * Arrays hold 8 entries. */
 int specmg_get_profile(specmg_ctx* ctx, double* ms, int32_t* launches, double* bytes);
 
 /* Releases every device and host resource of the context (NULL is a no-op). */

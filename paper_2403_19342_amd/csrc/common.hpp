@@ -186,8 +186,11 @@ template <typename T>
 void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
                     Scalars* sc, int check_done, hipStream_t s);
 template <typename T>
+void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
+                     int check_done, hipStream_t s);
+template <typename T>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
-                        const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
+                        const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
 void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
                      double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first,
                      hipStream_t s);

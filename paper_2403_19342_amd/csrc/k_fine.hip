@@ -253,6 +253,142 @@ __device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* Tx, const T
 }
 
 // ---------------------------------------------------------------------------
+// Pencil layout of the block IC(0) solves: one wavefront per 8^3 element;
+// lane (j, k) = (lane & 7, lane >> 3) owns the x-pencil of cells (m, j, k).
+// Slot r of a lane's registers holds cell m = (r - j - k) & 7, so on the
+// hyperplane s = m + j + k every lane works on slot s & 7, a static register
+// index.  A cell's neighbours in y and z are the same cell of lanes -+1 and
+// -+8, kept there one slot lower (j-1, k-1) or higher (j+1, k+1); the
+// neighbours in x are the lane's own slots r -+ 1.
+
+__device__ __forceinline__ int pencil_m(int r, int jk) { return (r - jk) & 7; }
+
+// The lane's 8 cells are contiguous in memory (64 bytes for float64): they
+// move with 16-byte vector accesses and are rotated into (out of) the slot
+// order in registers by a 3-stage barrel shifter on j + k.
+template <typename T>
+__device__ __forceinline__ void rotate_slots(T (&v)[8], int jk, bool inverse) {
+#pragma unroll
+    for (int b = 1; b < 8; b <<= 1) {
+        const bool on = (jk & b) != 0;
+        T t[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) t[s] = on ? v[inverse ? ((s + b) & 7) : ((s - b) & 7)] : v[s];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = t[s];
+    }
+}
+
+// v[slot] = p[pencil cell of slot], p points at cell (0, j, k)
+__device__ __forceinline__ void load_pencil(const double* __restrict__ p, double (&v)[8], int jk) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 d = q[i];
+        v[2 * i] = d.x;
+        v[2 * i + 1] = d.y;
+    }
+    rotate_slots(v, jk, false);
+}
+__device__ __forceinline__ void load_pencil(const float* __restrict__ p, float (&v)[8], int jk) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float4 d = q[i];
+        v[4 * i] = d.x;
+        v[4 * i + 1] = d.y;
+        v[4 * i + 2] = d.z;
+        v[4 * i + 3] = d.w;
+    }
+    rotate_slots(v, jk, false);
+}
+// p[pencil cell of slot] = v[slot] (v is consumed)
+__device__ __forceinline__ void store_pencil(double* p, double (&v)[8], int jk) {
+    rotate_slots(v, jk, true);
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+__device__ __forceinline__ void store_pencil(float* p, float (&v)[8], int jk) {
+    rotate_slots(v, jk, true);
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) q[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+}
+
+// value of the same cell in lanes -+1 (y) and -+8 (z); lanes at the edge of
+// the wavefront get their own value, which the callers mask
+template <typename T>
+__device__ __forceinline__ T from_ym(const T (&v)[8], int r) { return __shfl_up(v[(r + 7) & 7], 1, 64); }
+template <typename T>
+__device__ __forceinline__ T from_yp(const T (&v)[8], int r) { return __shfl_down(v[(r + 1) & 7], 1, 64); }
+template <typename T>
+__device__ __forceinline__ T from_zm(const T (&v)[8], int r) { return __shfl_up(v[(r + 7) & 7], 8, 64); }
+template <typename T>
+__device__ __forceinline__ T from_zp(const T (&v)[8], int r) { return __shfl_down(v[(r + 1) & 7], 8, 64); }
+
+// Forward and backward IC(0) substitution of the wavefront's element.
+// y: in t, out (D+L^T)^{-1} D (D+L)^{-1} t.  ix: inverse pivots; fx, fy, fz:
+// transmissibilities of each cell's minus faces (a_ij = -T).  A cell's plus
+// face in y (z) is the minus face of the same cell in lane +1 (+8), fetched
+// with the neighbour's value; its plus face in x is fx of the next slot.
+// Faces that leave the element are dropped here: in y and z by the lane's
+// position, in x at the pencil's ends.
+template <typename T>
+__device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (&fx)[8], const T (&fy)[8],
+                                          const T (&fz)[8], int j, int k) {
+    const int jk = j + k;
+    const T wym = j > 0 ? T(1) : T(0), wyp = j < 7 ? T(1) : T(0);
+    const T wzm = k > 0 ? T(1) : T(0), wzp = k < 7 ? T(1) : T(0);
+    T cur = T(0);
+#pragma unroll
+    for (int s = 0; s < kPlanes; ++s) {
+        const int r = s & 7, rp = (s + 7) & 7;
+        const T ny = __shfl_up(cur, 1, 64);
+        const T nz = __shfl_up(cur, 8, 64);
+        const T xm = s - jk > 0 ? y[rp] : T(0);
+        T acc = y[r];
+        acc += fx[r] * xm;
+        acc += (fy[r] * wym) * ny;
+        acc += (fz[r] * wzm) * nz;
+        const T v = acc * ix[r];
+        const bool act = (unsigned)(s - jk) < 8u;
+        y[r] = act ? v : y[r];
+        cur = act ? v : cur;
+    }
+    cur = T(0);
+#pragma unroll
+    for (int s = kPlanes - 1; s >= 0; --s) {
+        const int r = s & 7, rn = (s + 1) & 7;
+        const T ny = __shfl_down(cur, 1, 64);
+        const T nz = __shfl_down(cur, 8, 64);
+        const T gy = __shfl_down(fy[rn], 1, 64) * wyp;
+        const T gz = __shfl_down(fz[rn], 8, 64) * wzp;
+        const T xp = s - jk < 7 ? y[rn] : T(0);
+        T acc = fx[rn] * xp;
+        acc += gy * ny;
+        acc += gz * nz;
+        const T v = y[r] + ix[r] * acc;
+        const bool act = (unsigned)(s - jk) < 8u;
+        y[r] = act ? v : y[r];
+        cur = act ? v : cur;
+    }
+}
+
+// Minus-face transmissibilities of the pencil's cells inside the element
+// (the neighbour's copy of kappa~ comes from the lane below).
+template <typename T>
+__device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8], T (&fy)[8], T (&fz)[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        fx[r] = harm(kc[r], kc[(r + 7) & 7]);
+        fy[r] = harm(kc[r], from_ym(kc, r));
+        fz[r] = harm(kc[r], from_zm(kc, r));
+    }
+    (void)jk;
+}
+
+// ---------------------------------------------------------------------------
 // pre-smoothing: (optionally r -= alpha q with ||r||^2) then u = M^{-1} r
 // mode bit0: update r and reduce ||r||^2 (sets the converged flag)
 // mode bit1: return at once when the solve is finished
@@ -261,81 +397,48 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
                                                         const T* __restrict__ invd, double* r,
                                                         const double* __restrict__ q, T* __restrict__ u,
                                                         Scalars* sc, RedBuf rb, int mode) {
-    using TT = TileT<EX>;
     if ((mode & 2) && sc->done) return;
-    // region 1: kappa~ tile, then the three face-transmissibility tiles
-    __shared__ T smem[5 * TT::NCP];
-    T* sK = smem;
-    T* sTx = smem;
-    T* sTy = smem + TT::NCP;
-    T* sTz = smem + 2 * TT::NCP;
-    T* sY = smem + 3 * TT::NCP;
-    T* sD = smem + 4 * TT::NCP;
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = lane & 7, k = lane >> 3, jk = j + k;
+    const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);   // cell (0, j, k) of the element
     const double alpha = (mode & 1) ? sc->alpha : 0.0;
+    // phases in order, each one's registers released before the next
+    // (faces first, then the residual update, then the pivots)
+    T fx[8], fy[8], fz[8];
+    {
+        T kc[8];
+        load_pencil(kt + row, kc, jk);
+        pencil_faces(kc, jk, fx, fy, fz);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    T y[8];
     double rr = 0.0;
-    constexpr int IT = TT::NC / TT::NT;
-    double vr[IT], vq[IT];
-    T vk[IT], vd[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int c = threadIdx.x + it * TT::NT;
-        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
-        const size_t gi = gidx(g, x0 + x, y0 + y, z0 + z);
-        vr[it] = r[gi];
-        vq[it] = (mode & 1) ? q[gi] : 0.0;
-        vk[it] = kt[gi];
-        vd[it] = invd[gi];
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int c = threadIdx.x + it * TT::NT;
-        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
-        double rv = vr[it];
+    {
+        double vr[8], vq[8];
+        load_pencil(r + row, vr, jk);
         if (mode & 1) {
-            rv -= alpha * vq[it];
-            r[gidx(g, x0 + x, y0 + y, z0 + z)] = rv;
-            rr += rv * rv;
+            load_pencil(q + row, vq, jk);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                vr[s] -= alpha * vq[s];
+                rr += vr[s] * vr[s];
+            }
         }
-        const int pc = tidx<EX>(x, y, z);
-        sY[pc] = (T)rv;
-        sK[pc] = vk[it];
-        sD[pc] = vd[it];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) y[s] = (T)vr[s];
+        if (mode & 1) store_pencil(r + row, vr, jk);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    T ix[8];
+    load_pencil(invd + row, ix, jk);
+    ic_pencil(y, ix, fx, fy, fz, j, k);
+    store_pencil(u + row, y, jk);
     if (mode & 1) {
         double v[1] = {block_sum(rr, sred)};
         write_partials<1>(v, rb);
-    }
-    __syncthreads();
-    // face transmissibilities inside the tile (faces on the tile boundary are
-    // never used by the block solves)
-    T tx[IT], ty[IT], tz[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int c = threadIdx.x + it * TT::NT;
-        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
-        const int pc = tidx<EX>(x, y, z);
-        const T kc = sK[pc];
-        tx[it] = x + 1 < TT::TX ? harm(kc, sK[pc + 1]) : T(0);
-        ty[it] = y + 1 < 8 ? harm(kc, sK[pc + TT::PX]) : T(0);
-        tz[it] = z + 1 < 8 ? harm(kc, sK[pc + 8 * TT::PX]) : T(0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int c = threadIdx.x + it * TT::NT;
-        const int pc = tidx<EX>(c % TT::TX, (c / TT::TX) & 7, c / (TT::TX * 8));
-        sTx[pc] = tx[it];
-        sTy[pc] = ty[it];
-        sTz[pc] = tz[it];
-    }
-    __syncthreads();
-    ic_sweep<EX, T>(sY, sD, sTx, sTy, sTz);
-    for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
-        const int x = c % TT::TX, y = (c / TT::TX) & 7, z = c / (TT::TX * 8);
-        u[gidx(g, x0 + x, y0 + y, z0 + z)] = sY[tidx<EX>(x, y, z)];
     }
 }
 
@@ -417,78 +520,93 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const T* __re
     }
 }
 
-// post-smoothing: t = r - A u;  z = u + M^{-1} t  (Algorithm 1 step 9)
-// mode bit0: reduce r.z (and z.q when flexible) and update the CG beta
-// mode bit1: return at once when the solve is finished
+// Residual t = r - A u, one cell per thread: the block covers 64 x 4 cells
+// of a plane and walks RZ planes in z, keeping the z-neighbours of u and
+// kappa~ in registers; x- and y-neighbours come from the L1 cache.
+// Faces leaving the domain have zero transmissibility.
+constexpr int kResZ = 8;
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, const T* __restrict__ kt,
+                                                  const T* __restrict__ u, const double* __restrict__ r,
+                                                  T* __restrict__ t, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int z0 = blockIdx.z * kResZ;
+    if (x >= nx) return;   // ragged last column of blocks (no barriers below)
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    size_t gi = (size_t)x + sy * y + sz * z0;
+    const bool xm = x > 0, xp = x + 1 < nx, ym = y > 0, yp = y + 1 < ny;
+    T uc = u[gi], kc = kt[gi];
+    T um = z0 > 0 ? u[gi - sz] : T(0), km = z0 > 0 ? kt[gi - sz] : T(0);
+#pragma unroll 2
+    for (int z = z0; z < z0 + kResZ; ++z, gi += sz) {
+        const bool zp = z + 1 < nz;
+        const T up = zp ? u[gi + sz] : T(0), kp = zp ? kt[gi + sz] : T(0);
+        const T uxm = xm ? u[gi - 1] : T(0), kxm = xm ? kt[gi - 1] : T(0);
+        const T uxp = xp ? u[gi + 1] : T(0), kxp = xp ? kt[gi + 1] : T(0);
+        const T uym = ym ? u[gi - sy] : T(0), kym = ym ? kt[gi - sy] : T(0);
+        const T uyp = yp ? u[gi + sy] : T(0), kyp = yp ? kt[gi + sy] : T(0);
+        T a = harm(kc, kxm) * (uc - uxm);
+        a += harm(kc, kxp) * (uc - uxp);
+        a += harm(kc, kym) * (uc - uym);
+        a += harm(kc, kyp) * (uc - uyp);
+        a += harm(kc, km) * (uc - um);
+        a += harm(kc, kp) * (uc - up);
+        t[gi] = (T)r[gi] - a;
+        um = uc;
+        km = kc;
+        uc = up;
+        kc = kp;
+    }
+}
+
+// post-smoothing (Algorithm 1 step 9): z = u + M^{-1} t with t = r - A u
+// from k_residual.  mode bit0: reduce r.z (and z.q when flexible) and update
+// the CG beta; bit1: return at once when the solve is finished.
 template <int EX, typename T>
 __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __restrict__ kt,
                                                          const T* __restrict__ invd,
-                                                         const T* __restrict__ u,
+                                                         const T* __restrict__ u, const T* __restrict__ tres,
                                                          const double* __restrict__ r,
                                                          const double* __restrict__ q,
                                                          double* __restrict__ z, Scalars* sc, RedBuf rb,
                                                          int mode) {
-    using TT = TileT<EX>;
     if ((mode & 2) && sc->done) return;
-    // region 1 holds the haloed u and kappa~ tiles, later the three face
-    // transmissibility tiles
-    constexpr int R1 = (2 * TT::NHP > 3 * TT::NCP) ? 2 * TT::NHP : 3 * TT::NCP;
-    __shared__ T smem[R1 + 2 * TT::NCP];
-    T* sU = smem;
-    T* sK = smem + TT::NHP;
-    T* sTx = smem;
-    T* sTy = smem + TT::NCP;
-    T* sTz = smem + 2 * TT::NCP;
-    T* sY = smem + R1;
-    T* sD = smem + R1 + TT::NCP;
     __shared__ double sred[EX];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
-    load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
-    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
-    double rv[8];
-    T dv[8];
-#pragma unroll
-    for (int zz = 0; zz < 8; ++zz) {
-        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        rv[zz] = r[gi];
-        dv[zz] = invd[gi];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int j = lane & 7, k = lane >> 3, jk = j + k;
+    const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);
+    T fx[8], fy[8], fz[8];
+    {
+        T kc[8];
+        load_pencil(kt + row, kc, jk);
+        pencil_faces(kc, jk, fx, fy, fz);
     }
-    __syncthreads();
-    T uo[8], fx[8], fy[8], fz[8];
-#pragma unroll
-    for (int zz = 0; zz < 8; ++zz) {
-        const int h = hidx<EX>(tx, ty, zz);
-        const int ti = tidx<EX>(tx, ty, zz);
-        uo[zz] = sU[h];
-        sY[ti] = (T)rv[zz] - apply_stencil<EX, T>(sU, sK, h);
-        sD[ti] = dv[zz];
-        const T kc = sK[h];
-        fx[zz] = harm(kc, sK[h + 1]);
-        fy[zz] = harm(kc, sK[h + TT::HX]);
-        fz[zz] = harm(kc, sK[h + TT::HXY]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int zz = 0; zz < 8; ++zz) {
-        const int ti = tidx<EX>(tx, ty, zz);
-        sTx[ti] = fx[zz];
-        sTy[ti] = fy[zz];
-        sTz[ti] = fz[zz];
-    }
-    __syncthreads();
-    ic_sweep<EX, T>(sY, sD, sTx, sTy, sTz);
+    __builtin_amdgcn_sched_barrier(0);
+    T y[8], ix[8];
+    load_pencil(tres + row, y, jk);
+    load_pencil(invd + row, ix, jk);
+    ic_pencil(y, ix, fx, fy, fz, j, k);
     double rz = 0.0, zq = 0.0;
     const int flex = (mode & 1) ? sc->flexible : 0;
+    {
+        T uo[8];
+        double zv[8], rv[8], qv[8];
+        load_pencil(u + row, uo, jk);
+        if (mode & 1) load_pencil(r + row, rv, jk);
+        if (flex) load_pencil(q + row, qv, jk);
 #pragma unroll
-    for (int zz = 0; zz < 8; ++zz) {
-        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const double zv = (double)uo[zz] + (double)sY[tidx<EX>(tx, ty, zz)];
-        z[gi] = zv;
-        if (mode & 1) {
-            rz += r[gi] * zv;
-            if (flex) zq += zv * q[gi];
+        for (int s = 0; s < 8; ++s) {
+            zv[s] = (double)uo[s] + (double)y[s];
+            if (mode & 1) {
+                rz += rv[s] * zv[s];
+                if (flex) zq += zv[s] * qv[s];
+            }
         }
+        store_pencil(z + row, zv, jk);
     }
     if (mode & 1) {
         double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
@@ -802,11 +920,20 @@ void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int
                        sc, check_done);
 }
 
+// t = r - A u (ny and nz are multiples of 8, nx any multiple of 8)
+template <typename T>
+void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
+                     int check_done, hipStream_t s) {
+    if (g.ny % 4 || g.nz % kResZ) throw HipError{hipErrorInvalidValue, "residual tiling"};
+    SPECMG_TIMED_LAUNCH((k_residual<T>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ), dim3(256), 0, s, g.nx, g.ny,
+                        g.nz, kt, u, r, t, sc, check_done);
+}
+
 template <typename T>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
-                        const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
+                        const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
     SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
-                                                s, g, kt, invd, u, r, q, z, sc, rb, mode));
+                                                 s, g, kt, invd, u, tres, r, q, z, sc, rb, mode));
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
@@ -891,11 +1018,11 @@ template void launch_prolong<double>(const FineGeom&, double*, const double*, co
                                      const double*, Scalars*, int, hipStream_t);
 template void launch_prolong<float>(const FineGeom&, float*, const float*, const int*, int, const float*,
                                     Scalars*, int, hipStream_t);
-template void launch_post_smooth<double>(const FineGeom&, const double*, const double*, const double*,
-                                         const double*, const double*, double*, Scalars*, RedBuf, int,
-                                         hipStream_t);
-template void launch_post_smooth<float>(const FineGeom&, const float*, const float*, const float*,
-                                        const double*, const double*, double*, Scalars*, RedBuf, int,
-                                        hipStream_t);
+template void launch_residual<double>(const FineGeom&, const double*, const double*, const double*, double*,
+                                      const Scalars*, int, hipStream_t);
+template void launch_residual<float>(const FineGeom&, const float*, const float*, const double*, float*,
+                                     const Scalars*, int, hipStream_t);
+template void launch_post_smooth<double>(const FineGeom&, const double*, const double*, const double*, const double*, const double*, double*, double*, Scalars*, RedBuf, int, hipStream_t);
+template void launch_post_smooth<float>(const FineGeom&, const float*, const float*, const float*, const double*, const double*, double*, float*, Scalars*, RedBuf, int, hipStream_t);
 
 }  // namespace specmg

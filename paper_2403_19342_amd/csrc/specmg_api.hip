@@ -96,6 +96,7 @@ struct specmg_ctx {
     int* cmap = nullptr;
     // CG state
     double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *u1 = nullptr;
+    double* tres = nullptr;     // r - A u of the post-smoother (float in FP32 mode)
     float* u1_32 = nullptr;
     double* dtmp = nullptr;     // scratch scalars
     int* dflag = nullptr;       // error flags
@@ -150,7 +151,7 @@ double now_ms() {
 // dispatch); prof_begin_range / prof_end record plain events around a group
 // of launches (the coarse levels).
 enum ProfClass { PC_SPMV = 0, PC_PRE = 1, PC_RESTRICT = 2, PC_PROLONG = 3, PC_POST = 4, PC_COARSE = 5,
-                 PC_COARSEST = 6 };
+                 PC_COARSEST = 6, PC_POSTRES = 7 };
 
 static size_t prof_events(specmg_ctx* c) {
     if (c->ev_used + 2 > c->ev_pool.size()) {
@@ -245,8 +246,12 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     ev = prof_begin(c, s);
     launch_prolong<T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
     prof_end(c, ev, PC_PROLONG, s);
+    T* tres = pick<T>(c->tres, (float*)c->tres);
     ev = prof_begin(c, s);
-    launch_post_smooth<T>(c->fg, kt, invd, u1, r, q, z, c->sc, c->rb, post_mode, s);
+    launch_residual<T>(c->fg, kt, u1, r, tres, c->sc, (post_mode & 2) ? 1 : 0, s);
+    prof_end(c, ev, PC_POSTRES, s);
+    ev = prof_begin(c, s);
+    launch_post_smooth<T>(c->fg, kt, invd, u1, r, q, z, tres, c->sc, c->rb, post_mode, s);
     prof_end(c, ev, PC_POST, s);
 }
 
@@ -511,6 +516,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->p[1] = c->alloc<double>(c->n);
     c->q = c->alloc<double>(c->n);
     c->u1 = c->alloc<double>(c->n);
+    c->tres = c->alloc<double>(c->n);
     if (c->fp32) c->u1_32 = c->alloc<float>(c->n);
     c->dtmp = c->alloc<double>(8);
     c->sc = c->alloc<Scalars>(1);
@@ -822,7 +828,8 @@ extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, 
     b[PC_PRE] = n * (8.0 * 3.0 + 2.0 * w + w);       // r, q in, r out; kappa~, 1/d in; u out
     b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * w;   // u, kappa~, r; phi
     b[PC_PROLONG] = n * 2.0 * w + phi_cells * w;             // u in/out; phi
-    b[PC_POST] = n * (3.0 * w + 8.0 * 2.0 + (c->fp32 ? 8.0 : 0.0));  // u, kappa~, 1/d, r in; z out (q)
+    b[PC_POST] = n * (4.0 * w + 8.0 * 2.0 + (c->fp32 ? 8.0 : 0.0));  // t, kappa~, 1/d, u, r in; z out (q)
+    b[PC_POSTRES] = n * (3.0 * w + 8.0);                                // u, kappa~, r in; t out
     for (int i = 0; i < 8; ++i) {
         if (ms) ms[i] = c->prof_ms[i];
         if (launches) launches[i] = c->prof_count[i];

@@ -26,7 +26,7 @@ EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
             "specmg_cnn_loss_backward", "specmg_cnn_adam"]
 PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_levels",
-                   "coarsest", "unused"]
+                   "coarsest", "post_residual"]
 
 
 class Grid(ctypes.Structure):
@@ -219,7 +219,7 @@ class SpecMG:
         cnt = (ctypes.c_int32 * 8)()
         by = (ctypes.c_double * 8)()
         _check(_lib.specmg_get_profile(self._ctx, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)))
-        return {PROFILE_CLASSES[i]: (ms[i], cnt[i], by[i]) for i in range(7)}
+        return {PROFILE_CLASSES[i]: (ms[i], cnt[i], by[i]) for i in range(8)}
 
     def info(self):
         lv = ctypes.c_int32()
