@@ -274,7 +274,6 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
 
 // dense coarsest factorization (k_dense.hip); np is a multiple of 32
 int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s);
-void launch_pinv_finish(double* a, int np, int n, const double* z, double alpha, hipStream_t s);
 void launch_add_rank1(double* a, int np, int n, const double* z, double alpha, hipStream_t s);
 void launch_pad_identity(double* a, int np, int n, hipStream_t s);
 

@@ -318,26 +318,39 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
     }
 }
 
-// e = A_L^+ r at the coarsest level: dense symmetric product over the
-// compact unknowns (cmap: compact index -> padded index)
+// e = B r at the coarsest level, B the dense inverse of the regularised
+// coarsest matrix: a product over the compact unknowns (cmap: compact index
+// -> padded index).  Each block owns 16 rows (4 per wave, 4 accumulators so
+// that four row streams are in flight); r is gathered into LDS in chunks of
+// kCoarsestChunk values, so any size fits the 160 KB of LDS.
+constexpr int kCoarsestChunk = 8192;
+constexpr int kCoarsestRows = 16;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* __restrict__ Pinv,
                                                    const int* __restrict__ cmap, const T* __restrict__ r,
                                                    T* __restrict__ e, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
     extern __shared__ double srz[];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) srz[j] = (double)r[cmap[j]];
-    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int rows_per_block = 16;
-    for (int rr = w; rr < rows_per_block; rr += 4) {
-        const int i = blockIdx.x * rows_per_block + rr;
-        if (i >= n) break;
-        const double* pr = Pinv + (size_t)i * np;
-        double s = 0.0;
-        for (int j = lane; j < n; j += 64) s += pr[j] * srz[j];
-        s = wave_sum(s);
-        if (lane == 0) e[cmap[i]] = (T)s;
+    const int i0 = blockIdx.x * kCoarsestRows + w * 4;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < n; c0 += kCoarsestChunk) {
+        const int cn = min(kCoarsestChunk, n - c0);
+        if (c0) __syncthreads();
+        for (int j = threadIdx.x; j < cn; j += blockDim.x) srz[j] = (double)r[cmap[c0 + j]];
+        __syncthreads();
+        for (int j = lane; j < cn; j += 64) {
+            const double v = srz[j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (i0 + q < n) acc[q] += Pinv[(size_t)(i0 + q) * np + c0 + j] * v;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0 && i0 + q < n) e[cmap[i0 + q]] = (T)s;
     }
 }
 
@@ -715,9 +728,9 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
 template <typename T>
 void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, const Scalars* sc,
                      int check_done, hipStream_t s) {
-    const int blocks = (n + 15) / 16;
-    hipLaunchKernelGGL((k_coarsest<T>), dim3(blocks), dim3(256), (size_t)n * sizeof(double), s, n, np, Pinv, cmap, r,
-                       e, sc, check_done);
+    const int blocks = (n + kCoarsestRows - 1) / kCoarsestRows;
+    const size_t lds = (size_t)std::min(n, kCoarsestChunk) * sizeof(double);
+    hipLaunchKernelGGL((k_coarsest<T>), dim3(blocks), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc, check_done);
 }
 
 void launch_galerkin2(const FineGeom& g, const double* kt, const double* phi, const int* nkeep, int L, double* D,

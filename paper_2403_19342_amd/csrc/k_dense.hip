@@ -220,8 +220,5 @@ void launch_add_rank1(double* a, int np, int n, const double* z, double alpha, h
     hipLaunchKernelGGL(k_rank1, dim3(1024), dim3(256), 0, s, a, np, n, z, alpha);
 }
 
-void launch_pinv_finish(double* a, int np, int n, const double* z, double alpha, hipStream_t s) {
-    hipLaunchKernelGGL(k_rank1, dim3(1024), dim3(256), 0, s, a, np, n, z, -1.0 / alpha);
-}
 
 }  // namespace specmg

@@ -466,9 +466,14 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         const double alpha = tr / nL;
         double* dz = c->alloc<double>(nL);
         HIPCHK(hipMemcpyAsync(dz, zc.data(), nL * sizeof(double), hipMemcpyHostToDevice, s));
+        // B = (A_L + alpha z z^T)^-1 is applied as the coarsest solve.  It
+        // differs from A_L^+ = B - z z^T / alpha only along z, which every
+        // level prolongs to the constant function (the kernel of A), so the
+        // mean-projected CG iterates are the same; unlike the difference, B
+        // stays positive definite when rounding spoils the inverse of an
+        // ill-conditioned A_L.
         launch_add_rank1(c->Pinv, np, nL, dz, alpha, s);
         dense_spd_inverse(c->Pinv, np, work, c->dflag + 3, s);
-        launch_pinv_finish(c->Pinv, np, nL, dz, alpha, s);
         HIPCHK(hipStreamSynchronize(s));
         (void)hipFree(work);
     }
@@ -621,6 +626,8 @@ extern "C" int specmg_apply_precond(specmg_ctx* c, const double* r, double* z, v
 static void read_scalars(specmg_ctx* c, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(c->sc_host, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    // a launch that failed since the last check (it did no work)
+    HIPCHK(hipGetLastError());
 }
 
 static double dev_dot(specmg_ctx* c, const double* a, const double* b, hipStream_t s) {
