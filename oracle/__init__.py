@@ -23,11 +23,11 @@ with plain NumPy/SciPy building blocks and no blocking or fusion:
   dense      Brute-force dense references for tiny grids.
 """
 from .assembly import Grid, transmissibilities, assemble, weight_diag, neumann_local
-from .spectral import Hierarchy, build_hierarchy, cluster_cut
+from .spectral import Hierarchy, build_hierarchy, cluster_cut, threshold_target
 from .vcycle import Preconditioner
 from .pcg import pcg
 
 __all__ = [
     "Grid", "transmissibilities", "assemble", "weight_diag", "neumann_local",
-    "Hierarchy", "build_hierarchy", "cluster_cut", "Preconditioner", "pcg",
+    "Hierarchy", "build_hierarchy", "cluster_cut", "threshold_target", "Preconditioner", "pcg",
 ]

@@ -21,7 +21,9 @@ below (T_cc and beyond).
 How many eigenvectors to keep (strategy 1 of Section 5 with a fixed target
 count L) is decided by `cluster_cut`, which never splits a cluster of equal
 eigenvalues; the paper picks its counts 4, 8, 11, 17 from the same concern
-(the Laplace eigenvalue ladder of Section 5.2).
+(the Laplace eigenvalue ladder of Section 5.2).  Levels >= 3 may use their
+own count L_cc, and strategy 2 of Section 5 (keep the eigenvalues below a
+threshold B_cc, out of L_cc candidates) through `threshold_target`.
 """
 from __future__ import annotations
 
@@ -68,6 +70,18 @@ def cluster_cut(lam, target: int, extra: int = CLUSTER_EXTRA, rtol: float = CLUS
         while k > 1 and same(k):
             k -= 1
     return k
+
+
+def threshold_target(lam, target: int, threshold: float) -> int:
+    """Target count under strategy 2 of Section 5: the number of eigenvalues
+    below the threshold B, at least one (the constant function) and at most
+    `target` (the number of candidates kept per element).  A threshold <= 0
+    selects strategy 1, the fixed count `target`.  The cluster rule is applied
+    to the result afterwards."""
+    if threshold <= 0:
+        return target
+    below = int(np.sum(np.asarray(lam, dtype=np.float64) < threshold))
+    return max(1, min(target, below))
 
 
 # ----------------------------------------------------------------------------
@@ -171,10 +185,18 @@ def _children(egrid_parent, agg, egrid_child):
 
 
 def build_hierarchy(perm, grid: Grid, nlevels: int, target: int, sub: int = 8, agg: int = 4,
-                    workers: int | None = None, A=None) -> Hierarchy:
-    """Set-up phase: local spectral problems and the Galerkin chain."""
+                    workers: int | None = None, A=None, target_cc: int | None = None,
+                    threshold_cc: float = 0.0) -> Hierarchy:
+    """Set-up phase: local spectral problems and the Galerkin chain.
+
+    `target` is the count per level-2 element (L_c of Section 5); levels >= 3
+    use `target_cc` (L_cc, default `target`) and, when `threshold_cc` > 0,
+    keep only the eigenvalues below it (B_cc, strategy 2 of Section 5), with
+    `target_cc` as the number of candidates."""
     if nlevels < 2:
         raise ValueError("need at least two levels")
+    if target_cc is None:
+        target_cc = target
     if workers is None:
         workers = os.cpu_count() or 1
     if A is None:
@@ -236,12 +258,13 @@ def build_hierarchy(perm, grid: Grid, nlevels: int, target: int, sub: int = 8, a
             return _payload(h_all[d][:, d]), _payload(g_all[d][:, d])
 
         mup = kids.shape[0]
-        res = _solve_all(mup, getl, target, CLUSTER_EXTRA, workers)
+        res = _solve_all(mup, getl, target_cc, CLUSTER_EXTRA, workers)
         gerr = 0.0
         for e in range(mup):
             g = _dense(getl(e)[1])
             gerr = max(gerr, float(np.max(np.abs(g - np.eye(g.shape[0])))))
-        nk = np.array([cluster_cut(w, target) for (w, _) in res], dtype=np.int64)
+        nk = np.array([cluster_cut(w, threshold_target(w, target_cc, threshold_cc)) for (w, _) in res],
+                      dtype=np.int64)
         offs = np.concatenate([[0], np.cumsum(nk)])
         rows, cols, vals = [], [], []
         for e, (w, v) in enumerate(res):

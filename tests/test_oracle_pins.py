@@ -11,7 +11,7 @@ import pytest
 import scipy.linalg as sla
 import scipy.sparse as sp
 
-from oracle import Grid, assemble, build_hierarchy, cluster_cut, Preconditioner, pcg
+from oracle import Grid, assemble, build_hierarchy, cluster_cut, threshold_target, Preconditioner, pcg
 from oracle.assembly import transmissibilities, normalized_perm, element_cells, neumann_local
 from oracle.smoothers import FineIC, CoarseBlockIC
 from oracle.spectral import _children
@@ -427,3 +427,41 @@ def test_paper_ladder_on_homogeneous_element():
     for c in cuts:
         assert c in clean
         assert cluster_cut(np.asarray(lam), c) == c
+
+
+# --------------------------------------------------------------------------
+# Section 5: coarse-coarse counts L_cc and strategy 2 (threshold B_cc)
+
+def _full_level2(levels=3, **kw):
+    # sub = 4 and 64 vectors per level-2 element: W_c = W_h, so eq. spectral cc
+    # on a level-3 element of 8^3 cells is the fine Neumann problem there,
+    # whose spectrum is the DCT ladder of an 8^3 block
+    g = Grid.unit_cube(8)
+    return build_hierarchy(np.ones(g.shape), g, levels, 64, sub=4, agg=2, workers=1, **kw)
+
+
+def test_coarse_coarse_spectrum_with_full_level2_space():
+    h = _full_level2(target_cc=10)
+    assert list(h.level(2).nkeep) == [64] * 8
+    ref = _dct_ladder(8)
+    assert np.allclose(h.level(3).lam[0][:14], ref[:14], rtol=0, atol=1e-12)
+    assert list(h.level(3).nkeep) == [11]      # L_cc = 10 cuts the cluster 8..10: grows to 11
+
+
+@pytest.mark.parametrize("b_between,expect", [((0, 1), 1), ((3, 4), 4), ((7, 8), 8)])
+def test_threshold_strategy_counts_ladder(b_between, expect):
+    # B_cc placed between two rungs of the ladder keeps every eigenvalue below it
+    ref = _dct_ladder(8)
+    lo, hi = b_between
+    B = 0.5 * (ref[lo] + ref[hi])
+    h = _full_level2(target_cc=10, threshold_cc=B)
+    assert list(h.level(3).nkeep) == [expect]
+
+
+def test_threshold_strategy_caps_at_candidates():
+    # more eigenvalues below B than candidates: L_cc = 4 of them, a clean cut
+    ref = _dct_ladder(8)
+    h = _full_level2(target_cc=4, threshold_cc=0.5 * (ref[10] + ref[11]))
+    assert list(h.level(3).nkeep) == [4]
+    assert threshold_target(ref, 4, 0.0) == 4            # strategy 1
+    assert threshold_target(ref, 4, 1e-300) == 1         # never below one vector
