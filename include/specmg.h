@@ -64,12 +64,16 @@ typedef struct {
 } specmg_grid;
 
 /* Options.  levels >= 2 is the number of grids (Algorithm 1 has three);
- * eigs_per_subdomain is the target count of eigenvectors kept per element at
- * every coarse level (strategy 1 of Section 5), grown or shrunk by at most 3
- * so that no cluster of equal eigenvalues is split (relative gap
- * cluster_rtol).  nu is the number of smoothing sweeps (only 1, the paper's
- * value, is supported).  eig_tol is the residual tolerance of the local
- * eigensolves relative to the spectral radius of the local pencil. */
+ * eigs_per_subdomain (1..8) is the target count of eigenvectors kept per
+ * level-2 element (L_c, strategy 1 of Section 5), grown or shrunk by at most
+ * 3 so that no cluster of equal eigenvalues is split (relative gap
+ * cluster_rtol).  Levels >= 3 use eigs_coarse (L_cc) the same way, or, when
+ * eig_threshold_coarse > 0, keep the eigenvectors whose eigenvalues lie below
+ * that threshold (B_cc, strategy 2 of Section 5; at least one, at most
+ * eigs_coarse, then the cluster rule).  Each level's arrays are padded to its
+ * own width, target + 3.  nu is the number of smoothing sweeps (only 1, the
+ * paper's value, is supported).  eig_tol is the residual tolerance of the
+ * local eigensolves relative to the spectral radius of the local pencil. */
 typedef struct {
     int32_t levels;
     int32_t eigs_per_subdomain;
@@ -90,6 +94,11 @@ typedef struct {
                                 eig_tol); an element that does not reach it
                                 within 4 Chebyshev cycles falls back to the
                                 exact solve (eig_tol) from the cold start */
+    int32_t eigs_coarse;     /* L_cc, 0..10; 0 = eigs_per_subdomain.  With
+                                agg 4 and four or more levels at most 9 */
+    double eig_threshold_coarse; /* B_cc >= 0; 0 = fixed count eigs_coarse.
+                                Eigenvalues are those of eq. spectral cc with
+                                S-normalised bases (dimensionless) */
 } specmg_opts;
 
 /* Outcome of a solve.  iters counts products A p (one per CG iteration). */
@@ -137,19 +146,21 @@ int specmg_pcg_solve(specmg_ctx* ctx, const double* rhs_dev, double* x_dev, int3
 int specmg_apply_operator(specmg_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
 
 /* Set-up information: dims[l-1] = dim W_l for l = 1..levels, the element
- * counts per level, and the padded per-element width Lmax (the target count
- * plus 3).  Arrays must hold 8 entries. */
+ * counts per level, and widths[l-1] = the padded per-element width of level
+ * l (its target count plus 3; widths[0] = 1).  Arrays must hold 8 entries;
+ * any pointer may be NULL. */
 int specmg_get_info(specmg_ctx* ctx, int32_t* levels, int32_t* dims, int32_t* elems,
-                    int32_t* lmax, specmg_solve_info* setup_info);
+                    int32_t* widths, specmg_solve_info* setup_info);
 
 /* Copy one set-up array of coarse level `level` (2..levels) to host memory,
  * for inspection and tests.  `which`:
+ * With W = widths[level-1] and Wlo = widths[level-2] from specmg_get_info:
  *   0 nkeep   int32  [m]
- *   1 lambda  float64 [m][Lmax]       ascending local eigenvalues (padded with 0)
- *   2 basis   float64 level 2: [m][Lmax][512] columns of R_c^T per element,
- *             S-normalised; level >= 3: [m][Lmax][agg^3*Lmax] columns of R^T
- *   3 Adiag   float64 [m][Lmax][Lmax] diagonal blocks of A_l
- *   4 Aoff    float64 [m][3][Lmax][Lmax] blocks A_l(e, e + x|y|z)
+ *   1 lambda  float64 [m][W]          ascending local eigenvalues (padded with 0)
+ *   2 basis   float64 level 2: [m][W][512] columns of R_c^T per element,
+ *             S-normalised; level >= 3: [m][W][agg^3*Wlo] columns of R^T
+ *   3 Adiag   float64 [m][W][W] diagonal blocks of A_l
+ *   4 Aoff    float64 [m][3][W][W] blocks A_l(e, e + x|y|z)
  *   5 status  int32  [m]  Chebyshev cycles used by the local eigensolve, -1 if
  *             it stopped at the cycle cap
  * `bytes` must equal the array size; returns SPECMG_EINVAL otherwise. */

@@ -269,7 +269,7 @@ void launch_cnn_adam(float* theta, const float* grad, float* m1, float* m2, int6
                      float eps, float c1, float c2, uint16_t* theta16, hipStream_t s);
 void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
                    const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
-                   int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,
+                   int target, int nvec, double tol, double crtol, double thr, double* V, double* lam, int* nkeep,
                    double* Aint, double* zup, int* status, hipStream_t s);
 
 // dense coarsest factorization (k_dense.hip); np is a multiple of 32

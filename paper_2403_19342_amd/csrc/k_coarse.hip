@@ -69,7 +69,7 @@ __device__ void build_planes(int agg, int* pos, int* off) {
     __syncthreads();
 }
 
-constexpr int kMaxLc = 12;   // padded widths up to target 8 + 3
+constexpr int kMaxLc = 13;   // padded widths up to target 10 + 3
 
 // y_c = (A_l u)_c for row a of child element c; all block-row loads of the
 // thread are issued before the products
@@ -698,7 +698,9 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
         case 8: { constexpr int LP = 8; __VA_ARGS__; } break;     \
         case 9: { constexpr int LP = 9; __VA_ARGS__; } break;     \
         case 10: { constexpr int LP = 10; __VA_ARGS__; } break;   \
-        default: { constexpr int LP = 11; __VA_ARGS__; } break;   \
+        case 11: { constexpr int LP = 11; __VA_ARGS__; } break;   \
+        case 12: { constexpr int LP = 12; __VA_ARGS__; } break;   \
+        default: { constexpr int LP = 13; __VA_ARGS__; } break;   \
     }
 
 static int sweep_threads(const CoarseGeom& g) {
@@ -710,7 +712,7 @@ static int sweep_threads(const CoarseGeom& g) {
 template <typename T>
 void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const T* r, T* u, const Scalars* sc,
                           int check_done, hipStream_t s) {
-    if (g.L < 4 || g.L > 11 || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
+    if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
     SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
                                                0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
                                                (const T*)nullptr, u, sc, check_done));
@@ -720,7 +722,7 @@ void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const 
 template <typename T>
 void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* G,
                                 const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
-    if (g.L < 4 || g.L > 11 || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
+    if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
     SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
                                                1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
 }

@@ -228,7 +228,14 @@ __device__ bool chol_wave(const double* G, double* Rm, double* dinv, int* flag) 
 // Cluster rule on ascending values th[0..n-1] (n >= target+4 or all values):
 // keep `target`, grow to the end of a cluster of equal values up to
 // target+3, or shrink before the cluster when it runs past that cap.
-__device__ int cluster_cut_dev(const double* th, int n, int target, double rtol) {
+__device__ int cluster_cut_dev(const double* th, int n, int target, double rtol, double thr) {
+    if (thr > 0.0) {
+        // threshold rule (strategy 2 of Section 5): the eigenvalues below
+        // thr, at least one and at most target, then the cluster rule
+        int below = 0;
+        for (int j = 0; j < n; ++j) below += th[j] < thr ? 1 : 0;
+        target = below < 1 ? 1 : (below < target ? below : target);
+    }
     if (target >= n) return n;
     auto same = [&](int k) { return th[k] - th[k - 1] <= rtol * fmax(fabs(th[k]), 1e-12); };
     int k = target;
@@ -436,16 +443,18 @@ struct Op2 {
     }
 };
 
-// Levels >= 3: block 7-point H_E on the agg^3 children of E, LP slots per
-// child; row = p * LP + a (child position p, slot a), one row per thread.
-// The row's own diagonal block stays in registers; the coupling rows of the
-// six directions are re-read (from L2) on every apply, the LP loads of a
-// direction issued together; a missing neighbour reads its own child with
-// weight zero.
-template <int LP>
+// Levels >= 3: block 7-point H_E on the agg^3 children of E, lp slots per
+// child (the padded width of the lower level, at most kMaxLP); row =
+// p * lp + a (child position p, slot a), one row per thread.  The row's own
+// diagonal block stays in registers; the coupling rows of the six directions
+// are re-read (from L2) on every apply, the loads of a direction issued
+// together; a missing neighbour reads its own child with weight zero.
+constexpr int kMaxLP = 13;   // lower-level widths up to target 10 + 3
+
 struct OpUp {
-    const double* Aoff;   // [m_lo][3][LP][LP]
-    double hd[LP];        // H_d[c][a][0..LP-1]
+    const double* Aoff;   // [m_lo][3][lp][lp]
+    double hd[kMaxLP];    // H_d[c][a][0..lp-1], zero beyond lp
+    int lp;
     int c, a, p;          // child element, slot, child position in E
     int q[3];             // child coordinates inside E
     int cstep[3];         // element-index steps of the lower grid
@@ -457,9 +466,11 @@ struct OpUp {
         for (int j = 0; j < M; ++j) out[0][j] = 0.0;
         if (!valid) return;
 #pragma unroll
-        for (int b = 0; b < LP; ++b) {
+        for (int b = 0; b < kMaxLP; ++b) {
+            if (b < lp) {
 #pragma unroll
-            for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * LP + b];
+                for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * lp + b];
+            }
         }
 #pragma unroll 1
         for (int d = 0; d < 6; ++d) {
@@ -472,15 +483,17 @@ struct OpUp {
             const int pn = in ? ((d & 1) ? p + ps : p - ps) : p;
             const double msk = in ? 1.0 : 0.0;
             // + direction: A(c, cn)[a][b] = Aoff[c][ax][a][b]; - direction: Aoff[cn][ax][b][a]
-            const size_t base = (d & 1) ? (((size_t)c * 3 + ax) * LP + a) * LP : (((size_t)cn * 3 + ax) * LP) * LP + a;
-            const int st = (d & 1) ? 1 : LP;
-            double h[LP];
+            const size_t base = (d & 1) ? (((size_t)c * 3 + ax) * lp + a) * lp : (((size_t)cn * 3 + ax) * lp) * lp + a;
+            const int st = (d & 1) ? 1 : lp;
+            double h[kMaxLP];
 #pragma unroll
-            for (int b = 0; b < LP; ++b) h[b] = Aoff[base + (size_t)b * st] * msk;
+            for (int b = 0; b < kMaxLP; ++b) h[b] = b < lp ? Aoff[base + (size_t)b * st] * msk : 0.0;
 #pragma unroll
-            for (int b = 0; b < LP; ++b) {
+            for (int b = 0; b < kMaxLP; ++b) {
+                if (b < lp) {
 #pragma unroll
-                for (int j = 0; j < M; ++j) out[0][j] += h[b] * Y[j * ld + pn * LP + b];
+                    for (int j = 0; j < M; ++j) out[0][j] += h[b] * Y[j * ld + pn * lp + b];
+                }
             }
         }
     }
@@ -530,13 +543,20 @@ __device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, 
 // Rayleigh-Ritz on the orthonormal LDS block Y: X = Y Q (also left in
 // LDS), AX = A X, sh.th ascending.  A Y is dead while the small
 // eigenproblem runs; A X is formed afresh from X.
+// With nval < M the columns nval.. of Y are zero: their diagonal entries of
+// the projected matrix are set to pad (above the spectrum), so that they
+// sort last and their Ritz vectors stay zero.
 template <int M, int R, class OP>
 __device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
-                              double (&AX)[R][M], EigShared<M>& sh) {
+                              double (&AX)[R][M], EigShared<M>& sh, int nval = M, double pad = 0.0) {
     {
         double AY[R][M];
         op.template apply<M>(Y, ld, AY);
         gram_lds_reg<M, R>(Y, ld, n, AY, sh.G, sh.red);
+    }
+    if (nval < M) {
+        if ((int)threadIdx.x < M && (int)threadIdx.x >= nval) sh.G[threadIdx.x * M + threadIdx.x] = pad;
+        __syncthreads();
     }
     jacobi_eig<M>(sh.G, sh.Q, sh.th, sh.scr, sh.iscr);
     load_block<M, R>(Y, ld, n, X);
@@ -555,7 +575,7 @@ __device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X
 // through their eigenvalues (error <= residual^2 / gap), so sqrt(tol)*bnd.
 template <int M, int R, class OP>
 __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M], double (&AX)[R][M],
-                      double bnd, int need, double tol, int target, double crtol, EigShared<M>& sh,
+                      double bnd, int need, double tol, int target, double crtol, double thr, EigShared<M>& sh,
                       int max_cycles = kMaxCycles) {
     store_block<M, R>(Y, ld, n, X);
     __syncthreads();
@@ -570,7 +590,7 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
                 for (int j = 0; j < M; ++j) Rs[r][j] = AX[r][j] - sh.th[j] * X[r][j];
             colnorm2<M, R>(Rs, sh.nrm, sh.red);
         }
-        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol, thr);
         bool ok = true;
         for (int j = 0; j < need; ++j) ok = ok && (sqrt(sh.nrm[j]) <= (j < nk ? tol : sqrt(tol)) * bnd);
         if (ok) return cyc;
@@ -680,7 +700,7 @@ __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restri
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
     int cyc = -1, spent = 0;
     if (warm) {
-        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, sh, kWarmCycles);
+        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, 0.0, sh, kWarmCycles);
         const bool fb = cyc < 0;
         if (fb) {
             spent = kWarmCycles + 1;
@@ -695,12 +715,12 @@ __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restri
         __syncthreads();
     }
     if (cyc < 0) {
-        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, sh);
+        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, 0.0, sh);
         if (cyc >= 0) cyc += spent;
     }
 
     if (threadIdx.x == 0) {
-        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol, 0.0);
         sh.flag = nk;
         nkeep[e] = nk;
         status[e] = cyc;
@@ -748,26 +768,28 @@ __global__ void k_build_hd(CoarseGeom lo, const double* __restrict__ Aint, const
 }
 
 // level >= 3 kernel: one workgroup per parent element E, one thread per row
-// of H_E (blockDim = agg^3 * LP rounded up to whole wavefronts, <= 768)
-template <int M, int LP>
+// of H_E (blockDim = agg^3 * lo.L rounded up to whole wavefronts, <= 768).
+// thr > 0 selects the kept count by the threshold rule (see cluster_cut_dev).
+template <int M>
 __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Hd,
                                                 const double* __restrict__ Aoff,
                                                 const int* __restrict__ nkeep_lo,
                                                 const double* __restrict__ zlo, int target, double tol,
-                                                double crtol, double* __restrict__ V,
+                                                double crtol, double thr, double* __restrict__ V,
                                                 double* __restrict__ lam, int* __restrict__ nkeep,
                                                 double* __restrict__ Aint, double* __restrict__ zup,
                                                 int* __restrict__ status) {
     extern __shared__ double dyn[];
     __shared__ EigShared<M> sh;
     const int E = blockIdx.x;
-    const int agg = lo.agg, Lu = up.L;
+    const int agg = lo.agg, Lu = up.L, LP = lo.L;
     const int n = agg * agg * agg * LP;
     const int ld = n | 1;
     const int Ex = E % up.mx, Ey = (E / up.mx) % up.my, Ez = E / (up.mx * up.my);
     const int row = threadIdx.x;
-    OpUp<LP> op;
+    OpUp op;
     op.Aoff = Aoff;
+    op.lp = LP;
     const int rr = row < n ? row : n - 1;
     const int p = rr / LP, a = rr % LP;
     const int qx = p % agg, qy = (p / agg) % agg, qz = p / (agg * agg);
@@ -784,12 +806,12 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     op.agg = agg;
     op.valid = row < n && a < nkeep_lo[c];
 #pragma unroll
-    for (int b = 0; b < LP; ++b) op.hd[b] = Hd[((size_t)c * LP + a) * LP + b];
+    for (int b = 0; b < kMaxLP; ++b) op.hd[b] = b < LP ? Hd[((size_t)c * LP + a) * LP + b] : 0.0;
     // Gershgorin bound: absolute row sum of H_E
     double rs = 0.0;
     if (op.valid) {
 #pragma unroll
-        for (int b = 0; b < LP; ++b) rs += fabs(op.hd[b]);
+        for (int b = 0; b < kMaxLP; ++b) rs += fabs(op.hd[b]);
         for (int d = 0; d < 6; ++d) {
             const int ax = d >> 1;
             const int qa = op.q[ax];
@@ -802,29 +824,49 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
         }
     }
     const double bnd = block_max(rs, sh.misc);
-    // start block: the constant function, smooth weights of the children's
-    // constant modes, and noise on every kept slot
+    // dimension of H_E (the kept slots of the children) and the compact
+    // index of this row among them
+    int nval = 0, ci = a;
+    for (int pp = 0; pp < agg * agg * agg; ++pp) {
+        const int c2 = (Ex * agg + pp % agg) + lo.mx * ((Ey * agg + (pp / agg) % agg) + lo.my * (Ez * agg + pp / (agg * agg)));
+        const int k2 = nkeep_lo[c2];
+        nval += k2;
+        if (pp < p) ci += k2;
+    }
     const double zr = op.valid ? zlo[(size_t)c * LP + a] : 0.0;
     double X[1][M], AX[1][M];
-    const double pa = 3.14159265358979323846 / agg;
-    const double az = fabs(zr) + 1e-300;
+    int cyc = 0;
+    if (nval <= M) {
+        // the block can hold the whole space: unit vectors and one
+        // Rayleigh-Ritz step give the exact eigenpairs
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
-        if (j == 0) v = zr;
-        else if (a == 0)
-            v += zr * cos(pa * kModes[j & 15][0] * (qx + 0.5)) * cos(pa * kModes[j & 15][1] * (qy + 0.5)) *
-                 cos(pa * kModes[j & 15][2] * (qz + 0.5));
-        X[0][j] = op.valid ? v : 0.0;
+        for (int j = 0; j < M; ++j) X[0][j] = (op.valid && ci == j) ? 1.0 : 0.0;
+        store_block<M, 1>(dyn, ld, n, X);
+        __syncthreads();
+        rayleigh_ritz<M, 1>(op, dyn, ld, n, X, AX, sh, nval, 2.0 * bnd + 1.0);
+    } else {
+        // start block: the constant function, smooth weights of the
+        // children's constant modes, and noise on every kept slot
+        const double pa = 3.14159265358979323846 / agg;
+        const double az = fabs(zr) + 1e-300;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
+            if (j == 0) v = zr;
+            else if (a == 0)
+                v += zr * cos(pa * kModes[j & 15][0] * (qx + 0.5)) * cos(pa * kModes[j & 15][1] * (qy + 0.5)) *
+                     cos(pa * kModes[j & 15][2] * (qz + 0.5));
+            X[0][j] = op.valid ? v : 0.0;
+        }
+        const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
+        cyc = chefsi<M, 1>(op, dyn, ld, n, X, AX, bnd, need, tol, target, crtol, thr, sh);
     }
-    const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
-    const int cyc = chefsi<M, 1>(op, dyn, ld, n, X, AX, bnd, need, tol, target, crtol, sh);
     if (threadIdx.x == 0) {
-        const int nk = cluster_cut_dev(sh.th, M, target, crtol);
+        const int nk = cluster_cut_dev(sh.th, nval < M ? nval : M, target, crtol, thr);
         sh.flag = nk;
         nkeep[E] = nk;
         status[E] = cyc;
-        for (int b = 0; b < Lu; ++b) lam[(size_t)E * Lu + b] = sh.th[b];
+        for (int b = 0; b < Lu; ++b) lam[(size_t)E * Lu + b] = b < nval ? sh.th[b] : 0.0;
     }
     __syncthreads();
     const int nk = sh.flag;
@@ -875,34 +917,31 @@ void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, doub
                                                ws_fb));
 }
 
-// block size M and slot width LP = target + 3 are compile-time per target
-#define SPECMG_T_DISPATCH(TV, ...)                                        \
-    switch (TV) {                                                         \
-        case 1: { constexpr int M = 10, LP = 4; __VA_ARGS__; } break;    \
-        case 2: { constexpr int M = 10, LP = 5; __VA_ARGS__; } break;    \
-        case 3: { constexpr int M = 10, LP = 6; __VA_ARGS__; } break;    \
-        case 4: { constexpr int M = 10, LP = 7; __VA_ARGS__; } break;    \
-        case 5: { constexpr int M = 12, LP = 8; __VA_ARGS__; } break;    \
-        case 6: { constexpr int M = 12, LP = 9; __VA_ARGS__; } break;    \
-        case 7: { constexpr int M = 14, LP = 10; __VA_ARGS__; } break;   \
-        default: { constexpr int M = 14, LP = 11; __VA_ARGS__; } break;  \
-    }
-
 void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,
                    const double* Aofflo, const int* nkeep_lo, const double* zlo, double* Hd_work,
-                   int target, int nvec, double tol, double crtol, double* V, double* lam, int* nkeep,
+                   int target, int nvec, double tol, double crtol, double thr, double* V, double* lam, int* nkeep,
                    double* Aint, double* zup, int* status, hipStream_t s) {
     hipLaunchKernelGGL(k_build_hd, dim3(lo.m), dim3(128), 0, s, lo, Aint_lo, Dlo, Hd_work);
     const int n = lo.agg * lo.agg * lo.agg * lo.L;
     const int threads = (n + 63) / 64 * 64;
-    if (lo.L != target + 3 || threads > 768 || target < 1 || target > 8) throw HipError{hipErrorInvalidValue, "eig_up shape"};
+    if (up.L != target + 3 || lo.L > kMaxLP || threads > 768 || target < 1 || target > 10 || nvec < target + 6)
+        throw HipError{hipErrorInvalidValue, "eig_up shape"};
     const size_t shmem = (size_t)nvec * (n | 1) * sizeof(double);
-    SPECMG_T_DISPATCH(target, if (nvec != M) throw HipError{hipErrorInvalidValue, "eig_up block size"};
-                      hipFuncSetAttribute((const void*)k_eig_up<M, LP>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-                      hipLaunchKernelGGL((k_eig_up<M, LP>), dim3(up.m), dim3(threads), shmem, s, lo, up, Hd_work,
-                                         Aofflo, nkeep_lo, zlo, target, tol, crtol, V, lam, nkeep, Aint, zup,
-                                         status));
+    switch (nvec) {
+#define SPECMG_EIG_UP(MV)                                                                                      \
+    case MV:                                                                                                   \
+        hipFuncSetAttribute((const void*)k_eig_up<MV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem); \
+        hipLaunchKernelGGL((k_eig_up<MV>), dim3(up.m), dim3(threads), shmem, s, lo, up, Hd_work, Aofflo,       \
+                           nkeep_lo, zlo, target, tol, crtol, thr, V, lam, nkeep, Aint, zup, status);           \
+        break;
+        SPECMG_EIG_UP(10)
+        SPECMG_EIG_UP(12)
+        SPECMG_EIG_UP(14)
+        SPECMG_EIG_UP(16)
+#undef SPECMG_EIG_UP
+        default:
+            throw HipError{hipErrorInvalidValue, "eig_up block size"};
+    }
 }
 
 }  // namespace specmg

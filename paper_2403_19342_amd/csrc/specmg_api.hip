@@ -81,7 +81,9 @@ constexpr int kReplacePeriod = 25;     // FP32 V-cycle: iterations between resid
 struct specmg_ctx {
     specmg_grid grid{};
     specmg_opts opts{};
-    int levels = 0, target = 0, L = 0, nvec = 0;
+    int levels = 0, target = 0, L = 0, nvec = 0;          // level 2 (L: padded width)
+    int target_cc = 0, Lcc = 0, nvec_cc = 0;               // levels >= 3
+    double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
     int fp32 = 0;
     int64_t n = 0;
     FineGeom fg{};
@@ -373,12 +375,13 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         Level& up = c->lev[li];
         const int agg = G.agg;
         up.l = li + 2;
-        up.L = L;
+        const int Lu = c->Lcc;
+        up.L = Lu;
         up.g.mx = lo.g.mx / agg;
         up.g.my = lo.g.my / agg;
         up.g.mz = lo.g.mz / agg;
         up.g.m = up.g.mx * up.g.my * up.g.mz;
-        up.g.L = L;
+        up.g.L = Lu;
         up.rows = agg * agg * agg * lo.L;
         lo.g.agg = agg;
         lo.g.px = up.g.mx;
@@ -388,24 +391,24 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         const int m = up.g.m;
         up.nkeep = c->alloc<int>(m);
         up.status = c->alloc<int>(m);
-        up.lam = c->alloc<double>((size_t)m * L);
-        up.basis = c->alloc<double>((size_t)m * L * up.rows);
-        up.Aint = c->alloc<double>((size_t)m * L * L);
-        up.D = c->alloc<double>((size_t)m * 6 * L * L);
-        up.Aoff = c->alloc<double>((size_t)m * 3 * L * L);
-        up.Ad = c->alloc<double>((size_t)m * L * L);
-        up.z = c->alloc<double>((size_t)m * L);
-        double* hd = c->alloc<double>((size_t)lo.g.m * L * L);
-        launch_eig_up(lo.g, up.g, lo.Aint, lo.D, lo.Aoff, lo.nkeep, lo.z, hd, c->target, c->nvec, tol, crtol,
-                      up.basis, up.lam, up.nkeep, up.Aint, up.z, up.status, s);
+        up.lam = c->alloc<double>((size_t)m * Lu);
+        up.basis = c->alloc<double>((size_t)m * Lu * up.rows);
+        up.Aint = c->alloc<double>((size_t)m * Lu * Lu);
+        up.D = c->alloc<double>((size_t)m * 6 * Lu * Lu);
+        up.Aoff = c->alloc<double>((size_t)m * 3 * Lu * Lu);
+        up.Ad = c->alloc<double>((size_t)m * Lu * Lu);
+        up.z = c->alloc<double>((size_t)m * Lu);
+        double* hd = c->alloc<double>((size_t)lo.g.m * lo.L * lo.L);
+        launch_eig_up(lo.g, up.g, lo.Aint, lo.D, lo.Aoff, lo.nkeep, lo.z, hd, c->target_cc, c->nvec_cc, tol, crtol,
+                      c->thr_cc, up.basis, up.lam, up.nkeep, up.Aint, up.z, up.status, s);
         launch_galerkin_up(lo.g, up.g, lo.D, lo.Aoff, up.basis, up.nkeep, up.D, up.Aoff, s);
         launch_assemble_diag(up.g, up.Aint, up.D, up.Ad, s);
     }
     // ---- smoothers of the non-coarsest coarse levels
     for (int li = 0; li < levels - 2; ++li) {
         Level& lv = c->lev[li];
-        lv.Dinv = c->alloc<double>((size_t)lv.g.m * L * L);
-        lv.G = c->alloc<double>((size_t)lv.g.m * 6 * L * L);
+        lv.Dinv = c->alloc<double>((size_t)lv.g.m * lv.L * lv.L);
+        lv.G = c->alloc<double>((size_t)lv.g.m * 6 * lv.L * lv.L);
         launch_blockic_setup(lv.g, lv.Ad, lv.Aoff, lv.nkeep, lv.Dinv, lv.G, c->dflag + 2, s);
     }
     // ---- host copies of the kept counts, unconverged eigensolves
@@ -424,6 +427,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     {
         Level& top = c->lev.back();
         const int m = top.g.m;
+        const int L = top.L;
         std::vector<int> cmap, cinv((size_t)m * L, -1);
         for (int e = 0; e < m; ++e)
             for (int a = 0; a < top.nkeep_h[e]; ++a) {
@@ -481,8 +485,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     if (c->fp32) {
         for (size_t li = 0; li < c->lev.size(); ++li) {
             Level& lv = c->lev[li];
-            const size_t LL = (size_t)L * L;
-            const size_t nb = (size_t)lv.g.m * L * lv.rows;
+            const size_t LL = (size_t)lv.L * lv.L;
+            const size_t nb = (size_t)lv.g.m * lv.L * lv.rows;
             lv.basis32 = c->alloc<float>(nb);
             launch_convert<double, float>(lv.basis, lv.basis32, (int64_t)nb, s);
             lv.Ad32 = c->alloc<float>(lv.g.m * LL);
@@ -499,7 +503,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     }
     // ---- vectors
     for (auto& lv : c->lev) {
-        const size_t nv = (size_t)lv.g.m * L;
+        const size_t nv = (size_t)lv.g.m * lv.L;
         lv.r = c->alloc<double>(nv);
         lv.u = c->alloc<double>(nv);
         lv.e = c->alloc<double>(nv);
@@ -573,6 +577,12 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
         return fail(SPECMG_EINVAL, "warm_start CNN needs cnn_weights");
     if (opts->warm_start == SPECMG_WS_CNN && (opts->eigs_per_subdomain & 1))
         return fail(SPECMG_EINVAL, "warm_start CNN needs an even eigs_per_subdomain");
+    const int tcc = opts->eigs_coarse > 0 ? opts->eigs_coarse : opts->eigs_per_subdomain;
+    if (opts->eigs_coarse < 0 || tcc > 10) return fail(SPECMG_EINVAL, "eigs_coarse must be in [0, 10]");
+    if (G.agg == 4 && opts->levels >= 4 && tcc > 9)
+        return fail(SPECMG_EINVAL, "agg 4 with four or more levels needs eigs_coarse <= 9");
+    if (!(opts->eig_threshold_coarse >= 0.0) || !std::isfinite(opts->eig_threshold_coarse))
+        return fail(SPECMG_EINVAL, "eig_threshold_coarse must be finite and >= 0");
     long div = 8;
     for (int l = 2; l < opts->levels; ++l) div *= G.agg;
     if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.nx % div || G.ny % div || G.nz % div)
@@ -585,6 +595,10 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     c->target = opts->eigs_per_subdomain;
     c->L = c->target + 3;
     c->nvec = nvec_for(c->target);
+    c->target_cc = tcc;
+    c->Lcc = tcc + 3;
+    c->nvec_cc = nvec_for(tcc);
+    c->thr_cc = opts->eig_threshold_coarse;
     c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
     int rc;
     try {
@@ -774,11 +788,15 @@ extern "C" int specmg_pcg_solve(specmg_ctx* c, const double* rhs, double* x, int
     }
 }
 
-extern "C" int specmg_get_info(specmg_ctx* c, int32_t* levels, int32_t* dims, int32_t* elems, int32_t* lmax,
+extern "C" int specmg_get_info(specmg_ctx* c, int32_t* levels, int32_t* dims, int32_t* elems, int32_t* widths,
                                specmg_solve_info* setup_info) {
     if (!c) return fail(SPECMG_EINVAL, "null context");
     if (levels) *levels = c->levels;
-    if (lmax) *lmax = c->L;
+    if (widths) {
+        for (int i = 0; i < 8; ++i) widths[i] = 0;
+        widths[0] = 1;
+        for (size_t li = 0; li < c->lev.size() && li + 1 < 8; ++li) widths[li + 1] = c->lev[li].L;
+    }
     if (dims) {
         for (int i = 0; i < 8; ++i) dims[i] = 0;
         dims[0] = (int)c->n;

@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
                 ("nu", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("cnn_weights", ctypes.c_void_p),
                 ("eig_tol", ctypes.c_double), ("cluster_rtol", ctypes.c_double),
-                ("ws_resid_tol", ctypes.c_double)]
+                ("ws_resid_tol", ctypes.c_double), ("eigs_coarse", ctypes.c_int32),
+                ("eig_threshold_coarse", ctypes.c_double)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -80,7 +81,7 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_apply_operator.argtypes = [vp, vp, vp, vp]
     lib.specmg_apply_operator.restype = ctypes.c_int
     lib.specmg_get_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32 * 8), ctypes.POINTER(i32 * 8),
-                                    ctypes.POINTER(i32), ctypes.POINTER(SolveInfo)]
+                                    ctypes.POINTER(i32 * 8), ctypes.POINTER(SolveInfo)]
     lib.specmg_get_info.restype = ctypes.c_int
     lib.specmg_copy_level.argtypes = [vp, i32, i32, vp, ctypes.c_size_t]
     lib.specmg_copy_level.restype = ctypes.c_int
@@ -152,7 +153,8 @@ class SpecMG:
 
     def __init__(self, perm, levels: int, eigs_per_subdomain: int, h: float | None = None,
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
-                 allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3):
+                 allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3,
+                 eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0):
         lib = load_library()
         import torch
         if perm.dim() != 3:
@@ -171,7 +173,8 @@ class SpecMG:
             if cnn_weights.numel() != lib.specmg_cnn_param_count(eigs_per_subdomain):
                 raise ValueError("cnn_weights has the wrong length for eigs_per_subdomain")
             ws, wp = WS_CNN, ctypes.c_void_p(cnn_weights.data_ptr())
-        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol)
+        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol,
+                         eigs_coarse, eig_threshold_coarse)
         ctx = ctypes.c_void_p()
         perm = perm.contiguous()
         rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
@@ -225,21 +228,21 @@ class SpecMG:
         lv = ctypes.c_int32()
         dims = (ctypes.c_int32 * 8)()
         elems = (ctypes.c_int32 * 8)()
-        lmax = ctypes.c_int32()
+        widths = (ctypes.c_int32 * 8)()
         si = SolveInfo()
         _check(_lib.specmg_get_info(self._ctx, ctypes.byref(lv), ctypes.byref(dims), ctypes.byref(elems),
-                                    ctypes.byref(lmax), ctypes.byref(si)))
+                                    ctypes.byref(widths), ctypes.byref(si)))
         return {"levels": lv.value, "dims": list(dims)[: lv.value], "elems": list(elems)[: lv.value],
-                "lmax": lmax.value, "setup": si.as_dict()}
+                "widths": list(widths)[: lv.value], "setup": si.as_dict()}
 
     def level_arrays(self, level: int) -> LevelArrays:
         inf = self.info()
         m = inf["elems"][level - 1]
-        L = inf["lmax"]
+        L = inf["widths"][level - 1]
         if level == 2:
             rows = 512
         else:
-            rows = self.grid.agg ** 3 * L
+            rows = self.grid.agg ** 3 * inf["widths"][level - 2]
         out = {}
         for which, name, dtype, shape in ((0, "nkeep", np.int32, (m,)), (1, "lam", np.float64, (m, L)),
                                           (2, "basis", np.float64, (m, L, rows)),

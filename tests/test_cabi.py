@@ -39,6 +39,8 @@ def test_binding_covers_header():
 @pytest.mark.parametrize("field,value,code", [
     ("sub", 4, -1), ("agg", 3, -1), ("nx", 36, -1), ("levels", 1, -1), ("eigs_per_subdomain", 0, -1),
     ("eigs_per_subdomain", 9, -1), ("nu", 2, -1), ("precision", 7, -1), ("hy", 0.5, -1),
+    ("eigs_coarse", 11, -1), ("eigs_coarse", -1, -1), ("eig_threshold_coarse", -1.0, -1),
+    ("eig_threshold_coarse", float("inf"), -1),
 ])
 def test_setup_rejects_bad_arguments(field, value, code):
     lib = _lib()
@@ -62,6 +64,11 @@ def test_null_arguments():
     assert lib.specmg_apply_precond(None, None, None, None) == -1
     assert lib.specmg_pcg_solve(None, None, None, 0, 1e-6, 10, None, None) == -1
     assert lib.specmg_apply_operator(None, None, None, None) == -1
+    # the binding's argument types accept the arrays it passes
+    i8 = ctypes.c_int32 * 8
+    from paper_2403_19342_amd.specmg import SolveInfo
+    assert lib.specmg_get_info(None, ctypes.byref(ctypes.c_int32()), ctypes.byref(i8()), ctypes.byref(i8()),
+                               ctypes.byref(i8()), ctypes.byref(SolveInfo())) == -1
     lib.specmg_destroy(None)
 
 

@@ -1,0 +1,88 @@
+"""Separate coarse-coarse counts (L_cc) and the threshold rule (B_cc,
+strategy 2 of Section 5) on the GPU against the FP64 oracle.
+
+Same tolerances as the other parity tests: kept counts bit-exact, kept
+eigenvalues 1e-11 absolute, P^{-1} r max(1e-10, 1e-15 / lambda_min+(A_L))
+relative, PCG iterations within +-1 and the solution within 1e-8.  Each
+threshold lies at least 1e-2 (relative) away from every eigenvalue of the
+oracle, so that both sides count the same eigenvalues below it.
+"""
+import numpy as np
+import pytest
+
+from oracle import Grid, build_hierarchy, Preconditioner, pcg
+from synth.fields import make_field, make_source, random_zero_mean
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (name, kind, seed, levels, eigs, agg, eigs_coarse, threshold)
+    ("gauss32_l3_cc8", "gauss", 1, 3, 4, 2, 8, 0.0),
+    ("incl32_l4_thr", "inclusions", 3, 4, 6, 2, 10, 1e-3),
+    ("chan32_l3_thr", "channels", 2, 3, 6, 4, 9, 1e-3),
+]
+
+
+def _both(kind, seed, levels, eigs, agg, cc, thr):
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm = make_field(kind, 32, seed)
+    g = Grid.unit_cube(32)
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1, target_cc=cc, threshold_cc=thr)
+    if thr > 0:
+        for l in range(3, levels + 1):
+            for lam in hier.level(l).lam:
+                assert np.min(np.abs(np.asarray(lam) - thr)) > 1e-2 * thr, "threshold too close to an eigenvalue"
+    ctx = SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, eigs_coarse=cc,
+                 eig_threshold_coarse=thr)
+    return perm, g, hier, ctx
+
+
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
+def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr):
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+    widths = ctx.info()["widths"]
+    assert widths[1] == eigs + 3 and all(w == cc + 3 for w in widths[2:])
+    for l in range(2, levels + 1):
+        lv = ctx.level_arrays(l)
+        ref = hier.level(l)
+        assert np.array_equal(lv.nkeep, ref.nkeep), f"kept counts differ at level {l}"
+        worst = max(float(np.max(np.abs(lv.lam[e, :k] - ref.lam[e][:k]))) for e, k in enumerate(ref.nkeep))
+        print(f"{name}: level {l} kept {list(ref.nkeep)[:8]} eig err {worst:.2e}")
+        assert worst < 1e-11
+
+
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
+def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr):
+    import torch
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+    pre = Preconditioner(hier)
+    wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
+    tol = max(1e-10, 1e-15 / wL[1])
+    for s in range(2):
+        r = random_zero_mean(perm.shape, 300 + s).reshape(-1)
+        z = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        ctx.apply_precond(to_dev(r), z)
+        torch.cuda.synchronize()
+        zg, zo = to_host(z), pre.apply(r)
+        zg -= zg.mean()
+        zo -= zo.mean()
+        err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+        print(f"{name}: P^-1 r rel err {err:.2e} (tol {tol:.1e})")
+        assert err < tol
+
+
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
+def test_pcg(name, kind, seed, levels, eigs, agg, cc, thr):
+    import torch
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+    b = make_source("corner", perm.shape).reshape(-1)
+    ref = pcg(hier.A, b, Preconditioner(hier).apply, tol=1e-6)
+    x = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    rc, info = ctx.pcg_solve(to_dev(b), x, tol=1e-6)
+    xg = to_host(x)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"{name}: iters gpu {info.iters} oracle {ref.iters}, rel err {err:.2e}")
+    assert rc == 0 and info.converged
+    assert abs(info.iters - ref.iters) <= 1
+    assert err <= 1e-8
