@@ -451,25 +451,31 @@ struct Op2 {
 // together; a missing neighbour reads its own child with weight zero.
 constexpr int kMaxLP = 13;   // lower-level widths up to target 10 + 3
 
+// LPT > 0: the width is a compile-time constant; LPT = 0: run-time width lp
+// (arrays sized for kMaxLP, slots beyond lp masked)
+template <int LPT>
 struct OpUp {
+    static constexpr int kW = LPT > 0 ? LPT : kMaxLP;
     const double* Aoff;   // [m_lo][3][lp][lp]
-    double hd[kMaxLP];    // H_d[c][a][0..lp-1], zero beyond lp
-    int lp;
+    double hd[kW];        // H_d[c][a][0..lp-1], zero beyond lp
+    int lp_rt;
     int c, a, p;          // child element, slot, child position in E
     int q[3];             // child coordinates inside E
     int cstep[3];         // element-index steps of the lower grid
     int agg;
     bool valid;           // kept slot of an existing child row
+    __device__ __forceinline__ int lp() const { return LPT > 0 ? LPT : lp_rt; }
     template <int M>
     __device__ __forceinline__ void apply(const double* Y, int ld, double (&out)[1][M]) const {
+        const int w = lp();
 #pragma unroll
         for (int j = 0; j < M; ++j) out[0][j] = 0.0;
         if (!valid) return;
 #pragma unroll
-        for (int b = 0; b < kMaxLP; ++b) {
-            if (b < lp) {
+        for (int b = 0; b < kW; ++b) {
+            if (b < w) {
 #pragma unroll
-                for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * lp + b];
+                for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * w + b];
             }
         }
 #pragma unroll 1
@@ -483,16 +489,16 @@ struct OpUp {
             const int pn = in ? ((d & 1) ? p + ps : p - ps) : p;
             const double msk = in ? 1.0 : 0.0;
             // + direction: A(c, cn)[a][b] = Aoff[c][ax][a][b]; - direction: Aoff[cn][ax][b][a]
-            const size_t base = (d & 1) ? (((size_t)c * 3 + ax) * lp + a) * lp : (((size_t)cn * 3 + ax) * lp) * lp + a;
-            const int st = (d & 1) ? 1 : lp;
-            double h[kMaxLP];
+            const size_t base = (d & 1) ? (((size_t)c * 3 + ax) * w + a) * w : (((size_t)cn * 3 + ax) * w) * w + a;
+            const int st = (d & 1) ? 1 : w;
+            double h[kW];
 #pragma unroll
-            for (int b = 0; b < kMaxLP; ++b) h[b] = b < lp ? Aoff[base + (size_t)b * st] * msk : 0.0;
+            for (int b = 0; b < kW; ++b) h[b] = b < w ? Aoff[base + (size_t)b * st] * msk : 0.0;
 #pragma unroll
-            for (int b = 0; b < kMaxLP; ++b) {
-                if (b < lp) {
+            for (int b = 0; b < kW; ++b) {
+                if (b < w) {
 #pragma unroll
-                    for (int j = 0; j < M; ++j) out[0][j] += h[b] * Y[j * ld + pn * lp + b];
+                    for (int j = 0; j < M; ++j) out[0][j] += h[b] * Y[j * ld + pn * w + b];
                 }
             }
         }
@@ -770,7 +776,7 @@ __global__ void k_build_hd(CoarseGeom lo, const double* __restrict__ Aint, const
 // level >= 3 kernel: one workgroup per parent element E, one thread per row
 // of H_E (blockDim = agg^3 * lo.L rounded up to whole wavefronts, <= 768).
 // thr > 0 selects the kept count by the threshold rule (see cluster_cut_dev).
-template <int M>
+template <int M, int LPT>
 __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, const double* __restrict__ Hd,
                                                 const double* __restrict__ Aoff,
                                                 const int* __restrict__ nkeep_lo,
@@ -782,14 +788,14 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     extern __shared__ double dyn[];
     __shared__ EigShared<M> sh;
     const int E = blockIdx.x;
-    const int agg = lo.agg, Lu = up.L, LP = lo.L;
+    const int agg = lo.agg, Lu = up.L, LP = LPT > 0 ? LPT : lo.L;
     const int n = agg * agg * agg * LP;
     const int ld = n | 1;
     const int Ex = E % up.mx, Ey = (E / up.mx) % up.my, Ez = E / (up.mx * up.my);
     const int row = threadIdx.x;
-    OpUp op;
+    OpUp<LPT> op;
     op.Aoff = Aoff;
-    op.lp = LP;
+    op.lp_rt = LP;
     const int rr = row < n ? row : n - 1;
     const int p = rr / LP, a = rr % LP;
     const int qx = p % agg, qy = (p / agg) % agg, qz = p / (agg * agg);
@@ -806,12 +812,12 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     op.agg = agg;
     op.valid = row < n && a < nkeep_lo[c];
 #pragma unroll
-    for (int b = 0; b < kMaxLP; ++b) op.hd[b] = b < LP ? Hd[((size_t)c * LP + a) * LP + b] : 0.0;
+    for (int b = 0; b < OpUp<LPT>::kW; ++b) op.hd[b] = b < LP ? Hd[((size_t)c * LP + a) * LP + b] : 0.0;
     // Gershgorin bound: absolute row sum of H_E
     double rs = 0.0;
     if (op.valid) {
 #pragma unroll
-        for (int b = 0; b < kMaxLP; ++b) rs += fabs(op.hd[b]);
+        for (int b = 0; b < OpUp<LPT>::kW; ++b) rs += fabs(op.hd[b]);
         for (int d = 0; d < 6; ++d) {
             const int ax = d >> 1;
             const int qa = op.q[ax];
@@ -927,21 +933,38 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
     if (up.L != target + 3 || lo.L > kMaxLP || threads > 768 || target < 1 || target > 10 || nvec < target + 6)
         throw HipError{hipErrorInvalidValue, "eig_up shape"};
     const size_t shmem = (size_t)nvec * (n | 1) * sizeof(double);
-    switch (nvec) {
-#define SPECMG_EIG_UP(MV)                                                                                      \
-    case MV:                                                                                                   \
-        hipFuncSetAttribute((const void*)k_eig_up<MV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem); \
-        hipLaunchKernelGGL((k_eig_up<MV>), dim3(up.m), dim3(threads), shmem, s, lo, up, Hd_work, Aofflo,       \
-                           nkeep_lo, zlo, target, tol, crtol, thr, V, lam, nkeep, Aint, zup, status);           \
-        break;
-        SPECMG_EIG_UP(10)
-        SPECMG_EIG_UP(12)
-        SPECMG_EIG_UP(14)
-        SPECMG_EIG_UP(16)
-#undef SPECMG_EIG_UP
-        default:
-            throw HipError{hipErrorInvalidValue, "eig_up block size"};
+    // compile-time widths for the pairs (block size, lower width) that occur
+    // when both levels have the same target; the run-time width otherwise
+#define SPECMG_EIG_UP(MV, LV)                                                                                    \
+    {                                                                                                            \
+        hipFuncSetAttribute((const void*)k_eig_up<MV, LV>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem); \
+        hipLaunchKernelGGL((k_eig_up<MV, LV>), dim3(up.m), dim3(threads), shmem, s, lo, up, Hd_work, Aofflo,       \
+                           nkeep_lo, zlo, target, tol, crtol, thr, V, lam, nkeep, Aint, zup, status);               \
+        return;                                                                                                  \
     }
+    const int key = nvec * 100 + lo.L;
+    switch (key) {
+        case 1004: SPECMG_EIG_UP(10, 4)
+        case 1005: SPECMG_EIG_UP(10, 5)
+        case 1006: SPECMG_EIG_UP(10, 6)
+        case 1007: SPECMG_EIG_UP(10, 7)
+        case 1208: SPECMG_EIG_UP(12, 8)
+        case 1209: SPECMG_EIG_UP(12, 9)
+        case 1410: SPECMG_EIG_UP(14, 10)
+        case 1411: SPECMG_EIG_UP(14, 11)
+        case 1612: SPECMG_EIG_UP(16, 12)
+        case 1613: SPECMG_EIG_UP(16, 13)
+        default: break;
+    }
+    switch (nvec) {
+        case 10: SPECMG_EIG_UP(10, 0)
+        case 12: SPECMG_EIG_UP(12, 0)
+        case 14: SPECMG_EIG_UP(14, 0)
+        case 16: SPECMG_EIG_UP(16, 0)
+        default: break;
+    }
+#undef SPECMG_EIG_UP
+    throw HipError{hipErrorInvalidValue, "eig_up block size"};
 }
 
 }  // namespace specmg

@@ -136,33 +136,6 @@ __device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restri
     }
 }
 
-// p = z + beta * pold on the haloed tile, together with kappa~
-template <int EX>
-__device__ __forceinline__ void load_halo_p(const FineGeom& g, const double* __restrict__ z,
-                                            const double* __restrict__ pold, double beta, int first,
-                                            double* dst, const double* __restrict__ kt, double* dk, int x0,
-                                            int y0, int z0) {
-    using TT = TileT<EX>;
-    constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
-    double vp[IT], vk[IT];
-    int pp[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        size_t gi;
-        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi, pp[it]);
-        vp[it] = in ? (first ? z[gi] : z[gi] + beta * pold[gi]) : 0.0;
-        vk[it] = in ? kt[gi] : 0.0;
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int h = threadIdx.x + it * TT::NT;
-        if (h < TT::NH) {
-            dst[pp[it]] = vp[it];
-            dk[pp[it]] = vk[it];
-        }
-    }
-}
-
 // (A u) at haloed index h
 template <int EX, typename T>
 __device__ __forceinline__ T apply_stencil(const T* U, const T* K, int h) {
@@ -614,40 +587,117 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     }
 }
 
-// p = z + beta pold (or p = z), x += alpha_x pold, q = A p, alpha = rz / p.q
-template <int EX>
-__global__ __launch_bounds__(64 * EX) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
-                                                      const double* __restrict__ zv,
-                                                      const double* __restrict__ pold,
-                                                      double* __restrict__ pnew, double* x,
-                                                      double* __restrict__ q, Scalars* sc, RedBuf rb,
-                                                      int first, int pbuf) {
-    using TT = TileT<EX>;
+// One CG step of the fused direction update: p = z + beta p_old (p = z on
+// the first iteration), q = A p, x += alpha_x p_old (the x update deferred
+// from the previous iteration) and the block sums of p.q.  A block owns 64 x
+// kSpY columns and marches kSpZ planes in z.  Each plane's p and kappa~ are
+// staged in a double-buffered LDS tile with a one-cell halo in x and y, so
+// p is formed once per cell; the z neighbours stay in registers, and the
+// next plane's values are loaded before the current plane's barrier.  Block
+// ids are remapped so that each XCD walks a contiguous range of tiles.
+constexpr int kSpY = 4, kSpZ = 8;
+
+__global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
+                                                       const double* __restrict__ zv,
+                                                       const double* __restrict__ pold,
+                                                       double* __restrict__ pnew, double* __restrict__ x,
+                                                       double* __restrict__ q, Scalars* sc, RedBuf rb, int first,
+                                                       int pbuf) {
     if (sc->done) return;
-    __shared__ double sP[TT::NHP];
-    __shared__ double sK[TT::NHP];
-    __shared__ double sred[EX];
-    int x0, y0, z0;
-    tile_origin(g, x0, y0, z0);
-    const double beta = sc->beta;
+    __shared__ double sp[2][kSpY + 2][66];
+    __shared__ double sk[2][kSpY + 2][66];
+    __shared__ double sred[kSpY];
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nb = gridDim.x * gridDim.y * gridDim.z;
+    int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int bx = b % gridDim.x, by = (b / gridDim.x) % gridDim.y, bz = b / (gridDim.x * gridDim.y);
+    const int xi = bx * 64 + lane, yi = by * kSpY + w, z0 = bz * kSpZ;
+    const bool in = xi < nx;
+    const int xc = in ? xi : nx - 1;
+    const double beta = first ? 0.0 : sc->beta;
     const double ax = first ? 0.0 : sc->alpha_x;
-    load_halo_p<EX>(g, zv, pold, beta, first, sP, kt, sK, x0, y0, z0);
-    __syncthreads();
-    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
+    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+    // halo duties: waves 0 and kSpY-1 also carry rows y0-1 and y0+kSpY,
+    // lanes 0 and 63 columns x0-1 and x0+64 (zero outside the domain)
+    const bool hrow_w = (w == 0 || w == kSpY - 1);
+    const int hy = (w == 0) ? yi - 1 : yi + 1;
+    const bool hyv = in && hrow_w && hy >= 0 && hy < ny;
+    const int hx = (lane == 0) ? xi - 1 : xi + 1;
+    const bool hcol_l = (lane == 0 || lane == 63);
+    const bool hxv = hcol_l && hx >= 0 && hx < nx;
+    const int hrow = (w == 0) ? 0 : kSpY + 1;
+    const int hcol = (lane == 0) ? 0 : 65;
+    size_t gi = (size_t)xc + sy * yi + sz * z0;
+    const size_t ghy = (size_t)xc + sy * (hyv ? hy : yi) + sz * z0;
+    const size_t ghx = (size_t)(hxv ? hx : xc) + sy * yi + sz * z0;
+    auto pval = [&](size_t i) { return first ? zv[i] : zv[i] + beta * pold[i]; };
+    double po = (in && !first) ? pold[gi] : 0.0;
+    double pc = in ? (first ? zv[gi] : zv[gi] + beta * po) : 0.0, kc = in ? kt[gi] : 0.0;
+    double pyh = hyv ? pval(ghy) : 0.0, kyh = hyv ? kt[ghy] : 0.0;
+    double pxh = hxv ? pval(ghx) : 0.0, kxh = hxv ? kt[ghx] : 0.0;
+    double pm = (in && z0 > 0) ? pval(gi - sz) : 0.0, km = (in && z0 > 0) ? kt[gi - sz] : 0.0;
     double pq = 0.0;
-    for (int zz = 0; zz < 8; ++zz) {
-        const int h = hidx<EX>(tx, ty, zz);
-        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const double p = sP[h];
-        const double qq = apply_stencil<EX, double>(sP, sK, h);
-        if (!first && ax != 0.0) x[gi] += ax * pold[gi];
-        pnew[gi] = p;
-        q[gi] = qq;
-        pq += p * qq;
+    for (int zz = 0; zz < kSpZ; ++zz, gi += sz) {
+        const int buf = zz & 1;
+        sp[buf][w + 1][lane + 1] = pc;
+        sk[buf][w + 1][lane + 1] = kc;
+        if (hrow_w) {
+            sp[buf][hrow][lane + 1] = pyh;
+            sk[buf][hrow][lane + 1] = kyh;
+        }
+        if (hcol_l) {
+            sp[buf][w + 1][hcol] = pxh;
+            sk[buf][w + 1][hcol] = kxh;
+        }
+        // the next plane, in flight across the barrier
+        const bool zp = z0 + zz + 1 < nz;
+        const size_t o = (size_t)(zz + 1) * sz;
+        const double pon = (in && zp && !first) ? pold[gi + sz] : 0.0;
+        const double pp = (in && zp) ? (first ? zv[gi + sz] : zv[gi + sz] + beta * pon) : 0.0;
+        const double kp = (in && zp) ? kt[gi + sz] : 0.0;
+        double pyh2 = 0.0, kyh2 = 0.0, pxh2 = 0.0, kxh2 = 0.0;
+        if (zz + 1 < kSpZ && zp) {
+            if (hyv) {
+                pyh2 = pval(ghy + o);
+                kyh2 = kt[ghy + o];
+            }
+            if (hxv) {
+                pxh2 = pval(ghx + o);
+                kxh2 = kt[ghx + o];
+            }
+        }
+        __syncthreads();
+        const double pxm = sp[buf][w + 1][lane], kxm = sk[buf][w + 1][lane];
+        const double pxp = sp[buf][w + 1][lane + 2], kxp = sk[buf][w + 1][lane + 2];
+        const double pym = sp[buf][w][lane + 1], kym = sk[buf][w][lane + 1];
+        const double pyp = sp[buf][w + 2][lane + 1], kyp = sk[buf][w + 2][lane + 1];
+        double a = harm(kc, kxm) * (pc - pxm);
+        a += harm(kc, kxp) * (pc - pxp);
+        a += harm(kc, kym) * (pc - pym);
+        a += harm(kc, kyp) * (pc - pyp);
+        a += harm(kc, km) * (pc - pm);
+        a += harm(kc, kp) * (pc - pp);
+        if (in) {
+            if (ax != 0.0) x[gi] += ax * po;
+            pnew[gi] = pc;
+            q[gi] = a;
+            pq += pc * a;
+        }
+        pm = pc;
+        km = kc;
+        pc = pp;
+        kc = kp;
+        po = pon;
+        pyh = pyh2;
+        kyh = kyh2;
+        pxh = pxh2;
+        kxh = kxh2;
     }
     double v[1] = {block_sum(pq, sred)};
     write_partials<1>(v, rb);
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
 }
 
 // y = A x  (resid = 0)   or   y = b - A x  (resid = 1)
@@ -943,9 +993,12 @@ void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const
     // final x update
     const int pbuf = first & 2 ? 1 : 0;
     const int f = first & 1;
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_spmv_pcg<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
-                                                kt, z, pold, pnew, x, q, sc, rb, f, pbuf));
-    launch_finalize(RS_PQ, g.ntiles, sc, rb, nullptr, 1, s);
+    if (g.ny % kSpY || g.nz % kSpZ) throw HipError{hipErrorInvalidValue, "spmv tiling"};
+    const dim3 grid((g.nx + 63) / 64, g.ny / kSpY, g.nz / kSpZ);
+    const int nblocks = (int)(grid.x * grid.y * grid.z);
+    if (nblocks > kMaxRedBlocks) throw HipError{hipErrorInvalidValue, "spmv grid too large for the reduction buffer"};
+    SPECMG_TIMED_LAUNCH(k_spmv_pcg, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f, pbuf);
+    launch_finalize(RS_PQ, nblocks, sc, rb, nullptr, 1, s);
 }
 
 void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
