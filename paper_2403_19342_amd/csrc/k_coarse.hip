@@ -118,7 +118,7 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
     return acc;
 }
 
-constexpr int kCoarseThreads = 256;
+constexpr int kCoarseThreads = 1024;   // upper bound; launches use agg^3 L rounded to waves
 constexpr int kMaxChildren = 64;   // agg <= 4
 constexpr int kMaxL = 16;
 
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     __syncthreads();
     if ((int)threadIdx.x < Lup) {
         double t = 0.0;
-        for (int ww = 0; ww < kCoarseThreads / 64; ++ww) t += sacc[ww][threadIdx.x];
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) t += sacc[ww][threadIdx.x];
         rup[(size_t)E * Lup + threadIdx.x] = (int)threadIdx.x < nk ? (T)t : T(0);
     }
     (void)sred;
@@ -326,15 +326,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
 constexpr int kCoarsestChunk = 8192;
 constexpr int kCoarsestRows = 16;
 
-template <typename T>
+template <typename T, int RW>
 __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* __restrict__ Pinv,
                                                    const int* __restrict__ cmap, const T* __restrict__ r,
                                                    T* __restrict__ e, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
     extern __shared__ double srz[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i0 = blockIdx.x * kCoarsestRows + w * 4;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int i0 = blockIdx.x * 4 * RW + w * RW;
+    double acc[RW];
+#pragma unroll
+    for (int qq = 0; qq < RW; ++qq) acc[qq] = 0.0;
     for (int c0 = 0; c0 < n; c0 += kCoarsestChunk) {
         const int cn = min(kCoarsestChunk, n - c0);
         if (c0) __syncthreads();
@@ -343,12 +345,12 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* _
         for (int j = lane; j < cn; j += 64) {
             const double v = srz[j];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < RW; ++q)
                 if (i0 + q < n) acc[q] += Pinv[(size_t)(i0 + q) * np + c0 + j] * v;
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < RW; ++q) {
         const double s = wave_sum(acc[q]);
         if (lane == 0 && i0 + q < n) e[cmap[i0 + q]] = (T)s;
     }
@@ -677,14 +679,18 @@ template <typename T>
 void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
                                   const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
                                   int check_done, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_resid_restrict<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, Ad, Aoff, r, u, V,
+    const int rows = g.agg * g.agg * g.agg * g.L;
+    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_coarse_resid_restrict<T>), dim3(g.M), dim3(th), 0, s, g, Ad, Aoff, r, u, V,
                        nkeep_up, Lup, rup, sc, check_done);
 }
 
 template <typename T>
 void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nkeep_up, int Lup, const T* eup,
                            const Scalars* sc, int check_done, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(kCoarseThreads), 0, s, g, u, V, nkeep_up, Lup, eup,
+    const int rows = g.agg * g.agg * g.agg * g.L;
+    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup,
                        sc, check_done);
 }
 
@@ -730,9 +736,14 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
 template <typename T>
 void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, const Scalars* sc,
                      int check_done, hipStream_t s) {
-    const int blocks = (n + kCoarsestRows - 1) / kCoarsestRows;
     const size_t lds = (size_t)std::min(n, kCoarsestChunk) * sizeof(double);
-    hipLaunchKernelGGL((k_coarsest<T>), dim3(blocks), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc, check_done);
+    if (n <= kCoarsestChunk) {
+        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
+                           check_done);
+    } else {
+        hipLaunchKernelGGL((k_coarsest<T, 4>), dim3((n + 15) / 16), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
+                           check_done);
+    }
 }
 
 void launch_galerkin2(const FineGeom& g, const double* kt, const double* phi, const int* nkeep, int L, double* D,
