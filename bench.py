@@ -89,7 +89,7 @@ def main():
     perm = torch.as_tensor(perm_h, device=dev)
     b = torch.as_tensor(b_h.reshape(-1), device=dev)
     x = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
-    agg = 4
+    agg = wl.agg
     precision = FP32_VCYCLE if prec == "fp32_vcycle" else FP64
 
     if args.copy_calibration:
@@ -101,7 +101,8 @@ def main():
         del src, dst
 
     def step(profile):
-        ctx = SpecMG(perm, levels=wl.levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision)
+        ctx = SpecMG(perm, levels=wl.levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision,
+                     eigs_coarse=wl.eigs_coarse, allow_unconverged=True)
         if profile:
             ctx.set_profiling(True)
         rc, info = ctx.pcg_solve(b, x, tol=1e-6, max_iter=1000)
@@ -157,12 +158,14 @@ def main():
         "dtype": "f64" if precision == FP64 else "f32 V-cycle / f64 CG",
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": f"{n}^3", "dof": dof, "levels": wl.levels,
-                   "eigs_per_subdomain": wl.eigs, "agg": agg, "field": wl.kind, "source": wl.source,
+                   "eigs_per_subdomain": wl.eigs, "eigs_coarse": wl.eigs_coarse or wl.eigs, "agg": agg,
+                   "field": wl.kind, "source": wl.source,
                    "tol": 1e-6, "precision": prec},
         "solve_ms": solve_s * 1e3,
         "setup_ms": setup_s * 1e3,
         "iters": iters,
         "rel_resid_true": [i.rel_resid_true for i in infos],
+        "eig_unconverged": [i.eig_unconverged for i in infos],
         "dims": list(infos[-1].dims)[: wl.levels],
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -578,7 +578,13 @@ __device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X
 // tolerance (relative to bnd) was not met within max_cycles.
 // Convergence: vectors that the cluster rule keeps need residual <= tol*bnd;
 // the remaining ones up to index need-1 only feed the cluster decision
-// through their eigenvalues (error <= residual^2 / gap), so sqrt(tol)*bnd.
+// through their eigenvalues (error <= residual^2 / gap), so sqrt(tol)*bnd,
+// unless their Ritz value already lies 5 % above the last kept one: then the
+// decision cannot change (a partner of a kept eigenvalue would have been
+// amplified like the kept vectors, which have converged).  Without that
+// exception a degenerate cluster straddling the block's end (the Laplace
+// ladder of a homogeneous element) is never resolved: the filter's cut sits
+// on the cluster.
 template <int M, int R, class OP>
 __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M], double (&AX)[R][M],
                       double bnd, int need, double tol, int target, double crtol, double thr, EigShared<M>& sh,
@@ -598,7 +604,11 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
         }
         const int nk = cluster_cut_dev(sh.th, M, target, crtol, thr);
         bool ok = true;
-        for (int j = 0; j < need; ++j) ok = ok && (sqrt(sh.nrm[j]) <= (j < nk ? tol : sqrt(tol)) * bnd);
+        for (int j = 0; j < need; ++j) {
+            const double rj = sqrt(sh.nrm[j]);
+            const bool sep = j >= nk && nk > 0 && sh.th[j] - sh.th[nk - 1] > 0.05 * fabs(sh.th[j]);
+            ok = ok && (rj <= (j < nk ? tol : sqrt(tol)) * bnd || sep);
+        }
         if (ok) return cyc;
         if (cyc >= max_cycles) return -1;
         const double a = fmin(sh.th[M - 1], 0.5 * bnd);

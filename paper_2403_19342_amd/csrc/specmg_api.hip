@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -243,7 +244,17 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     launch_resid_restrict<T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
     prof_end(c, ev, PC_RESTRICT, s);
     ev = prof_begin_range(c, s);
-    coarse_cycle<T>(c, 0, check, s);
+    if constexpr (std::is_same<T, float>::value) {
+        // the coarse levels stay FP64: their kept modes include inclusion
+        // and channel modes with eigenvalues near float32 rounding (1e-7 of
+        // the operator's scale), which FP32 residuals would lose
+        const int64_t n2 = (int64_t)l2.g.m * l2.L;
+        launch_convert<float, double>(l2.r32, l2.r, n2, s);
+        coarse_cycle<double>(c, 0, check, s);
+        launch_convert<double, float>(l2.e, l2.e32, n2, s);
+    } else {
+        coarse_cycle<double>(c, 0, check, s);
+    }
     prof_end(c, ev, c->lev.size() == 1 ? PC_COARSEST : PC_COARSE, s);
     ev = prof_begin(c, s);
     launch_prolong<T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
@@ -481,25 +492,12 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         HIPCHK(hipStreamSynchronize(s));
         (void)hipFree(work);
     }
-    // ---- float32 copies for the mixed-precision V-cycle
+    // ---- float32 copy of the level-2 basis for the mixed-precision fine level
     if (c->fp32) {
-        for (size_t li = 0; li < c->lev.size(); ++li) {
-            Level& lv = c->lev[li];
-            const size_t LL = (size_t)lv.L * lv.L;
-            const size_t nb = (size_t)lv.g.m * lv.L * lv.rows;
-            lv.basis32 = c->alloc<float>(nb);
-            launch_convert<double, float>(lv.basis, lv.basis32, (int64_t)nb, s);
-            lv.Ad32 = c->alloc<float>(lv.g.m * LL);
-            launch_convert<double, float>(lv.Ad, lv.Ad32, (int64_t)(lv.g.m * LL), s);
-            lv.Aoff32 = c->alloc<float>(lv.g.m * 3 * LL);
-            launch_convert<double, float>(lv.Aoff, lv.Aoff32, (int64_t)(lv.g.m * 3 * LL), s);
-            if (lv.Dinv) {
-                lv.Dinv32 = c->alloc<float>(lv.g.m * LL);
-                launch_convert<double, float>(lv.Dinv, lv.Dinv32, (int64_t)(lv.g.m * LL), s);
-                lv.G32 = c->alloc<float>(lv.g.m * 6 * LL);
-                launch_convert<double, float>(lv.G, lv.G32, (int64_t)(lv.g.m * 6 * LL), s);
-            }
-        }
+        Level& lv = c->lev[0];
+        const size_t nb = (size_t)lv.g.m * lv.L * lv.rows;
+        lv.basis32 = c->alloc<float>(nb);
+        launch_convert<double, float>(lv.basis, lv.basis32, (int64_t)nb, s);
     }
     // ---- vectors
     for (auto& lv : c->lev) {
@@ -510,12 +508,10 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         HIPCHK(hipMemsetAsync(lv.r, 0, nv * sizeof(double), s));
         HIPCHK(hipMemsetAsync(lv.u, 0, nv * sizeof(double), s));
         HIPCHK(hipMemsetAsync(lv.e, 0, nv * sizeof(double), s));
-        if (c->fp32) {
+        if (c->fp32 && &lv == &c->lev[0]) {
             lv.r32 = c->alloc<float>(nv);
-            lv.u32 = c->alloc<float>(nv);
             lv.e32 = c->alloc<float>(nv);
             HIPCHK(hipMemsetAsync(lv.r32, 0, nv * sizeof(float), s));
-            HIPCHK(hipMemsetAsync(lv.u32, 0, nv * sizeof(float), s));
             HIPCHK(hipMemsetAsync(lv.e32, 0, nv * sizeof(float), s));
         }
     }

@@ -183,13 +183,17 @@ class Workload:
     seed: int
     kind: str                # field generator
     source: str
+    agg: int = 4             # level-l elements per level-(l+1) element along each axis
+    eigs_coarse: int = 0     # kept count at levels >= 3 (0: same as eigs)
 
 
 WORKLOADS = {
     "boxes32": Workload("boxes32", 32, 2, 4, "fp64", 0, "boxes", "corner"),
     "gauss128": Workload("gauss128", 128, 3, 6, "fp64", 1, "gauss", "quarter_five_spot"),
     "channels256": Workload("channels256", 256, 3, 8, "fp32_vcycle", 2, "channels", "five_spot"),
-    "inclusions512": Workload("inclusions512", 512, 4, 6, "fp32_vcycle", 3, "inclusions", "five_spot"),
+    # 32^3-cell coarse elements hold up to ~9 inclusions: 2x aggregation and
+    # 10 vectors per coarse element keep every inclusion mode in the hierarchy
+    "inclusions512": Workload("inclusions512", 512, 4, 6, "fp32_vcycle", 3, "inclusions", "five_spot", 2, 10),
 }
 
 
