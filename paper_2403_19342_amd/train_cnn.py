@@ -2,6 +2,7 @@
 
     python -m paper_2403_19342_amd.train_cnn --out DIR [--n 128] [--fields 16]
         [--k 6] [--steps 3000] [--batch 512] [--lr 2e-3] [--eval 4]
+    python -m paper_2403_19342_amd.train_cnn --out DIR --weights FILE --eval 32
 
 Training fields are Gaussian log-permeability fields with sigma ~ U[2,4] and
 correlation length ~ U[0.05,0.2] (seeds 10000, 10001, ...); each field's
@@ -172,7 +173,15 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", type=int, default=4)
     ap.add_argument("--ws-resid-tol", type=float, default=1e-3)
+    ap.add_argument("--weights", default=None,
+                    help="evaluate these bf16 parameters (int16 .npy) instead of training")
     a = ap.parse_args(argv)
+    if a.weights:
+        import torch
+        theta16 = torch.as_tensor(np.load(a.weights), device="cuda")
+        rows = evaluate(theta16, a.n, range(1000, 1000 + a.eval), a.k, ws_resid_tol=a.ws_resid_tol)
+        print(json.dumps({"summary": summarize(rows), "fields": len(rows), "weights": a.weights}), flush=True)
+        return
     P, S, F = dataset(a.n, range(10000, 10000 + a.fields), a.k)
     theta, theta16, hist, secs = train(P, S, F, a.k, a.steps, a.batch, a.lr)
     os.makedirs(a.out, exist_ok=True)
