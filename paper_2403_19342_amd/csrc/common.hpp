@@ -229,7 +229,7 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
                                 const T* G, const T* r, const T* u, T* e, const Scalars* sc,
                                 int check_done, hipStream_t s);
 template <typename T>
-void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e,
+void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, double* rc,
                      const Scalars* sc, int check_done, hipStream_t s);
 
 // set-up (k_coarse.hip)

@@ -319,16 +319,23 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
 }
 
 // e = B r at the coarsest level, B the dense inverse of the regularised
-// coarsest matrix: a product over the compact unknowns (cmap: compact index
-// -> padded index).  Each block owns 16 rows (4 per wave, 4 accumulators so
-// that four row streams are in flight); r is gathered into LDS in chunks of
-// kCoarsestChunk values, so any size fits the 160 KB of LDS.
+// coarsest matrix, over the compact unknowns (cmap: compact index -> padded
+// index).  r is first gathered into a compact FP64 vector rc; the product
+// then gives each wavefront RW rows (RW accumulators, RW row streams in
+// flight) and stages rc through LDS in chunks of kCoarsestChunk values, so
+// any size fits the 160 KB of LDS and each block reads rc once.
 constexpr int kCoarsestChunk = 8192;
-constexpr int kCoarsestRows = 16;
+
+template <typename T>
+__global__ void k_gather_compact(int n, const int* __restrict__ cmap, const T* __restrict__ r,
+                                 double* __restrict__ rc, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) rc[i] = (double)r[cmap[i]];
+}
 
 template <typename T, int RW>
 __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* __restrict__ Pinv,
-                                                   const int* __restrict__ cmap, const T* __restrict__ r,
+                                                   const int* __restrict__ cmap, const double* __restrict__ rc,
                                                    T* __restrict__ e, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
     extern __shared__ double srz[];
@@ -340,7 +347,7 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* _
     for (int c0 = 0; c0 < n; c0 += kCoarsestChunk) {
         const int cn = min(kCoarsestChunk, n - c0);
         if (c0) __syncthreads();
-        for (int j = threadIdx.x; j < cn; j += blockDim.x) srz[j] = (double)r[cmap[c0 + j]];
+        for (int j = threadIdx.x; j < cn; j += blockDim.x) srz[j] = rc[c0 + j];
         __syncthreads();
         for (int j = lane; j < cn; j += 64) {
             const double v = srz[j];
@@ -734,14 +741,16 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
 }
 
 template <typename T>
-void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, const Scalars* sc,
-                     int check_done, hipStream_t s) {
+void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, double* rc,
+                     const Scalars* sc, int check_done, hipStream_t s) {
     const size_t lds = (size_t)std::min(n, kCoarsestChunk) * sizeof(double);
+    hipLaunchKernelGGL((k_gather_compact<T>), dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, n, cmap, r, rc,
+                       sc, check_done);
     if (n <= kCoarsestChunk) {
-        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
+        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, rc, e, sc,
                            check_done);
     } else {
-        hipLaunchKernelGGL((k_coarsest<T, 4>), dim3((n + 15) / 16), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
+        hipLaunchKernelGGL((k_coarsest<T, 16>), dim3((n + 63) / 64), dim3(256), lds, s, n, np, Pinv, cmap, rc, e, sc,
                            check_done);
     }
 }
@@ -799,10 +808,10 @@ template void launch_coarse_resid_smooth<double>(const CoarseGeom&, const double
 template void launch_coarse_resid_smooth<float>(const CoarseGeom&, const float*, const float*, const float*,
                                                 const float*, const float*, const float*, float*, const Scalars*,
                                                 int, hipStream_t);
-template void launch_coarsest<double>(int, int, const double*, const int*, const double*, double*, const Scalars*,
-                                      int, hipStream_t);
-template void launch_coarsest<float>(int, int, const double*, const int*, const float*, float*, const Scalars*, int,
-                                     hipStream_t);
+template void launch_coarsest<double>(int, int, const double*, const int*, const double*, double*, double*,
+                                      const Scalars*, int, hipStream_t);
+template void launch_coarsest<float>(int, int, const double*, const int*, const float*, float*, double*,
+                                     const Scalars*, int, hipStream_t);
 template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
 template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
 

@@ -97,6 +97,7 @@ struct specmg_ctx {
     int nL = 0, npL = 0;
     double* Pinv = nullptr;
     int* cmap = nullptr;
+    double* rc = nullptr;       // coarsest right-hand side, compact
     // CG state
     double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *u1 = nullptr;
     double* tres = nullptr;     // r - A u of the post-smoother (float in FP32 mode)
@@ -210,7 +211,7 @@ void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
     T* r = pick<T>(lv.r, lv.r32);
     T* e = pick<T>(lv.e, lv.e32);
     if (li + 1 == c->lev.size()) {
-        launch_coarsest<T>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->sc, check, s);
+        launch_coarsest<T>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->rc, c->sc, check, s);
         return;
     }
     Level& up = c->lev[li + 1];
@@ -450,6 +451,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         c->nL = nL;
         c->npL = np;
         c->cmap = c->alloc<int>(nL);
+        c->rc = c->alloc<double>(nL);
         int* dcinv = c->alloc<int>(cinv.size());
         HIPCHK(hipMemcpyAsync(c->cmap, cmap.data(), nL * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(dcinv, cinv.data(), cinv.size() * sizeof(int), hipMemcpyHostToDevice, s));
@@ -488,9 +490,10 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         // stays positive definite when rounding spoils the inverse of an
         // ill-conditioned A_L.
         launch_add_rank1(c->Pinv, np, nL, dz, alpha, s);
-        dense_spd_inverse(c->Pinv, np, work, c->dflag + 3, s);
+        const int de = dense_spd_inverse(c->Pinv, np, work, c->dflag + 3, s);
         HIPCHK(hipStreamSynchronize(s));
         (void)hipFree(work);
+        if (de != 0) return fail(SPECMG_EDEVICE, std::string("coarsest inverse: ") + hipGetErrorString((hipError_t)de));
     }
     // ---- float32 copy of the level-2 basis for the mixed-precision fine level
     if (c->fp32) {
