@@ -816,30 +816,38 @@ __global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, i
 
 // Sums the block partials of one reduction in block order and applies the
 // CG scalar update of the reduction site.
-__global__ __launch_bounds__(256) void k_finalize(int site, int nb, Scalars* sc, RedBuf rb, double* out,
-                                                   int check_done) {
+// one 1024-thread block sums the block partials in a fixed order (16 loads in
+// flight per thread: a 65,536-partial sum is four rounds)
+constexpr int kFinThreads = 1024;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(int site, int nb, Scalars* sc, RedBuf rb, double* out,
+                                                          int check_done) {
     if (check_done && sc->done) return;
-    __shared__ double sh[2][4];
+    __shared__ double sh[2][kFinThreads / 64];
     const int nv = (site == RS_RZ || site == RS_GEN2) ? 2 : 1;
     double t[2] = {0.0, 0.0};
     for (int k = 0; k < nv; ++k) {
         const double* pk = rb.partial + (size_t)k * kMaxRedBlocks;
-        double a[8];
-        for (int base = 0; base < nb; base += 256 * 8) {
+        double a[16];
+        for (int base = 0; base < nb; base += kFinThreads * 16) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int i = base + u * 256 + threadIdx.x;
+            for (int u = 0; u < 16; ++u) {
+                const int i = base + u * kFinThreads + threadIdx.x;
                 a[u] = i < nb ? pk[i] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) t[k] += a[u];
+            for (int u = 0; u < 16; ++u) t[k] += a[u];
         }
         t[k] = wave_sum(t[k]);
         if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = t[k];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int k = 0; k < nv; ++k) t[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
+    for (int k = 0; k < nv; ++k) {
+        double v = 0.0;
+        for (int w = 0; w < kFinThreads / 64; ++w) v += sh[k][w];
+        t[k] = v;
+    }
     if (site == RS_PQ) {
         sc->pq = t[0];
         sc->iter += 1;
@@ -871,7 +879,7 @@ __global__ __launch_bounds__(256) void k_finalize(int site, int nb, Scalars* sc,
 
 void launch_finalize(int site, int nblocks, Scalars* sc, RedBuf rb, double* out, int check_done,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, site, nblocks, sc, rb, out, check_done);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, site, nblocks, sc, rb, out, check_done);
 }
 
 __global__ void k_axpy_x(double* x, const double* __restrict__ p0, const double* __restrict__ p1,
