@@ -415,52 +415,128 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     }
 }
 
-// s = r - A u, then r2[e][j] = sum_c phi[e][j][c] s_c for every element
-template <int EX, typename T>
-__global__ __launch_bounds__(64 * EX) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
-                                                            const T* __restrict__ u,
-                                                            const double* __restrict__ r,
-                                                            const T* __restrict__ phi,
-                                                            const int* __restrict__ nkeep, int L,
-                                                            T* __restrict__ r2, const Scalars* sc,
-                                                            int check_done) {
-    using TT = TileT<EX>;
+// s = r - A u, then r2[e][j] = sum_c phi[e][j][c] s_c for every element.
+// One wavefront per 8^3 element, lane (j, k) holding the x-pencil of row
+// (j, k) in its natural order; y and z neighbours come from the lanes +-1
+// and +-8, the element's boundary pencils and pencil ends from global
+// memory (zero kappa~ outside the domain).  No LDS; the basis is read one
+// column (a contiguous 64-byte pencil per lane) at a time.
+template <typename T>
+__device__ __forceinline__ void load8(const T* __restrict__ p, T (&v)[8]);
+template <>
+__device__ __forceinline__ void load8<double>(const double* __restrict__ p, double (&v)[8]) {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const double2 d = q[i];
+        v[2 * i] = d.x;
+        v[2 * i + 1] = d.y;
+    }
+}
+template <>
+__device__ __forceinline__ void load8<float>(const float* __restrict__ p, float (&v)[8]) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float4 d = q[i];
+        v[4 * i] = d.x;
+        v[4 * i + 1] = d.y;
+        v[4 * i + 2] = d.z;
+        v[4 * i + 3] = d.w;
+    }
+}
+
+// s -= T (u - u_nb) over the pencil for one neighbour pencil (nu, nk)
+template <typename T>
+__device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T (&kc)[8], const T (&nu)[8],
+                                            const T (&nk)[8]) {
+#pragma unroll
+    for (int x = 0; x < 8; ++x) s[x] -= harm(kc[x], nk[x]) * (uc[x] - nu[x]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
+                                                       const T* __restrict__ u, const double* __restrict__ r,
+                                                       const T* __restrict__ phi, const int* __restrict__ nkeep,
+                                                       int L, T* __restrict__ r2, const Scalars* sc,
+                                                       int check_done) {
     if (check_done && sc->done) return;
-    __shared__ T sU[TT::NHP];
-    __shared__ T sK[TT::NHP];
-    __shared__ T sS[TT::NCP];
-    int x0, y0, z0;
-    tile_origin(g, x0, y0, z0);
-    load_halo2<EX>(g, u, sU, kt, sK, x0, y0, z0);
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int m = g.mx * g.my * g.mz;
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int e = b * 4 + (threadIdx.x >> 6);
+    if (e >= m) return;   // whole wavefront; no block barriers below
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    const int j = lane & 7, k = lane >> 3;
+    const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
+    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const size_t row = (size_t)x0 + sy * y + sz * z;
+    T uc[8], kc[8], s[8];
+    load8(u + row, uc);
+    load8(kt + row, kc);
     {
-        const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
-        for (int z = 0; z < 8; ++z) {
-            const int h = hidx<EX>(tx, ty, z);
-            const T s = (T)r[gidx(g, x0 + tx, y0 + ty, z0 + z)] - apply_stencil<EX, T>(sU, sK, h);
-            sS[tidx<EX>(tx, ty, z)] = s;
+        const double2* q = reinterpret_cast<const double2*>(r + row);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 d = q[i];
+            s[2 * i] = (T)d.x;
+            s[2 * i + 1] = (T)d.y;
         }
     }
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int e = (x0 >> 3) + w + g.mx * ((y0 >> 3) + g.my * (z0 >> 3));
-    T sv[8];
+    // x faces: inside the pencil, then the two ends
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int c = lane + 64 * i;
-        sv[i] = sS[tidx<EX>(8 * w + (c & 7), (c >> 3) & 7, c >> 6)];
+    for (int x = 0; x < 7; ++x) {
+        const T d = harm(kc[x], kc[x + 1]) * (uc[x] - uc[x + 1]);
+        s[x] -= d;
+        s[x + 1] += d;
     }
-    const int nk = nkeep[e];
-    const T* ph = phi + (size_t)e * L * kSub3;
-    // all basis loads of the lane first, then one wave reduction per column
+    if (x0 > 0) s[0] -= harm(kc[0], kt[row - 1]) * (uc[0] - u[row - 1]);
+    if (x0 + 8 < g.nx) s[7] -= harm(kc[7], kt[row + 8]) * (uc[7] - u[row + 8]);
+    // y and z neighbours, one direction at a time
+#pragma unroll 1
+    for (int d = 0; d < 4; ++d) {
+        T nu[8], nk[8];
+        // source lane of the neighbour row: -1, +1, -8, +8 (wrapping lanes are
+        // the element's edge lanes, which load instead)
+        const int src = (lane + (d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -8 : 8)))) & 63;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            nu[x] = __shfl(uc[x], src, 64);
+            nk[x] = __shfl(kc[x], src, 64);
+        }
+        const bool edge = d == 0 ? j == 0 : (d == 1 ? j == 7 : (d == 2 ? k == 0 : k == 7));
+        if (edge) {
+            const bool inside = d == 0 ? y > 0 : (d == 1 ? y + 1 < g.ny : (d == 2 ? z > 0 : z + 1 < g.nz));
+            if (inside) {
+                const size_t o = d == 0 ? row - sy : (d == 1 ? row + sy : (d == 2 ? row - sz : row + sz));
+                load8(u + o, nu);
+                load8(kt + o, nk);
+            } else {
+#pragma unroll
+                for (int x = 0; x < 8; ++x) nk[x] = T(0);
+            }
+        }
+        face_pencil(s, uc, kc, nu, nk);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // restriction onto the element's kept basis vectors
+    const int nkp = nkeep[e];
+    const T* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
     T acc[kMaxCols];
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
-        const int jc = jj < nk ? jj : nk - 1;
         T a = T(0);
+        if (jj < nkp) {
+            T pv[8];
+            load8(ph + (size_t)jj * kSub3, pv);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) a += ph[(size_t)jc * kSub3 + lane + 64 * i] * sv[i];
-        acc[jj] = jj < nk ? a : T(0);
+            for (int x = 0; x < 8; ++x) a += pv[x] * s[x];
+        }
+        acc[jj] = a;
+        // at most three columns of loads in flight (register budget)
+        if (jj % 3 == 2) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
@@ -967,8 +1043,9 @@ void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r,
 template <typename T>
 void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
                            const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_resid_restrict<EX, T>), dim3(g.ntiles), dim3(64 * EX),
-                                                0, s, g, kt, u, r, phi, nkeep, L, r2, sc, check_done));
+    const int m = g.mx * g.my * g.mz;
+    SPECMG_TIMED_LAUNCH((k_resid_restrict<T>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L, r2,
+                        sc, check_done);
 }
 
 template <typename T>
