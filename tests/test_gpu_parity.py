@@ -242,3 +242,29 @@ def test_coarsest_wider_than_one_chunk():
         iters[levels] = info.iters
         ctx.close()
     assert iters[2] <= iters[3] + 1
+
+
+def test_homogeneous_elements_converge_at_a_split_cluster():
+    """L = 8 on homogeneous 8^3 elements: the Laplace ladder's 6-fold cluster
+    (indices 11-16) straddles the end of the eigensolver's 14-vector block.
+    Every local eigensolve must converge, the kept count must be 8 (the cut
+    between mu_1 and mu_2 / 3 splits no cluster), and the kept eigenvalues and
+    the first guard value must be an upper bound separated from them, against
+    the closed-form ladder
+    (mu_a + mu_b + mu_c) / 3, mu_m = 2 - 2 cos(m pi / 8)."""
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm = np.ones((32, 32, 32))
+    ctx = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=8, agg=2)
+    assert ctx.info()["setup"]["eig_unconverged"] == 0
+    lv = ctx.level_arrays(2)
+    mu = 2 - 2 * np.cos(np.arange(8) * np.pi / 8)
+    ladder = np.sort((mu[:, None, None] + mu[None, :, None] + mu[None, None, :]).reshape(-1) / 3)
+    assert np.all(lv.nkeep == 8)
+    err = np.max(np.abs(lv.lam[:, :8] - ladder[None, :8]))
+    # the first guard value (an upper bound of mu_2 / 3) is clearly above the kept set
+    assert np.all(lv.lam[:, 8] >= ladder[8] - 1e-12)
+    assert np.all(lv.lam[:, 8] > 1.05 * lv.lam[:, 7])
+    print(f"homogeneous L=8: max |lambda - ladder| = {err:.2e}, cycles {lv.status.min()}..{lv.status.max()}")
+    assert err < 1e-11
+    ctx.close()
