@@ -454,26 +454,14 @@ __device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T
     for (int x = 0; x < 8; ++x) s[x] -= harm(kc[x], nk[x]) * (uc[x] - nu[x]);
 }
 
+// s = r - A u on the x-pencil of row (j, k) of an element (x0 = the
+// element's first x, (y, z) the row), natural order; row = index of (x0, y, z)
 template <typename T>
-__global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
-                                                       const T* __restrict__ u, const double* __restrict__ r,
-                                                       const T* __restrict__ phi, const int* __restrict__ nkeep,
-                                                       int L, T* __restrict__ r2, const Scalars* sc,
-                                                       int check_done) {
-    if (check_done && sc->done) return;
-    const int lane = threadIdx.x & 63;
-    const int m = g.mx * g.my * g.mz;
-    const int nb = gridDim.x;
-    int b = blockIdx.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int e = b * 4 + (threadIdx.x >> 6);
-    if (e >= m) return;   // whole wavefront; no block barriers below
-    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
-    const int j = lane & 7, k = lane >> 3;
-    const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
+__device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
+                                                const double* __restrict__ r, size_t row, int x0, int y, int z,
+                                                int lane, int j, int k, T (&s)[8]) {
     const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-    const size_t row = (size_t)x0 + sy * y + sz * z;
-    T uc[8], kc[8], s[8];
+    T uc[8], kc[8];
     load8(u + row, uc);
     load8(kt + row, kc);
     {
@@ -521,6 +509,28 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
         face_pencil(s, uc, kc, nu, nk);
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
+                                                       const T* __restrict__ u, const double* __restrict__ r,
+                                                       const T* __restrict__ phi, const int* __restrict__ nkeep,
+                                                       int L, T* __restrict__ r2, const Scalars* sc,
+                                                       int check_done) {
+    if (check_done && sc->done) return;
+    const int lane = threadIdx.x & 63;
+    const int m = g.mx * g.my * g.mz;
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    const int e = b * 4 + (threadIdx.x >> 6);
+    if (e >= m) return;   // whole wavefront; no block barriers below
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    const int j = lane & 7, k = lane >> 3;
+    const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
+    const size_t row = (size_t)x0 + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+    T s[8];
+    pencil_residual(g, kt, u, r, row, x0, y, z, lane, j, k, s);
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
     const T* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
