@@ -19,7 +19,9 @@
 
 namespace specmg {
 
-constexpr int kDeg = 20;          // Chebyshev degree per cycle
+constexpr int kDeg = 20;          // Chebyshev degree per cycle of a relaxed, warm-started solve
+constexpr int kDegExact = 40;     // ... of an exact solve (fewer cycles, so fewer orthonormalisations
+                                  //     and Rayleigh-Ritz steps per filtered vector)
 constexpr int kMaxCycles = 300;
 constexpr int kMaxEigWaves = 12;   // workgroups of at most 768 threads
 constexpr int kWarmCycles = 4;     // cycles a learned start gets to reach the relaxed residual
@@ -87,7 +89,7 @@ __device__ __forceinline__ void jac_rot(const double* H, int M, int p, int q, do
 // 1e-15 times the largest diagonal entry.  H (M*M) is destroyed; Q (M*M)
 // receives the eigenvectors as columns.  Must be called by all threads.
 template <int M>
-__device__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
+__device__ __forceinline__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
     static_assert(M % 2 == 0 && M <= 16, "Jacobi block size");
     constexpr int MM = M * M;
     constexpr int PER = (MM + 63) / 64;
@@ -177,7 +179,7 @@ __device__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* i
 // lane-parallel trailing update.  G is left intact.  Returns false (in every
 // thread) when G is not numerically positive definite.
 template <int M>
-__device__ bool chol_wave(const double* G, double* Rm, double* dinv, int* flag) {
+__device__ __forceinline__ bool chol_wave(const double* G, double* Rm, double* dinv, int* flag) {
     constexpr int MM = M * M;
     constexpr int PER = (MM + 63) / 64;
     if (threadIdx.x < 64) {
@@ -247,6 +249,14 @@ __device__ int cluster_cut_dev(const double* th, int n, int target, double rtol,
     }
     return k;
 }
+
+// Empty asm statements that take v as an operand: the arithmetic producing v
+// runs before them, and no memory access moves across pin().  Used after
+// every few columns of an operator apply, so that the compiler cannot hoist
+// all of its LDS loads ahead of the arithmetic (a register per loaded value,
+// which halves the waves per SIMD).
+__device__ __forceinline__ void pin(double& v) { asm volatile("" : "+v"(v)::"memory"); }
+__device__ __forceinline__ void pin_value(double& v) { asm volatile("" : "+v"(v)); }
 
 // ---------------------------------------------------------------------------
 // Block storage: the current block lives in LDS as Y[j * ld + row] (ld odd,
@@ -379,7 +389,7 @@ __device__ __forceinline__ void load_block(const double* Y, int ld, int n, doubl
 // Inverse of the upper triangular factor (Rm, dinv from chol_wave) into
 // Ri, by wavefront 0: rows from the bottom up, lane l owning column l.
 template <int M>
-__device__ void trtri_wave(const double* Rm, const double* dinv, double* Ri) {
+__device__ __forceinline__ void trtri_wave(const double* Rm, const double* dinv, double* Ri) {
     if (threadIdx.x < 64) {
         const int l = threadIdx.x;
 #pragma unroll 1
@@ -398,7 +408,7 @@ __device__ void trtri_wave(const double* Rm, const double* dinv, double* Ri) {
 // Orthonormalise the LDS block (Cholesky-QR, twice): Y <- Y R^-1 with
 // Y^T Y = R^T R.
 template <int M, int R>
-__device__ void orthonormalise(double* Y, int ld, int n, EigShared<M>& sh) {
+__device__ __forceinline__ void orthonormalise(double* Y, int ld, int n, EigShared<M>& sh) {
 #pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
         double A[R][M];
@@ -439,6 +449,11 @@ struct Op2 {
 #pragma unroll
             for (int d = 0; d < 6; ++d) s -= off[d] * Y[j * ld + nb[d]];
             out[0][j] = s;
+            if (j % 3 == 2) {
+                pin_value(out[0][j - 2]);
+                pin_value(out[0][j - 1]);
+                pin(out[0][j]);
+            }
         }
     }
 };
@@ -460,8 +475,9 @@ struct OpUp {
     double hd[kW];        // H_d[c][a][0..lp-1], zero beyond lp
     int lp_rt;
     int c, a, p;          // child element, slot, child position in E
-    int q[3];             // child coordinates inside E
-    int cstep[3];         // element-index steps of the lower grid
+    int qx, qy, qz;       // child coordinates inside E (scalars: an indexed
+    int sy, sz;           // array would live in scratch); element-index steps
+                          // of the lower grid in y and z (1 in x)
     int agg;
     bool valid;           // kept slot of an existing child row
     __device__ __forceinline__ int lp() const { return LPT > 0 ? LPT : lp_rt; }
@@ -471,18 +487,23 @@ struct OpUp {
 #pragma unroll
         for (int j = 0; j < M; ++j) out[0][j] = 0.0;
         if (!valid) return;
+        // row base recomputed on every apply: hoisted out of the solver's loops,
+        // one address per (column, slot) would stay live and spill
+        int pw = p * w;
+        asm volatile("" : "+v"(pw));
+        const double* ys = Y + pw;
 #pragma unroll
         for (int b = 0; b < kW; ++b) {
             if (b < w) {
 #pragma unroll
-                for (int j = 0; j < M; ++j) out[0][j] += hd[b] * Y[j * ld + p * w + b];
+                for (int j = 0; j < M; ++j) out[0][j] += hd[b] * ys[j * ld + b];
             }
         }
 #pragma unroll 1
         for (int d = 0; d < 6; ++d) {
             const int ax = d >> 1;
-            const int qa = ax == 0 ? q[0] : (ax == 1 ? q[1] : q[2]);
-            const int cs = ax == 0 ? cstep[0] : (ax == 1 ? cstep[1] : cstep[2]);
+            const int qa = ax == 0 ? qx : (ax == 1 ? qy : qz);
+            const int cs = ax == 0 ? 1 : (ax == 1 ? sy : sz);
             const int ps = ax == 0 ? 1 : (ax == 1 ? agg : agg * agg);
             const bool in = (d & 1) ? (qa < agg - 1) : (qa > 0);
             const int cn = in ? ((d & 1) ? c + cs : c - cs) : c;
@@ -505,12 +526,12 @@ struct OpUp {
     }
 };
 
-// Chebyshev filter of degree kDeg applied to X (registers); the filtered
+// Chebyshev filter of degree deg applied to X (registers); the filtered
 // block is left in LDS.  Wanted spectrum below a, damped interval [a, b],
 // a0 below the whole spectrum.
 template <int M, int R, class OP>
 __device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, int n, double a, double b,
-                            double a0) {
+                            double a0, int deg) {
     const double e = 0.5 * (b - a), cc = 0.5 * (b + a);
     double sigma = e / (a0 - cc);
     const double tau = 2.0 / sigma;
@@ -526,12 +547,16 @@ __device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, 
     store_block<M, R>(Y, ld, n, T);
     __syncthreads();
 #pragma unroll 1
-    for (int it = 2; it <= kDeg; ++it) {
+    for (int it = 2; it <= deg; ++it) {
         const double sn = 1.0 / (tau - sigma);
         op.template apply<M>(Y, ld, T);
+        // own rows' base recomputed every step (hoisted, one address per
+        // column would stay live across the loop)
+        int tb = threadIdx.x;
+        asm volatile("" : "+v"(tb));
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int row = threadIdx.x + r * blockDim.x;
+            const int row = tb + r * blockDim.x;
 #pragma unroll
             for (int j = 0; j < M; ++j) {
                 const double yc = row < n ? Y[j * ld + row] : 0.0;
@@ -540,7 +565,14 @@ __device__ void cheb_filter(const OP& op, double (&X)[R][M], double* Y, int ld, 
             }
         }
         __syncthreads();
-        store_block<M, R>(Y, ld, n, T);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int row = tb + r * blockDim.x;
+            if (row < n) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) Y[j * ld + row] = T[r][j];
+            }
+        }
         __syncthreads();
         sigma = sn;
     }
@@ -588,7 +620,7 @@ __device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X
 template <int M, int R, class OP>
 __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M], double (&AX)[R][M],
                       double bnd, int need, double tol, int target, double crtol, double thr, EigShared<M>& sh,
-                      int max_cycles = kMaxCycles) {
+                      int max_cycles = kMaxCycles, int deg = kDegExact) {
     store_block<M, R>(Y, ld, n, X);
     __syncthreads();
     orthonormalise<M, R>(Y, ld, n, sh);
@@ -614,7 +646,7 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
         const double a = fmin(sh.th[M - 1], 0.5 * bnd);
         const double a0 = fmin(sh.th[0], 0.0) - 1e-3 * bnd;
         __syncthreads();
-        cheb_filter<M, R>(op, X, Y, ld, n, a, bnd, a0);
+        cheb_filter<M, R>(op, X, Y, ld, n, a, bnd, a0, deg);
         orthonormalise<M, R>(Y, ld, n, sh);
     }
 }
@@ -662,13 +694,15 @@ __device__ void column_sums(const double (&A)[R][M], double* dst, int cnt, int n
 // kWarmCycles cycles; an element that does not get there falls back to the
 // exact solve (tolerance tol) from the cold start, and ws_fb[e] = 1.
 // status[e] counts the cycles of both attempts.
+// At most 128 VGPRs (four waves per SIMD): with about 68 KB of LDS per
+// workgroup, two elements then share a CU, and one element's serial phases
+// (Jacobi, Cholesky) overlap the other's filter.
 template <int M>
-__global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restrict__ kt, int target, int L,
-                                              double tol, double crtol, double* __restrict__ phi,
-                                              double* __restrict__ lam, int* __restrict__ nkeep,
-                                              double* __restrict__ Aint, double* __restrict__ zc,
-                                              int* __restrict__ status, int e0, const float* __restrict__ warm,
-                                              int kp, int kw, double ws_tol, int* __restrict__ ws_fb) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_eig2(
+    FineGeom g, const double* __restrict__ kt, int target, int L, double tol, double crtol,
+    double* __restrict__ phi, double* __restrict__ lam, int* __restrict__ nkeep, double* __restrict__ Aint,
+    double* __restrict__ zc, int* __restrict__ status, int e0, const float* __restrict__ warm, int kp, int kw,
+    double ws_tol, int* __restrict__ ws_fb) {
     constexpr int LD = 513;
     __shared__ double sY[M * LD];
     __shared__ EigShared<M> sh;
@@ -716,7 +750,7 @@ __global__ __launch_bounds__(512) void k_eig2(FineGeom g, const double* __restri
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
     int cyc = -1, spent = 0;
     if (warm) {
-        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, 0.0, sh, kWarmCycles);
+        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, 0.0, sh, kWarmCycles, kDeg);
         const bool fb = cyc < 0;
         if (fb) {
             spent = kWarmCycles + 1;
@@ -813,12 +847,11 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
     op.c = c;
     op.a = a;
     op.p = p;
-    op.q[0] = qx;
-    op.q[1] = qy;
-    op.q[2] = qz;
-    op.cstep[0] = 1;
-    op.cstep[1] = lo.mx;
-    op.cstep[2] = lo.mx * lo.my;
+    op.qx = qx;
+    op.qy = qy;
+    op.qz = qz;
+    op.sy = lo.mx;
+    op.sz = lo.mx * lo.my;
     op.agg = agg;
     op.valid = row < n && a < nkeep_lo[c];
 #pragma unroll
@@ -830,10 +863,11 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
         for (int b = 0; b < OpUp<LPT>::kW; ++b) rs += fabs(op.hd[b]);
         for (int d = 0; d < 6; ++d) {
             const int ax = d >> 1;
-            const int qa = op.q[ax];
+            const int qa = ax == 0 ? qx : (ax == 1 ? qy : qz);
+            const int cs = ax == 0 ? 1 : (ax == 1 ? lo.mx : lo.mx * lo.my);
             const bool in = (d & 1) ? (qa < agg - 1) : (qa > 0);
             if (!in) continue;
-            const int cn = (d & 1) ? c + op.cstep[ax] : c - op.cstep[ax];
+            const int cn = (d & 1) ? c + cs : c - cs;
             for (int b = 0; b < LP; ++b)
                 rs += fabs((d & 1) ? Aoff[(((size_t)c * 3 + ax) * LP + a) * LP + b]
                                    : Aoff[(((size_t)cn * 3 + ax) * LP + b) * LP + a]);

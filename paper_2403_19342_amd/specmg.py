@@ -70,6 +70,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2403_19342_amd.build`")
+    # The device buffers handed to the library come from torch, so the library must bind to
+    # the HIP runtime torch loads: import torch first, so that the runtime's soname already
+    # resolves to that copy when the library's own dependency is looked up.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     lib.specmg_setup.argtypes = [vp, i32, ctypes.POINTER(Grid), ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
