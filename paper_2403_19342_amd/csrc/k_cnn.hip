@@ -181,6 +181,113 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution for the layers with 32 input channels (a dense
+// contraction of K = 27 taps x 32 channels per output), on the bf16 matrix
+// cores: v_mfma_f32_16x16x32_bf16, D[16 positions][16 outputs] +=
+// A[16 positions][32 channels] B[32 channels][16 outputs] per tap.  Lane l
+// supplies A row l%16, channels 8(l/16)..+7, and B column l%16, the same
+// channels; it receives D rows 4(l/16)..+3 of column l%16.
+// Each activation is split into a bf16 high part and the bf16 rounding of
+// the remainder, and both pass through the MFMA: with the weights exactly
+// bf16 the products keep about 16 significant bits of the float32
+// activation (relative error near 2^-17), and every sum is float32.
+// One element per workgroup of 8 waves; the element's input is staged in
+// LDS as [part][padded position (10^3)][channel], zero halo, and wave w
+// owns position tiles 4w..4w+3 (positions 16 tile + row, x fastest).
+// mf[t][o][c] (bf16, c fastest, o < COUTP) holds the weights.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMfPos = 1000;   // padded positions of the staged element
+
+template <int COUT, int COUTP, int ACT>
+__global__ __launch_bounds__(512) void k_conv_mfma(const float* __restrict__ x, const uint16_t* __restrict__ mf,
+                                                   const float* __restrict__ bias, float* __restrict__ y) {
+    static_assert(COUTP % 16 == 0 && COUT <= COUTP, "output tiles of 16");
+    constexpr int NT = COUTP / 16;
+    __shared__ uint4 tile[2 * kMfPos * 4];   // [part][position][4 x 8 channels]
+    const int e = blockIdx.x;
+    for (int i = threadIdx.x; i < 2 * kMfPos * 4; i += blockDim.x) tile[i] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+    {
+        const int p = threadIdx.x;   // one interior position per thread
+        const int P = ((p >> 6) + 1) * 100 + (((p >> 3) & 7) + 1) * 10 + (p & 7) + 1;
+        const float* xe = x + (size_t)e * 32 * 512 + p;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const float v0 = xe[(size_t)(8 * g + 2 * h) * 512], v1 = xe[(size_t)(8 * g + 2 * h + 1) * 512];
+                const uint16_t h0 = f2bf(v0), h1 = f2bf(v1);
+                const uint16_t l0 = f2bf(v0 - bf2f(h0)), l1 = f2bf(v1 - bf2f(h1));
+                hw[h] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+                lw[h] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+            }
+            tile[P * 4 + g] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            tile[(kMfPos + P) * 4 + g] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = l & 15, g = l >> 4;
+    int base[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = 16 * (4 * w + j) + r;
+        base[j] = (p >> 6) * 100 + ((p >> 3) & 7) * 10 + (p & 7);
+    }
+    f32x4_t acc[4][NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int o = 16 * n + r;
+        const float b0 = (bias && o < COUT) ? bias[o] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j][n] = f32x4_t{b0, b0, b0, b0};
+    }
+#pragma unroll 1
+    for (int t = 0; t < 27; ++t) {
+        const int off = (t / 9) * 100 + ((t / 3) % 3) * 10 + (t % 3);
+        bf16x8_t bw[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+            bw[n] = __builtin_bit_cast(bf16x8_t,
+                                       *(const uint4*)(mf + ((size_t)(t * COUTP + 16 * n + r) * 32 + 8 * g)));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int P = base[j] + off;
+            const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, tile[P * 4 + g]);
+            const bf16x8_t al = __builtin_bit_cast(bf16x8_t, tile[(kMfPos + P) * 4 + g]);
+#pragma unroll
+            for (int n = 0; n < NT; ++n) {
+                acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[n], acc[j][n], 0, 0, 0);
+                acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[n], acc[j][n], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int o = 16 * n + r;
+        if (o >= COUT) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p0 = 16 * (4 * w + j) + 4 * g;
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = acc[j][n][i];
+                if (ACT == 1) v[i] = fmaxf(v[i], 0.0f);
+                if (ACT == 3) {
+                    const int p = p0 + i;
+                    v[i] += cnn_mode(o, p & 7, (p >> 3) & 7, p >> 6);
+                }
+            }
+            *(float4*)(y + ((size_t)e * COUT + o) * 512 + p0) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradients: part[b][(o*CIN + c)*27 + t] = sum over the elements of
 // block column b of sum_p gy[e][o][p] x[e][c][p + t] (padded coordinates),
 // and part[b][COUT*CIN*27 + o] = sum_p gy[e][o][p].  Thread = (c, o) pair of
@@ -370,6 +477,8 @@ __global__ __launch_bounds__(512) void k_cnn_loss(const float* __restrict__ X, c
 // vector or, rounded to bf16, from the float32 master vector.
 //   fwd1[c][t][16], fwd2[c][t][16], fwd3[c][t][KP/2]       (pairs of outputs)
 //   bwd2[o][t][16], bwd3[o][t][16] with flipped taps       (pairs of inputs)
+//   mf2[t][32][32], mf3[t][16][32]: bf16 [tap][output][input] for the
+//   matrix-core kernel (outputs of layer 3 beyond k are zero), 16-byte aligned
 struct CnnPacks {
     uint32_t* fwd1;
     uint32_t* fwd2;
@@ -379,6 +488,8 @@ struct CnnPacks {
     float* b1;
     float* b2;
     float* b3;
+    uint16_t* mf2;
+    uint16_t* mf3;
 };
 
 __device__ __forceinline__ float cnn_param(const float* t32, const uint16_t* t16, size_t i) {
@@ -449,6 +560,22 @@ __global__ void k_cnn_pack(const float* __restrict__ t32, const uint16_t* __rest
     }
 }
 
+__global__ void k_cnn_pack_mf(const float* __restrict__ t32, const uint16_t* __restrict__ t16, int k,
+                              CnnPacks pk) {
+    const int c1 = 1 + k;
+    const size_t oW2 = (size_t)32 * c1 * 27 + 32, oW3 = oW2 + 32 * 32 * 27 + 32;
+    const int n2 = 27 * 32 * 32, n3 = 27 * 16 * 32;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2 + n3; i += gridDim.x * blockDim.x) {
+        if (i < n2) {
+            const int t = i / 1024, o = (i / 32) % 32, c = i % 32;
+            pk.mf2[i] = f2bf(cnn_param(t32, t16, oW2 + ((size_t)o * 32 + c) * 27 + t));
+        } else {
+            const int j = i - n2, t = j / 512, o = (j / 32) % 16, c = j % 32;
+            pk.mf3[j] = o < k ? f2bf(cnn_param(t32, t16, oW3 + ((size_t)o * 32 + c) * 27 + t)) : (uint16_t)0;
+        }
+    }
+}
+
 // Adam on the float32 master parameters; the bf16 copy used by inference
 // is refreshed in the same pass.
 __global__ void k_cnn_adam(float* __restrict__ theta, const float* __restrict__ grad, float* __restrict__ m1,
@@ -473,10 +600,14 @@ int64_t cnn_param_count(int k) {
     return (int64_t)32 * (1 + k) * 27 + 32 + 32 * 32 * 27 + 32 + (int64_t)k * 32 * 27 + k;
 }
 
-size_t cnn_pack_words(int kp) {
-    return (size_t)(1 + kp) * 27 * 16 + 32 * 27 * 16 + 32 * 27 * (kp / 2) + 32 * 27 * 16 + (size_t)kp * 27 * 16 +
-           32 + 32 + kp;
+// 32-bit words of the packs before the matrix-core copies, rounded up to 16 bytes
+static size_t cnn_pack_words_vec(int kp) {
+    const size_t w = (size_t)(1 + kp) * 27 * 16 + 32 * 27 * 16 + 32 * 27 * (kp / 2) + 32 * 27 * 16 +
+                     (size_t)kp * 27 * 16 + 32 + 32 + kp;
+    return (w + 3) & ~(size_t)3;
 }
+
+size_t cnn_pack_words(int kp) { return cnn_pack_words_vec(kp) + (27 * 32 * 32 + 27 * 16 * 32) / 2; }
 
 CnnPacks cnn_pack_view(void* base, int kp) {
     CnnPacks p;
@@ -489,6 +620,8 @@ CnnPacks cnn_pack_view(void* base, int kp) {
     p.b1 = (float*)(p.bwd3 + (size_t)kp * 27 * 16);
     p.b2 = p.b1 + 32;
     p.b3 = p.b2 + 32;
+    p.mf2 = (uint16_t*)(u + cnn_pack_words_vec(kp));
+    p.mf3 = p.mf2 + 27 * 32 * 32;
     return p;
 }
 
@@ -499,6 +632,7 @@ void launch_cnn_patches(const FineGeom& g, const double* perm, int e0, int count
 
 void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void* packs, hipStream_t s) {
     hipLaunchKernelGGL(k_cnn_pack, dim3(64), dim3(256), 0, s, t32, t16, k, kp, cnn_pack_view(packs, kp));
+    hipLaunchKernelGGL(k_cnn_pack_mf, dim3(64), dim3(256), 0, s, t32, t16, k, cnn_pack_view(packs, kp));
 }
 
 #define SPECMG_KP_DISPATCH(KPV, ...)                                          \
@@ -516,9 +650,9 @@ void launch_cnn_forward(const void* packs, int kp, const float* patches, int cou
     const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
     SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<C1, 32, 2, 1>), dim3(count), dim3(512), 0, s, patches,
                                               p.fwd1, p.b1, nullptr, a1));
-    hipLaunchKernelGGL((k_conv<32, 32, 1, 1>), dim3(count), dim3(512), 0, s, a1, p.fwd2, p.b2, nullptr, a2);
-    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<32, KP, 1, 3>), dim3(count), dim3(512), 0, s, a2, p.fwd3,
-                                              p.b3, nullptr, X));
+    hipLaunchKernelGGL((k_conv_mfma<32, 32, 1>), dim3(count), dim3(512), 0, s, a1, p.mf2, p.b2, a2);
+    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_mfma<KP, 16, 3>), dim3(count), dim3(512), 0, s, a2, p.mf3,
+                                              p.b3, X));
 }
 
 void launch_cnn_loss(const float* X, const double* phi, int ldphi, const double* sdiag, int k, int kp, int count,
