@@ -114,6 +114,12 @@ __device__ __forceinline__ T wave_sum_dpp(T v) {
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 __device__ __forceinline__ float wave_sum(float v) { return wave_sum_dpp(v); }
 
+// orders this wave's LDS and memory accesses (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // every source lane of the four patterns lies in the same row, so no
 // lane falls back to the identity
 __device__ __forceinline__ double wave_max(double v) {

@@ -562,98 +562,135 @@ __global__ void k_assemble_diag(CoarseGeom g, const double* __restrict__ Aint, c
     }
 }
 
-// in-place inverse of an SPD n x n matrix (n <= kMaxL) by one thread;
-// padded slots (index >= nk) get identity.  Returns false if not SPD.
-__device__ bool small_spd_inverse(double* A, int n, int nk, double* Lw) {
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
-            if (i >= nk || j >= nk) A[i * n + j] = (i == j) ? 1.0 : 0.0;
-    bool ok = true;
-    // Cholesky A = L L^T (lower, in Lw)
-    for (int j = 0; j < n; ++j) {
-        double d = A[j * n + j];
-        for (int k = 0; k < j; ++k) d -= Lw[j * n + k] * Lw[j * n + k];
-        if (!(d > 0.0)) {
-            ok = false;
-            d = 1.0;
-        }
-        const double ljj = sqrt(d);
-        Lw[j * n + j] = ljj;
-        for (int i = j + 1; i < n; ++i) {
-            double v = A[i * n + j];
-            for (int k = 0; k < j; ++k) v -= Lw[i * n + k] * Lw[j * n + k];
-            Lw[i * n + j] = v / ljj;
-        }
-        for (int i = 0; i < j; ++i) Lw[i * n + j] = 0.0;
+// In-place inverse of an SPD n x n matrix (n <= kMaxL) by one wavefront:
+// lane 0 factors A = L L^T (Lw, lower), then lane k < n solves
+// L L^T x = e_k for column k.  Padded slots (index >= nk) get identity.
+// Returns false (in every lane) if A is not numerically SPD.
+__device__ bool small_spd_inverse_wave(double* A, int n, int nk, double* Lw, int* flag) {
+    const int lane = threadIdx.x & 63;
+    for (int t = lane; t < n * n; t += 64) {
+        const int i = t / n, j = t % n;
+        if (i >= nk || j >= nk) A[t] = (i == j) ? 1.0 : 0.0;
     }
-    // A^{-1} column by column: solve L y = e_k, L^T x = y
-    for (int kcol = 0; kcol < n; ++kcol) {
+    wave_sync();
+    if (lane == 0) {
+        int ok = 1;
+        for (int j = 0; j < n; ++j) {
+            double d = A[j * n + j];
+            for (int k = 0; k < j; ++k) d -= Lw[j * n + k] * Lw[j * n + k];
+            if (!(d > 0.0)) {
+                ok = 0;
+                d = 1.0;
+            }
+            const double ljj = sqrt(d);
+            Lw[j * n + j] = ljj;
+            for (int i = j + 1; i < n; ++i) {
+                double v = A[i * n + j];
+                for (int k = 0; k < j; ++k) v -= Lw[i * n + k] * Lw[j * n + k];
+                Lw[i * n + j] = v / ljj;
+            }
+            for (int i = 0; i < j; ++i) Lw[i * n + j] = 0.0;
+        }
+        *flag = ok;
+    }
+    wave_sync();
+    if (lane < n) {
+        const int kcol = lane;
         double y[kMaxL];
-        for (int i = 0; i < n; ++i) {
-            double v = (i == kcol) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) v -= Lw[i * n + k] * y[k];
-            y[i] = v / Lw[i * n + i];
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i) {
+            if (i < n) {
+                double v = (i == kcol) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < kMaxL; ++k)
+                    if (k < i) v -= Lw[i * n + k] * y[k];
+                y[i] = v / Lw[i * n + i];
+            }
         }
-        for (int i = n - 1; i >= 0; --i) {
-            double v = y[i];
-            for (int k = i + 1; k < n; ++k) v -= Lw[k * n + i] * y[k];
-            y[i] = v / Lw[i * n + i];
+#pragma unroll
+        for (int i = kMaxL - 1; i >= 0; --i) {
+            if (i < n) {
+                double v = y[i];
+#pragma unroll
+                for (int k = 0; k < kMaxL; ++k)
+                    if (k > i && k < n) v -= Lw[k * n + i] * y[k];
+                y[i] = v / Lw[i * n + i];
+            }
         }
-        for (int i = 0; i < n; ++i) A[i * n + kcol] = y[i];
+#pragma unroll
+        for (int i = 0; i < kMaxL; ++i)
+            if (i < n) A[i * n + kcol] = y[i];
     }
-    return ok;
+    wave_sync();
+    return *flag != 0;
 }
 
-// block IC(0) pivots of the level-l smoother, one workgroup per parent;
-// children of one hyperplane are factored in parallel, one thread each
-__global__ __launch_bounds__(64) void k_blockic_setup(CoarseGeom g, const double* __restrict__ Ad,
-                                                      const double* __restrict__ Aoff,
-                                                      const int* __restrict__ nkeep, double* Dinv, int* bad) {
+// Block IC(0) pivots of the level-l smoother, one workgroup per parent:
+// the children of one hyperplane (at most 12) are factored in parallel,
+// one wavefront each, with the Schur updates of the lower neighbours'
+// couplings lane-parallel over the L x L entries.
+constexpr int kMaxPlane = 12;   // children per hyperplane of a 4^3 parent
+__global__ __launch_bounds__(64 * kMaxPlane) void k_blockic_setup(CoarseGeom g, const double* __restrict__ Ad,
+                                                                   const double* __restrict__ Aoff,
+                                                                   const int* __restrict__ nkeep, double* Dinv,
+                                                                   int* bad) {
     __shared__ int pos[kMaxChildren], off[12];
-    __shared__ double work[12][2][kMaxL * kMaxL];
+    __shared__ double work[kMaxPlane][3][kMaxL * kMaxL];
+    __shared__ int flags[kMaxPlane];
     const int E = blockIdx.x;
     const int L = g.L, agg = g.agg, LL = L * L;
     build_planes(agg, pos, off);
     const int nplanes = 3 * (agg - 1) + 1;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int s = 0; s < nplanes; ++s) {
         const int cnt = off[s + 1] - off[s];
-        const int k = threadIdx.x;
-        if (k < cnt) {
-            const int p = pos[off[s] + k];
+        if (w < cnt) {
+            const int p = pos[off[s] + w];
             const int c = child_of(g, E, p);
-            double* P = work[k][0];
-            double* T = work[k][1];
-            for (int t = 0; t < LL; ++t) P[t] = Ad[(size_t)c * LL + t];
+            double* P = work[w][0];
+            double* T = work[w][1];
+            double* Lw = work[w][2];
+            for (int t = lane; t < LL; t += 64) P[t] = Ad[(size_t)c * LL + t];
             const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
             const int cstep[3] = {1, g.mx, g.mx * g.my};
+            wave_sync();
             for (int ax = 0; ax < 3; ++ax) {
                 if (q[ax] == 0) continue;
                 const int cn = c - cstep[ax];
                 const double* O = Aoff + ((size_t)cn * 3 + ax) * LL;   // A(cn, c)
                 const double* Di = Dinv + (size_t)cn * LL;
                 // T = Dinv_cn O ; P -= O^T T
-                for (int i = 0; i < L; ++i)
-                    for (int j = 0; j < L; ++j) {
-                        double v = 0.0;
-                        for (int b = 0; b < L; ++b) v += Di[i * L + b] * O[b * L + j];
-                        T[i * L + j] = v;
-                    }
-                for (int i = 0; i < L; ++i)
-                    for (int j = 0; j < L; ++j) {
-                        double v = 0.0;
-                        for (int b = 0; b < L; ++b) v += O[b * L + i] * T[b * L + j];
-                        P[i * L + j] -= v;
-                    }
-            }
-            // symmetrise, invert
-            for (int i = 0; i < L; ++i)
-                for (int j = i + 1; j < L; ++j) {
-                    const double v = 0.5 * (P[i * L + j] + P[j * L + i]);
-                    P[i * L + j] = v;
-                    P[j * L + i] = v;
+                for (int t = lane; t < LL; t += 64) {
+                    const int i = t / L, j = t % L;
+                    double v = 0.0;
+                    for (int b = 0; b < L; ++b) v += Di[i * L + b] * O[b * L + j];
+                    T[t] = v;
                 }
-            if (!small_spd_inverse(P, L, nkeep[c], T)) atomicOr(bad, 2);
-            for (int t = 0; t < LL; ++t) Dinv[(size_t)c * LL + t] = P[t];
+                wave_sync();
+                for (int t = lane; t < LL; t += 64) {
+                    const int i = t / L, j = t % L;
+                    double v = 0.0;
+                    for (int b = 0; b < L; ++b) v += O[b * L + i] * T[b * L + j];
+                    P[t] -= v;
+                }
+                wave_sync();
+            }
+            // symmetrise (all reads before the writes), invert
+            double sym[(kMaxL * kMaxL + 63) / 64];
+#pragma unroll
+            for (int u = 0; u < (kMaxL * kMaxL + 63) / 64; ++u) {
+                const int t = lane + 64 * u;
+                sym[u] = t < LL ? 0.5 * (P[t] + P[(t % L) * L + t / L]) : 0.0;
+            }
+            wave_sync();
+#pragma unroll
+            for (int u = 0; u < (kMaxL * kMaxL + 63) / 64; ++u) {
+                const int t = lane + 64 * u;
+                if (t < LL) P[t] = sym[u];
+            }
+            wave_sync();
+            if (!small_spd_inverse_wave(P, L, nkeep[c], Lw, &flags[w]) && lane == 0) atomicOr(bad, 2);
+            for (int t = lane; t < LL; t += 64) Dinv[(size_t)c * LL + t] = P[t];
         }
         __threadfence();
         __syncthreads();
@@ -815,7 +852,7 @@ void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double*
 
 void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
                           double* Dinv, double* G, int* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64), 0, s, g, Ad, Aoff, nkeep, Dinv, bad);
+    hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64 * kMaxPlane), 0, s, g, Ad, Aoff, nkeep, Dinv, bad);
     hipLaunchKernelGGL(k_blockic_couple, dim3(g.m), dim3(256), 0, s, g, Aoff, Dinv, G);
 }
 

@@ -26,10 +26,6 @@ constexpr int kMaxCycles = 300;
 constexpr int kMaxEigWaves = 12;   // workgroups of at most 768 threads
 constexpr int kWarmCycles = 4;     // cycles a learned start gets to reach the relaxed residual
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-}
 
 __device__ __forceinline__ double hash_noise(unsigned a, unsigned b, unsigned c) {
     unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
