@@ -17,6 +17,8 @@ with plain NumPy/SciPy building blocks and no blocking or fusion:
   vcycle     Algorithm 1 (three-grid iteration) applied recursively, with the
              pseudo-inverse at the coarsest level.
   pcg        Preconditioned conjugate gradients around the V-cycle.
+  gmres      Restarted flexible GMRES around the V-cycle (the outer solver
+             of the paper's experiments, Section 5).
   cnn        Extension, not in the paper: the 3D CNN that predicts start
              blocks for the level-2 eigenproblems, its subspace loss and
              gradients (forward and backward written out in float64).
@@ -26,8 +28,9 @@ from .assembly import Grid, transmissibilities, assemble, weight_diag, neumann_l
 from .spectral import Hierarchy, build_hierarchy, cluster_cut, threshold_target
 from .vcycle import Preconditioner
 from .pcg import pcg
+from .gmres import fgmres
 
 __all__ = [
     "Grid", "transmissibilities", "assemble", "weight_diag", "neumann_local",
-    "Hierarchy", "build_hierarchy", "cluster_cut", "threshold_target", "Preconditioner", "pcg",
+    "Hierarchy", "build_hierarchy", "cluster_cut", "threshold_target", "Preconditioner", "pcg", "fgmres",
 ]
