@@ -38,7 +38,8 @@ extern "C" {
 #define SPECMG_EINVAL_PERM (-2)  /* permeability not positive and finite    */
 #define SPECMG_ERHS (-3)         /* |sum f| > 1e-12 sum |f| (no compatible source) */
 #define SPECMG_ENOCONV (-4)      /* max_iter reached; x holds the last iterate */
-#define SPECMG_EBREAKDOWN (-5)   /* p^T A p <= 0 or not finite in CG        */
+#define SPECMG_EBREAKDOWN (-5)   /* p^T A p <= 0 or not finite in CG, or a
+                                    singular Hessenberg column in GMRES     */
 #define SPECMG_EEIG (-6)         /* a local eigensolve did not converge     */
 #define SPECMG_EFACT (-7)        /* a smoother pivot or the coarsest factor is not SPD */
 #define SPECMG_EDEVICE (-8)      /* HIP runtime error                       */
@@ -141,6 +142,25 @@ int specmg_apply_precond(specmg_ctx* ctx, const double* r_dev, double* z_dev, vo
  * SPECMG_ENOCONV, SPECMG_EBREAKDOWN, SPECMG_EDEVICE. */
 int specmg_pcg_solve(specmg_ctx* ctx, const double* rhs_dev, double* x_dev, int32_t use_x0,
                      double tol, int32_t max_iter, specmg_solve_info* info, void* stream);
+
+/* Restarted flexible GMRES with the preconditioner applied on the right,
+ * the outer Krylov solver of the paper's experiments (Section 5: GMRES,
+ * relative tolerance 1e-6; restart length 30 is that library's default).
+ * Solves A x = rhs to ||b - A x|| <= tol ||b||: a cycle of at most
+ * `restart` Arnoldi steps (classical Gram-Schmidt applied twice) ends when
+ * the Arnoldi residual reaches tol ||b||, then the true residual decides;
+ * if it is still above, GMRES restarts from it.  The stored directions
+ * z_j = P^{-1} v_j make the FP32 V-cycle (a preconditioner that is not a
+ * fixed linear map) admissible.  rhs_dev must sum to zero; x_dev as for
+ * specmg_pcg_solve (out: zero mean).  info->iters counts Arnoldi steps,
+ * info->replacements the restarts.  Workspace: (2 restart + 2) float64 cell
+ * vectors, allocated on the first call that needs them and kept by the
+ * context.  Errors: SPECMG_ERHS, SPECMG_EINVAL (tol <= 0, max_iter < 1,
+ * restart outside [1, 64], rhs_dev == x_dev), SPECMG_ENOCONV,
+ * SPECMG_EBREAKDOWN (a singular Hessenberg column), SPECMG_EDEVICE. */
+int specmg_gmres_solve(specmg_ctx* ctx, const double* rhs_dev, double* x_dev, int32_t use_x0,
+                       int32_t restart, double tol, int32_t max_iter, specmg_solve_info* info,
+                       void* stream);
 
 /* y = A x with the fine TPFA operator (eq. p).  Asynchronous. */
 int specmg_apply_operator(specmg_ctx* ctx, const double* x_dev, double* y_dev, void* stream);

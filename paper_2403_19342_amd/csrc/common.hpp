@@ -215,6 +215,25 @@ void launch_sum_abs(const double* a, int64_t n, double* out_sum, double* out_abs
 void launch_axpy_x(double* x, const double* p0, const double* p1, Scalars* sc, int64_t n,
                    hipStream_t s);
 void launch_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s);
+
+// flexible GMRES (k_krylov.hip): device state of one restart cycle
+constexpr int kMaxRestart = 64;
+struct GmresState {
+    double H[(kMaxRestart + 1) * kMaxRestart];   // column j at H + j (kMaxRestart + 1)
+    double cs[kMaxRestart], sn[kMaxRestart], y[kMaxRestart];
+    double g[kMaxRestart + 1], h[kMaxRestart + 1], h2[kMaxRestart + 1];
+    double nrm2, inv, res, beta;
+    int done;   // 1: converged or invariant space, 2: singular Hessenberg column
+};
+size_t mdot_part_doubles();
+void launch_mdot(const double* V, int64_t pitch, int cnt, const double* w, int64_t n, double* part, double* out,
+                 hipStream_t s);
+void launch_maxpy(const double* V, int64_t pitch, int cnt, const double* coef, double sign, double* w, int64_t n,
+                  hipStream_t s);
+void launch_scale_dev(double* dst, const double* src, const double* factor, int64_t n, hipStream_t s);
+void launch_gmres_begin(GmresState* st, double thr, hipStream_t s);
+void launch_gmres_step(GmresState* st, int j, double thr, hipStream_t s);
+void launch_gmres_lsq(GmresState* st, int k, hipStream_t s);
 void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
 void launch_fill(double* dst, double v, int64_t n, hipStream_t s);
 void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s);

@@ -107,6 +107,10 @@ struct specmg_ctx {
     Scalars* sc = nullptr;
     Scalars* sc_host = nullptr; // pinned
     int* ws_fb = nullptr;       // per level-2 element: 1 if the predicted start fell back
+    // flexible GMRES workspace (allocated on first use, grown with the restart length)
+    double* gm_buf = nullptr;
+    int gm_restart = 0;
+    GmresState* gm_state = nullptr;
     RedBuf rb{};
     specmg_solve_info setup_info{};
     // per-kernel-class event timing of pcg_solve (see specmg_set_profiling)
@@ -130,6 +134,8 @@ struct specmg_ctx {
     ~specmg_ctx() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* a : allocs) (void)hipFree(a);
+        if (gm_buf) (void)hipFree(gm_buf);
+        if (gm_state) (void)hipFree(gm_state);
         if (sc_host) (void)hipHostFree(sc_host);
     }
 };
@@ -782,6 +788,138 @@ extern "C" int specmg_pcg_solve(specmg_ctx* c, const double* rhs, double* x, int
     if (!(tol > 0) || max_iter < 1) return fail(SPECMG_EINVAL, "tol must be > 0 and max_iter >= 1");
     try {
         return do_solve(c, rhs, x, use_x0, tol, max_iter, info, (hipStream_t)stream);
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+}
+
+// Restarted flexible GMRES around the V-cycle (right preconditioning):
+// x = x0 + Z_k y_k with z_j = P^{-1} v_j; classical Gram-Schmidt twice per
+// Arnoldi step; the Arnoldi residual |g_{j+1}| decides the end of a cycle,
+// the true residual b - A x the end of the solve (else a restart from it).
+static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int restart, double tol, int max_iter,
+                    specmg_solve_info* info, hipStream_t s) {
+    const double t0 = now_ms();
+    const int64_t n = c->n;
+    specmg_solve_info si = c->setup_info;
+    si.iters = 0;
+    si.converged = 0;
+    si.replacements = 0;
+    const int prof_saved = c->prof_on;   // the per-kernel timing covers pcg_solve only
+    c->prof_on = 0;
+    struct Restore {
+        specmg_ctx* c;
+        int v;
+        ~Restore() { c->prof_on = v; }
+    } restore{c, prof_saved};
+    launch_sum_abs(b, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    double sa[2];
+    HIPCHK(hipMemcpyAsync(sa, c->dtmp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (std::fabs(sa[0]) > 1e-12 * sa[1]) return fail(SPECMG_ERHS, "source does not sum to zero");
+    const double nb = std::sqrt(dev_dot(c, b, b, s));
+    if (nb == 0.0) {
+        launch_fill(x, 0.0, n, s);
+        si.converged = 1;
+        si.solve_ms = now_ms() - t0;
+        if (info) *info = si;
+        return SPECMG_OK;
+    }
+    if (restart > c->gm_restart) {
+        if (c->gm_buf) HIPCHK(hipFree(c->gm_buf));
+        c->gm_buf = nullptr;
+        c->gm_restart = 0;
+        const size_t doubles = (size_t)(2 * restart + 2) * (size_t)n + mdot_part_doubles();
+        HIPCHK(hipMalloc(&c->gm_buf, doubles * sizeof(double)));
+        c->gm_restart = restart;
+    }
+    if (!c->gm_state) HIPCHK(hipMalloc(&c->gm_state, sizeof(GmresState)));
+    double* V = c->gm_buf;                          // restart + 1 vectors
+    double* Z = V + (size_t)(restart + 1) * n;      // restart vectors
+    double* w = Z + (size_t)restart * n;
+    double* part = w + n;
+    GmresState* st = c->gm_state;
+    const double thr = tol * nb;
+    struct Host {
+        double res, beta;
+        int done;
+    } hs{};
+    auto read_state = [&]() {
+        HIPCHK(hipMemcpyAsync(&hs.res, &st->res, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hs.beta, &st->beta, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&hs.done, &st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipGetLastError());
+    };
+    // r0 into V_0
+    if (use_x0) launch_apply_A(c->fg, c->kt, x, b, V, 1, s);
+    else {
+        launch_fill(x, 0.0, n, s);
+        launch_copy(V, b, n, s);
+    }
+    launch_mdot(V, n, 1, V, n, part, &st->nrm2, s);
+    launch_gmres_begin(st, thr, s);
+    read_state();
+    bool converged = hs.done != 0;
+    int rc = SPECMG_OK;
+    int it = 0;
+    while (!converged && it < max_iter) {
+        launch_scale_dev(V, V, &st->inv, n, s);
+        int k = 0;
+        for (int j = 0; j < restart && it < max_iter; ++j) {
+            double* vj = V + (size_t)j * n;
+            double* zj = Z + (size_t)j * n;
+            run_vcycle(c, vj, zj, nullptr, 0, 0, 0, s);
+            launch_apply_A(c->fg, c->kt, zj, nullptr, w, 0, s);
+            launch_mdot(V, n, j + 1, w, n, part, st->h, s);
+            launch_maxpy(V, n, j + 1, st->h, -1.0, w, n, s);
+            launch_mdot(V, n, j + 1, w, n, part, st->h2, s);
+            launch_maxpy(V, n, j + 1, st->h2, -1.0, w, n, s);
+            launch_mdot(w, n, 1, w, n, part, &st->nrm2, s);
+            launch_gmres_step(st, j, thr, s);
+            launch_scale_dev(V + (size_t)(j + 1) * n, w, &st->inv, n, s);
+            ++it;
+            k = j + 1;
+            read_state();
+            if (hs.done) break;
+        }
+        if (hs.done == 2) {
+            rc = fail(SPECMG_EBREAKDOWN, "GMRES breakdown: singular Hessenberg column");
+            break;
+        }
+        launch_gmres_lsq(st, k, s);
+        launch_maxpy(Z, n, k, st->y, 1.0, x, n, s);
+        launch_apply_A(c->fg, c->kt, x, b, V, 1, s);
+        launch_mdot(V, n, 1, V, n, part, &st->nrm2, s);
+        launch_gmres_begin(st, thr, s);
+        read_state();
+        converged = hs.done != 0;
+        if (!converged && it < max_iter) si.replacements += 1;
+    }
+    si.iters = it;
+    si.rel_resid = hs.beta / nb;
+    launch_sum_abs(x, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    launch_sub_mean(x, n, c->dtmp, s);
+    launch_apply_A(c->fg, c->kt, x, b, w, 1, s);
+    si.rel_resid_true = std::sqrt(dev_dot(c, w, w, s)) / nb;
+    si.converged = converged ? 1 : 0;
+    HIPCHK(hipStreamSynchronize(s));
+    si.solve_ms = now_ms() - t0;
+    if (info) *info = si;
+    if (rc != SPECMG_OK) return rc;
+    if (!converged) return fail(SPECMG_ENOCONV, "maximum number of iterations reached");
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_gmres_solve(specmg_ctx* c, const double* rhs, double* x, int32_t use_x0, int32_t restart,
+                                  double tol, int32_t max_iter, specmg_solve_info* info, void* stream) {
+    g_last_error.clear();
+    if (!c || !rhs || !x) return fail(SPECMG_EINVAL, "null argument");
+    if (!(tol > 0) || max_iter < 1) return fail(SPECMG_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (restart < 1 || restart > kMaxRestart) return fail(SPECMG_EINVAL, "restart must be in [1, 64]");
+    if (rhs == x) return fail(SPECMG_EINVAL, "rhs and x must not alias");
+    try {
+        return do_gmres(c, rhs, x, use_x0, restart, tol, max_iter, info, (hipStream_t)stream);
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
     }

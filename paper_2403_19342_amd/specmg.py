@@ -20,7 +20,7 @@ OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1
 FP64, FP32_VCYCLE = 0, 1
 WS_NONE, WS_CNN = 0, 1
 
-EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_apply_operator",
+EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve", "specmg_apply_operator",
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
@@ -82,6 +82,8 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_apply_precond.restype = ctypes.c_int
     lib.specmg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolveInfo), vp]
     lib.specmg_pcg_solve.restype = ctypes.c_int
+    lib.specmg_gmres_solve.argtypes = [vp, vp, vp, i32, i32, dbl, i32, ctypes.POINTER(SolveInfo), vp]
+    lib.specmg_gmres_solve.restype = ctypes.c_int
     lib.specmg_apply_operator.argtypes = [vp, vp, vp, vp]
     lib.specmg_apply_operator.restype = ctypes.c_int
     lib.specmg_get_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32 * 8), ctypes.POINTER(i32 * 8),
@@ -213,6 +215,16 @@ class SpecMG:
         info = SolveInfo()
         rc = _lib.specmg_pcg_solve(self._ctx, _dev_ptr(rhs), _dev_ptr(x), int(use_x0), tol, max_iter,
                                    ctypes.byref(info), _stream())
+        if rc != OK and raise_on_error:
+            _check(rc)
+        return rc, info
+
+    def gmres_solve(self, rhs, x, restart: int = 30, tol: float = 1e-6, max_iter: int = 1000,
+                    use_x0: bool = False, raise_on_error: bool = True):
+        """Restarted flexible GMRES around the V-cycle (specmg_gmres_solve)."""
+        info = SolveInfo()
+        rc = _lib.specmg_gmres_solve(self._ctx, _dev_ptr(rhs), _dev_ptr(x), int(use_x0), int(restart), tol,
+                                     max_iter, ctypes.byref(info), _stream())
         if rc != OK and raise_on_error:
             _check(rc)
         return rc, info

@@ -1,0 +1,94 @@
+"""Flexible GMRES on the GPU against the oracle's flexible GMRES (same
+restart length, same stopping rule) on seeded synthetic fields.
+
+Bar, as for PCG: Arnoldi-step counts within +-1 (the two sides
+orthogonalise in a different order, classical Gram-Schmidt twice against
+modified Gram-Schmidt, so the residual history agrees to rounding and a
+step can move across the threshold), restart counts within +-1, and the
+zero-mean solutions within 1e-8 relative L2.  Cases cover three levels and
+the exact two-grid variant (levels = 2), a restart length short enough to
+restart several times, the FP32 V-cycle (a preconditioner that is not a
+fixed linear map, admissible because the directions P^-1 v_j are stored),
+and the argument checks.
+"""
+import numpy as np
+import pytest
+
+from oracle import Grid, Preconditioner, build_hierarchy, fgmres
+from synth.fields import make_field, make_source
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (name, kind, seed, levels, eigs, agg, restart)
+    ("gauss32_l3_r30", "gauss", 1, 3, 4, 2, 30),
+    ("gauss32_l3_r5", "gauss", 1, 3, 4, 2, 5),
+    ("chan32_l2_r30", "channels", 2, 2, 6, 2, 30),
+    ("incl32_l2_r8", "inclusions", 3, 2, 6, 2, 8),
+]
+
+
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,restart", CASES)
+def test_gmres_matches_oracle(name, kind, seed, levels, eigs, agg, restart):
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm = make_field(kind, 32, seed)
+    g = Grid.unit_cube(32)
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
+    b = make_source("corner", perm.shape).reshape(-1)
+    ref = fgmres(hier.A, b, Preconditioner(hier).apply, tol=1e-6, restart=restart)
+    ctx = SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg)
+    x = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres_solve(to_dev(b), x, restart=restart, tol=1e-6)
+    xg = to_host(x)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"{name}: steps gpu {info.iters} oracle {ref.iters}, restarts gpu {info.replacements} "
+          f"oracle {ref.restarts}, rel err {err:.2e}, true resid {info.rel_resid_true:.2e}")
+    assert rc == 0 and info.converged and ref.converged
+    assert abs(info.iters - ref.iters) <= 1
+    assert abs(info.replacements - ref.restarts) <= 1
+    assert info.rel_resid_true <= 1e-6
+    assert err <= 1e-8
+    ctx.close()
+
+
+def test_gmres_agrees_with_pcg_and_runs_the_fp32_vcycle():
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG, FP32_VCYCLE
+    perm = make_field("gauss", 32, 4)
+    b = make_source("quarter_five_spot", perm.shape).reshape(-1)
+    n = b.size
+    res = {}
+    for prec in (0, FP32_VCYCLE):
+        ctx = SpecMG(to_dev(perm), levels=3, eigs_per_subdomain=4, agg=2, precision=prec)
+        xg = torch.empty(n, dtype=torch.float64, device="cuda")
+        xp = torch.empty(n, dtype=torch.float64, device="cuda")
+        _, ig = ctx.gmres_solve(to_dev(b), xg, restart=30, tol=1e-8)
+        _, ip = ctx.pcg_solve(to_dev(b), xp, tol=1e-8)
+        res[prec] = (to_host(xg), ig, to_host(xp), ip)
+        ctx.close()
+    x64, ig64, xp64, ip64 = res[0]
+    x32, ig32, _, _ = res[FP32_VCYCLE]
+    print(f"fp64: gmres {ig64.iters} steps, pcg {ip64.iters} iterations; fp32 V-cycle: gmres {ig32.iters} steps")
+    assert ig64.converged and ip64.converged and ig32.converged
+    assert ig32.rel_resid_true <= 1e-8
+    assert ig32.iters <= int(1.1 * ig64.iters) + 1
+    # both solve A x = b to 1e-8: their difference is bounded by the residuals
+    assert np.linalg.norm(x64 - xp64) <= 1e-5 * np.linalg.norm(xp64)
+    assert np.linalg.norm(x32 - x64) <= 1e-5 * np.linalg.norm(x64)
+
+
+def test_gmres_rejects_bad_arguments():
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG, EINVAL
+    perm = make_field("gauss", 16, 1)
+    ctx = SpecMG(to_dev(perm), levels=2, eigs_per_subdomain=4, agg=2)
+    b = torch.as_tensor(make_source("corner", perm.shape).reshape(-1), device="cuda")
+    x = torch.empty_like(b)
+    for restart in (0, 65):
+        rc, _ = ctx.gmres_solve(b, x, restart=restart, raise_on_error=False)
+        assert rc == EINVAL
+    rc, _ = ctx.gmres_solve(b, b, raise_on_error=False)
+    assert rc == EINVAL
+    ctx.close()
