@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="gauss128", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_vcycle"])
+    ap.add_argument("--solver", default="pcg", choices=["pcg", "gmres"],
+                    help="outer Krylov solver (GMRES: restarted, flexible, right-preconditioned)")
+    ap.add_argument("--restart", type=int, default=30, help="GMRES restart length")
+    ap.add_argument("--levels", type=int, default=None, help="override the workload's number of levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="edge of the field crop timed on the CPU oracle")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -74,13 +78,14 @@ def cpu_baseline(perm, wl, edge):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, not code).", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE
 
     wl = WORKLOADS[args.config]
+    levels = args.levels or wl.levels
     prec = args.precision or wl.precision
     n = wl.n
     perm_h = make_field(wl.kind, n, wl.seed)
@@ -101,8 +106,13 @@ def main():
         del src, dst
 
     def step(profile):
-        ctx = SpecMG(perm, levels=wl.levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision,
+        ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision,
                      eigs_coarse=wl.eigs_coarse, allow_unconverged=True)
+        if args.solver == "gmres":
+            # the per-kernel timing covers the CG solve only
+            rc, info = ctx.gmres_solve(b, x, restart=args.restart, tol=1e-6, max_iter=1000)
+            ctx.close()
+            return info, None
         if profile:
             ctx.set_profiling(True)
         rc, info = ctx.pcg_solve(b, x, tol=1e-6, max_iter=1000)
@@ -114,15 +124,21 @@ def main():
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # Only the last timed step records HIP events around every kernel (the
+    # per-kernel durations of the roofline); with two or more steps the solve
+    # time comes from the steps without them, whose solve the events do not
+    # slow down.
     infos, profs = [], []
-    for _ in range(args.steps):
-        info, prof = step(True)
+    for i in range(args.steps):
+        info, prof = step(i == args.steps - 1)
         infos.append(info)
-        profs.append(prof)
+        if prof is not None:
+            profs.append(prof)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
 
-    solve_s = float(np.mean([i.solve_ms for i in infos])) / 1e3
+    plain = infos[:-1] if (len(infos) > 1 and profs) else infos
+    solve_s = float(np.mean([i.solve_ms for i in plain])) / 1e3
     setup_s = float(np.mean([i.setup_ms for i in infos])) / 1e3
     iters = [i.iters for i in infos]
     dof = n ** 3
@@ -135,17 +151,23 @@ def main():
             a[1] += cnt
     fine = [k for k in tot if k in ("cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth",
                                     "post_residual")]
-    dom = max(fine, key=lambda k: tot[k][0])
-    ms, cnt, by = tot[dom]
-    from paper_2403_19342_amd.profile_summary import read_traffic
-    measured = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{wl.name}.md"))
-    avg_ms = ms / max(cnt, 1)
-    achieved = by / (avg_ms * 1e-3) / 1e9
+    roofline = None
+    if fine:
+        dom = max(fine, key=lambda k: tot[k][0])
+        ms, cnt, by = tot[dom]
+        from paper_2403_19342_amd.profile_summary import read_traffic
+        measured = read_traffic(os.path.join(ROOT, "profiles", f"hbm_traffic_{wl.name}.md"))
+        avg_ms = ms / max(cnt, 1)
+        achieved = by / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured.get(dom),
+                    "bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3}
     kernels = {k: {"avg_us": 1e3 * v[0] / max(v[1], 1), "launches": v[1],
                    "GBps": (v[2] / (v[0] / max(v[1], 1) * 1e-3) / 1e9) if v[2] and v[0] else None}
                for k, v in tot.items() if v[1]}
     out = {
-        "metric": "PCG solve to 1e-6 relative residual, DoF per second of solve time",
+        "metric": ("PCG" if args.solver == "pcg" else "GMRES") +
+                  " solve to 1e-6 relative residual, DoF per second of solve time",
         "value": dof / solve_s,
         "unit": "DoF/s",
         "n_gpus": 1,
@@ -155,22 +177,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == FP64 else "f32 V-cycle / f64 CG",
+        "dtype": "f64" if precision == FP64 else ("f32 V-cycle / f64 " + ("CG" if args.solver == "pcg" else "GMRES")),
         "data": "synthetic",
-        "config": {"workload": wl.name, "grid": f"{n}^3", "dof": dof, "levels": wl.levels,
+        "config": {"workload": wl.name, "grid": f"{n}^3", "dof": dof, "levels": levels, "solver": args.solver,
                    "eigs_per_subdomain": wl.eigs, "eigs_coarse": wl.eigs_coarse or wl.eigs, "agg": agg,
                    "field": wl.kind, "source": wl.source,
                    "tol": 1e-6, "precision": prec},
         "solve_ms": solve_s * 1e3,
+        "solve_ms_profiled_step": infos[-1].solve_ms,
         "setup_ms": setup_s * 1e3,
         "iters": iters,
         "rel_resid_true": [i.rel_resid_true for i in infos],
         "eig_unconverged": [i.eig_unconverged for i in infos],
-        "dims": list(infos[-1].dims)[: wl.levels],
+        "dims": list(infos[-1].dims)[: levels],
         "kernels": kernels,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured.get(dom),
-                     "bytes_per_launch": by, "avg_launch_us": avg_ms * 1e3},
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(perm_h, wl, args.cpu_sample)
