@@ -238,7 +238,14 @@ __device__ __forceinline__ int pencil_m(int r, int jk) { return (r - jk) & 7; }
 
 // The lane's 8 cells are contiguous in memory (64 bytes for float64): they
 // move with 16-byte vector accesses and are rotated into (out of) the slot
-// order in registers by a 3-stage barrel shifter on j + k.
+// order in registers by a 3-stage barrel shifter on j + k.  Both candidates
+// of each select pass through an empty asm statement: left alone, the
+// compiler turns "on ? v[a] : v[b]" into v[on ? a : b], an access by a
+// run-time index that it expands into 7 compares and 14 selects per slot
+// and stage instead of 2 selects.
+__device__ __forceinline__ void keep_value(double& v) { asm volatile("" : "+v"(v)); }
+__device__ __forceinline__ void keep_value(float& v) { asm volatile("" : "+v"(v)); }
+
 template <typename T>
 __device__ __forceinline__ void rotate_slots(T (&v)[8], int jk, bool inverse) {
 #pragma unroll
@@ -246,7 +253,12 @@ __device__ __forceinline__ void rotate_slots(T (&v)[8], int jk, bool inverse) {
         const bool on = (jk & b) != 0;
         T t[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) t[s] = on ? v[inverse ? ((s + b) & 7) : ((s - b) & 7)] : v[s];
+        for (int s = 0; s < 8; ++s) {
+            T moved = v[inverse ? ((s + b) & 7) : ((s - b) & 7)], kept = v[s];
+            keep_value(moved);
+            keep_value(kept);
+            t[s] = on ? moved : kept;
+        }
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = t[s];
     }
