@@ -47,21 +47,29 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
 // cosine mode j (j < 8, by increasing p^2+q^2+r^2, ties x before y before z)
-// at integer cell coordinates (x, y, z) of an 8^3 block
-__device__ __forceinline__ float cnn_mode(int j, int x, int y, int z) {
-    int p = 0, q = 0, r = 0;
-    switch (j) {
-        case 1: p = 1; break;
-        case 2: q = 1; break;
-        case 3: r = 1; break;
-        case 4: p = 1; q = 1; break;
-        case 5: p = 1; r = 1; break;
-        case 6: q = 1; r = 1; break;
-        case 7: p = 1; q = 1; r = 1; break;
-        default: break;
-    }
-    const double w = 3.14159265358979323846 / 8.0;
-    return (float)(cos(w * p * (x + 0.5)) * cos(w * q * (y + 0.5)) * cos(w * r * (z + 0.5)));
+// at integer cell coordinates (x, y, z) of an 8^3 block (-1..8 on the patch
+// grid), cos(pi p (x+1/2)/8) cos(pi q (y+1/2)/8) cos(pi r (z+1/2)/8) with
+// p, q, r in {0, 1}: a product of 1-D factors, read from c1[x + 1] =
+// cos(pi (x+1/2)/8) (a factor with exponent 0 is 1).
+// (p, q, r) of mode j as bit j of three masks: p for j in {1, 4, 5, 7},
+// q for {2, 4, 6, 7}, r for {3, 5, 6, 7}
+__device__ __forceinline__ void cnn_mode_pqr(int j, int& p, int& q, int& r) {
+    p = (0xB2 >> j) & 1;
+    q = (0xD4 >> j) & 1;
+    r = (0xE8 >> j) & 1;
+}
+
+// the 10 factors c1[0..9] for x = -1..8; every thread of the block calls it
+__device__ __forceinline__ void cnn_cos_table(double* c1) {
+    if (threadIdx.x < 10) c1[threadIdx.x] = cos(3.14159265358979323846 / 8.0 * ((int)threadIdx.x - 1 + 0.5));
+    __syncthreads();
+}
+
+__device__ __forceinline__ float cnn_mode(const double* c1, int j, int x, int y, int z) {
+    int p, q, r;
+    cnn_mode_pqr(j, p, q, r);
+    const double fx = p ? c1[x + 1] : 1.0, fy = q ? c1[y + 1] : 1.0, fz = r ? c1[z + 1] : 1.0;
+    return (float)(fx * fy * fz);
 }
 
 // ---------------------------------------------------------------------------
@@ -109,13 +117,13 @@ __global__ __launch_bounds__(256) void k_cnn_patches(FineGeom g, const double* _
 //   IN = 2: the network input: channel 0 the patch [e][1000], channel
 //           c >= 1 the cosine mode c-1 on the patch grid
 template <int IN>
-__device__ __forceinline__ float stage_value(const float* xe, int c, int r) {
+__device__ __forceinline__ float stage_value(const float* xe, int c, int r, const double* c1) {
     const int X = r % 10 - 1, Y = (r / 10) % 10 - 1, Z = r / 100 - 1;
     if (IN == 1) {
         const bool in = X >= 0 && X < 8 && Y >= 0 && Y < 8 && Z >= 0 && Z < 8;
         return in ? xe[(size_t)c * 512 + X + 8 * Y + 64 * Z] : 0.0f;
     }
-    return c == 0 ? xe[r] : cnn_mode(c - 1, X, Y, Z);
+    return c == 0 ? xe[r] : cnn_mode(c1, c - 1, X, Y, Z);
 }
 
 template <int CIN>
@@ -140,6 +148,8 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
     constexpr int INSZ = IN == 1 ? 512 : kCnnIn;
     constexpr int ESZ = IN == 1 ? CIN * INSZ : kCnnIn;
     __shared__ float tile[CH * kCnnTile];
+    __shared__ double c1[10];
+    cnn_cos_table(c1);
     const int e = blockIdx.x;
     const int p = threadIdx.x;
     const int base = (p >> 6) * 100 + ((p >> 3) & 7) * 10 + (p & 7);
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
     for (int c0 = 0; c0 < CIN; c0 += CH) {
         __syncthreads();
         for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x)
-            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile);
+            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile, c1);
         __syncthreads();
 #pragma unroll 1
         for (int cl = 0; cl < CH; ++cl) {
@@ -175,7 +185,7 @@ __global__ __launch_bounds__(512) void k_conv(const float* __restrict__ x, const
         float v = acc[o];
         if (ACT == 1) v = fmaxf(v, 0.0f);
         if (ACT == 2) v = mask[i] > 0.0f ? v : 0.0f;
-        if (ACT == 3) v += cnn_mode(o, p & 7, (p >> 3) & 7, p >> 6);
+        if (ACT == 3) v += cnn_mode(c1, o, p & 7, (p >> 3) & 7, p >> 6);
         y[i] = v;
     }
 }
@@ -206,6 +216,8 @@ __global__ __launch_bounds__(512) void k_conv_mfma(const float* __restrict__ x, 
     static_assert(COUTP % 16 == 0 && COUT <= COUTP, "output tiles of 16");
     constexpr int NT = COUTP / 16;
     __shared__ uint4 tile[2 * kMfPos * 4];   // [part][position][4 x 8 channels]
+    __shared__ double c1[10];
+    if (ACT == 3) cnn_cos_table(c1);
     const int e = blockIdx.x;
     for (int i = threadIdx.x; i < 2 * kMfPos * 4; i += blockDim.x) tile[i] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
@@ -279,7 +291,7 @@ __global__ __launch_bounds__(512) void k_conv_mfma(const float* __restrict__ x, 
                 if (ACT == 1) v[i] = fmaxf(v[i], 0.0f);
                 if (ACT == 3) {
                     const int p = p0 + i;
-                    v[i] += cnn_mode(o, p & 7, (p >> 3) & 7, p >> 6);
+                    v[i] += cnn_mode(c1, o, p & 7, (p >> 3) & 7, p >> 6);
                 }
             }
             *(float4*)(y + ((size_t)e * COUT + o) * 512 + p0) = make_float4(v[0], v[1], v[2], v[3]);
@@ -305,6 +317,8 @@ __global__ __launch_bounds__(320) void k_conv_wgrad(const float* __restrict__ x,
     constexpr int GLD = 513;   // odd row pitch: lanes with different o hit different banks
     __shared__ float tile[CH * kCnnTile];
     __shared__ float sg[COUT * GLD];
+    __shared__ double c1[10];
+    cnn_cos_table(c1);
     const int c0 = blockIdx.y * CH;
     const int q = threadIdx.x;
     const bool act = q < CH * COUT;
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(320) void k_conv_wgrad(const float* __restrict__ x,
         __syncthreads();
         const float* xe = x + (size_t)e * ESZ;
         for (int t = threadIdx.x; t < CH * kCnnTile; t += blockDim.x)
-            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile);
+            tile[t] = stage_value<IN>(xe, c0 + t / kCnnTile, t % kCnnTile, c1);
         const float* ge = gy + (size_t)e * COUT * 512;
         for (int t = threadIdx.x; t < COUT * 512; t += blockDim.x) sg[(t >> 9) * GLD + (t & 511)] = ge[t];
         __syncthreads();
