@@ -299,6 +299,92 @@ __global__ __launch_bounds__(512) void k_conv_mfma(const float* __restrict__ x, 
     }
 }
 
+// The first layer (C1 = 1 + k <= 8 input channels: the patch and the mode
+// channels, valid 3x3x3 over the 10^3 patch grid) on the same matrix-core
+// tile: K = 32 is 4 taps x 8 channels (channels >= C1 and the 28th tap are
+// zero), so the 27 taps take 7 K-steps.  Lane l supplies tap 4 step + l/16.
+// The patch is staged as [part][position (10^3)][8 channels] bf16.
+// mf1[step][o][tap in step][8 channels] (bf16) holds the weights.
+constexpr int kMf1Steps = 7;
+
+template <int C1>
+__global__ __launch_bounds__(512) void k_conv1_mfma(const float* __restrict__ x, const uint16_t* __restrict__ mf,
+                                                    const float* __restrict__ bias, float* __restrict__ y) {
+    static_assert(C1 <= 8, "at most 8 input channels");
+    __shared__ uint4 tile[2 * kMfPos];   // [part][position]: 8 channels
+    __shared__ double c1[10];
+    cnn_cos_table(c1);
+    const int e = blockIdx.x;
+    const float* xe = x + (size_t)e * kCnnIn;
+    for (int P = threadIdx.x; P < kMfPos; P += blockDim.x) {
+        const int X = P % 10 - 1, Y = (P / 10) % 10 - 1, Z = P / 100 - 1;
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            float v[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int c = 2 * h + u;
+                v[u] = c == 0 ? xe[P] : (c < C1 ? cnn_mode(c1, c - 1, X, Y, Z) : 0.0f);
+            }
+            const uint16_t h0 = f2bf(v[0]), h1 = f2bf(v[1]);
+            const uint16_t l0 = f2bf(v[0] - bf2f(h0)), l1 = f2bf(v[1] - bf2f(h1));
+            hw[h] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            lw[h] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        }
+        tile[P] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        tile[kMfPos + P] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int r = l & 15, g = l >> 4;
+    int base[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int p = 16 * (4 * w + j) + r;
+        base[j] = (p >> 6) * 100 + ((p >> 3) & 7) * 10 + (p & 7);
+    }
+    f32x4_t acc[4][2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const float b0 = bias[16 * n + r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j][n] = f32x4_t{b0, b0, b0, b0};
+    }
+#pragma unroll 1
+    for (int st = 0; st < kMf1Steps; ++st) {
+        const int t = 4 * st + g;   // this lane's tap (t = 27: zero weights)
+        const int off = t < 27 ? (t / 9) * 100 + ((t / 3) % 3) * 10 + (t % 3) : 0;
+        bf16x8_t bw[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+            bw[n] = __builtin_bit_cast(bf16x8_t,
+                                       *(const uint4*)(mf + ((size_t)(st * 32 + 16 * n + r) * 4 + g) * 8));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int P = base[j] + off;
+            const bf16x8_t ah = __builtin_bit_cast(bf16x8_t, tile[P]);
+            const bf16x8_t al = __builtin_bit_cast(bf16x8_t, tile[kMfPos + P]);
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bw[n], acc[j][n], 0, 0, 0);
+                acc[j][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bw[n], acc[j][n], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int o = 16 * n + r;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p0 = 16 * (4 * w + j) + 4 * g;
+            *(float4*)(y + ((size_t)e * 32 + o) * 512 + p0) =
+                make_float4(fmaxf(acc[j][n][0], 0.0f), fmaxf(acc[j][n][1], 0.0f), fmaxf(acc[j][n][2], 0.0f),
+                            fmaxf(acc[j][n][3], 0.0f));
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradients: part[b][(o*CIN + c)*27 + t] = sum over the elements of
 // block column b of sum_p gy[e][o][p] x[e][c][p + t] (padded coordinates),
@@ -492,7 +578,9 @@ __global__ __launch_bounds__(512) void k_cnn_loss(const float* __restrict__ X, c
 //   fwd1[c][t][16], fwd2[c][t][16], fwd3[c][t][KP/2]       (pairs of outputs)
 //   bwd2[o][t][16], bwd3[o][t][16] with flipped taps       (pairs of inputs)
 //   mf2[t][32][32], mf3[t][16][32]: bf16 [tap][output][input] for the
-//   matrix-core kernel (outputs of layer 3 beyond k are zero), 16-byte aligned
+//   matrix-core kernel (outputs of layer 3 beyond k are zero), 16-byte aligned;
+//   mf1[step][32][4][8]: layer 1 as K-steps of 4 taps x 8 channels (zero
+//   beyond C1 channels and beyond tap 26)
 struct CnnPacks {
     uint32_t* fwd1;
     uint32_t* fwd2;
@@ -504,6 +592,7 @@ struct CnnPacks {
     float* b3;
     uint16_t* mf2;
     uint16_t* mf3;
+    uint16_t* mf1;
 };
 
 __device__ __forceinline__ float cnn_param(const float* t32, const uint16_t* t16, size_t i) {
@@ -578,9 +667,13 @@ __global__ void k_cnn_pack_mf(const float* __restrict__ t32, const uint16_t* __r
                               CnnPacks pk) {
     const int c1 = 1 + k;
     const size_t oW2 = (size_t)32 * c1 * 27 + 32, oW3 = oW2 + 32 * 32 * 27 + 32;
-    const int n2 = 27 * 32 * 32, n3 = 27 * 16 * 32;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2 + n3; i += gridDim.x * blockDim.x) {
-        if (i < n2) {
+    const int n2 = 27 * 32 * 32, n3 = 27 * 16 * 32, n1 = kMf1Steps * 32 * 4 * 8;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2 + n3 + n1; i += gridDim.x * blockDim.x) {
+        if (i >= n2 + n3) {
+            const int j = i - n2 - n3, st = j / 1024, o = (j / 32) % 32, gg = (j / 8) % 4, c = j % 8;
+            const int t = 4 * st + gg;
+            pk.mf1[j] = (t < 27 && c < c1) ? f2bf(cnn_param(t32, t16, ((size_t)o * c1 + c) * 27 + t)) : (uint16_t)0;
+        } else if (i < n2) {
             const int t = i / 1024, o = (i / 32) % 32, c = i % 32;
             pk.mf2[i] = f2bf(cnn_param(t32, t16, oW2 + ((size_t)o * 32 + c) * 27 + t));
         } else {
@@ -621,7 +714,9 @@ static size_t cnn_pack_words_vec(int kp) {
     return (w + 3) & ~(size_t)3;
 }
 
-size_t cnn_pack_words(int kp) { return cnn_pack_words_vec(kp) + (27 * 32 * 32 + 27 * 16 * 32) / 2; }
+size_t cnn_pack_words(int kp) {
+    return cnn_pack_words_vec(kp) + (27 * 32 * 32 + 27 * 16 * 32 + kMf1Steps * 32 * 4 * 8) / 2;
+}
 
 CnnPacks cnn_pack_view(void* base, int kp) {
     CnnPacks p;
@@ -636,6 +731,7 @@ CnnPacks cnn_pack_view(void* base, int kp) {
     p.b3 = p.b2 + 32;
     p.mf2 = (uint16_t*)(u + cnn_pack_words_vec(kp));
     p.mf3 = p.mf2 + 27 * 32 * 32;
+    p.mf1 = p.mf3 + 27 * 16 * 32;
     return p;
 }
 
@@ -662,8 +758,13 @@ void launch_cnn_pack(const float* t32, const uint16_t* t16, int k, int kp, void*
 void launch_cnn_forward(const void* packs, int kp, const float* patches, int count, float* a1, float* a2, float* X,
                         hipStream_t s) {
     const CnnPacks p = cnn_pack_view(const_cast<void*>(packs), kp);
-    SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<C1, 32, 2, 1>), dim3(count), dim3(512), 0, s, patches,
-                                              p.fwd1, p.b1, nullptr, a1));
+    if (kp <= 6) {
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv1_mfma<(C1 <= 8 ? C1 : 8)>), dim3(count), dim3(512), 0, s,
+                                                  patches, p.mf1, p.b1, a1));
+    } else {
+        SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv<C1, 32, 2, 1>), dim3(count), dim3(512), 0, s, patches,
+                                                  p.fwd1, p.b1, nullptr, a1));
+    }
     hipLaunchKernelGGL((k_conv_mfma<32, 32, 1>), dim3(count), dim3(512), 0, s, a1, p.mf2, p.b2, a2);
     SPECMG_KP_DISPATCH(kp, hipLaunchKernelGGL((k_conv_mfma<KP, 16, 3>), dim3(count), dim3(512), 0, s, a2, p.mf3,
                                               p.b3, X));
