@@ -19,6 +19,8 @@ with plain NumPy/SciPy building blocks and no blocking or fusion:
   pcg        Preconditioned conjugate gradients around the V-cycle.
   gmres      Restarted flexible GMRES around the V-cycle (the outer solver
              of the paper's experiments, Section 5).
+  flux       Section 2.2: velocity recovery v = M_t^{-1} B^T p (the
+             two-point flux of eq. (velocity)) and the cell mass balance.
   cnn        Extension, not in the paper: the 3D CNN that predicts start
              blocks for the level-2 eigenproblems, its subspace loss and
              gradients (forward and backward written out in float64).
@@ -29,8 +31,10 @@ from .spectral import Hierarchy, build_hierarchy, cluster_cut, threshold_target
 from .vcycle import Preconditioner
 from .pcg import pcg
 from .gmres import fgmres
+from .flux import recover_flux, mass_balance
 
 __all__ = [
     "Grid", "transmissibilities", "assemble", "weight_diag", "neumann_local",
     "Hierarchy", "build_hierarchy", "cluster_cut", "threshold_target", "Preconditioner", "pcg", "fgmres",
+    "recover_flux", "mass_balance",
 ]
