@@ -162,6 +162,27 @@ int specmg_gmres_solve(specmg_ctx* ctx, const double* rhs_dev, double* x_dev, in
                        int32_t restart, double tol, int32_t max_iter, specmg_solve_info* info,
                        void* stream);
 
+/* Velocity recovery v = M_t^{-1} B^T p (Section 2.2; the two-point flux of
+ * eq. (velocity)): vx_dev[i] (vy, vz) receives the flux through the +x (+y,
+ * +z) face of cell i, -kappa_f (p_j - p_i) / h with the harmonic mean
+ * kappa_f of the two cells' permeabilities, and 0 on the no-flow boundary.
+ * p_dev: float64 cell vector (a pressure from specmg_pcg_solve or
+ * specmg_gmres_solve); all arrays n float64 values, x fastest, caller-owned,
+ * none may alias another.  Asynchronous.  Errors: SPECMG_EINVAL,
+ * SPECMG_EDEVICE. */
+int specmg_recover_flux(specmg_ctx* ctx, const double* p_dev, double* vx_dev, double* vy_dev,
+                        double* vz_dev, void* stream);
+
+/* Cell mass balance of a face flux (Section 2.2, conservation on a fine
+ * element): res_dev[i] = (1/h) sum_axes (v_{+} - v_{-}) - f_dev[i], the
+ * discrete divergence of v minus the source, with v_{-} the + face of the
+ * lower neighbour (0 at the boundary).  For the flux recovered from p it
+ * equals (A p - f)_i up to rounding.  Layout and ownership as for
+ * specmg_recover_flux.  Asynchronous.  Errors: SPECMG_EINVAL,
+ * SPECMG_EDEVICE. */
+int specmg_mass_balance(specmg_ctx* ctx, const double* vx_dev, const double* vy_dev,
+                        const double* vz_dev, const double* f_dev, double* res_dev, void* stream);
+
 /* y = A x with the fine TPFA operator (eq. p).  Asynchronous. */
 int specmg_apply_operator(specmg_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
 

@@ -925,6 +925,39 @@ extern "C" int specmg_gmres_solve(specmg_ctx* c, const double* rhs, double* x, i
     }
 }
 
+namespace specmg {
+void launch_flux(int nx, int ny, int nz, double h, const double* kt, const double* p, double* vx, double* vy,
+                 double* vz, hipStream_t s);
+void launch_mass_balance(int nx, int ny, int nz, double h, const double* vx, const double* vy, const double* vz,
+                         const double* f, double* res, hipStream_t s);
+}  // namespace specmg
+
+extern "C" int specmg_recover_flux(specmg_ctx* c, const double* p, double* vx, double* vy, double* vz,
+                                   void* stream) {
+    g_last_error.clear();
+    if (!c || !p || !vx || !vy || !vz) return fail(SPECMG_EINVAL, "null argument");
+    try {
+        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->kt, p, vx, vy, vz, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_mass_balance(specmg_ctx* c, const double* vx, const double* vy, const double* vz,
+                                   const double* f, double* res, void* stream) {
+    g_last_error.clear();
+    if (!c || !vx || !vy || !vz || !f || !res) return fail(SPECMG_EINVAL, "null argument");
+    try {
+        launch_mass_balance(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, vx, vy, vz, f, res, (hipStream_t)stream);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError& e) {
+        return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return SPECMG_OK;
+}
+
 extern "C" int specmg_get_info(specmg_ctx* c, int32_t* levels, int32_t* dims, int32_t* elems, int32_t* widths,
                                specmg_solve_info* setup_info) {
     if (!c) return fail(SPECMG_EINVAL, "null context");

@@ -20,7 +20,8 @@ OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1
 FP64, FP32_VCYCLE = 0, 1
 WS_NONE, WS_CNN = 0, 1
 
-EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve", "specmg_apply_operator",
+EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve",
+            "specmg_recover_flux", "specmg_mass_balance", "specmg_apply_operator",
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
@@ -84,6 +85,10 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_pcg_solve.restype = ctypes.c_int
     lib.specmg_gmres_solve.argtypes = [vp, vp, vp, i32, i32, dbl, i32, ctypes.POINTER(SolveInfo), vp]
     lib.specmg_gmres_solve.restype = ctypes.c_int
+    lib.specmg_recover_flux.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.specmg_recover_flux.restype = ctypes.c_int
+    lib.specmg_mass_balance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.specmg_mass_balance.restype = ctypes.c_int
     lib.specmg_apply_operator.argtypes = [vp, vp, vp, vp]
     lib.specmg_apply_operator.restype = ctypes.c_int
     lib.specmg_get_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32 * 8), ctypes.POINTER(i32 * 8),
@@ -228,6 +233,16 @@ class SpecMG:
         if rc != OK and raise_on_error:
             _check(rc)
         return rc, info
+
+    def recover_flux(self, p, vx, vy, vz):
+        """Face fluxes of the recovered velocity (specmg_recover_flux)."""
+        _check(_lib.specmg_recover_flux(self._ctx, _dev_ptr(p), _dev_ptr(vx), _dev_ptr(vy), _dev_ptr(vz),
+                                        _stream()))
+
+    def mass_balance(self, vx, vy, vz, f, res):
+        """res = discrete divergence of v minus f (specmg_mass_balance)."""
+        _check(_lib.specmg_mass_balance(self._ctx, _dev_ptr(vx), _dev_ptr(vy), _dev_ptr(vz), _dev_ptr(f),
+                                        _dev_ptr(res), _stream()))
 
     def set_profiling(self, on: bool = True):
         _check(_lib.specmg_set_profiling(self._ctx, int(on)))
