@@ -92,3 +92,21 @@ def test_gmres_rejects_bad_arguments():
     rc, _ = ctx.gmres_solve(b, b, raise_on_error=False)
     assert rc == EINVAL
     ctx.close()
+
+
+def test_gmres_from_a_converged_start():
+    # use_x0: started from a solution that already meets the tolerance, GMRES
+    # takes no step and returns that solution (shifted to zero mean)
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm = make_field("gauss", 32, 1)
+    b = make_source("corner", perm.shape).reshape(-1)
+    ctx = SpecMG(to_dev(perm), levels=3, eigs_per_subdomain=4, agg=2)
+    x = torch.empty(b.size, dtype=torch.float64, device="cuda")
+    ctx.pcg_solve(to_dev(b), x, tol=1e-9)
+    x0 = to_host(x).copy()
+    rc, info = ctx.gmres_solve(to_dev(b), x, tol=1e-6, use_x0=True)
+    print(f"restart from a 1e-9 solution: {info.iters} steps, true resid {info.rel_resid_true:.2e}")
+    assert rc == 0 and info.converged and info.iters == 0
+    assert np.linalg.norm(to_host(x) - x0) <= 1e-14 * np.linalg.norm(x0)
+    ctx.close()
