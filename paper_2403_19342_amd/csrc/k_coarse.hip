@@ -377,9 +377,11 @@ __global__ __launch_bounds__(256) void k_coarsest_rows(int n, int np, const doub
     if (t < kCoarsestRows && i0 + t < n) e[cmap[i0 + t]] = (T)((red[0][t] + red[1][t]) + (red[2][t] + red[3][t]));
 }
 
+// (spaces of one LDS chunk: each block gathers the compact right-hand side
+// itself from the level vector r through cmap, so no separate gather launch)
 template <typename T, int RW>
 __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* __restrict__ Pinv,
-                                                   const int* __restrict__ cmap, const double* __restrict__ rc,
+                                                   const int* __restrict__ cmap, const T* __restrict__ r,
                                                    T* __restrict__ e, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
     extern __shared__ double srz[];
@@ -391,7 +393,7 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* _
     for (int c0 = 0; c0 < n; c0 += kCoarsestChunk) {
         const int cn = min(kCoarsestChunk, n - c0);
         if (c0) __syncthreads();
-        for (int j = threadIdx.x; j < cn; j += blockDim.x) srz[j] = rc[c0 + j];
+        for (int j = threadIdx.x; j < cn; j += blockDim.x) srz[j] = (double)r[cmap[c0 + j]];
         __syncthreads();
         for (int j = lane; j < cn; j += 64) {
             const double v = srz[j];
@@ -825,12 +827,12 @@ template <typename T>
 void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, double* rc,
                      const Scalars* sc, int check_done, hipStream_t s) {
     const size_t lds = (size_t)std::min(n, kCoarsestChunk) * sizeof(double);
-    hipLaunchKernelGGL((k_gather_compact<T>), dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, n, cmap, r, rc,
-                       sc, check_done);
     if (n <= kCoarsestChunk) {
-        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, rc, e, sc,
+        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
                            check_done);
     } else {
+        hipLaunchKernelGGL((k_gather_compact<T>), dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, n, cmap, r,
+                           rc, sc, check_done);
         hipLaunchKernelGGL((k_coarsest_rows<T>), dim3((n + kCoarsestRows - 1) / kCoarsestRows), dim3(256), lds, s, n,
                            np, Pinv, cmap, rc, e, sc, check_done);
     }
