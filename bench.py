@@ -34,7 +34,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="gauss128", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_vcycle"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32_vcycle", "fp32_basis"])
     ap.add_argument("--solver", default="pcg", choices=["pcg", "gmres"],
                     help="outer Krylov solver (GMRES: restarted, flexible, right-preconditioned)")
     ap.add_argument("--restart", type=int, default=30, help="GMRES restart length")
@@ -82,7 +82,7 @@ def main():
               "(the multi-GPU sharding is a design, not code).", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE
+    from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE, FP32_BASIS
 
     wl = WORKLOADS[args.config]
     levels = args.levels or wl.levels
@@ -95,7 +95,7 @@ def main():
     b = torch.as_tensor(b_h.reshape(-1), device=dev)
     x = torch.zeros(n ** 3, dtype=torch.float64, device=dev)
     agg = wl.agg
-    precision = FP32_VCYCLE if prec == "fp32_vcycle" else FP64
+    precision = {"fp32_vcycle": FP32_VCYCLE, "fp32_basis": FP32_BASIS}.get(prec, FP64)
 
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
@@ -177,7 +177,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if precision == FP64 else ("f32 V-cycle / f64 " + ("CG" if args.solver == "pcg" else "GMRES")),
+        "dtype": {FP64: "f64", FP32_BASIS: "f64, f32 level-2 basis"}.get(
+            precision, "f32 V-cycle / f64 " + ("CG" if args.solver == "pcg" else "GMRES")),
         "data": "synthetic",
         "config": {"workload": wl.name, "grid": f"{n}^3", "dof": dof, "levels": levels, "solver": args.solver,
                    "eigs_per_subdomain": wl.eigs, "eigs_coarse": wl.eigs_coarse or wl.eigs, "agg": agg,

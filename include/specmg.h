@@ -46,6 +46,9 @@ extern "C" {
 
 #define SPECMG_FP64 0            /* every level in float64                  */
 #define SPECMG_FP32_VCYCLE 1     /* V-cycle in float32, CG and coarsest in float64 */
+#define SPECMG_FP32_BASIS 2      /* float64 throughout, the level-2 basis stored
+                                    in float32 (restriction and prolongation
+                                    read it and sum in float64)               */
 
 #define SPECMG_WS_NONE 0         /* cold-started local eigensolves          */
 #define SPECMG_WS_CNN 1          /* warm starts predicted by the 3D CNN     */
@@ -79,7 +82,7 @@ typedef struct {
     int32_t levels;
     int32_t eigs_per_subdomain;
     int32_t nu;
-    int32_t precision;       /* SPECMG_FP64 or SPECMG_FP32_VCYCLE */
+    int32_t precision;       /* SPECMG_FP64, SPECMG_FP32_VCYCLE or SPECMG_FP32_BASIS */
     int32_t warm_start;      /* SPECMG_WS_NONE or SPECMG_WS_CNN   */
     const void* cnn_weights; /* WS_CNN only (eigs_per_subdomain even): device
                                 pointer to the network's bf16 parameter vector

@@ -185,11 +185,11 @@ struct CoarseGeom {
 template <typename T>
 void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q,
                        T* u, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
-template <typename T>
-void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
+template <typename T, typename TB>
+void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const TB* phi,
                            const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s);
-template <typename T>
-void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
+template <typename T, typename TB>
+void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const T* e2,
                     Scalars* sc, int check_done, hipStream_t s);
 template <typename T>
 void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,

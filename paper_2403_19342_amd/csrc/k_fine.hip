@@ -523,10 +523,12 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
     }
 }
 
-template <typename T>
+// TB: word type of the stored basis (float32 copy with float64 vectors in
+// the FP32-basis mode; the products are formed in T)
+template <typename T, typename TB>
 __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
                                                        const T* __restrict__ u, const double* __restrict__ r,
-                                                       const T* __restrict__ phi, const int* __restrict__ nkeep,
+                                                       const TB* __restrict__ phi, const int* __restrict__ nkeep,
                                                        int L, T* __restrict__ r2, const Scalars* sc,
                                                        int check_done) {
     if (check_done && sc->done) return;
@@ -545,16 +547,16 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     pencil_residual(g, kt, u, r, row, x0, y, z, lane, j, k, s);
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
-    const T* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
+    const TB* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
     T acc[kMaxCols];
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
         T a = T(0);
         if (jj < nkp) {
-            T pv[8];
+            TB pv[8];
             load8(ph + (size_t)jj * kSub3, pv);
 #pragma unroll
-            for (int x = 0; x < 8; ++x) a += pv[x] * s[x];
+            for (int x = 0; x < 8; ++x) a += (T)pv[x] * s[x];
         }
         acc[jj] = a;
         // at most three columns of loads in flight (register budget)
@@ -568,8 +570,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
 }
 
 // u += phi e2 on every element (prolongation, Algorithm 1 step 8)
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const T* __restrict__ phi,
+template <typename T, typename TB>
+__global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __restrict__ phi,
                                                   const int* __restrict__ nkeep, int L,
                                                   const T* __restrict__ e2, const Scalars* sc,
                                                   int check_done) {
@@ -577,14 +579,14 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const T* __re
     const int e = blockIdx.x;
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int nk = nkeep[e];
-    const T* ph = phi + (size_t)e * L * kSub3;
+    const TB* ph = phi + (size_t)e * L * kSub3;
     const T* ee = e2 + (size_t)e * L;
     for (int c = threadIdx.x; c < kSub3; c += 256) {
         T acc = T(0);
 #pragma unroll
         for (int jj = 0; jj < kMaxCols; ++jj) {
             const int jc = jj < nk ? jj : nk - 1;
-            acc += (jj < nk ? ph[(size_t)jc * kSub3 + c] : T(0)) * ee[jc];
+            acc += (jj < nk ? (T)ph[(size_t)jc * kSub3 + c] : T(0)) * ee[jc];
         }
         const size_t gi = gidx(g, ex * 8 + (c & 7), ey * 8 + ((c >> 3) & 7), ez * 8 + (c >> 6));
         u[gi] += acc;
@@ -1062,18 +1064,18 @@ void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r,
     if (mode & 1) launch_finalize(RS_RR, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
-template <typename T>
-void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const T* phi,
+template <typename T, typename TB>
+void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const TB* phi,
                            const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s) {
     const int m = g.mx * g.my * g.mz;
-    SPECMG_TIMED_LAUNCH((k_resid_restrict<T>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L, r2,
-                        sc, check_done);
+    SPECMG_TIMED_LAUNCH((k_resid_restrict<T, TB>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L,
+                        r2, sc, check_done);
 }
 
-template <typename T>
-void launch_prolong(const FineGeom& g, T* u, const T* phi, const int* nkeep, int L, const T* e2,
+template <typename T, typename TB>
+void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const T* e2,
                     Scalars* sc, int check_done, hipStream_t s) {
-    SPECMG_TIMED_LAUNCH((k_prolong<T>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
+    SPECMG_TIMED_LAUNCH((k_prolong<T, TB>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
                        sc, check_done);
 }
 
@@ -1168,16 +1170,21 @@ template void launch_pre_smooth<double>(const FineGeom&, const double*, const do
                                         const double*, double*, Scalars*, RedBuf, int, hipStream_t);
 template void launch_pre_smooth<float>(const FineGeom&, const float*, const float*, double*,
                                        const double*, float*, Scalars*, RedBuf, int, hipStream_t);
-template void launch_resid_restrict<double>(const FineGeom&, const double*, const double*, const double*,
-                                            const double*, const int*, int, double*, Scalars*, int,
-                                            hipStream_t);
-template void launch_resid_restrict<float>(const FineGeom&, const float*, const float*, const double*,
-                                           const float*, const int*, int, float*, Scalars*, int,
-                                           hipStream_t);
-template void launch_prolong<double>(const FineGeom&, double*, const double*, const int*, int,
-                                     const double*, Scalars*, int, hipStream_t);
-template void launch_prolong<float>(const FineGeom&, float*, const float*, const int*, int, const float*,
-                                    Scalars*, int, hipStream_t);
+template void launch_resid_restrict<double, double>(const FineGeom&, const double*, const double*, const double*,
+                                                    const double*, const int*, int, double*, Scalars*, int,
+                                                    hipStream_t);
+template void launch_resid_restrict<double, float>(const FineGeom&, const double*, const double*, const double*,
+                                                   const float*, const int*, int, double*, Scalars*, int,
+                                                   hipStream_t);
+template void launch_resid_restrict<float, float>(const FineGeom&, const float*, const float*, const double*,
+                                                  const float*, const int*, int, float*, Scalars*, int,
+                                                  hipStream_t);
+template void launch_prolong<double, double>(const FineGeom&, double*, const double*, const int*, int,
+                                             const double*, Scalars*, int, hipStream_t);
+template void launch_prolong<double, float>(const FineGeom&, double*, const float*, const int*, int,
+                                            const double*, Scalars*, int, hipStream_t);
+template void launch_prolong<float, float>(const FineGeom&, float*, const float*, const int*, int, const float*,
+                                           Scalars*, int, hipStream_t);
 template void launch_residual<double>(const FineGeom&, const double*, const double*, const double*, double*,
                                       const Scalars*, int, hipStream_t);
 template void launch_residual<float>(const FineGeom&, const float*, const float*, const double*, float*,

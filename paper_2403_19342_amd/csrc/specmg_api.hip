@@ -86,6 +86,7 @@ struct specmg_ctx {
     int target_cc = 0, Lcc = 0, nvec_cc = 0;               // levels >= 3
     double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
     int fp32 = 0;
+    int fp32_basis = 0;   // float64 fine level with a float32 copy of the level-2 basis
     int64_t n = 0;
     FineGeom fg{};
     std::vector<void*> allocs;
@@ -248,7 +249,11 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     launch_pre_smooth<T>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
     prof_end(c, ev, PC_PRE, s);
     ev = prof_begin(c, s);
-    launch_resid_restrict<T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
+    if (c->fp32_basis)
+        launch_resid_restrict<T, float>(c->fg, kt, u1, r, l2.basis32, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc,
+                                        check, s);
+    else
+        launch_resid_restrict<T, T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
     prof_end(c, ev, PC_RESTRICT, s);
     ev = prof_begin_range(c, s);
     if constexpr (std::is_same<T, float>::value) {
@@ -264,7 +269,10 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     }
     prof_end(c, ev, c->lev.size() == 1 ? PC_COARSEST : PC_COARSE, s);
     ev = prof_begin(c, s);
-    launch_prolong<T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
+    if (c->fp32_basis)
+        launch_prolong<T, float>(c->fg, u1, l2.basis32, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
+    else
+        launch_prolong<T, T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
     prof_end(c, ev, PC_PROLONG, s);
     T* tres = pick<T>(c->tres, (float*)c->tres);
     ev = prof_begin(c, s);
@@ -502,7 +510,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         if (de != 0) return fail(SPECMG_EDEVICE, std::string("coarsest inverse: ") + hipGetErrorString((hipError_t)de));
     }
     // ---- float32 copy of the level-2 basis for the mixed-precision fine level
-    if (c->fp32) {
+    if (c->fp32 || c->fp32_basis) {
         Level& lv = c->lev[0];
         const size_t nb = (size_t)lv.g.m * lv.L * lv.rows;
         lv.basis32 = c->alloc<float>(nb);
@@ -574,7 +582,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     if (opts->eigs_per_subdomain < 1 || opts->eigs_per_subdomain > 8)
         return fail(SPECMG_EINVAL, "eigs_per_subdomain must be in [1, 8]");
     if (opts->nu != 1) return fail(SPECMG_EINVAL, "only nu = 1 is supported");
-    if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE)
+    if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE &&
+        opts->precision != SPECMG_FP32_BASIS)
         return fail(SPECMG_EINVAL, "unknown precision");
     if (opts->warm_start != SPECMG_WS_NONE && opts->warm_start != SPECMG_WS_CNN)
         return fail(SPECMG_EINVAL, "unknown warm_start");
@@ -605,6 +614,7 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     c->nvec_cc = nvec_for(tcc);
     c->thr_cc = opts->eig_threshold_coarse;
     c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
+    c->fp32_basis = opts->precision == SPECMG_FP32_BASIS;
     int rc;
     try {
         rc = do_setup(c, perm_dev, (hipStream_t)stream);
@@ -1021,8 +1031,9 @@ extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, 
     double b[8] = {0};
     b[PC_SPMV] = n * 8.0 * 7.0;                      // z, p_old, x, kappa~ in; p, q, x out
     b[PC_PRE] = n * (8.0 * 3.0 + 2.0 * w + w);       // r, q in, r out; kappa~, 1/d in; u out
-    b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * w;   // u, kappa~, r; phi
-    b[PC_PROLONG] = n * 2.0 * w + phi_cells * w;             // u in/out; phi
+    const double wb = c->fp32_basis ? 4.0 : w;       // basis word size
+    b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * wb;  // u, kappa~, r; phi
+    b[PC_PROLONG] = n * 2.0 * w + phi_cells * wb;            // u in/out; phi
     b[PC_POST] = n * (4.0 * w + 8.0 * 2.0 + (c->fp32 ? 8.0 : 0.0));  // t, kappa~, 1/d, u, r in; z out (q)
     b[PC_POSTRES] = n * (3.0 * w + 8.0);                                // u, kappa~, r in; t out
     for (int i = 0; i < 8; ++i) {

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspecmg.so")
 
 OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-FP64, FP32_VCYCLE = 0, 1
+FP64, FP32_VCYCLE, FP32_BASIS = 0, 1, 2
 WS_NONE, WS_CNN = 0, 1
 
 EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve",
