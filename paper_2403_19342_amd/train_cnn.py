@@ -114,16 +114,18 @@ def modes_only(k: int):
 
 
 def evaluate(theta16, n: int, seeds, k: int, levels: int = 3, ws_resid_tol: float = 1e-3):
-    """Set-up and solve per test field for four forms: the plain FP64 method
-    (exact local eigensolves), the FP32 V-cycle alone, and the FP32 V-cycle
-    with the learned set-up started from the cosine modes (no network) and
-    from the trained network.  Solutions are compared with the plain one."""
+    """Set-up and solve per test field for five forms: the plain FP64 method
+    (exact local eigensolves), the FP32 V-cycle alone, the FP32 V-cycle with
+    the learned set-up started from the cosine modes (no network) and from
+    the trained network, and the FP32-basis mode with the trained network.
+    Solutions are compared with the plain one."""
     import torch
-    from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE
+    from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE, FP32_BASIS
     from synth.fields import make_source
     out = []
     variants = (("fp64_exact", None, FP64), ("fp32_exact", None, FP32_VCYCLE),
-                ("fp32_modes", modes_only(k), FP32_VCYCLE), ("fp32_trained", theta16, FP32_VCYCLE))
+                ("fp32_modes", modes_only(k), FP32_VCYCLE), ("fp32_trained", theta16, FP32_VCYCLE),
+                ("fp32basis_trained", theta16, FP32_BASIS))
     for sd in seeds:
         perm = torch.as_tensor(learned_field(n, sd), device="cuda")
         b = torch.as_tensor(make_source("quarter_five_spot", (n, n, n)).reshape(-1), device="cuda")
