@@ -73,7 +73,7 @@ constexpr int kMaxLc = 13;   // padded widths up to target 10 + 3
 
 // y_c = (A_l u)_c for row a of child element c; all block-row loads of the
 // thread are issued before the products
-template <typename T>
+template <typename T, int LP = kMaxLc>
 __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __restrict__ Ad,
                                              const T* __restrict__ Aoff, const T* __restrict__ u, int c,
                                              int a) {
@@ -87,7 +87,7 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
         const T* ad = Ad + ((size_t)c * L + a) * L;
         const T* uc = u + (size_t)c * L;
 #pragma unroll
-        for (int b = 0; b < kMaxLc; ++b) {
+        for (int b = 0; b < LP; ++b) {
             const int bb = b < L ? b : L - 1;
             acc += (b < L ? ad[bb] : T(0)) * uc[bb];
         }
@@ -99,7 +99,7 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
             const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
             const T* un = u + (size_t)cn * L;
 #pragma unroll
-            for (int b = 0; b < kMaxLc; ++b) {
+            for (int b = 0; b < LP; ++b) {
                 const int bb = b < L ? b : L - 1;
                 acc += (b < L ? o[bb] : T(0)) * un[bb];
             }
@@ -109,7 +109,7 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
             const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
             const T* un = u + (size_t)cn * L;
 #pragma unroll
-            for (int b = 0; b < kMaxLc; ++b) {
+            for (int b = 0; b < LP; ++b) {
                 const int bb = b < L ? b : L - 1;
                 acc += (b < L ? o[bb * L + a] : T(0)) * un[bb];
             }
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
 }
 
 // s = r - A_l u on the children of E, then r_up[E] = V_E^T s
-template <typename T>
+template <typename T, int LP>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Aoff, const T* __restrict__ r,
     const T* __restrict__ u, const T* __restrict__ V, const int* __restrict__ nkeep_up, int Lup,
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int p = t / L, a = t % L;
         const int c = child_of(g, E, p);
-        sS[t] = r[(size_t)c * L + a] - block_row_apply<T>(g, Ad, Aoff, u, c, a);
+        sS[t] = r[(size_t)c * L + a] - block_row_apply<T, LP>(g, Ad, Aoff, u, c, a);
     }
     __syncthreads();
     const int nk = nkeep_up[E];
@@ -765,26 +765,6 @@ __global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_
 // ---------------------------------------------------------------------------
 // launchers
 
-template <typename T>
-void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
-                                  const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
-                                  int check_done, hipStream_t s) {
-    const int rows = g.agg * g.agg * g.agg * g.L;
-    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_coarse_resid_restrict<T>), dim3(g.M), dim3(th), 0, s, g, Ad, Aoff, r, u, V,
-                       nkeep_up, Lup, rup, sc, check_done);
-}
-
-template <typename T>
-void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nkeep_up, int Lup, const T* eup,
-                           const Scalars* sc, int check_done, hipStream_t s) {
-    const int rows = g.agg * g.agg * g.agg * g.L;
-    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup,
-                       sc, check_done);
-}
-
-// dynamic LDS of the sweep kernels; couplings are staged when they fit
 #define SPECMG_LP_DISPATCH(LV, ...)                           \
     switch (LV) {                                             \
         case 4: { constexpr int LP = 4; __VA_ARGS__; } break;     \
@@ -799,6 +779,27 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
         default: { constexpr int LP = 13; __VA_ARGS__; } break;   \
     }
 
+template <typename T>
+void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
+                                  const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
+                                  int check_done, hipStream_t s) {
+    const int rows = g.agg * g.agg * g.agg * g.L;
+    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
+    if (g.L < 4 || g.L > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual width"};
+    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict<T, LP>), dim3(g.M), dim3(th), 0, s, g, Ad,
+                                               Aoff, r, u, V, nkeep_up, Lup, rup, sc, check_done));
+}
+
+template <typename T>
+void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nkeep_up, int Lup, const T* eup,
+                           const Scalars* sc, int check_done, hipStream_t s) {
+    const int rows = g.agg * g.agg * g.agg * g.L;
+    const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
+    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup,
+                       sc, check_done);
+}
+
+// dynamic LDS of the sweep kernels; couplings are staged when they fit
 static int sweep_threads(const CoarseGeom& g) {
     const int rows = g.agg * g.agg * g.agg * g.L;
     return (rows + 63) / 64 * 64;
