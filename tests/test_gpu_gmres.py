@@ -110,3 +110,24 @@ def test_gmres_from_a_converged_start():
     assert rc == 0 and info.converged and info.iters == 0
     assert np.linalg.norm(to_host(x) - x0) <= 1e-14 * np.linalg.norm(x0)
     ctx.close()
+
+
+def test_gmres_iteration_cap_and_shortest_restart():
+    # max_iter reached: ENOCONV with the last iterate (zero mean, residual
+    # reported); restart length 1 (a minimal-residual step per restart) still
+    # converges on this positive definite preconditioned system
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG, ENOCONV
+    perm = make_field("gauss", 32, 1)
+    b = make_source("corner", perm.shape).reshape(-1)
+    ctx = SpecMG(to_dev(perm), levels=3, eigs_per_subdomain=4, agg=2)
+    x = torch.empty(b.size, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres_solve(to_dev(b), x, restart=30, tol=1e-6, max_iter=3, raise_on_error=False)
+    xh = to_host(x)
+    print(f"capped: rc {rc}, {info.iters} steps, true resid {info.rel_resid_true:.2e}")
+    assert rc == ENOCONV and info.iters == 3 and not info.converged
+    assert abs(xh.mean()) <= 1e-12 * np.max(np.abs(xh)) and 1e-6 < info.rel_resid_true < 1.0
+    rc, info = ctx.gmres_solve(to_dev(b), x, restart=1, tol=1e-6, max_iter=2000)
+    print(f"restart 1: {info.iters} steps, {info.replacements} restarts, true resid {info.rel_resid_true:.2e}")
+    assert rc == 0 and info.converged and info.rel_resid_true <= 1e-6
+    ctx.close()
