@@ -738,6 +738,10 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
     double pyh = hyv ? pval(ghy) : 0.0, kyh = hyv ? kt[ghy] : 0.0;
     double pxh = hxv ? pval(ghx) : 0.0, kxh = hxv ? kt[ghx] : 0.0;
     double pm = (in && z0 > 0) ? pval(gi - sz) : 0.0, km = (in && z0 > 0) ? kt[gi - sz] : 0.0;
+    // x of the deferred update x += alpha p_old, loaded a plane ahead like
+    // the stencil operands (loaded and used in the same plane, its latency
+    // was exposed once per plane)
+    double xv = (in && ax != 0.0) ? x[gi] : 0.0;
     double pq = 0.0;
     for (int zz = 0; zz < kSpZ; ++zz, gi += sz) {
         const int buf = zz & 1;
@@ -757,6 +761,7 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         const double pon = (in && zp && !first) ? pold[gi + sz] : 0.0;
         const double pp = (in && zp) ? (first ? zv[gi + sz] : zv[gi + sz] + beta * pon) : 0.0;
         const double kp = (in && zp) ? kt[gi + sz] : 0.0;
+        const double xvn = (in && zp && ax != 0.0 && zz + 1 < kSpZ) ? x[gi + sz] : 0.0;
         double pyh2 = 0.0, kyh2 = 0.0, pxh2 = 0.0, kxh2 = 0.0;
         if (zz + 1 < kSpZ && zp) {
             if (hyv) {
@@ -780,7 +785,7 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         a += harm(kc, km) * (pc - pm);
         a += harm(kc, kp) * (pc - pp);
         if (in) {
-            if (ax != 0.0) x[gi] += ax * po;
+            if (ax != 0.0) x[gi] = xv + ax * po;
             pnew[gi] = pc;
             q[gi] = a;
             pq += pc * a;
@@ -790,6 +795,7 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         pc = pp;
         kc = kp;
         po = pon;
+        xv = xvn;
         pyh = pyh2;
         kyh = kyh2;
         pxh = pxh2;
