@@ -189,22 +189,33 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
         tv -= acc;
     }
     if (row_ok) sY[t] = tv;
-    // lower coupling rows G[c][2 ax][a][0..LP-1], loaded while the block
-    // synchronises; the upper ones follow the forward sweep, so the two
-    // sets are never live together
-    T gl[3][LP];
+    // lower coupling rows G[c][2 ax][a][0..LP-1] and the pivot row, loaded
+    // while the block synchronises; at widths up to 8 the upper rows too
+    // (one memory round less), wider ones follow the forward sweep so that
+    // the two sets are never live together
+    constexpr bool kUpperEarly = LP <= 8;
+    T gl[3][LP], gu[3][LP], dv[LP];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
 #pragma unroll
         for (int b = 0; b < LP; ++b) gl[ax][b] = G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] * wgt[2 * ax];
     }
+#pragma unroll
+    for (int b = 0; b < LP; ++b) dv[b] = Dinv[row * LP + b];
+    if (kUpperEarly) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+#pragma unroll
+            for (int b = 0; b < LP; ++b)
+                gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
+        }
+    }
     __syncthreads();
     T w = T(0);
     {
-        const T* di = Dinv + row * LP;
         const T* ty = sY + k * LP;
 #pragma unroll
-        for (int b = 0; b < LP; ++b) w += di[b] * ty[b];
+        for (int b = 0; b < LP; ++b) w += dv[b] * ty[b];
     }
     __syncthreads();
     // forward: y = w - sum_lower G y
@@ -224,12 +235,13 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
         __syncthreads();
     }
     // backward: z = y - sum_upper G z
-    T gu[3][LP];
+    if (!kUpperEarly) {
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
+        for (int ax = 0; ax < 3; ++ax) {
 #pragma unroll
-        for (int b = 0; b < LP; ++b)
-            gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
+            for (int b = 0; b < LP; ++b)
+                gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
+        }
     }
     T z = T(0);
     for (int s = nplanes - 1; s >= 0; --s) {
