@@ -21,6 +21,9 @@ with plain NumPy/SciPy building blocks and no blocking or fusion:
              of the paper's experiments, Section 5).
   flux       Section 2.2: velocity recovery v = M_t^{-1} B^T p (the
              two-point flux of eq. (velocity)) and the cell mass balance.
+  impes      Section 6: the two-phase model (relative permeabilities,
+             total mobility, fractional flow) and the improved IMPES step
+             with upstream-weighted explicit saturation sub-steps.
   cnn        Extension, not in the paper: the 3D CNN that predicts start
              blocks for the level-2 eigenproblems, its subspace loss and
              gradients (forward and backward written out in float64).
@@ -32,9 +35,10 @@ from .vcycle import Preconditioner
 from .pcg import pcg
 from .gmres import fgmres
 from .flux import recover_flux, mass_balance
+from . import impes
 
 __all__ = [
     "Grid", "transmissibilities", "assemble", "weight_diag", "neumann_local",
     "Hierarchy", "build_hierarchy", "cluster_cut", "threshold_target", "Preconditioner", "pcg", "fgmres",
-    "recover_flux", "mass_balance",
+    "recover_flux", "mass_balance", "impes",
 ]

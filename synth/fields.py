@@ -165,6 +165,27 @@ def five_spot(shape: tuple[int, int, int]) -> np.ndarray:
     return f
 
 
+def porosity_field(perm: np.ndarray, seed: int, mean: float = 0.2, spread: float = 0.05,
+                   floor: float = 0.05) -> np.ndarray:
+    """Porosity loosely following log-permeability, truncated below at `floor`.
+
+    phi = mean + spread * (standardised log kappa + 0.5 N(0,1)), clipped to
+    [floor, 0.5]; the floor mirrors the truncation of inactive cells in the
+    two-phase model (Section 6).
+    """
+    rng = np.random.default_rng(seed)
+    lk = np.log(np.asarray(perm, dtype=np.float64))
+    sd = lk.std()
+    z = (lk - lk.mean()) / (sd if sd > 0 else 1.0)
+    phi = mean + spread * (z + 0.5 * rng.standard_normal(lk.shape))
+    return np.clip(phi, floor, 0.5)
+
+
+def random_saturation(shape: tuple[int, int, int], seed: int, lo: float = 0.2, hi: float = 0.8) -> np.ndarray:
+    """Uniform water saturation in [lo, hi] per cell."""
+    return np.random.default_rng(seed).uniform(lo, hi, shape)
+
+
 def random_zero_mean(shape: tuple[int, int, int], seed: int) -> np.ndarray:
     """Standard normal vector with its mean removed (a compatible source)."""
     rng = np.random.default_rng(seed)
