@@ -189,6 +189,44 @@ int specmg_mass_balance(specmg_ctx* ctx, const double* vx_dev, const double* vy_
 /* y = A x with the fine TPFA operator (eq. p).  Asynchronous. */
 int specmg_apply_operator(specmg_ctx* ctx, const double* x_dev, double* y_dev, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Two-phase flow (Section 6, eqs. v, div_v, trans_S and the improved IMPES
+ * scheme, eqs. IMP and ES).  Water saturation S, fluid law of Section 6:
+ * S* = clamp((S - 0.2)/0.6, 0, 1), k_w = S*^2, k_o = (1 - S*)^2,
+ * mu_w = 0.3, mu_o = 3.0, lambda = k_w/mu_w + k_o/mu_o,
+ * f_w = (k_w/mu_w)/lambda.  Rate-controlled wells: q > 0 injects water,
+ * q < 0 produces the cell's mixture (q_w = f_w(S) q).  Pressure steps use
+ * specmg_setup on the permeability lambda(S) kappa and a solve warm-started
+ * from the previous pressure; these calls need no context.
+ * ---------------------------------------------------------------------- */
+
+/* perm_eff_dev[i] = perm_dev[i] * lambda(s_dev[i]) for i < n (eq. v: the
+ * pressure system of a step has the permeability lambda(S) K).  Device
+ * arrays of n doubles, owned by the caller; perm_eff_dev may alias
+ * perm_dev.  Asynchronous.  Errors: SPECMG_EINVAL (null pointer, n < 0),
+ * SPECMG_EDEVICE. */
+int specmg_total_mobility(const double* perm_dev, const double* s_dev, double* perm_eff_dev, int64_t n,
+                          void* stream);
+
+/* `substeps` explicit Euler steps of the saturation equation (eq. ES) with
+ * the face velocity held fixed:
+ *   phi_i (S_i' - S_i)/dt + (1/h) sum_faces f_w(S_upstream) v.n = q_w,i,
+ * the upstream cell being the one the face velocity leaves, and
+ * dt = ds_max / max_i |dS_i/dt| (0 when every rate is zero), so that no cell
+ * changes by more than ds_max per sub-step.
+ * grid: nx, ny, nz >= 1 (any sizes), hx = hy = hz > 0; sub and agg unused.
+ * phi_dev, q_dev: porosity (> 0) and total source density per cell;
+ * vx/vy/vz_dev: the velocity through the +x/+y/+z face of every cell (the
+ * layout of specmg_recover_flux; values on boundary faces are not read);
+ * s_dev: in: S at the start, out: S after the sub-steps.  All (nz, ny, nx),
+ * x fastest, doubles.  work_dev: caller-owned scratch of at least
+ * 2 n + 2048 doubles.  t_dev: out, one double, the summed sub-step lengths.
+ * ds_max in (0, 1], substeps >= 0.  Asynchronous; no host synchronisation
+ * between sub-steps.  Errors: SPECMG_EINVAL, SPECMG_EDEVICE. */
+int specmg_transport(const specmg_grid* grid, const double* phi_dev, const double* q_dev, const double* vx_dev,
+                     const double* vy_dev, const double* vz_dev, double* s_dev, int32_t substeps, double ds_max,
+                     double* work_dev, double* t_dev, void* stream);
+
 /* Set-up information: dims[l-1] = dim W_l for l = 1..levels, the element
  * counts per level, and widths[l-1] = the padded per-element width of level
  * l (its target count plus 3; widths[0] = 1).  Arrays must hold 8 entries;

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspecmg.so")
 SOURCES = ["k_fine.hip", "k_coarse.hip", "k_eig.hip", "k_dense.hip", "k_cnn.hip", "k_krylov.hip", "k_flux.hip",
-           "specmg_api.hip", "cnn_api.hip"]
+           "k_transport.hip", "specmg_api.hip", "cnn_api.hip"]
 ARCH = os.environ.get("SPECMG_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC",

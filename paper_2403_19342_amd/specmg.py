@@ -25,7 +25,7 @@ EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
-            "specmg_cnn_loss_backward", "specmg_cnn_adam"]
+            "specmg_cnn_loss_backward", "specmg_cnn_adam", "specmg_total_mobility", "specmg_transport"]
 PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_levels",
                    "coarsest", "post_residual"]
 
@@ -121,6 +121,10 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_cnn_loss_backward.restype = ctypes.c_int
     lib.specmg_cnn_adam.argtypes = [vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, i32, vp, vp]
     lib.specmg_cnn_adam.restype = ctypes.c_int
+    lib.specmg_total_mobility.argtypes = [vp, vp, vp, i64, vp]
+    lib.specmg_total_mobility.restype = ctypes.c_int
+    lib.specmg_transport.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp, i32, dbl, vp, vp, vp]
+    lib.specmg_transport.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -147,6 +151,42 @@ def _dev_ptr(t, dtype=None):
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
         raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def transport_work_size(n: int) -> int:
+    """Doubles of scratch specmg_transport needs for n cells: rates, f_w, per-block maxima."""
+    return 2 * n + 2048
+
+
+def total_mobility(perm, s, perm_eff):
+    """perm_eff = perm * lambda(S) on the device (specmg_total_mobility)."""
+    lib = load_library()
+    if not (perm.numel() == s.numel() == perm_eff.numel()):
+        raise ValueError("perm, s and perm_eff must have the same size")
+    _check(lib.specmg_total_mobility(_dev_ptr(perm), _dev_ptr(s), _dev_ptr(perm_eff), perm.numel(), _stream()))
+
+
+def transport(phi, q, vx, vy, vz, s, h: float, substeps: int, ds_max: float, work, t):
+    """Explicit saturation sub-steps with the face velocity fixed (specmg_transport).
+
+    All fields (nz, ny, nx) float64 CUDA tensors; `s` is updated in place,
+    `work` holds at least transport_work_size(s.numel()) doubles, `t` (one double) receives
+    the summed sub-step lengths.
+    """
+    lib = load_library()
+    if s.dim() != 3:
+        raise ValueError("s must have shape (nz, ny, nx)")
+    nz, ny, nx = s.shape
+    n = s.numel()
+    for a in (phi, q, vx, vy, vz):
+        if a.numel() != n:
+            raise ValueError("every field must have s.numel() entries")
+    if work.numel() < transport_work_size(n) or t.numel() < 1:
+        raise ValueError(f"work needs {transport_work_size(n)} doubles and t one")
+    g = Grid(nx, ny, nz, h, h, h, 8, 2)
+    _check(lib.specmg_transport(ctypes.byref(g), _dev_ptr(phi), _dev_ptr(q), _dev_ptr(vx), _dev_ptr(vy),
+                                _dev_ptr(vz), _dev_ptr(s), int(substeps), float(ds_max), _dev_ptr(work),
+                                _dev_ptr(t), _stream()))
 
 
 @dataclass
