@@ -98,7 +98,16 @@ def main():
     ap.add_argument("--eigs", type=int, default=6)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run three plain device copies of 256 MiB each (counter calibration)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        src = torch.ones((256 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = a.n
     perm = make_field("gauss", n, a.seed)
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
