@@ -12,7 +12,8 @@
   rates zero: dt = 0), and the argument checks.
 - The improved IMPES driver (set-up on lambda(S) kappa, warm-started CG,
   flux recovery, sub-steps) for three pressure steps against the oracle's
-  IMPES with a direct pressure solve: S within 1e-7, p within 1e-7
+  IMPES with a direct pressure solve, on a cube, on a grid whose three
+  extents differ, and with the FP32 V-cycle: S within 1e-7, p within 1e-7
   relative, step lengths within 1e-7 relative (CG stops at 1e-10, and S
   depends on the velocity linearly through M sub-steps).
 """
@@ -105,27 +106,28 @@ def test_transport_edge_cases():
         transport(to_dev(phi), to_dev(q), *[to_dev(x) for x in v], s, 0.125, 1, 1e-3, work[:10], t)
 
 
-def test_impes_driver_matches_oracle():
+@pytest.mark.parametrize("nx,ny,nz,precision", [(32, 32, 32, 0), (48, 32, 16, 0), (32, 32, 32, 1)])
+def test_impes_driver_matches_oracle(nx, ny, nz, precision):
     import torch
     from paper_2403_19342_amd.impes import Impes
-    n = 32
-    g = Grid.unit_cube(n)
-    perm = make_field("gauss", n, 6, sigma=2.0)
+    h = 1.0 / nx
+    g = Grid(nx, ny, nz, h, h, h)
+    perm = make_field("gauss", nx, 6, sigma=2.0, shape=g.shape)
     phi = porosity_field(perm, 6)
     q = five_spot(g.shape)
     s0 = np.full(g.shape, 0.2)
     steps, substeps, ds_max = 3, 20, 1e-2
     sref, pref, tref = im.impes(perm, phi, q, s0, g, steps, substeps, ds_max)
-    run = Impes(to_dev(perm), to_dev(phi), to_dev(q), to_dev(s0), levels=3, eigs=4, agg=2, tol=1e-10,
-                substeps=substeps, ds_max=ds_max)
+    run = Impes(to_dev(perm), to_dev(phi), to_dev(q), to_dev(s0), levels=3, eigs=4, agg=2, h=h, tol=1e-10,
+                substeps=substeps, ds_max=ds_max, precision=precision)
     infos = [run.step() for _ in range(steps)]
     torch.cuda.synchronize()
     s, p = to_host(run.s), to_host(run.p)
     es = np.max(np.abs(s - sref))
     ep = np.linalg.norm(p - pref) / np.linalg.norm(pref)
     et = max(abs(i.dt_total - t) / t for i, t in zip(infos, tref))
-    print(f"IMPES 32^3, 3 steps: iterations {[i.iters for i in infos]}, max |dS| {es:.2e}, p rel {ep:.2e}, "
-          f"t rel {et:.2e}, S range [{s.min():.4f}, {s.max():.4f}]")
+    print(f"IMPES {nx}x{ny}x{nz} precision {precision}, 3 steps: iterations {[i.iters for i in infos]}, "
+          f"max |dS| {es:.2e}, p rel {ep:.2e}, t rel {et:.2e}, S range [{s.min():.4f}, {s.max():.4f}]")
     assert all(i.rel_resid <= 1e-10 for i in infos)
     assert es <= 1e-7 and ep <= 1e-7 and et <= 1e-7
     assert s.max() > 0.3                                   # water has entered
