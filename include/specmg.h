@@ -55,10 +55,14 @@ extern "C" {
 
 typedef struct specmg_ctx specmg_ctx;
 
-/* Grid: nx, ny, nz cells with spacings hx, hy, hz (Section 5 uses the unit
- * cube, h = 1/N).  `sub` is the edge of the level-2 elements in cells (the
- * coarse grid T_c; only 8 is supported), `agg` the number of level-l
- * elements per axis in one level-(l+1) element (2 or 4).  Each of nx, ny, nz
+/* Grid: nx, ny, nz cells with spacings hx, hy, hz, any positive values
+ * (Section 5 uses the unit cube, h = 1/N; Section 6 a grid whose three
+ * spacings differ).  The normalised permeability of eq. (velocity) is
+ * kappa / h_d^2 on the faces of axis d and the weight of eq. (spepb) is its
+ * trace.  The learned warm start needs equal spacings.  `sub` is the edge
+ * of the level-2 elements in cells (the coarse grid T_c; only 8 is
+ * supported), `agg` the number of level-l elements per axis in one
+ * level-(l+1) element (2 or 4).  Each of nx, ny, nz
  * must be divisible by sub * agg^(levels-2). */
 typedef struct {
     int32_t nx, ny, nz;
@@ -214,7 +218,8 @@ int specmg_total_mobility(const double* perm_dev, const double* s_dev, double* p
  * the upstream cell being the one the face velocity leaves, and
  * dt = ds_max / max_i |dS_i/dt| (0 when every rate is zero), so that no cell
  * changes by more than ds_max per sub-step.
- * grid: nx, ny, nz >= 1 (any sizes), hx = hy = hz > 0; sub and agg unused.
+ * grid: nx, ny, nz >= 1 (any sizes), hx = hy = hz > 0 (the sub-step
+ * rule of this call assumes one spacing); sub and agg unused.
  * phi_dev, q_dev: porosity (> 0) and total source density per cell;
  * vx/vy/vz_dev: the velocity through the +x/+y/+z face of every cell (the
  * layout of specmg_recover_flux; values on boundary faces are not read);

@@ -170,6 +170,10 @@ struct FineGeom {
     int ntx, nty, ntz;    // tiles per axis
     int ntiles;
     int xcd_remap;        // 1: blockIdx -> tile mapping keeps each XCD on a slab
+    // y and z face factors (hx/hy)^2 and (hx/hz)^2: kappa~ is stored as
+    // kappa / hx^2, so a y (z) face coefficient is cy (cz) times the
+    // harmonic mean of kappa~; exactly 1 on equal spacings
+    double cy = 1.0, cz = 1.0;
 };
 
 // Coarse level l >= 2: elements on an (mx,my,mz) grid, padded width L.

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __r
         double T = 0.0;
         if (inside) {
             const double a = kt[gid(gx, gy, gz)], b = kt[gid(nx_, ny_, nz_)];
-            T = 2.0 * a * b / (a + b);
+            T = 2.0 * a * b / (a + b) * (ax == 0 ? 1.0 : (ax == 1 ? g.cy : g.cz));
         }
         sT[d][f] = T;
         const int c = i + 8 * (j + 8 * k);

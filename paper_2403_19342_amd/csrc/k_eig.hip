@@ -710,7 +710,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
     };
     const double kc = kt[gid(ex * 8 + i, ey * 8 + j, ez * 8 + k)];
-    const double S = 3.0 * kc;
+    // weight tr K~ = kappa~ (1 + cy + cz); y and z faces carry cy and cz
+    const double wsum = 1.0 + g.cy + g.cz;
+    const double S = wsum * kc;
     const double sq = sqrt(S);
     Op2 op;
     double diag = 0.0, rowsum = 0.0;
@@ -723,9 +725,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         op.nb[d] = c;
         if (ii >= 0 && ii < 8 && jj >= 0 && jj < 8 && kk >= 0 && kk < 8) {
             const double kn = kt[gid(ex * 8 + ii, ey * 8 + jj, ez * 8 + kk)];
-            const double T = harm_e(kc, kn);
+            const double T = harm_e(kc, kn) * (d < 2 ? 1.0 : (d < 4 ? g.cy : g.cz));
             diag += T;
-            op.off[d] = T / (sq * sqrt(3.0 * kn));
+            op.off[d] = T / (sq * sqrt(wsum * kn));
             op.nb[d] = ii + 8 * (jj + 8 * kk);
             rowsum += op.off[d];
         }

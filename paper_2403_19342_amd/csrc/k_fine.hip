@@ -138,15 +138,15 @@ __device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restri
 
 // (A u) at haloed index h
 template <int EX, typename T>
-__device__ __forceinline__ T apply_stencil(const T* U, const T* K, int h) {
+__device__ __forceinline__ T apply_stencil(const T* U, const T* K, int h, T cy, T cz) {
     constexpr int HX = TileT<EX>::HX, HXY = TileT<EX>::HXY;
     const T uc = U[h], kc = K[h];
     T a = harm(kc, K[h - 1]) * (uc - U[h - 1]);
     a += harm(kc, K[h + 1]) * (uc - U[h + 1]);
-    a += harm(kc, K[h - HX]) * (uc - U[h - HX]);
-    a += harm(kc, K[h + HX]) * (uc - U[h + HX]);
-    a += harm(kc, K[h - HXY]) * (uc - U[h - HXY]);
-    a += harm(kc, K[h + HXY]) * (uc - U[h + HXY]);
+    a += harm(kc, K[h - HX]) * cy * (uc - U[h - HX]);
+    a += harm(kc, K[h + HX]) * cy * (uc - U[h + HX]);
+    a += harm(kc, K[h - HXY]) * cz * (uc - U[h - HXY]);
+    a += harm(kc, K[h + HXY]) * cz * (uc - U[h + HXY]);
     return a;
 }
 
@@ -363,12 +363,13 @@ __device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (
 // Minus-face transmissibilities of the pencil's cells inside the element
 // (the neighbour's copy of kappa~ comes from the lane below).
 template <typename T>
-__device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8], T (&fy)[8], T (&fz)[8]) {
+__device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8], T (&fy)[8], T (&fz)[8], T cy,
+                                             T cz) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         fx[r] = harm(kc[r], kc[(r + 7) & 7]);
-        fy[r] = harm(kc[r], from_ym(kc, r));
-        fz[r] = harm(kc[r], from_zm(kc, r));
+        fy[r] = harm(kc[r], from_ym(kc, r)) * cy;
+        fz[r] = harm(kc[r], from_zm(kc, r)) * cz;
     }
     (void)jk;
 }
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     {
         T kc[8];
         load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz);
+        pencil_faces(kc, jk, fx, fy, fz, (T)g.cy, (T)g.cz);
     }
     __builtin_amdgcn_sched_barrier(0);
     T y[8];
@@ -461,9 +462,9 @@ __device__ __forceinline__ void load8<float>(const float* __restrict__ p, float 
 // s -= T (u - u_nb) over the pencil for one neighbour pencil (nu, nk)
 template <typename T>
 __device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T (&kc)[8], const T (&nu)[8],
-                                            const T (&nk)[8]) {
+                                            const T (&nk)[8], T cf) {
 #pragma unroll
-    for (int x = 0; x < 8; ++x) s[x] -= harm(kc[x], nk[x]) * (uc[x] - nu[x]);
+    for (int x = 0; x < 8; ++x) s[x] -= harm(kc[x], nk[x]) * cf * (uc[x] - nu[x]);
 }
 
 // s = r - A u on the x-pencil of row (j, k) of an element (x0 = the
@@ -518,7 +519,7 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
                 for (int x = 0; x < 8; ++x) nk[x] = T(0);
             }
         }
-        face_pencil(s, uc, kc, nu, nk);
+        face_pencil(s, uc, kc, nu, nk, (T)(d < 2 ? g.cy : g.cz));
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
 // Faces leaving the domain have zero transmissibility.
 constexpr int kResZ = 8;
 template <typename T>
-__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, const T* __restrict__ kt,
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, T cy, T cz, const T* __restrict__ kt,
                                                   const T* __restrict__ u, const double* __restrict__ r,
                                                   T* __restrict__ t, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
@@ -622,10 +623,10 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, const 
         const T uyp = yp ? u[gi + sy] : T(0), kyp = yp ? kt[gi + sy] : T(0);
         T a = harm(kc, kxm) * (uc - uxm);
         a += harm(kc, kxp) * (uc - uxp);
-        a += harm(kc, kym) * (uc - uym);
-        a += harm(kc, kyp) * (uc - uyp);
-        a += harm(kc, km) * (uc - um);
-        a += harm(kc, kp) * (uc - up);
+        a += harm(kc, kym) * cy * (uc - uym);
+        a += harm(kc, kyp) * cy * (uc - uyp);
+        a += harm(kc, km) * cz * (uc - um);
+        a += harm(kc, kp) * cz * (uc - up);
         t[gi] = (T)r[gi] - a;
         um = uc;
         km = kc;
@@ -656,7 +657,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     {
         T kc[8];
         load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz);
+        pencil_faces(kc, jk, fx, fy, fz, (T)g.cy, (T)g.cz);
     }
     __builtin_amdgcn_sched_barrier(0);
     T y[8], ix[8];
@@ -780,10 +781,10 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         const double pyp = sp[buf][w + 2][lane + 1], kyp = sk[buf][w + 2][lane + 1];
         double a = harm(kc, kxm) * (pc - pxm);
         a += harm(kc, kxp) * (pc - pxp);
-        a += harm(kc, kym) * (pc - pym);
-        a += harm(kc, kyp) * (pc - pyp);
-        a += harm(kc, km) * (pc - pm);
-        a += harm(kc, kp) * (pc - pp);
+        a += harm(kc, kym) * g.cy * (pc - pym);
+        a += harm(kc, kyp) * g.cy * (pc - pyp);
+        a += harm(kc, km) * g.cz * (pc - pm);
+        a += harm(kc, kp) * g.cz * (pc - pp);
         if (in) {
             if (ax != 0.0) x[gi] = xv + ax * po;
             pnew[gi] = pc;
@@ -823,7 +824,7 @@ __global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* _
     for (int zz = 0; zz < 8; ++zz) {
         const int h = hidx<EX>(tx, ty, zz);
         const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const double a = apply_stencil<EX, double>(sX, sK, h);
+        const double a = apply_stencil<EX, double>(sX, sK, h, g.cy, g.cz);
         y[gi] = resid ? b[gi] - a : a;
     }
 }
@@ -857,18 +858,19 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
             const int ti = 8 * w + i + TX * (j + 8 * k);
             const int h = hidx<EX>(8 * w + i, j, k);
             const double kc = sK[h];
-            double diag = harm(kc, sK[h - 1]) + harm(kc, sK[h + 1]) + harm(kc, sK[h - HX]) +
-                          harm(kc, sK[h + HX]) + harm(kc, sK[h - HXY]) + harm(kc, sK[h + HXY]);
+            double diag = harm(kc, sK[h - 1]) + harm(kc, sK[h + 1]) + harm(kc, sK[h - HX]) * g.cy +
+                          harm(kc, sK[h + HX]) * g.cy + harm(kc, sK[h - HXY]) * g.cz +
+                          harm(kc, sK[h + HXY]) * g.cz;
             if (i > 0) {
                 const double t = harm(kc, sK[h - 1]);
                 diag -= t * t / sDg[ti - 1];
             }
             if (j > 0) {
-                const double t = harm(kc, sK[h - HX]);
+                const double t = harm(kc, sK[h - HX]) * g.cy;
                 diag -= t * t / sDg[ti - TX];
             }
             if (k > 0) {
-                const double t = harm(kc, sK[h - HXY]);
+                const double t = harm(kc, sK[h - HXY]) * g.cz;
                 diag -= t * t / sDg[ti - 8 * TX];
             }
             sDg[ti] = diag;
@@ -1091,7 +1093,7 @@ void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r
                      int check_done, hipStream_t s) {
     if (g.ny % 4 || g.nz % kResZ) throw HipError{hipErrorInvalidValue, "residual tiling"};
     SPECMG_TIMED_LAUNCH((k_residual<T>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ), dim3(256), 0, s, g.nx, g.ny,
-                        g.nz, kt, u, r, t, sc, check_done);
+                        g.nz, (T)g.cy, (T)g.cz, kt, u, r, t, sc, check_done);
 }
 
 template <typename T>

@@ -1,10 +1,10 @@
 // Velocity recovery and the cell mass balance (Section 2.2).  Once A p = f
 // is solved, v = M_t^{-1} B^T p; with the trapezoidal quadrature this is
-// the two-point flux of eq. (velocity) on every interior face,
-//   v_{i+1/2} = -kappa_{i+1/2} (p_{i+1} - p_i) / h = -h kappa~_{i+1/2} (p_{i+1} - p_i)
-// (kappa~ = kappa / h^2, harmonic mean on the face), and zero on the
-// no-flow boundary.  The mass balance of a cell is
-//   (1/h) sum_axes (v_{i+1/2} - v_{i-1/2}) - f_i,
+// the two-point flux of eq. (velocity) on every interior face of axis d,
+//   v_{i+1/2} = -kappa_{i+1/2} (p_{i+1} - p_i) / h_d = -h_d c_d kappa~_{i+1/2} (p_{i+1} - p_i)
+// (kappa~ = kappa / hx^2 as stored, c_d = (hx/h_d)^2, harmonic mean on the
+// face), and zero on the no-flow boundary.  The mass balance of a cell is
+// the face areas times the flux jumps over the cell volume, minus f_i,
 // which is (A p - f)_i up to rounding.  One thread per cell, grid-stride.
 #include "common.hpp"
 
@@ -15,29 +15,31 @@ __device__ __forceinline__ double face_harm(double a, double b) {
     return s > 0.0 ? (2.0 * a * b) / s : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_flux(int nx, int ny, int nz, double h, const double* __restrict__ kt,
+__global__ __launch_bounds__(256) void k_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy,
+                                              double cz, const double* __restrict__ kt,
                                               const double* __restrict__ p, double* __restrict__ vx,
                                               double* __restrict__ vy, double* __restrict__ vz) {
     const int64_t sy = nx, sz = (int64_t)nx * ny, n = sz * nz;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / sy) % ny), z = (int)(i / sz);
         const double kc = kt[i], pc = p[i];
-        vx[i] = x + 1 < nx ? -h * face_harm(kc, kt[i + 1]) * (p[i + 1] - pc) : 0.0;
-        vy[i] = y + 1 < ny ? -h * face_harm(kc, kt[i + sy]) * (p[i + sy] - pc) : 0.0;
-        vz[i] = z + 1 < nz ? -h * face_harm(kc, kt[i + sz]) * (p[i + sz] - pc) : 0.0;
+        vx[i] = x + 1 < nx ? -hx * face_harm(kc, kt[i + 1]) * (p[i + 1] - pc) : 0.0;
+        vy[i] = y + 1 < ny ? -hy * (face_harm(kc, kt[i + sy]) * cy) * (p[i + sy] - pc) : 0.0;
+        vz[i] = z + 1 < nz ? -hz * (face_harm(kc, kt[i + sz]) * cz) * (p[i + sz] - pc) : 0.0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_mass_balance(int nx, int ny, int nz, double h,
+__global__ __launch_bounds__(256) void k_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz,
                                                       const double* __restrict__ vx, const double* __restrict__ vy,
                                                       const double* __restrict__ vz, const double* __restrict__ f,
                                                       double* __restrict__ res) {
     const int64_t sy = nx, sz = (int64_t)nx * ny, n = sz * nz;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / sy) % ny), z = (int)(i / sz);
-        const double net = (vx[i] - (x > 0 ? vx[i - 1] : 0.0)) + (vy[i] - (y > 0 ? vy[i - sy] : 0.0)) +
-                           (vz[i] - (z > 0 ? vz[i - sz] : 0.0));
-        res[i] = net / h - f[i];
+        const double net = hy * hz * (vx[i] - (x > 0 ? vx[i - 1] : 0.0)) +
+                           hx * hz * (vy[i] - (y > 0 ? vy[i - sy] : 0.0)) +
+                           hx * hy * (vz[i] - (z > 0 ? vz[i - sz] : 0.0));
+        res[i] = net / (hx * hy * hz) - f[i];
     }
 }
 
@@ -46,16 +48,16 @@ static int flux_blocks(int64_t n) {
     return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
-void launch_flux(int nx, int ny, int nz, double h, const double* kt, const double* p, double* vx, double* vy,
-                 double* vz, hipStream_t s) {
-    hipLaunchKernelGGL(k_flux, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, h, kt, p, vx,
-                       vy, vz);
+void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
+                 const double* p, double* vx, double* vy, double* vz, hipStream_t s) {
+    hipLaunchKernelGGL(k_flux, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, hx, hy, hz, cy,
+                       cz, kt, p, vx, vy, vz);
 }
 
-void launch_mass_balance(int nx, int ny, int nz, double h, const double* vx, const double* vy, const double* vz,
-                         const double* f, double* res, hipStream_t s) {
-    hipLaunchKernelGGL(k_mass_balance, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, h, vx,
-                       vy, vz, f, res);
+void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,
+                         const double* vz, const double* f, double* res, hipStream_t s) {
+    hipLaunchKernelGGL(k_mass_balance, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, hx, hy,
+                       hz, vx, vy, vz, f, res);
 }
 
 }  // namespace specmg

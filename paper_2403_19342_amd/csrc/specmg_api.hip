@@ -325,6 +325,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     fg.ntz = fg.mz;
     fg.ntiles = fg.ntx * fg.nty * fg.ntz;
     fg.xcd_remap = (fg.ntiles % 8 == 0) ? 1 : 0;
+    fg.cy = (G.hx / G.hy) * (G.hx / G.hy);
+    fg.cz = (G.hx / G.hz) * (G.hx / G.hz);
     if (fg.ntiles > kMaxRedBlocks) return fail(SPECMG_EINVAL, "grid too large for the reduction buffer");
 
     c->dflag = c->alloc<int>(8);
@@ -577,7 +579,9 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     const specmg_grid& G = *grid;
     if (G.sub != 8) return fail(SPECMG_EINVAL, "sub must be 8");
     if (G.agg != 2 && G.agg != 4) return fail(SPECMG_EINVAL, "agg must be 2 or 4");
-    if (!(G.hx > 0) || G.hx != G.hy || G.hx != G.hz) return fail(SPECMG_EINVAL, "equal positive spacings required");
+    if (!(G.hx > 0) || !(G.hy > 0) || !(G.hz > 0) || !std::isfinite(G.hx) || !std::isfinite(G.hy) ||
+        !std::isfinite(G.hz))
+        return fail(SPECMG_EINVAL, "spacings must be positive and finite");
     if (opts->levels < 2 || opts->levels > 8) return fail(SPECMG_EINVAL, "levels must be in [2, 8]");
     if (opts->eigs_per_subdomain < 1 || opts->eigs_per_subdomain > 8)
         return fail(SPECMG_EINVAL, "eigs_per_subdomain must be in [1, 8]");
@@ -589,6 +593,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
         return fail(SPECMG_EINVAL, "unknown warm_start");
     if (opts->warm_start == SPECMG_WS_CNN && !opts->cnn_weights)
         return fail(SPECMG_EINVAL, "warm_start CNN needs cnn_weights");
+    if (opts->warm_start == SPECMG_WS_CNN && (G.hx != G.hy || G.hx != G.hz))
+        return fail(SPECMG_EINVAL, "warm_start CNN needs equal spacings (the network saw only those)");
     if (opts->warm_start == SPECMG_WS_CNN && (opts->eigs_per_subdomain & 1))
         return fail(SPECMG_EINVAL, "warm_start CNN needs an even eigs_per_subdomain");
     const int tcc = opts->eigs_coarse > 0 ? opts->eigs_coarse : opts->eigs_per_subdomain;
@@ -936,10 +942,10 @@ extern "C" int specmg_gmres_solve(specmg_ctx* c, const double* rhs, double* x, i
 }
 
 namespace specmg {
-void launch_flux(int nx, int ny, int nz, double h, const double* kt, const double* p, double* vx, double* vy,
-                 double* vz, hipStream_t s);
-void launch_mass_balance(int nx, int ny, int nz, double h, const double* vx, const double* vy, const double* vz,
-                         const double* f, double* res, hipStream_t s);
+void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
+                 const double* p, double* vx, double* vy, double* vz, hipStream_t s);
+void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,
+                         const double* vz, const double* f, double* res, hipStream_t s);
 }  // namespace specmg
 
 extern "C" int specmg_recover_flux(specmg_ctx* c, const double* p, double* vx, double* vy, double* vz,
@@ -947,7 +953,8 @@ extern "C" int specmg_recover_flux(specmg_ctx* c, const double* p, double* vx, d
     g_last_error.clear();
     if (!c || !p || !vx || !vy || !vz) return fail(SPECMG_EINVAL, "null argument");
     try {
-        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->kt, p, vx, vy, vz, (hipStream_t)stream);
+        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->grid.hy, c->grid.hz, c->fg.cy, c->fg.cz, c->kt, p, vx,
+                    vy, vz, (hipStream_t)stream);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -960,7 +967,8 @@ extern "C" int specmg_mass_balance(specmg_ctx* c, const double* vx, const double
     g_last_error.clear();
     if (!c || !vx || !vy || !vz || !f || !res) return fail(SPECMG_EINVAL, "null argument");
     try {
-        launch_mass_balance(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, vx, vy, vz, f, res, (hipStream_t)stream);
+        launch_mass_balance(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->grid.hy, c->grid.hz, vx, vy, vz, f, res,
+                            (hipStream_t)stream);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));

@@ -202,7 +202,7 @@ class LevelArrays:
 class SpecMG:
     """Set-up context of the multiscale spectral multigrid preconditioner."""
 
-    def __init__(self, perm, levels: int, eigs_per_subdomain: int, h: float | None = None,
+    def __init__(self, perm, levels: int, eigs_per_subdomain: int, h=None,
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
                  allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3,
                  eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0):
@@ -215,7 +215,8 @@ class SpecMG:
         self.n = nx * ny * nz
         if h is None:
             h = 1.0 / nx
-        self.grid = Grid(nx, ny, nz, h, h, h, 8, agg)
+        hx, hy, hz = (h, h, h) if isinstance(h, (int, float)) else (float(v) for v in h)
+        self.grid = Grid(nx, ny, nz, hx, hy, hz, 8, agg)
         ws, wp = WS_NONE, None
         if cnn_weights is not None:
             # bf16 parameter vector, stored as int16 bits in a torch tensor
