@@ -32,7 +32,9 @@ Readings (where the paper leaves a choice):
   - The sub-step length is dt = DS_max / max_cells |dS/dt|, the rate being
     (q_w - div(f_w v)) / phi at the start of the sub-step; dt = 0 when every
     rate is zero.
-  - K is isotropic (one kappa per cell) and the spacing is equal on all axes.
+  - K is isotropic (one kappa per cell); the spacings may differ per axis
+    (the cells of Section 6 measure 20 x 10 x 2 ft): the surface integral of
+    eq. ES over a cell is then sum_d (F_+ - F_-) / h_d.
 
 Arrays are (nz, ny, nx) in C order; each face array holds the velocity
 through the + face of every cell, zero on the no-flow boundary.
@@ -74,12 +76,19 @@ def water_source(q, s):
     return np.where(q > 0.0, q, frac_flow(s) * q)
 
 
+def _spacings(h):
+    """(hx, hy, hz) from one spacing or a triple."""
+    return (float(h),) * 3 if np.ndim(h) == 0 else tuple(float(v) for v in h)
+
+
 def saturation_rate(phi, q, vx, vy, vz, s, h):
-    """dS/dt of eq. ES per cell: (q_w - (1/h) sum_faces f_w(S_up) v . n) / phi."""
+    """dS/dt of eq. ES per cell: (q_w - sum_d (F_+ - F_-) / h_d) / phi, with
+    F = f_w(S_upstream) v on the faces of axis d; h one spacing or (hx, hy, hz)."""
     s = np.asarray(s, dtype=np.float64)
+    hx, hy, hz = _spacings(h)
     fw = frac_flow(s)
     div = np.zeros(s.shape)
-    for axis, v in ((2, vx), (1, vy), (0, vz)):
+    for axis, v, hd in ((2, vx, hx), (1, vy, hy), (0, vz, hz)):
         v = np.asarray(v, dtype=np.float64).reshape(s.shape)
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
@@ -92,7 +101,7 @@ def saturation_rate(phi, q, vx, vy, vz, s, h):
         fplus[lo] = up * v[lo]
         fminus = np.zeros(s.shape)                # the - face is the + face of the lower cell
         fminus[hi] = fplus[lo]
-        div += (fplus - fminus) / h
+        div += (fplus - fminus) / hd
     return (water_source(q, s) - div) / np.asarray(phi, dtype=np.float64)
 
 
@@ -125,7 +134,6 @@ def pressure_solve(perm_eff, grid: Grid, q):
 
 def impes(perm, phi, q, s0, grid: Grid, steps, substeps, ds_max):
     """Improved IMPES (eqs. IMP, ES): returns (S, p, per-step total times)."""
-    assert grid.hx == grid.hy == grid.hz
     s = np.array(s0, dtype=np.float64, copy=True).reshape(grid.shape)
     perm = np.asarray(perm, dtype=np.float64).reshape(grid.shape)
     p = None
@@ -134,6 +142,7 @@ def impes(perm, phi, q, s0, grid: Grid, steps, substeps, ds_max):
         keff = perm * total_mobility(s)
         p = pressure_solve(keff, grid, q)
         vx, vy, vz = recover_flux(keff, grid, p)
-        s, t = transport(phi, np.asarray(q).reshape(grid.shape), vx, vy, vz, s, grid.hx, substeps, ds_max)
+        s, t = transport(phi, np.asarray(q).reshape(grid.shape), vx, vy, vz, s, (grid.hx, grid.hy, grid.hz),
+                         substeps, ds_max)
         times.append(t)
     return s, p, times

@@ -72,30 +72,39 @@ def _bl_profile(x, t, u, phi):
     return out, 0.2 + 0.6 * snf, xf
 
 
-def _flood_1d(n, t_end, phi=0.2, u=1.0, ds_max=0.01):
+def _flood_1d(n, t_end, phi=0.2, u=1.0, ds_max=0.01, axis=2, other=1.0):
+    """Water flood along one axis (2: x, 0: z) of a column of n cells; the
+    two other spacings are `other`, which must not enter the result."""
     h = 1.0 / n
-    shape = (1, 1, n)
-    q = np.zeros(shape)
-    q[0, 0, 0] = u / h
-    q[0, 0, -1] = -u / h
-    vx = np.zeros(shape)
-    vx[0, 0, :-1] = u                 # uniform total velocity through every interior face
-    vy = np.zeros(shape)
-    vz = np.zeros(shape)
+    shape = [1, 1, 1]
+    shape[axis] = n
+    shape = tuple(shape)
+    hs = [other, other, other]
+    hs[2 - axis] = h                   # (hx, hy, hz) with the flow axis at spacing h
+    q = np.zeros(n)
+    q[0] = u / h
+    q[-1] = -u / h
+    v = np.zeros(n)
+    v[:-1] = u                         # uniform total velocity through every interior face
+    zero = np.zeros(shape)
+    vel = [zero, zero, zero]
+    vel[2 - axis] = v.reshape(shape)
     ph = np.full(shape, phi)
     s = np.full(shape, 0.2)
     t = 0.0
     while t < t_end:
-        s, dt = im.transport(ph, q, vx, vy, vz, s, h, 1, ds_max)
+        s, dt = im.transport(ph, q.reshape(shape), vel[0], vel[1], vel[2], s, tuple(hs), 1, ds_max)
         t += dt
     x = (np.arange(n) + 0.5) * h
     return x, s.reshape(-1), t
 
 
-def test_buckley_leverett_front():
+@pytest.mark.parametrize("axis,other", [(2, 1.0), (0, 7.0)])
+def test_buckley_leverett_front(axis, other):
+    # along x with unit cross spacings, and along z with cross spacings of 7
     errs = []
     for n in (200, 400):
-        x, s, t = _flood_1d(n, 0.02)
+        x, s, t = _flood_1d(n, 0.02, axis=axis, other=other)
         exact, sf, xf = _bl_profile(x, t, 1.0, 0.2)
         err = np.mean(np.abs(s - exact))
         errs.append(err)
