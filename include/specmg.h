@@ -214,12 +214,12 @@ int specmg_total_mobility(const double* perm_dev, const double* s_dev, double* p
 
 /* `substeps` explicit Euler steps of the saturation equation (eq. ES) with
  * the face velocity held fixed:
- *   phi_i (S_i' - S_i)/dt + (1/h) sum_faces f_w(S_upstream) v.n = q_w,i,
+ *   phi_i (S_i' - S_i)/dt + sum_d (F_+ - F_-)/h_d = q_w,i,
+ * F = f_w(S_upstream) v on the faces of axis d,
  * the upstream cell being the one the face velocity leaves, and
  * dt = ds_max / max_i |dS_i/dt| (0 when every rate is zero), so that no cell
  * changes by more than ds_max per sub-step.
- * grid: nx, ny, nz >= 1 (any sizes), hx = hy = hz > 0 (the sub-step
- * rule of this call assumes one spacing); sub and agg unused.
+ * grid: nx, ny, nz >= 1 (any sizes), hx, hy, hz > 0; sub and agg unused.
  * phi_dev, q_dev: porosity (> 0) and total source density per cell;
  * vx/vy/vz_dev: the velocity through the +x/+y/+z face of every cell (the
  * layout of specmg_recover_flux; values on boundary faces are not read);

@@ -8,7 +8,7 @@
 // water, q < 0 produces the cell's mixture (q_w = f_w(S) q).
 //
 // One sub-step is two grid-stride passes over the cells:
-//   k_sat_rate    r_i = (q_w - (1/h) sum_axes (F_+ - F_-)) / phi_i with the
+//   k_sat_rate    r_i = (q_w - sum_d (F_+ - F_-) / h_d) / phi_i with the
 //                 face water flux F = f_w(S_upstream) v; each block writes
 //                 the largest |r| of its cells to its own slot;
 //   k_sat_update  every block first reduces those slots to the grid's
@@ -87,7 +87,8 @@ __device__ __forceinline__ void cell_xyz(int64_t i, int nx, int ny, int64_t n, i
     }
 }
 
-__global__ __launch_bounds__(256) void k_sat_rate(int nx, int ny, int nz, double h, const double* __restrict__ phi,
+__global__ __launch_bounds__(256) void k_sat_rate(int nx, int ny, int nz, double hx, double hy, double hz,
+                                                  const double* __restrict__ phi,
                                                   const double* __restrict__ q, const double* __restrict__ vx,
                                                   const double* __restrict__ vy, const double* __restrict__ vz,
                                                   const double* __restrict__ fw, double* __restrict__ rate,
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void k_sat_rate(int nx, int ny, int nz, double
         const double fi = fw[i];
         // water flux through the + and - faces of one axis, upstream weighted;
         // the boundary faces carry nothing
-        auto axis_div = [&](bool has_plus, bool has_minus, const double* __restrict__ v, int64_t st) {
+        auto axis_div = [&](bool has_plus, bool has_minus, const double* __restrict__ v, int64_t st, double h) {
             double fp = 0.0, fm = 0.0;
             if (has_plus) {
                 const double vp = v[i];
@@ -113,9 +114,9 @@ __global__ __launch_bounds__(256) void k_sat_rate(int nx, int ny, int nz, double
             }
             return (fp - fm) / h;
         };
-        double div = axis_div(x + 1 < nx, x > 0, vx, 1);
-        div += axis_div(y + 1 < ny, y > 0, vy, sy);
-        div += axis_div(z + 1 < nz, z > 0, vz, sz);
+        double div = axis_div(x + 1 < nx, x > 0, vx, 1, hx);
+        div += axis_div(y + 1 < ny, y > 0, vy, sy, hy);
+        div += axis_div(z + 1 < nz, z > 0, vz, sz, hz);
         const double qi = q[i];
         const double qw = qi > 0.0 ? qi : fi * qi;
         const double r = (qw - div) / phi[i];
@@ -177,8 +178,8 @@ extern "C" int specmg_transport(const specmg_grid* grid, const double* phi_dev, 
     if (!grid || !phi_dev || !q_dev || !vx_dev || !vy_dev || !vz_dev || !s_dev || !work_dev || !t_dev)
         return fail_message(SPECMG_EINVAL, "null argument");
     if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail_message(SPECMG_EINVAL, "grid sizes must be >= 1");
-    if (!(grid->hx > 0) || grid->hx != grid->hy || grid->hx != grid->hz)
-        return fail_message(SPECMG_EINVAL, "equal positive spacings required");
+    if (!(grid->hx > 0) || !(grid->hy > 0) || !(grid->hz > 0))
+        return fail_message(SPECMG_EINVAL, "spacings must be positive");
     if (substeps < 0) return fail_message(SPECMG_EINVAL, "substeps must be >= 0");
     if (!(ds_max > 0) || ds_max > 1.0) return fail_message(SPECMG_EINVAL, "ds_max must be in (0, 1]");
     const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
@@ -189,7 +190,8 @@ extern "C" int specmg_transport(const specmg_grid* grid, const double* phi_dev, 
     const int nb = blocks_for(n, kMaxRateBlocks), nu = blocks_for(n, kMaxUpdateBlocks);
     hipLaunchKernelGGL(k_transport_begin, dim3(nu), dim3(256), 0, s, n, s_dev, fw, t_dev);
     for (int m = 0; m < substeps; ++m) {
-        hipLaunchKernelGGL(k_sat_rate, dim3(nb), dim3(256), 0, s, grid->nx, grid->ny, grid->nz, grid->hx, phi_dev,
+        hipLaunchKernelGGL(k_sat_rate, dim3(nb), dim3(256), 0, s, grid->nx, grid->ny, grid->nz, grid->hx, grid->hy,
+                           grid->hz, phi_dev,
                            q_dev, vx_dev, vy_dev, vz_dev, fw, rate, block_max);
         hipLaunchKernelGGL(k_sat_update, dim3(nu), dim3(256), 0, s, n, rate, s_dev, fw, block_max, nb, ds_max,
                            t_dev);

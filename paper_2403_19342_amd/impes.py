@@ -10,7 +10,7 @@ Each pressure step runs on the device, through the C ABI:
   5. specmg_transport: M explicit saturation sub-steps with v^{n+1} fixed.
 
 Wells are rate controlled (q > 0 injects water, q < 0 produces the cell's
-mixture); K is isotropic.  This module only sequences the calls and keeps
+mixture); K is isotropic; `h` is one spacing or (hx, hy, hz).  This module only sequences the calls and keeps
 the device arrays; there is no host arithmetic on the fields.
 
     python -m paper_2403_19342_amd.impes --n 128 --steps 6
@@ -40,7 +40,7 @@ class StepInfo:
 class Impes:
     """Device state of an improved IMPES run: kappa, phi, q, S, p, v."""
 
-    def __init__(self, perm, phi, q, s0, levels: int = 3, eigs: int = 4, agg: int = 4, h: float | None = None,
+    def __init__(self, perm, phi, q, s0, levels: int = 3, eigs: int = 4, agg: int = 4, h=None,
                  tol: float = 1e-9, substeps: int = 50, ds_max: float = 1e-3, precision: int = FP64):
         import torch
         for a in (perm, phi, q, s0):

@@ -166,7 +166,7 @@ def total_mobility(perm, s, perm_eff):
     _check(lib.specmg_total_mobility(_dev_ptr(perm), _dev_ptr(s), _dev_ptr(perm_eff), perm.numel(), _stream()))
 
 
-def transport(phi, q, vx, vy, vz, s, h: float, substeps: int, ds_max: float, work, t):
+def transport(phi, q, vx, vy, vz, s, h, substeps: int, ds_max: float, work, t):
     """Explicit saturation sub-steps with the face velocity fixed (specmg_transport).
 
     All fields (nz, ny, nx) float64 CUDA tensors; `s` is updated in place,
@@ -183,7 +183,8 @@ def transport(phi, q, vx, vy, vz, s, h: float, substeps: int, ds_max: float, wor
             raise ValueError("every field must have s.numel() entries")
     if work.numel() < transport_work_size(n) or t.numel() < 1:
         raise ValueError(f"work needs {transport_work_size(n)} doubles and t one")
-    g = Grid(nx, ny, nz, h, h, h, 8, 2)
+    hx, hy, hz = (h, h, h) if isinstance(h, (int, float)) else (float(v) for v in h)
+    g = Grid(nx, ny, nz, hx, hy, hz, 8, 2)
     _check(lib.specmg_transport(ctypes.byref(g), _dev_ptr(phi), _dev_ptr(q), _dev_ptr(vx), _dev_ptr(vy),
                                 _dev_ptr(vz), _dev_ptr(s), int(substeps), float(ds_max), _dev_ptr(work),
                                 _dev_ptr(t), _stream()))

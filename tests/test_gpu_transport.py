@@ -13,7 +13,8 @@
 - The improved IMPES driver (set-up on lambda(S) kappa, warm-started CG,
   flux recovery, sub-steps) for three pressure steps against the oracle's
   IMPES with a direct pressure solve, on a cube, on a grid whose three
-  extents differ, and with the FP32 V-cycle: S within 1e-7, p within 1e-7
+  extents differ, with the FP32 V-cycle, and with the 20 : 10 : 2 cell
+  spacings of the two-phase grid of Section 6: S within 1e-7, p within 1e-7
   relative, step lengths within 1e-7 relative (CG stops at 1e-10, and S
   depends on the velocity linearly through M sub-steps).
 """
@@ -55,19 +56,20 @@ def test_total_mobility_matches_oracle():
     assert err <= 1e-15
 
 
-@pytest.mark.parametrize("shape,substeps,ds_max,seed", [
-    ((32, 32, 32), 25, 1e-3, 1),
-    ((7, 13, 19), 40, 1e-2, 2),
-    ((1, 1, 257), 60, 5e-3, 3),
-    ((1, 1, 1), 3, 1e-3, 4),
+@pytest.mark.parametrize("shape,substeps,ds_max,seed,hs", [
+    ((32, 32, 32), 25, 1e-3, 1, None),
+    ((7, 13, 19), 40, 1e-2, 2, None),
+    ((7, 13, 19), 40, 1e-2, 5, (0.1, 0.05, 0.01)),
+    ((1, 1, 257), 60, 5e-3, 3, None),
+    ((1, 1, 1), 3, 1e-3, 4, None),
 ])
-def test_transport_matches_oracle(shape, substeps, ds_max, seed):
+def test_transport_matches_oracle(shape, substeps, ds_max, seed, hs):
     import torch
     from paper_2403_19342_amd.specmg import transport
     s0, phi, q, (vx, vy, vz) = _random_inputs(shape, seed)
     if s0.size == 1:
         q[...] = 1.0                  # a lone injector cell: S rises by ds_max per sub-step
-    h = 1.0 / shape[2]
+    h = 1.0 / shape[2] if hs is None else hs
     ref, tref = im.transport(phi, q, vx, vy, vz, s0, h, substeps, ds_max)
     s = to_dev(s0)
     work = torch.empty(_work_size(s0.size), dtype=torch.float64, device="cuda")
@@ -106,12 +108,14 @@ def test_transport_edge_cases():
         transport(to_dev(phi), to_dev(q), *[to_dev(x) for x in v], s, 0.125, 1, 1e-3, work[:10], t)
 
 
-@pytest.mark.parametrize("nx,ny,nz,precision", [(32, 32, 32, 0), (48, 32, 16, 0), (32, 32, 32, 1)])
-def test_impes_driver_matches_oracle(nx, ny, nz, precision):
+@pytest.mark.parametrize("nx,ny,nz,precision,ratios", [(32, 32, 32, 0, None), (48, 32, 16, 0, None),
+                                                       (32, 32, 32, 1, None), (32, 32, 32, 0, (20, 10, 2))])
+def test_impes_driver_matches_oracle(nx, ny, nz, precision, ratios):
+    # ratios: hx : hy : hz of the two-phase grid of Section 6
     import torch
     from paper_2403_19342_amd.impes import Impes
-    h = 1.0 / nx
-    g = Grid(nx, ny, nz, h, h, h)
+    h = 1.0 / nx if ratios is None else tuple(r / (20.0 * nx) for r in ratios)
+    g = Grid(nx, ny, nz, *((h,) * 3 if ratios is None else h))
     perm = make_field("gauss", nx, 6, sigma=2.0, shape=g.shape)
     phi = porosity_field(perm, 6)
     q = five_spot(g.shape)
@@ -126,7 +130,7 @@ def test_impes_driver_matches_oracle(nx, ny, nz, precision):
     es = np.max(np.abs(s - sref))
     ep = np.linalg.norm(p - pref) / np.linalg.norm(pref)
     et = max(abs(i.dt_total - t) / t for i, t in zip(infos, tref))
-    print(f"IMPES {nx}x{ny}x{nz} precision {precision}, 3 steps: iterations {[i.iters for i in infos]}, "
+    print(f"IMPES {nx}x{ny}x{nz} precision {precision} spacing ratios {ratios}, 3 steps: iterations {[i.iters for i in infos]}, "
           f"max |dS| {es:.2e}, p rel {ep:.2e}, t rel {et:.2e}, S range [{s.min():.4f}, {s.max():.4f}]")
     assert all(i.rel_resid <= 1e-10 for i in infos)
     assert es <= 1e-7 and ep <= 1e-7 and et <= 1e-7
