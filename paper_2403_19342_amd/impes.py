@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--eigs", type=int, default=6)
     ap.add_argument("--tol", type=float, default=1e-9)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--spacing", default="1,1,1",
+                    help="hx:hy:hz ratios, e.g. 20,10,2 for the cells of the paper's two-phase grid (hx = 1/n)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain device copies of 256 MiB each (counter calibration)")
     a = ap.parse_args()
@@ -109,10 +111,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     n = a.n
+    ratios = [float(v) for v in a.spacing.split(",")]
+    h = tuple(r / (ratios[0] * n) for r in ratios)
     perm = make_field("gauss", n, a.seed)
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     run = Impes(dev(perm), dev(porosity_field(perm, a.seed)), dev(five_spot(perm.shape)),
-                dev(np.full(perm.shape, 0.2)), levels=a.levels, eigs=a.eigs, agg=4, tol=a.tol,
+                dev(np.full(perm.shape, 0.2)), levels=a.levels, eigs=a.eigs, agg=4, h=h, tol=a.tol,
                 substeps=a.substeps, ds_max=a.ds_max)
     for k in range(a.steps):
         si = run.step()
