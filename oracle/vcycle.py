@@ -40,9 +40,12 @@ def pseudo_inverse(a: np.ndarray) -> np.ndarray:
 class Preconditioner:
     """P^{-1} r for a hierarchy built by `build_hierarchy`."""
 
-    def __init__(self, hier: Hierarchy, nu: int = 1):
+    def __init__(self, hier: Hierarchy, nu: int = 1, nu_c: int | None = None):
+        # nu sweeps on the fine level, nu_c on the coarse levels (Section 5
+        # names both; nu_c defaults to nu)
         self.h = hier
         self.nu = nu
+        self.nu_c = nu if nu_c is None else nu_c
         self.fine = FineIC(hier.A, hier.grid, hier.sub)
         self.coarse = {}
         for l in range(2, hier.nlevels):
@@ -54,7 +57,7 @@ class Preconditioner:
 
     def _smooth(self, l, A, f, u=None):
         sm = self.fine if l == 1 else self.coarse[l]
-        for it in range(self.nu):
+        for it in range(self.nu if l == 1 else self.nu_c):
             if u is None:
                 u = sm.apply(f)
             else:
