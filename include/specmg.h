@@ -79,8 +79,10 @@ typedef struct {
  * eig_threshold_coarse > 0, keep the eigenvectors whose eigenvalues lie below
  * that threshold (B_cc, strategy 2 of Section 5; at least one, at most
  * eigs_coarse, then the cluster rule).  Each level's arrays are padded to its
- * own width, target + 3.  nu is the number of smoothing sweeps (only 1, the
- * paper's value, is supported).  eig_tol is the residual tolerance of the
+ * own width, target + 3.  nu (fine level) and nu_c (coarse levels) are the
+ * numbers of block-Jacobi sweeps before and after the coarse correction
+ * (Section 5: nu, nu_c in {1, 2}; the repeated sweep is
+ * u += M^-1 (f - A u)).  eig_tol is the residual tolerance of the
  * local eigensolves relative to the spectral radius of the local pencil. */
 typedef struct {
     int32_t levels;
@@ -107,6 +109,7 @@ typedef struct {
     double eig_threshold_coarse; /* B_cc >= 0; 0 = fixed count eigs_coarse.
                                 Eigenvalues are those of eq. spectral cc with
                                 S-normalised bases (dimensionless) */
+    int32_t nu_c;            /* coarse-level sweeps nu_c (1 or 2); 0 = nu */
 } specmg_opts;
 
 /* Outcome of a solve.  iters counts products A p (one per CG iteration). */

@@ -87,6 +87,7 @@ struct specmg_ctx {
     double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
     int fp32 = 0;
     int fp32_basis = 0;   // float64 fine level with a float32 copy of the level-2 basis
+    int nu = 1, nu_c = 1; // block-Jacobi sweeps before and after the correction: fine, coarse levels
     int64_t n = 0;
     FineGeom fg{};
     std::vector<void*> allocs;
@@ -228,11 +229,37 @@ void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
     const T* Dinv = pick<T>(lv.Dinv, lv.Dinv32);
     const T* G = pick<T>(lv.G, lv.G32);
     const T* V = pick<T>(up.basis, up.basis32);
+    // a repeated sweep u += M^-1 (r - A u) reads neighbouring blocks' u, so
+    // it writes e (free until the last sweep) and copies back
+    const int64_t nrow = (int64_t)lv.g.m * lv.g.L;
     launch_coarse_smooth<T>(lv.g, Dinv, G, r, u, c->sc, check, s);
+    for (int it = 1; it < c->nu_c; ++it) {
+        launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
+        launch_copy(u, e, nrow, s);
+    }
     launch_coarse_resid_restrict<T>(lv.g, Ad, Aoff, r, u, V, up.nkeep, up.L, pick<T>(up.r, up.r32), c->sc, check, s);
     coarse_cycle<T>(c, li + 1, check, s);
     launch_coarse_prolong<T>(lv.g, u, V, up.nkeep, up.L, pick<T>(up.e, up.e32), c->sc, check, s);
+    for (int it = 1; it < c->nu_c; ++it) {
+        launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
+        launch_copy(u, e, nrow, s);
+    }
     launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
+}
+
+// One repeated fine sweep u1 += M^-1 (r - A u1): the residual, the sweep
+// written to z (the V-cycle's output, free until the last sweep), and z
+// copied back into u1 (converted in the FP32 V-cycle).
+template <typename T>
+void extra_fine_sweep(specmg_ctx* c, double* r, double* z, int check, hipStream_t s) {
+    const T* kt = pick<T>(c->kt, c->kt32);
+    const T* invd = pick<T>(c->invd, c->invd32);
+    T* u1 = pick<T>(c->u1, c->u1_32);
+    T* tres = pick<T>(c->tres, (float*)c->tres);
+    launch_residual<T>(c->fg, kt, u1, r, tres, c->sc, check, s);
+    launch_post_smooth<T>(c->fg, kt, invd, u1, r, nullptr, z, tres, c->sc, c->rb, check ? 2 : 0, s);
+    if constexpr (std::is_same<T, float>::value) launch_convert<double, float>(z, u1, c->n, s);
+    else launch_copy(u1, z, c->n, s);
 }
 
 // z = P^{-1} r (fine level + recursion).  pre_mode / post_mode are the mode
@@ -248,6 +275,7 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     size_t ev = prof_begin(c, s);
     launch_pre_smooth<T>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
     prof_end(c, ev, PC_PRE, s);
+    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T>(c, r, z, check, s);
     ev = prof_begin(c, s);
     if (c->fp32_basis)
         launch_resid_restrict<T, float>(c->fg, kt, u1, r, l2.basis32, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc,
@@ -274,6 +302,7 @@ void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, 
     else
         launch_prolong<T, T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
     prof_end(c, ev, PC_PROLONG, s);
+    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T>(c, r, z, check, s);
     T* tres = pick<T>(c->tres, (float*)c->tres);
     ev = prof_begin(c, s);
     launch_residual<T>(c->fg, kt, u1, r, tres, c->sc, (post_mode & 2) ? 1 : 0, s);
@@ -585,7 +614,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     if (opts->levels < 2 || opts->levels > 8) return fail(SPECMG_EINVAL, "levels must be in [2, 8]");
     if (opts->eigs_per_subdomain < 1 || opts->eigs_per_subdomain > 8)
         return fail(SPECMG_EINVAL, "eigs_per_subdomain must be in [1, 8]");
-    if (opts->nu != 1) return fail(SPECMG_EINVAL, "only nu = 1 is supported");
+    if (opts->nu < 1 || opts->nu > 2) return fail(SPECMG_EINVAL, "nu must be 1 or 2");
+    if (opts->nu_c < 0 || opts->nu_c > 2) return fail(SPECMG_EINVAL, "nu_c must be 0 (= nu), 1 or 2");
     if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE &&
         opts->precision != SPECMG_FP32_BASIS)
         return fail(SPECMG_EINVAL, "unknown precision");
@@ -621,6 +651,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     c->thr_cc = opts->eig_threshold_coarse;
     c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
     c->fp32_basis = opts->precision == SPECMG_FP32_BASIS;
+    c->nu = opts->nu;
+    c->nu_c = opts->nu_c > 0 ? opts->nu_c : opts->nu;
     int rc;
     try {
         rc = do_setup(c, perm_dev, (hipStream_t)stream);

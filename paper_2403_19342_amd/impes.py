@@ -42,7 +42,7 @@ class Impes:
 
     def __init__(self, perm, phi, q, s0, levels: int = 3, eigs: int = 4, agg: int = 4, h=None,
                  tol: float = 1e-9, substeps: int = 50, ds_max: float = 1e-3, precision: int = FP64,
-                 eigs_coarse: int = 0):
+                 eigs_coarse: int = 0, nu: int = 1, nu_c: int = 0):
         import torch
         for a in (perm, phi, q, s0):
             if not (a.is_cuda and a.dtype == torch.float64 and a.shape == perm.shape and a.dim() == 3):
@@ -55,7 +55,7 @@ class Impes:
         n = perm.numel()
         self.h = 1.0 / self.shape[2] if h is None else h
         self.levels, self.eigs, self.agg, self.precision = levels, eigs, agg, precision
-        self.eigs_coarse = eigs_coarse
+        self.eigs_coarse, self.nu, self.nu_c = eigs_coarse, nu, nu_c
         self.tol, self.substeps, self.ds_max = tol, substeps, ds_max
         self.keff = torch.empty_like(self.perm)
         self.p = torch.zeros(n, dtype=torch.float64, device=perm.device)
@@ -69,7 +69,7 @@ class Impes:
         t0 = time.perf_counter()
         total_mobility(self.perm, self.s, self.keff)
         ctx = SpecMG(self.keff, levels=self.levels, eigs_per_subdomain=self.eigs, h=self.h, agg=self.agg,
-                     precision=self.precision, eigs_coarse=self.eigs_coarse)
+                     precision=self.precision, eigs_coarse=self.eigs_coarse, nu=self.nu, nu_c=self.nu_c)
         t1 = time.perf_counter()
         try:
             _, info = ctx.pcg_solve(self.q.reshape(-1), self.p, tol=self.tol, use_x0=self.steps_done > 0)
@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--eigs", type=int, default=6, help="L_c: eigenvectors per level-2 element")
     ap.add_argument("--eigs-coarse", type=int, default=0, help="L_cc at levels >= 3 (0: same as --eigs)")
     ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--nu", type=int, default=1, help="block-Jacobi sweeps on the fine level")
+    ap.add_argument("--nu-c", type=int, default=0, help="sweeps on the coarse levels (0: same as --nu)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--spacing", default="1,1,1",
                     help="hx:hy:hz ratios, e.g. 20,10,2 for the cells of the paper's two-phase grid (hx = 1/n)")
@@ -120,7 +122,7 @@ def main():
     dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), device="cuda")
     run = Impes(dev(perm), dev(porosity_field(perm, a.seed)), dev(five_spot(perm.shape)),
                 dev(np.full(perm.shape, 0.2)), levels=a.levels, eigs=a.eigs, agg=4, h=h, tol=a.tol,
-                substeps=a.substeps, ds_max=a.ds_max, eigs_coarse=a.eigs_coarse)
+                substeps=a.substeps, ds_max=a.ds_max, eigs_coarse=a.eigs_coarse, nu=a.nu, nu_c=a.nu_c)
     for k in range(a.steps):
         si = run.step()
         print(json.dumps({"step": k, "iters": si.iters, "rel_resid": si.rel_resid, "dt_total": si.dt_total,

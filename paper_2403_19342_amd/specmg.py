@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("cnn_weights", ctypes.c_void_p),
                 ("eig_tol", ctypes.c_double), ("cluster_rtol", ctypes.c_double),
                 ("ws_resid_tol", ctypes.c_double), ("eigs_coarse", ctypes.c_int32),
-                ("eig_threshold_coarse", ctypes.c_double)]
+                ("eig_threshold_coarse", ctypes.c_double), ("nu_c", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -206,7 +206,7 @@ class SpecMG:
     def __init__(self, perm, levels: int, eigs_per_subdomain: int, h=None,
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
                  allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3,
-                 eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0):
+                 eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0, nu: int = 1, nu_c: int = 0):
         lib = load_library()
         import torch
         if perm.dim() != 3:
@@ -226,8 +226,8 @@ class SpecMG:
             if cnn_weights.numel() != lib.specmg_cnn_param_count(eigs_per_subdomain):
                 raise ValueError("cnn_weights has the wrong length for eigs_per_subdomain")
             ws, wp = WS_CNN, ctypes.c_void_p(cnn_weights.data_ptr())
-        self.opts = Opts(levels, eigs_per_subdomain, 1, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol,
-                         eigs_coarse, eig_threshold_coarse)
+        self.opts = Opts(levels, eigs_per_subdomain, nu, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol,
+                         eigs_coarse, eig_threshold_coarse, nu_c)
         ctx = ctypes.c_void_p()
         perm = perm.contiguous()
         rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
