@@ -12,6 +12,7 @@ Prints one JSON line (rank 0, single GPU).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -39,6 +40,10 @@ def parse():
                     help="outer Krylov solver (GMRES: restarted, flexible, right-preconditioned)")
     ap.add_argument("--restart", type=int, default=30, help="GMRES restart length")
     ap.add_argument("--levels", type=int, default=None, help="override the workload's number of levels")
+    ap.add_argument("--contrast", type=float, default=None,
+                    help="channel / inclusion permeability over the background 1 (channels and inclusions fields)")
+    ap.add_argument("--eigs", type=int, default=None, help="override L_c, eigenvectors per level-2 element")
+    ap.add_argument("--eigs-coarse", type=int, default=None, help="override L_cc at levels >= 3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="edge of the field crop timed on the CPU oracle")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -85,10 +90,15 @@ def main():
     from paper_2403_19342_amd.specmg import SpecMG, FP64, FP32_VCYCLE, FP32_BASIS
 
     wl = WORKLOADS[args.config]
+    if args.contrast is not None and wl.kind not in ("channels", "inclusions"):
+        raise SystemExit("--contrast applies to the channels and inclusions fields")
+    if args.eigs is not None or args.eigs_coarse is not None:
+        wl = dataclasses.replace(wl, eigs=args.eigs or wl.eigs,
+                                 eigs_coarse=wl.eigs_coarse if args.eigs_coarse is None else args.eigs_coarse)
     levels = args.levels or wl.levels
     prec = args.precision or wl.precision
     n = wl.n
-    perm_h = make_field(wl.kind, n, wl.seed)
+    perm_h = make_field(wl.kind, n, wl.seed, **({} if args.contrast is None else {"value": args.contrast}))
     b_h = make_source(wl.source, perm_h.shape)
     dev = torch.device("cuda:0")
     perm = torch.as_tensor(perm_h, device=dev)
@@ -183,6 +193,7 @@ def main():
         "config": {"workload": wl.name, "grid": f"{n}^3", "dof": dof, "levels": levels, "solver": args.solver,
                    "eigs_per_subdomain": wl.eigs, "eigs_coarse": wl.eigs_coarse or wl.eigs, "agg": agg,
                    "field": wl.kind, "source": wl.source,
+                   **({} if args.contrast is None else {"contrast": args.contrast}),
                    "tol": 1e-6, "precision": prec},
         "solve_ms": solve_s * 1e3,
         "solve_ms_profiled_step": infos[-1].solve_ms,

@@ -223,13 +223,13 @@ def make_field(kind: str, n: int, seed: int, shape=None, **kw) -> np.ndarray:
         return boxes_field(n, seed, n_boxes=kw.get("n_boxes", 20), value=1.0e4,
                            edge_lo=2, edge_hi=8, shape=shape)
     if kind == "inclusions":
-        return boxes_field(n, seed, n_boxes=None, value=1.0e6, edge_lo=2, edge_hi=16,
+        return boxes_field(n, seed, n_boxes=None, value=kw.get("value", 1.0e6), edge_lo=2, edge_hi=16,
                            cover=kw.get("cover", 0.05), shape=shape)
     if kind == "gauss":
         return gaussian_log_field(n, seed, sigma=kw.get("sigma", 3.0),
                                   corr_len=kw.get("corr_len", 0.1), shape=shape)
     if kind == "channels":
-        return channel_field(n, seed, n_channels=kw.get("n_channels", 24), shape=shape)
+        return channel_field(n, seed, n_channels=kw.get("n_channels", 24), value=kw.get("value", 1.0e6), shape=shape)
     if kind == "homogeneous":
         s = shape if shape is not None else (n, n, n)
         return np.ones(s, dtype=np.float64)
