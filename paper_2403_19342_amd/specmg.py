@@ -153,6 +153,16 @@ def _dev_ptr(t, dtype=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _spacings(h):
+    """(hx, hy, hz) from one spacing or a sequence of three."""
+    if isinstance(h, (int, float)):
+        return float(h), float(h), float(h)
+    hs = tuple(float(v) for v in h)
+    if len(hs) != 3:
+        raise ValueError("h must be one spacing or (hx, hy, hz)")
+    return hs
+
+
 def transport_work_size(n: int) -> int:
     """Doubles of scratch specmg_transport needs for n cells: rates, f_w, per-block maxima."""
     return 2 * n + 2048
@@ -183,7 +193,7 @@ def transport(phi, q, vx, vy, vz, s, h, substeps: int, ds_max: float, work, t):
             raise ValueError("every field must have s.numel() entries")
     if work.numel() < transport_work_size(n) or t.numel() < 1:
         raise ValueError(f"work needs {transport_work_size(n)} doubles and t one")
-    hx, hy, hz = (h, h, h) if isinstance(h, (int, float)) else (float(v) for v in h)
+    hx, hy, hz = _spacings(h)
     g = Grid(nx, ny, nz, hx, hy, hz, 8, 2)
     _check(lib.specmg_transport(ctypes.byref(g), _dev_ptr(phi), _dev_ptr(q), _dev_ptr(vx), _dev_ptr(vy),
                                 _dev_ptr(vz), _dev_ptr(s), int(substeps), float(ds_max), _dev_ptr(work),
@@ -216,7 +226,7 @@ class SpecMG:
         self.n = nx * ny * nz
         if h is None:
             h = 1.0 / nx
-        hx, hy, hz = (h, h, h) if isinstance(h, (int, float)) else (float(v) for v in h)
+        hx, hy, hz = _spacings(h)
         self.grid = Grid(nx, ny, nz, hx, hy, hz, 8, agg)
         ws, wp = WS_NONE, None
         if cnn_weights is not None:
