@@ -44,6 +44,8 @@ def parse():
                     help="channel / inclusion permeability over the background 1 (channels and inclusions fields)")
     ap.add_argument("--eigs", type=int, default=None, help="override L_c, eigenvectors per level-2 element")
     ap.add_argument("--eigs-coarse", type=int, default=None, help="override L_cc at levels >= 3")
+    ap.add_argument("--nu", type=int, default=1, help="block-Jacobi sweeps on the fine level")
+    ap.add_argument("--nu-c", type=int, default=0, help="sweeps on the coarse levels (0: same as --nu)")
     ap.add_argument("--eig-threshold-coarse", type=float, default=0.0,
                     help="B_cc > 0: keep the coarse-coarse eigenvalues below it (strategy 2), at most L_cc")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -120,7 +122,7 @@ def main():
     def step(profile):
         ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision,
                      eigs_coarse=wl.eigs_coarse, eig_threshold_coarse=args.eig_threshold_coarse,
-                     allow_unconverged=True)
+                     nu=args.nu, nu_c=args.nu_c, allow_unconverged=True)
         if args.solver == "gmres":
             # the per-kernel timing covers the CG solve only
             rc, info = ctx.gmres_solve(b, x, restart=args.restart, tol=1e-6, max_iter=1000)
@@ -198,6 +200,7 @@ def main():
                    "field": wl.kind, "source": wl.source,
                    **({} if args.contrast is None else {"contrast": args.contrast}),
                    **({"eig_threshold_coarse": args.eig_threshold_coarse} if args.eig_threshold_coarse > 0 else {}),
+                   **({"nu": args.nu, "nu_c": args.nu_c or args.nu} if (args.nu, args.nu_c) != (1, 0) else {}),
                    "tol": 1e-6, "precision": prec},
         "solve_ms": solve_s * 1e3,
         "solve_ms_profiled_step": infos[-1].solve_ms,
