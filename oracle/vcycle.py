@@ -37,10 +37,46 @@ def pseudo_inverse(a: np.ndarray) -> np.ndarray:
     return (q[:, keep] / w[keep]) @ q[:, keep].T
 
 
-class Preconditioner:
-    """P^{-1} r for a hierarchy built by `build_hierarchy`."""
+class MinNormSolve:
+    """The same map as `pseudo_inverse`, e = A_L^+ r, for coarsest spaces too
+    large for a dense eigendecomposition: the minimum-norm solution of
+    A_L e = r on the range of A_L.
 
-    def __init__(self, hier: Hierarchy, nu: int = 1, nu_c: int | None = None):
+    The kernel of A_L is spanned by z, the coarse coefficients of the
+    constant function (the paragraph after eq. spectral cc).  The right-hand
+    side is projected onto z's complement, one unknown i0 (the largest |z_i|)
+    is fixed at zero and the remaining equations are solved by sparse LU; the
+    dropped equation holds by itself because z^T (A_L e - r) = 0 and
+    z_i0 != 0.  Removing the component along z gives the solution orthogonal
+    to the kernel, which is A_L^+ r.
+    """
+
+    def __init__(self, a, z: np.ndarray):
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        self.z = z / np.linalg.norm(z)
+        self.i0 = int(np.argmax(np.abs(self.z)))
+        keep = np.ones(a.shape[0], dtype=bool)
+        keep[self.i0] = False
+        self.keep = keep
+        self.lu = spla.splu(sp.csc_matrix(a)[keep][:, keep].tocsc())
+
+    def __matmul__(self, r: np.ndarray) -> np.ndarray:
+        rp = r - (self.z @ r) * self.z
+        e = np.zeros_like(rp)
+        e[self.keep] = self.lu.solve(rp[self.keep])
+        return e - (self.z @ e) * self.z
+
+
+class Preconditioner:
+    """P^{-1} r for a hierarchy built by `build_hierarchy`.
+
+    `coarsest` selects how the coarsest map A_L^+ is formed: "pinv" (dense
+    eigendecomposition, `pseudo_inverse`) or "minnorm" (sparse LU on the
+    range, `MinNormSolve`, for coarsest spaces of thousands of unknowns).
+    Both give the Moore-Penrose inverse."""
+
+    def __init__(self, hier: Hierarchy, nu: int = 1, nu_c: int | None = None, coarsest: str = "pinv"):
         # nu sweeps on the fine level, nu_c on the coarse levels (Section 5
         # names both; nu_c defaults to nu)
         self.h = hier
@@ -53,7 +89,14 @@ class Preconditioner:
             kids = _children(up.egrid, hier.agg, low.egrid)
             self.coarse[l] = CoarseBlockIC(low.A, low.offsets, kids, hier.agg)
         top = hier.level(hier.nlevels)
-        self.pinv = pseudo_inverse(top.A.toarray())
+        if coarsest == "pinv":
+            self.pinv = pseudo_inverse(top.A.toarray())
+        elif coarsest == "minnorm":
+            # coefficients of the constant function in the S-orthonormal basis P_L
+            z = top.P.T @ hier.S
+            self.pinv = MinNormSolve(top.A, np.asarray(z).ravel())
+        else:
+            raise ValueError(f"unknown coarsest solve {coarsest!r}")
 
     def _smooth(self, l, A, f, u=None):
         sm = self.fine if l == 1 else self.coarse[l]

@@ -311,6 +311,35 @@ def test_pseudo_inverse_penrose():
     assert np.allclose(X, np.linalg.pinv(A, hermitian=True), atol=1e-8 * np.abs(X).max())
 
 
+@pytest.mark.parametrize("levels,target,agg", [(2, 4, 2), (3, 2, 2)])
+def test_min_norm_coarsest_is_the_pseudo_inverse(levels, target, agg):
+    """The sparse minimum-norm coarsest solve is the Moore-Penrose map: its
+    output is orthogonal to the kernel of A_L, solves A_L e = r on the range,
+    matches the dense pseudo-inverse, and the whole preconditioner built on it
+    matches the one built on the dense pseudo-inverse."""
+    from oracle.vcycle import MinNormSolve
+    g = Grid.unit_cube(16)
+    perm = _rand_perm(g.shape, 11, contrast=1e4)
+    h = build_hierarchy(perm, g, levels, target, sub=4, agg=agg, workers=1)
+    top = h.level(levels)
+    A = top.A.toarray()
+    z = np.asarray(top.P.T @ h.S).ravel()
+    ms = MinNormSolve(top.A, z)
+    zn = z / np.linalg.norm(z)
+    assert np.linalg.norm(A @ zn) < 1e-10 * np.abs(A).max()   # z spans the kernel
+    r = np.random.default_rng(3).standard_normal(A.shape[0])
+    e = ms @ r
+    rp = r - (zn @ r) * zn
+    assert abs(zn @ e) < 1e-12 * np.linalg.norm(e)
+    assert np.linalg.norm(A @ e - rp) < 1e-10 * np.linalg.norm(rp)
+    ref = np.linalg.pinv(A, hermitian=True) @ r
+    assert np.linalg.norm(e - ref) < 1e-9 * np.linalg.norm(ref)
+    f = random_zero_mean(g.shape, 4).reshape(-1)
+    p1 = Preconditioner(h).apply(f)
+    p2 = Preconditioner(h, coarsest="minnorm").apply(f)
+    assert np.linalg.norm(p1 - p2) < 1e-9 * np.linalg.norm(p1)
+
+
 # --------------------------------------------------------------------------
 # Algorithm 1 / Section 4: the preconditioner
 
