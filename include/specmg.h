@@ -49,6 +49,13 @@ extern "C" {
 #define SPECMG_FP32_BASIS 2      /* float64 throughout, the level-2 basis stored
                                     in float32 (restriction and prolongation
                                     read it and sum in float64)               */
+#define SPECMG_FP32_STORE 3      /* the fine level of the V-cycle stores kappa~,
+                                    the IC(0) pivots, the level-2 basis and its
+                                    vectors u and t in float32 and computes in
+                                    float64 (every residual formed in float64
+                                    from the stored values); coarse levels,
+                                    the coarsest solve and CG in float64;
+                                    flexible CG with residual replacement     */
 
 #define SPECMG_WS_NONE 0         /* cold-started local eigensolves          */
 #define SPECMG_WS_CNN 1          /* warm starts predicted by the 3D CNN     */
@@ -88,7 +95,7 @@ typedef struct {
     int32_t levels;
     int32_t eigs_per_subdomain;
     int32_t nu;
-    int32_t precision;       /* SPECMG_FP64, SPECMG_FP32_VCYCLE or SPECMG_FP32_BASIS */
+    int32_t precision;       /* SPECMG_FP64, _FP32_VCYCLE, _FP32_BASIS or _FP32_STORE */
     int32_t warm_start;      /* SPECMG_WS_NONE or SPECMG_WS_CNN   */
     const void* cnn_weights; /* WS_CNN only (eigs_per_subdomain even): device
                                 pointer to the network's bf16 parameter vector
@@ -257,9 +264,10 @@ int specmg_get_info(specmg_ctx* ctx, int32_t* levels, int32_t* dims, int32_t* el
 int specmg_copy_level(specmg_ctx* ctx, int32_t level, int32_t which, void* host_dst, size_t bytes);
 
 /* Per-kernel timing of later specmg_pcg_solve calls (on != 0) or off.
- * Each fine-level kernel of the CG iteration, and the coarse part of the
- * V-cycle as a whole, is bracketed by HIP events on the solve's stream;
- * turning it on resets the accumulated totals. */
+ * Each fine-level kernel of the CG iteration and the coarsest product are
+ * timed by HIP events the dispatch itself stamps on the solve's stream; the
+ * coarse part of the V-cycle as a whole is bracketed by events recorded
+ * around it.  Turning it on resets the accumulated totals. */
 int specmg_set_profiling(specmg_ctx* ctx, int32_t on);
 
 /* Accumulated event times (ms) and launch counts per kernel class since
@@ -267,8 +275,10 @@ int specmg_set_profiling(specmg_ctx* ctx, int32_t on);
  * moves (compulsory HBM traffic of its inputs and outputs).  Classes:
  * 0 CG operator (p update, A p, p.Ap)   1 pre-smoothing (r update, IC(0))
  * 2 residual + restriction             3 prolongation
- * 4 post-smoothing (IC(0), r.z)       5 coarse levels 2..L-1 (all kernels)
- * 6 coarsest solve (two-level set-ups) 7 residual before post-smoothing.
+ * 4 post-smoothing (IC(0), r.z)       5 coarse part of the V-cycle (every
+ *   kernel of levels 2..L, the coarsest product included)
+ * 6 coarsest product alone            7 residual before post-smoothing.
+ * Bytes of classes 5 and 6 count kept widths (not the padded storage).
  * Arrays hold 8 entries. */
 int specmg_get_profile(specmg_ctx* ctx, double* ms, int32_t* launches, double* bytes);
 

@@ -185,20 +185,25 @@ struct CoarseGeom {
 };
 
 // ---------------------------------------------------------------------------
-// launchers (k_fine.hip)
-template <typename T>
+// launchers (k_fine.hip).  The V-cycle's fine-level kernels take T, the
+// stored word of kappa~, the IC(0) pivots and the V-cycle vectors u and t,
+// TB that of the level-2 basis, and C, the word of the arithmetic and of the
+// level-2 vectors: (double, double, double) float64, (float, float, float)
+// the FP32 V-cycle, (double, float, double) the FP32-basis mode, (float,
+// float, double) float32 storage with float64 arithmetic.
+template <typename T, typename C>
 void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q,
                        T* u, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
-template <typename T, typename TB>
+template <typename T, typename TB, typename C>
 void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const TB* phi,
-                           const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s);
-template <typename T, typename TB>
-void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const T* e2,
+                           const int* nkeep, int L, C* r2, Scalars* sc, int check_done, hipStream_t s);
+template <typename T, typename TB, typename C>
+void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const C* e2,
                     Scalars* sc, int check_done, hipStream_t s);
-template <typename T>
+template <typename T, typename C>
 void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
                      int check_done, hipStream_t s);
-template <typename T>
+template <typename T, typename C>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
                         const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
 void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
@@ -238,7 +243,9 @@ void launch_scale_dev(double* dst, const double* src, const double* factor, int6
 void launch_gmres_begin(GmresState* st, double thr, hipStream_t s);
 void launch_gmres_step(GmresState* st, int j, double thr, hipStream_t s);
 void launch_gmres_lsq(GmresState* st, int k, hipStream_t s);
-void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+// copy / convert a vector; with sc non-null nothing is done once the solve
+// has converged (sc->done), as in the V-cycle kernels
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s, const Scalars* sc = nullptr);
 void launch_fill(double* dst, double v, int64_t n, hipStream_t s);
 void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s);
 
@@ -274,7 +281,7 @@ void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* A
 void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* Aoff,
                            const int* cmap_inv, int np, double* dense, hipStream_t s);
 template <typename S, typename T>
-void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s);
+void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s, const Scalars* sc = nullptr);
 
 // local eigensolves (k_eig.hip)
 void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,

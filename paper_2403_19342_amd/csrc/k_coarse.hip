@@ -768,7 +768,8 @@ __global__ void k_build_coarsest(CoarseGeom g, const double* __restrict__ Ad, co
 }
 
 template <typename S, typename T>
-__global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_t n) {
+__global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_t n, const Scalars* sc) {
+    if (sc && sc->done) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = (T)src[i];
@@ -841,13 +842,13 @@ void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T
                      const Scalars* sc, int check_done, hipStream_t s) {
     const size_t lds = (size_t)std::min(n, kCoarsestChunk) * sizeof(double);
     if (n <= kCoarsestChunk) {
-        hipLaunchKernelGGL((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
-                           check_done);
+        SPECMG_TIMED_LAUNCH((k_coarsest<T, 1>), dim3((n + 3) / 4), dim3(256), lds, s, n, np, Pinv, cmap, r, e, sc,
+                            check_done);
     } else {
         hipLaunchKernelGGL((k_gather_compact<T>), dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, n, cmap, r,
                            rc, sc, check_done);
-        hipLaunchKernelGGL((k_coarsest_rows<T>), dim3((n + kCoarsestRows - 1) / kCoarsestRows), dim3(256), lds, s, n,
-                           np, Pinv, cmap, rc, e, sc, check_done);
+        SPECMG_TIMED_LAUNCH((k_coarsest_rows<T>), dim3((n + kCoarsestRows - 1) / kCoarsestRows), dim3(256), lds, s,
+                            n, np, Pinv, cmap, rc, e, sc, check_done);
     }
 }
 
@@ -877,11 +878,11 @@ void launch_build_coarsest(const CoarseGeom& g, const double* Ad, const double* 
 }
 
 template <typename S, typename T>
-void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s) {
+void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s, const Scalars* sc) {
     int64_t b = (n + 255) / 256;
     if (b > 4096) b = 4096;
     if (b < 1) b = 1;
-    hipLaunchKernelGGL((k_convert<S, T>), dim3((int)b), dim3(256), 0, s, src, dst, n);
+    hipLaunchKernelGGL((k_convert<S, T>), dim3((int)b), dim3(256), 0, s, src, dst, n, sc);
 }
 
 template void launch_coarse_smooth<double>(const CoarseGeom&, const double*, const double*, const double*, double*,
@@ -908,7 +909,7 @@ template void launch_coarsest<double>(int, int, const double*, const int*, const
                                       const Scalars*, int, hipStream_t);
 template void launch_coarsest<float>(int, int, const double*, const int*, const float*, float*, double*,
                                      const Scalars*, int, hipStream_t);
-template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t);
-template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void launch_convert<double, float>(const double*, float*, int64_t, hipStream_t, const Scalars*);
+template void launch_convert<float, double>(const float*, double*, int64_t, hipStream_t, const Scalars*);
 
 }  // namespace specmg

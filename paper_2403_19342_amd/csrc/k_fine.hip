@@ -301,6 +301,28 @@ __device__ __forceinline__ void store_pencil(float* p, float (&v)[8], int jk) {
     for (int i = 0; i < 2; ++i) q[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
+// Float32-stored pencils with float64 arithmetic: converted on the load
+// (before the rotation) and on the store (after it).
+__device__ __forceinline__ void load_pencil(const float* __restrict__ p, double (&v)[8], int jk) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float4 d = q[i];
+        v[4 * i] = (double)d.x;
+        v[4 * i + 1] = (double)d.y;
+        v[4 * i + 2] = (double)d.z;
+        v[4 * i + 3] = (double)d.w;
+    }
+    rotate_slots(v, jk, false);
+}
+__device__ __forceinline__ void store_pencil(float* p, double (&v)[8], int jk) {
+    rotate_slots(v, jk, true);
+    float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
+}
+
 // value of the same cell in lanes -+1 (y) and -+8 (z); lanes at the edge of
 // the wavefront get their own value, which the callers mask
 template <typename T>
@@ -378,7 +400,9 @@ __device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8
 // pre-smoothing: (optionally r -= alpha q with ||r||^2) then u = M^{-1} r
 // mode bit0: update r and reduce ||r||^2 (sets the converged flag)
 // mode bit1: return at once when the solve is finished
-template <int EX, typename T>
+// T: stored word of kappa~, 1/d and u; C: arithmetic (T, or float64 with
+// float32 storage)
+template <int EX, typename T, typename C>
 __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __restrict__ kt,
                                                         const T* __restrict__ invd, double* r,
                                                         const double* __restrict__ q, T* __restrict__ u,
@@ -393,14 +417,14 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     const double alpha = (mode & 1) ? sc->alpha : 0.0;
     // phases in order, each one's registers released before the next
     // (faces first, then the residual update, then the pivots)
-    T fx[8], fy[8], fz[8];
+    C fx[8], fy[8], fz[8];
     {
-        T kc[8];
+        C kc[8];
         load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz, (T)g.cy, (T)g.cz);
+        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
     }
     __builtin_amdgcn_sched_barrier(0);
-    T y[8];
+    C y[8];
     double rr = 0.0;
     {
         double vr[8], vq[8];
@@ -414,11 +438,11 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
             }
         }
 #pragma unroll
-        for (int s = 0; s < 8; ++s) y[s] = (T)vr[s];
+        for (int s = 0; s < 8; ++s) y[s] = (C)vr[s];
         if (mode & 1) store_pencil(r + row, vr, jk);
     }
     __builtin_amdgcn_sched_barrier(0);
-    T ix[8];
+    C ix[8];
     load_pencil(invd + row, ix, jk);
     ic_pencil(y, ix, fx, fy, fz, j, k);
     store_pencil(u + row, y, jk);
@@ -459,6 +483,18 @@ __device__ __forceinline__ void load8<float>(const float* __restrict__ p, float 
     }
 }
 
+__device__ __forceinline__ void load8(const float* __restrict__ p, double (&v)[8]) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float4 d = q[i];
+        v[4 * i] = (double)d.x;
+        v[4 * i + 1] = (double)d.y;
+        v[4 * i + 2] = (double)d.z;
+        v[4 * i + 3] = (double)d.w;
+    }
+}
+
 // s -= T (u - u_nb) over the pencil for one neighbour pencil (nu, nk)
 template <typename T>
 __device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T (&kc)[8], const T (&nu)[8],
@@ -469,12 +505,12 @@ __device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T
 
 // s = r - A u on the x-pencil of row (j, k) of an element (x0 = the
 // element's first x, (y, z) the row), natural order; row = index of (x0, y, z)
-template <typename T>
+template <typename T, typename C>
 __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
                                                 const double* __restrict__ r, size_t row, int x0, int y, int z,
-                                                int lane, int j, int k, T (&s)[8]) {
+                                                int lane, int j, int k, C (&s)[8]) {
     const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
-    T uc[8], kc[8];
+    C uc[8], kc[8];
     load8(u + row, uc);
     load8(kt + row, kc);
     {
@@ -482,23 +518,23 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const double2 d = q[i];
-            s[2 * i] = (T)d.x;
-            s[2 * i + 1] = (T)d.y;
+            s[2 * i] = (C)d.x;
+            s[2 * i + 1] = (C)d.y;
         }
     }
     // x faces: inside the pencil, then the two ends
 #pragma unroll
     for (int x = 0; x < 7; ++x) {
-        const T d = harm(kc[x], kc[x + 1]) * (uc[x] - uc[x + 1]);
+        const C d = harm(kc[x], kc[x + 1]) * (uc[x] - uc[x + 1]);
         s[x] -= d;
         s[x + 1] += d;
     }
-    if (x0 > 0) s[0] -= harm(kc[0], kt[row - 1]) * (uc[0] - u[row - 1]);
-    if (x0 + 8 < g.nx) s[7] -= harm(kc[7], kt[row + 8]) * (uc[7] - u[row + 8]);
+    if (x0 > 0) s[0] -= harm(kc[0], (C)kt[row - 1]) * (uc[0] - (C)u[row - 1]);
+    if (x0 + 8 < g.nx) s[7] -= harm(kc[7], (C)kt[row + 8]) * (uc[7] - (C)u[row + 8]);
     // y and z neighbours, one direction at a time
 #pragma unroll 1
     for (int d = 0; d < 4; ++d) {
-        T nu[8], nk[8];
+        C nu[8], nk[8];
         // source lane of the neighbour row: -1, +1, -8, +8 (wrapping lanes are
         // the element's edge lanes, which load instead)
         const int src = (lane + (d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -8 : 8)))) & 63;
@@ -516,21 +552,21 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
                 load8(kt + o, nk);
             } else {
 #pragma unroll
-                for (int x = 0; x < 8; ++x) nk[x] = T(0);
+                for (int x = 0; x < 8; ++x) nk[x] = C(0);
             }
         }
-        face_pencil(s, uc, kc, nu, nk, (T)(d < 2 ? g.cy : g.cz));
+        face_pencil(s, uc, kc, nu, nk, (C)(d < 2 ? g.cy : g.cz));
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-// TB: word type of the stored basis (float32 copy with float64 vectors in
-// the FP32-basis mode; the products are formed in T)
-template <typename T, typename TB>
+// T: stored word of kappa~ and u; TB: stored word of the basis; C: the
+// arithmetic and the word of the level-2 residual r2
+template <typename T, typename TB, typename C>
 __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
                                                        const T* __restrict__ u, const double* __restrict__ r,
                                                        const TB* __restrict__ phi, const int* __restrict__ nkeep,
-                                                       int L, T* __restrict__ r2, const Scalars* sc,
+                                                       int L, C* __restrict__ r2, const Scalars* sc,
                                                        int check_done) {
     if (check_done && sc->done) return;
     const int lane = threadIdx.x & 63;
@@ -544,20 +580,20 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     const int j = lane & 7, k = lane >> 3;
     const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
     const size_t row = (size_t)x0 + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
-    T s[8];
+    C s[8];
     pencil_residual(g, kt, u, r, row, x0, y, z, lane, j, k, s);
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
-    T acc[kMaxCols];
+    C acc[kMaxCols];
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
-        T a = T(0);
+        C a = C(0);
         if (jj < nkp) {
             TB pv[8];
             load8(ph + (size_t)jj * kSub3, pv);
 #pragma unroll
-            for (int x = 0; x < 8; ++x) a += (T)pv[x] * s[x];
+            for (int x = 0; x < 8; ++x) a += (C)pv[x] * s[x];
         }
         acc[jj] = a;
         // at most three columns of loads in flight (register budget)
@@ -565,32 +601,33 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     }
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
-        const T v = wave_sum(acc[jj]);
+        const C v = wave_sum(acc[jj]);
         if (lane == 0 && jj < L) r2[(size_t)e * L + jj] = v;
     }
 }
 
-// u += phi e2 on every element (prolongation, Algorithm 1 step 8)
-template <typename T, typename TB>
+// u += phi e2 on every element (prolongation, Algorithm 1 step 8); the sum
+// is formed in C, the word of e2
+template <typename T, typename TB, typename C>
 __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __restrict__ phi,
                                                   const int* __restrict__ nkeep, int L,
-                                                  const T* __restrict__ e2, const Scalars* sc,
+                                                  const C* __restrict__ e2, const Scalars* sc,
                                                   int check_done) {
     if (check_done && sc->done) return;
     const int e = blockIdx.x;
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int nk = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3;
-    const T* ee = e2 + (size_t)e * L;
+    const C* ee = e2 + (size_t)e * L;
     for (int c = threadIdx.x; c < kSub3; c += 256) {
-        T acc = T(0);
+        C acc = C(0);
 #pragma unroll
         for (int jj = 0; jj < kMaxCols; ++jj) {
             const int jc = jj < nk ? jj : nk - 1;
-            acc += (jj < nk ? (T)ph[(size_t)jc * kSub3 + c] : T(0)) * ee[jc];
+            acc += (jj < nk ? (C)ph[(size_t)jc * kSub3 + c] : C(0)) * ee[jc];
         }
         const size_t gi = gidx(g, ex * 8 + (c & 7), ey * 8 + ((c >> 3) & 7), ez * 8 + (c >> 6));
-        u[gi] += acc;
+        u[gi] = (T)((C)u[gi] + acc);
     }
 }
 
@@ -599,8 +636,8 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
 // kappa~ in registers; x- and y-neighbours come from the L1 cache.
 // Faces leaving the domain have zero transmissibility.
 constexpr int kResZ = 8;
-template <typename T>
-__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, T cy, T cz, const T* __restrict__ kt,
+template <typename T, typename C>
+__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, C cy, C cz, const T* __restrict__ kt,
                                                   const T* __restrict__ u, const double* __restrict__ r,
                                                   T* __restrict__ t, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
@@ -611,23 +648,23 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, T cy, 
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
     size_t gi = (size_t)x + sy * y + sz * z0;
     const bool xm = x > 0, xp = x + 1 < nx, ym = y > 0, yp = y + 1 < ny;
-    T uc = u[gi], kc = kt[gi];
-    T um = z0 > 0 ? u[gi - sz] : T(0), km = z0 > 0 ? kt[gi - sz] : T(0);
+    C uc = u[gi], kc = kt[gi];
+    C um = z0 > 0 ? (C)u[gi - sz] : C(0), km = z0 > 0 ? (C)kt[gi - sz] : C(0);
 #pragma unroll 2
     for (int z = z0; z < z0 + kResZ; ++z, gi += sz) {
         const bool zp = z + 1 < nz;
-        const T up = zp ? u[gi + sz] : T(0), kp = zp ? kt[gi + sz] : T(0);
-        const T uxm = xm ? u[gi - 1] : T(0), kxm = xm ? kt[gi - 1] : T(0);
-        const T uxp = xp ? u[gi + 1] : T(0), kxp = xp ? kt[gi + 1] : T(0);
-        const T uym = ym ? u[gi - sy] : T(0), kym = ym ? kt[gi - sy] : T(0);
-        const T uyp = yp ? u[gi + sy] : T(0), kyp = yp ? kt[gi + sy] : T(0);
-        T a = harm(kc, kxm) * (uc - uxm);
+        const C up = zp ? (C)u[gi + sz] : C(0), kp = zp ? (C)kt[gi + sz] : C(0);
+        const C uxm = xm ? (C)u[gi - 1] : C(0), kxm = xm ? (C)kt[gi - 1] : C(0);
+        const C uxp = xp ? (C)u[gi + 1] : C(0), kxp = xp ? (C)kt[gi + 1] : C(0);
+        const C uym = ym ? (C)u[gi - sy] : C(0), kym = ym ? (C)kt[gi - sy] : C(0);
+        const C uyp = yp ? (C)u[gi + sy] : C(0), kyp = yp ? (C)kt[gi + sy] : C(0);
+        C a = harm(kc, kxm) * (uc - uxm);
         a += harm(kc, kxp) * (uc - uxp);
         a += harm(kc, kym) * cy * (uc - uym);
         a += harm(kc, kyp) * cy * (uc - uyp);
         a += harm(kc, km) * cz * (uc - um);
         a += harm(kc, kp) * cz * (uc - up);
-        t[gi] = (T)r[gi] - a;
+        t[gi] = (T)((C)r[gi] - a);
         um = uc;
         km = kc;
         uc = up;
@@ -638,7 +675,7 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, T cy, 
 // post-smoothing (Algorithm 1 step 9): z = u + M^{-1} t with t = r - A u
 // from k_residual.  mode bit0: reduce r.z (and z.q when flexible) and update
 // the CG beta; bit1: return at once when the solve is finished.
-template <int EX, typename T>
+template <int EX, typename T, typename C>
 __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __restrict__ kt,
                                                          const T* __restrict__ invd,
                                                          const T* __restrict__ u, const T* __restrict__ tres,
@@ -653,21 +690,21 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = lane & 7, k = lane >> 3, jk = j + k;
     const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);
-    T fx[8], fy[8], fz[8];
+    C fx[8], fy[8], fz[8];
     {
-        T kc[8];
+        C kc[8];
         load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz, (T)g.cy, (T)g.cz);
+        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
     }
     __builtin_amdgcn_sched_barrier(0);
-    T y[8], ix[8];
+    C y[8], ix[8];
     load_pencil(tres + row, y, jk);
     load_pencil(invd + row, ix, jk);
     ic_pencil(y, ix, fx, fy, fz, j, k);
     double rz = 0.0, zq = 0.0;
     const int flex = (mode & 1) ? sc->flexible : 0;
     {
-        T uo[8];
+        C uo[8];
         double zv[8], rv[8], qv[8];
         load_pencil(u + row, uo, jk);
         if (mode & 1) load_pencil(r + row, rv, jk);
@@ -1014,7 +1051,8 @@ __global__ void k_fill(double* d, double v, int64_t n) {
         d[i] = v;
 }
 
-__global__ void k_copy(double* d, const double* __restrict__ s, int64_t n) {
+__global__ void k_copy(double* d, const double* __restrict__ s, int64_t n, const Scalars* sc) {
+    if (sc && sc->done) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         d[i] = s[i];
@@ -1064,42 +1102,42 @@ static inline int grid_1d(int64_t n) {
         } break;                              \
     }
 
-template <typename T>
+template <typename T, typename C>
 void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q, T* u,
                        Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_pre_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0, s,
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_pre_smooth<EX, T, C>), dim3(g.ntiles), dim3(64 * EX), 0, s,
                                                 g, kt, invd, r, q, u, sc, rb, mode));
     if (mode & 1) launch_finalize(RS_RR, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
-template <typename T, typename TB>
+template <typename T, typename TB, typename C>
 void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const TB* phi,
-                           const int* nkeep, int L, T* r2, Scalars* sc, int check_done, hipStream_t s) {
+                           const int* nkeep, int L, C* r2, Scalars* sc, int check_done, hipStream_t s) {
     const int m = g.mx * g.my * g.mz;
-    SPECMG_TIMED_LAUNCH((k_resid_restrict<T, TB>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L,
+    SPECMG_TIMED_LAUNCH((k_resid_restrict<T, TB, C>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L,
                         r2, sc, check_done);
 }
 
-template <typename T, typename TB>
-void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const T* e2,
+template <typename T, typename TB, typename C>
+void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const C* e2,
                     Scalars* sc, int check_done, hipStream_t s) {
-    SPECMG_TIMED_LAUNCH((k_prolong<T, TB>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
+    SPECMG_TIMED_LAUNCH((k_prolong<T, TB, C>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
                        sc, check_done);
 }
 
 // t = r - A u (ny and nz are multiples of 8, nx any multiple of 8)
-template <typename T>
+template <typename T, typename C>
 void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
                      int check_done, hipStream_t s) {
     if (g.ny % 4 || g.nz % kResZ) throw HipError{hipErrorInvalidValue, "residual tiling"};
-    SPECMG_TIMED_LAUNCH((k_residual<T>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ), dim3(256), 0, s, g.nx, g.ny,
-                        g.nz, (T)g.cy, (T)g.cz, kt, u, r, t, sc, check_done);
+    SPECMG_TIMED_LAUNCH((k_residual<T, C>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ), dim3(256), 0, s, g.nx,
+                        g.ny, g.nz, (C)g.cy, (C)g.cz, kt, u, r, t, sc, check_done);
 }
 
-template <typename T>
+template <typename T, typename C>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
                         const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T>), dim3(g.ntiles), dim3(64 * EX), 0,
+    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T, C>), dim3(g.ntiles), dim3(64 * EX), 0,
                                                  s, g, kt, invd, u, tres, r, q, z, sc, rb, mode));
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
@@ -1162,8 +1200,8 @@ void launch_sub_mean(double* x, int64_t n, const double* sum, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_mean, dim3(grid_1d(n)), dim3(256), 0, s, x, n, sum);
 }
 
-void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n);
+void launch_copy(double* dst, const double* src, int64_t n, hipStream_t s, const Scalars* sc) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_1d(n)), dim3(256), 0, s, dst, src, n, sc);
 }
 
 void launch_fill(double* dst, double v, int64_t n, hipStream_t s) {
@@ -1174,30 +1212,27 @@ void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s) {
     hipLaunchKernelGGL(k_pcg_init, dim3(1), dim3(1), 0, s, sc, thresh2, flexible);
 }
 
-template void launch_pre_smooth<double>(const FineGeom&, const double*, const double*, double*,
-                                        const double*, double*, Scalars*, RedBuf, int, hipStream_t);
-template void launch_pre_smooth<float>(const FineGeom&, const float*, const float*, double*,
-                                       const double*, float*, Scalars*, RedBuf, int, hipStream_t);
-template void launch_resid_restrict<double, double>(const FineGeom&, const double*, const double*, const double*,
-                                                    const double*, const int*, int, double*, Scalars*, int,
-                                                    hipStream_t);
-template void launch_resid_restrict<double, float>(const FineGeom&, const double*, const double*, const double*,
-                                                   const float*, const int*, int, double*, Scalars*, int,
-                                                   hipStream_t);
-template void launch_resid_restrict<float, float>(const FineGeom&, const float*, const float*, const double*,
-                                                  const float*, const int*, int, float*, Scalars*, int,
-                                                  hipStream_t);
-template void launch_prolong<double, double>(const FineGeom&, double*, const double*, const int*, int,
-                                             const double*, Scalars*, int, hipStream_t);
-template void launch_prolong<double, float>(const FineGeom&, double*, const float*, const int*, int,
-                                            const double*, Scalars*, int, hipStream_t);
-template void launch_prolong<float, float>(const FineGeom&, float*, const float*, const int*, int, const float*,
-                                           Scalars*, int, hipStream_t);
-template void launch_residual<double>(const FineGeom&, const double*, const double*, const double*, double*,
-                                      const Scalars*, int, hipStream_t);
-template void launch_residual<float>(const FineGeom&, const float*, const float*, const double*, float*,
-                                     const Scalars*, int, hipStream_t);
-template void launch_post_smooth<double>(const FineGeom&, const double*, const double*, const double*, const double*, const double*, double*, double*, Scalars*, RedBuf, int, hipStream_t);
-template void launch_post_smooth<float>(const FineGeom&, const float*, const float*, const float*, const double*, const double*, double*, float*, Scalars*, RedBuf, int, hipStream_t);
+// (T, C): (double, double) float64; (float, float) the FP32 V-cycle;
+// (float, double) float32 storage with float64 arithmetic
+#define SPECMG_FINE_INST(T, TB, C)                                                                                 \
+    template void launch_pre_smooth<T, C>(const FineGeom&, const T*, const T*, double*, const double*, T*,         \
+                                          Scalars*, RedBuf, int, hipStream_t);                                     \
+    template void launch_resid_restrict<T, TB, C>(const FineGeom&, const T*, const T*, const double*, const TB*,   \
+                                                  const int*, int, C*, Scalars*, int, hipStream_t);                \
+    template void launch_prolong<T, TB, C>(const FineGeom&, T*, const TB*, const int*, int, const C*, Scalars*,    \
+                                           int, hipStream_t);                                                      \
+    template void launch_residual<T, C>(const FineGeom&, const T*, const T*, const double*, T*, const Scalars*,     \
+                                        int, hipStream_t);                                                         \
+    template void launch_post_smooth<T, C>(const FineGeom&, const T*, const T*, const T*, const double*,           \
+                                           const double*, double*, T*, Scalars*, RedBuf, int, hipStream_t);
+SPECMG_FINE_INST(double, double, double)
+SPECMG_FINE_INST(float, float, float)
+SPECMG_FINE_INST(float, float, double)
+template void launch_resid_restrict<double, float, double>(const FineGeom&, const double*, const double*,
+                                                           const double*, const float*, const int*, int, double*,
+                                                           Scalars*, int, hipStream_t);
+template void launch_prolong<double, float, double>(const FineGeom&, double*, const float*, const int*, int,
+                                                    const double*, Scalars*, int, hipStream_t);
+#undef SPECMG_FINE_INST
 
 }  // namespace specmg

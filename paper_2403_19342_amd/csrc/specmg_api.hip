@@ -56,13 +56,9 @@ struct Level {
     double* Dinv = nullptr;
     double* G = nullptr;       // D_c^{-1} A(c, neighbour) for the smoother
     double* z = nullptr;
-    float* basis32 = nullptr;
-    float* Aoff32 = nullptr;
-    float* Ad32 = nullptr;
-    float* Dinv32 = nullptr;
-    float* G32 = nullptr;
+    float* basis32 = nullptr;  // level 2, the mixed modes: float32 copy of the basis
     double *r = nullptr, *u = nullptr, *e = nullptr;
-    float *r32 = nullptr, *u32 = nullptr, *e32 = nullptr;
+    float *r32 = nullptr, *e32 = nullptr;  // level 2, FP32 V-cycle: the level's vectors as the fine kernels see them
 };
 
 }  // namespace
@@ -77,7 +73,6 @@ struct DevBuf {
 };
 
 constexpr int kCnnSetupBatch = 8192;   // level-2 elements per network batch in set-up
-constexpr int kReplacePeriod = 25;     // FP32 V-cycle: iterations between residual replacements
 
 struct specmg_ctx {
     specmg_grid grid{};
@@ -87,6 +82,8 @@ struct specmg_ctx {
     double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
     int fp32 = 0;
     int fp32_basis = 0;   // float64 fine level with a float32 copy of the level-2 basis
+    int fp32_store = 0;   // fine level stored in float32 (kappa~, 1/d, basis, u, t), float64 arithmetic
+    int flexible = 0;     // the V-cycle is not a fixed linear map: flexible (Polak-Ribiere) CG
     int nu = 1, nu_c = 1; // block-Jacobi sweeps before and after the correction: fine, coarse levels
     int64_t n = 0;
     FineGeom fg{};
@@ -124,6 +121,8 @@ struct specmg_ctx {
     std::vector<Rec> recs;
     double prof_ms[8] = {0};
     int prof_count[8] = {0};
+    double coarse_bytes = 0.0;     // algorithmic bytes of one V-cycle's coarse part (levels >= 2)
+    double coarsest_bytes = 0.0;   // of the coarsest product alone
 
     template <typename T>
     T* alloc(size_t count) {
@@ -212,110 +211,111 @@ double* pick<double>(double* d, float*) { return d; }
 template <>
 float* pick<float>(double*, float* f) { return f; }
 
-// coarse levels from level index li (lev[li] holds r, receives e)
-template <typename T>
+// coarse levels from level index li (lev[li] holds r, receives e), float64
+// in every precision mode: the kept coarse modes of high-contrast media have
+// eigenvalues near float32 rounding of the operator's scale (inclusion and
+// channel modes, about 1e-7), so float32 arithmetic at these levels, and even
+// float32 copies of their blocks with float64 arithmetic, lose them
 void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
     Level& lv = c->lev[li];
-    T* r = pick<T>(lv.r, lv.r32);
-    T* e = pick<T>(lv.e, lv.e32);
+    double* r = lv.r;
+    double* e = lv.e;
     if (li + 1 == c->lev.size()) {
-        launch_coarsest<T>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->rc, c->sc, check, s);
+        const size_t ev = prof_begin(c, s);
+        launch_coarsest<double>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->rc, c->sc, check, s);
+        prof_end(c, ev, PC_COARSEST, s);
         return;
     }
     Level& up = c->lev[li + 1];
-    T* u = pick<T>(lv.u, lv.u32);
-    const T* Ad = pick<T>(lv.Ad, lv.Ad32);
-    const T* Aoff = pick<T>(lv.Aoff, lv.Aoff32);
-    const T* Dinv = pick<T>(lv.Dinv, lv.Dinv32);
-    const T* G = pick<T>(lv.G, lv.G32);
-    const T* V = pick<T>(up.basis, up.basis32);
+    double* u = lv.u;
     // a repeated sweep u += M^-1 (r - A u) reads neighbouring blocks' u, so
     // it writes e (free until the last sweep) and copies back
     const int64_t nrow = (int64_t)lv.g.m * lv.g.L;
-    launch_coarse_smooth<T>(lv.g, Dinv, G, r, u, c->sc, check, s);
+    launch_coarse_smooth<double>(lv.g, lv.Dinv, lv.G, r, u, c->sc, check, s);
+    const Scalars* gate = check ? c->sc : nullptr;
     for (int it = 1; it < c->nu_c; ++it) {
-        launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
-        launch_copy(u, e, nrow, s);
+        launch_coarse_resid_smooth<double>(lv.g, lv.Ad, lv.Dinv, lv.Aoff, lv.G, r, u, e, c->sc, check, s);
+        launch_copy(u, e, nrow, s, gate);
     }
-    launch_coarse_resid_restrict<T>(lv.g, Ad, Aoff, r, u, V, up.nkeep, up.L, pick<T>(up.r, up.r32), c->sc, check, s);
-    coarse_cycle<T>(c, li + 1, check, s);
-    launch_coarse_prolong<T>(lv.g, u, V, up.nkeep, up.L, pick<T>(up.e, up.e32), c->sc, check, s);
+    launch_coarse_resid_restrict<double>(lv.g, lv.Ad, lv.Aoff, r, u, up.basis, up.nkeep, up.L, up.r, c->sc, check,
+                                         s);
+    coarse_cycle(c, li + 1, check, s);
+    launch_coarse_prolong<double>(lv.g, u, up.basis, up.nkeep, up.L, up.e, c->sc, check, s);
     for (int it = 1; it < c->nu_c; ++it) {
-        launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
-        launch_copy(u, e, nrow, s);
+        launch_coarse_resid_smooth<double>(lv.g, lv.Ad, lv.Dinv, lv.Aoff, lv.G, r, u, e, c->sc, check, s);
+        launch_copy(u, e, nrow, s, gate);
     }
-    launch_coarse_resid_smooth<T>(lv.g, Ad, Dinv, Aoff, G, r, u, e, c->sc, check, s);
+    launch_coarse_resid_smooth<double>(lv.g, lv.Ad, lv.Dinv, lv.Aoff, lv.G, r, u, e, c->sc, check, s);
 }
 
 // One repeated fine sweep u1 += M^-1 (r - A u1): the residual, the sweep
 // written to z (the V-cycle's output, free until the last sweep), and z
-// copied back into u1 (converted in the FP32 V-cycle).
-template <typename T>
+// copied back into u1 (converted when u1 is stored in float32).
+template <typename T, typename C>
 void extra_fine_sweep(specmg_ctx* c, double* r, double* z, int check, hipStream_t s) {
     const T* kt = pick<T>(c->kt, c->kt32);
     const T* invd = pick<T>(c->invd, c->invd32);
     T* u1 = pick<T>(c->u1, c->u1_32);
     T* tres = pick<T>(c->tres, (float*)c->tres);
-    launch_residual<T>(c->fg, kt, u1, r, tres, c->sc, check, s);
-    launch_post_smooth<T>(c->fg, kt, invd, u1, r, nullptr, z, tres, c->sc, c->rb, check ? 2 : 0, s);
-    if constexpr (std::is_same<T, float>::value) launch_convert<double, float>(z, u1, c->n, s);
-    else launch_copy(u1, z, c->n, s);
+    launch_residual<T, C>(c->fg, kt, u1, r, tres, c->sc, check, s);
+    launch_post_smooth<T, C>(c->fg, kt, invd, u1, r, nullptr, z, tres, c->sc, c->rb, check ? 2 : 0, s);
+    const Scalars* gate = check ? c->sc : nullptr;
+    if constexpr (std::is_same<T, float>::value) launch_convert<double, float>(z, u1, c->n, s, gate);
+    else launch_copy(u1, z, c->n, s, gate);
 }
 
-// z = P^{-1} r (fine level + recursion).  pre_mode / post_mode are the mode
-// bits of the fine smoother kernels; check: return early when solve is done.
-template <typename T>
-void vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
-            hipStream_t s) {
+// z = P^{-1} r (fine level + recursion).  T: stored word of the fine
+// level's coefficients and vectors, C: its arithmetic (see launch_pre_smooth).
+// pre_mode / post_mode are the mode bits of the fine smoother kernels; check:
+// return early when solve is done.
+template <typename T, typename C, typename TB>
+void vcycle_fine(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
+                 hipStream_t s) {
     const T* kt = pick<T>(c->kt, c->kt32);
     const T* invd = pick<T>(c->invd, c->invd32);
     T* u1 = pick<T>(c->u1, c->u1_32);
     Level& l2 = c->lev[0];
-    const T* phi = pick<T>(l2.basis, l2.basis32);
+    const TB* phi = pick<TB>(l2.basis, l2.basis32);
+    C* r2 = pick<C>(l2.r, l2.r32);
+    C* e2 = pick<C>(l2.e, l2.e32);
     size_t ev = prof_begin(c, s);
-    launch_pre_smooth<T>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
+    launch_pre_smooth<T, C>(c->fg, kt, invd, r, q, u1, c->sc, c->rb, pre_mode, s);
     prof_end(c, ev, PC_PRE, s);
-    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T>(c, r, z, check, s);
+    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T, C>(c, r, z, check, s);
     ev = prof_begin(c, s);
-    if (c->fp32_basis)
-        launch_resid_restrict<T, float>(c->fg, kt, u1, r, l2.basis32, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc,
-                                        check, s);
-    else
-        launch_resid_restrict<T, T>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, pick<T>(l2.r, l2.r32), c->sc, check, s);
+    launch_resid_restrict<T, TB, C>(c->fg, kt, u1, r, phi, l2.nkeep, l2.L, r2, c->sc, check, s);
     prof_end(c, ev, PC_RESTRICT, s);
     ev = prof_begin_range(c, s);
-    if constexpr (std::is_same<T, float>::value) {
-        // the coarse levels stay FP64: their kept modes include inclusion
-        // and channel modes with eigenvalues near float32 rounding (1e-7 of
-        // the operator's scale), which FP32 residuals would lose
+    if constexpr (std::is_same<C, float>::value) {
+        // the coarse levels run in float64 (see coarse_cycle)
         const int64_t n2 = (int64_t)l2.g.m * l2.L;
-        launch_convert<float, double>(l2.r32, l2.r, n2, s);
-        coarse_cycle<double>(c, 0, check, s);
-        launch_convert<double, float>(l2.e, l2.e32, n2, s);
+        const Scalars* gate = check ? c->sc : nullptr;
+        launch_convert<float, double>(l2.r32, l2.r, n2, s, gate);
+        coarse_cycle(c, 0, check, s);
+        launch_convert<double, float>(l2.e, l2.e32, n2, s, gate);
     } else {
-        coarse_cycle<double>(c, 0, check, s);
+        coarse_cycle(c, 0, check, s);
     }
-    prof_end(c, ev, c->lev.size() == 1 ? PC_COARSEST : PC_COARSE, s);
+    prof_end(c, ev, PC_COARSE, s);
     ev = prof_begin(c, s);
-    if (c->fp32_basis)
-        launch_prolong<T, float>(c->fg, u1, l2.basis32, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
-    else
-        launch_prolong<T, T>(c->fg, u1, phi, l2.nkeep, l2.L, pick<T>(l2.e, l2.e32), c->sc, check, s);
+    launch_prolong<T, TB, C>(c->fg, u1, phi, l2.nkeep, l2.L, e2, c->sc, check, s);
     prof_end(c, ev, PC_PROLONG, s);
-    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T>(c, r, z, check, s);
+    for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T, C>(c, r, z, check, s);
     T* tres = pick<T>(c->tres, (float*)c->tres);
     ev = prof_begin(c, s);
-    launch_residual<T>(c->fg, kt, u1, r, tres, c->sc, (post_mode & 2) ? 1 : 0, s);
+    launch_residual<T, C>(c->fg, kt, u1, r, tres, c->sc, (post_mode & 2) ? 1 : 0, s);
     prof_end(c, ev, PC_POSTRES, s);
     ev = prof_begin(c, s);
-    launch_post_smooth<T>(c->fg, kt, invd, u1, r, q, z, tres, c->sc, c->rb, post_mode, s);
+    launch_post_smooth<T, C>(c->fg, kt, invd, u1, r, q, z, tres, c->sc, c->rb, post_mode, s);
     prof_end(c, ev, PC_POST, s);
 }
 
 void run_vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mode, int post_mode, int check,
                 hipStream_t s) {
-    if (c->fp32) vcycle<float>(c, r, z, q, pre_mode, post_mode, check, s);
-    else vcycle<double>(c, r, z, q, pre_mode, post_mode, check, s);
+    if (c->fp32) vcycle_fine<float, float, float>(c, r, z, q, pre_mode, post_mode, check, s);
+    else if (c->fp32_store) vcycle_fine<float, double, float>(c, r, z, q, pre_mode, post_mode, check, s);
+    else if (c->fp32_basis) vcycle_fine<double, double, float>(c, r, z, q, pre_mode, post_mode, check, s);
+    else vcycle_fine<double, double, double>(c, r, z, q, pre_mode, post_mode, check, s);
 }
 
 int nvec_for(int target) {
@@ -330,6 +330,53 @@ int nvec_for(int target) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+
+// Algorithmic bytes of the coarse part of one V-cycle (kept widths, float64
+// words): per non-coarsest level with kept counts k_e, diag = sum k_e^2,
+// cpl = sum over neighbour pairs k_e k_f, dim = sum k_e, and the parents'
+// bases Vsz = sum_E K_E sum_{c in E} k_c (dimup = sum K_E):
+//   sweep (D^-1, the six couplings D^-1 A(c, n), r in; u out)   diag + 2 cpl + 2 dim
+//   residual + restriction (A_l blocks, r, u, V in; r_up out)    diag + cpl + 2 dim + Vsz + dimup
+//   prolongation (u in and out, V, e_up)                         2 dim + Vsz + dimup
+//   residual + sweep (A_l, D^-1, couplings, r, u in; e out)      2 diag + 3 cpl + 3 dim
+// and each further sweep pair (nu_c = 2) twice the last line plus a copy.
+// The coarsest product reads the n_L x n_L inverse and three n_L vectors.
+static void coarse_traffic(specmg_ctx* c) {
+    double words = 0.0;
+    for (size_t li = 0; li + 1 < c->lev.size(); ++li) {
+        const Level& lv = c->lev[li];
+        const Level& up = c->lev[li + 1];
+        const CoarseGeom& g = lv.g;
+        const int agg = g.agg;
+        double diag = 0.0, cpl = 0.0, dim = 0.0, vsz = 0.0, dimup = 0.0;
+        for (int e = 0; e < g.m; ++e) {
+            const double k = lv.nkeep_h[e];
+            const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+            diag += k * k;
+            dim += k;
+            if (ex + 1 < g.mx) cpl += k * lv.nkeep_h[e + 1];
+            if (ey + 1 < g.my) cpl += k * lv.nkeep_h[e + g.mx];
+            if (ez + 1 < g.mz) cpl += k * lv.nkeep_h[e + g.mx * g.my];
+        }
+        for (int E = 0; E < up.g.m; ++E) {
+            const int Ex = E % up.g.mx, Ey = (E / up.g.mx) % up.g.my, Ez = E / (up.g.mx * up.g.my);
+            double rows = 0.0;
+            for (int q = 0; q < agg * agg * agg; ++q) {
+                const int cx = Ex * agg + q % agg, cy = Ey * agg + (q / agg) % agg, cz = Ez * agg + q / (agg * agg);
+                rows += lv.nkeep_h[cx + g.mx * (cy + g.my * cz)];
+            }
+            vsz += up.nkeep_h[E] * rows;
+            dimup += up.nkeep_h[E];
+        }
+        words += 4 * diag + 7 * cpl + 9 * dim + 2 * vsz + 2 * dimup;
+        words += (c->nu_c - 1) * 2.0 * (2 * diag + 3 * cpl + 5 * dim);
+    }
+    double nl = 0.0;
+    for (int k : c->lev.back().nkeep_h) nl += k;
+    c->coarsest_bytes = 8.0 * (nl * nl + 3.0 * nl);
+    c->coarse_bytes = 8.0 * words + c->coarsest_bytes;
+    if (c->fp32) c->coarse_bytes += 2.0 * 12.0 * c->lev[0].dim;   // level-2 vectors widened and narrowed
+}
 
 extern "C" const char* specmg_last_error(void) { return g_last_error.c_str(); }
 
@@ -362,7 +409,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     HIPCHK(hipMemsetAsync(c->dflag, 0, 8 * sizeof(int), s));
     c->kt = c->alloc<double>(c->n);
     c->invd = c->alloc<double>(c->n);
-    if (c->fp32) {
+    if (c->fp32 || c->fp32_store) {
         c->kt32 = c->alloc<float>(c->n);
         c->invd32 = c->alloc<float>(c->n);
     }
@@ -480,6 +527,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         for (int k : lv.nkeep_h) lv.dim += k;
         for (int v : st) unconv += (v < 0);
     }
+    coarse_traffic(c);
     // ---- coarsest: A_L^+ = (A_L + alpha z z^T)^{-1} - z z^T / alpha
     {
         Level& top = c->lev.back();
@@ -541,7 +589,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         if (de != 0) return fail(SPECMG_EDEVICE, std::string("coarsest inverse: ") + hipGetErrorString((hipError_t)de));
     }
     // ---- float32 copy of the level-2 basis for the mixed-precision fine level
-    if (c->fp32 || c->fp32_basis) {
+    if (c->fp32 || c->fp32_basis || c->fp32_store) {
         Level& lv = c->lev[0];
         const size_t nb = (size_t)lv.g.m * lv.L * lv.rows;
         lv.basis32 = c->alloc<float>(nb);
@@ -570,7 +618,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->q = c->alloc<double>(c->n);
     c->u1 = c->alloc<double>(c->n);
     c->tres = c->alloc<double>(c->n);
-    if (c->fp32) c->u1_32 = c->alloc<float>(c->n);
+    if (c->fp32 || c->fp32_store) c->u1_32 = c->alloc<float>(c->n);
     c->dtmp = c->alloc<double>(8);
     c->sc = c->alloc<Scalars>(1);
     HIPCHK(hipHostMalloc((void**)&c->sc_host, sizeof(Scalars), hipHostMallocDefault));
@@ -617,7 +665,7 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     if (opts->nu < 1 || opts->nu > 2) return fail(SPECMG_EINVAL, "nu must be 1 or 2");
     if (opts->nu_c < 0 || opts->nu_c > 2) return fail(SPECMG_EINVAL, "nu_c must be 0 (= nu), 1 or 2");
     if (opts->precision != SPECMG_FP64 && opts->precision != SPECMG_FP32_VCYCLE &&
-        opts->precision != SPECMG_FP32_BASIS)
+        opts->precision != SPECMG_FP32_BASIS && opts->precision != SPECMG_FP32_STORE)
         return fail(SPECMG_EINVAL, "unknown precision");
     if (opts->warm_start != SPECMG_WS_NONE && opts->warm_start != SPECMG_WS_CNN)
         return fail(SPECMG_EINVAL, "unknown warm_start");
@@ -651,6 +699,8 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
     c->thr_cc = opts->eig_threshold_coarse;
     c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
     c->fp32_basis = opts->precision == SPECMG_FP32_BASIS;
+    c->fp32_store = opts->precision == SPECMG_FP32_STORE;
+    c->flexible = c->fp32 || c->fp32_store;
     c->nu = opts->nu;
     c->nu_c = opts->nu_c > 0 ? opts->nu_c : opts->nu;
     int rc;
@@ -738,13 +788,12 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
         launch_copy(c->r, b, n, s);
     }
     const double thresh2 = (tol * nb) * (tol * nb);
-    const int flexible = c->fp32;
+    const int flexible = c->flexible;
     launch_pcg_init(c->sc, thresh2, flexible, s);
     int rc = SPECMG_OK;
     double r0 = std::sqrt(dev_dot(c, c->r, c->r, s));
     bool converged = r0 <= tol * nb;
     int k = 0;   // CG iterations issued so far (= device iteration counter after a sync)
-    int last_replace = 0;
     bool restart = true;
     while (!converged) {
         if (restart) {
@@ -789,16 +838,6 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
         if (k >= max_iter) {
             launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
             break;
-        }
-        if (flexible && k - last_replace >= kReplacePeriod) {
-            // FP32 V-cycle: replace the recursive residual by the true FP64
-            // one, r = b - A x, and restart the V-cycle from it; the next
-            // direction update continues p = z + beta p
-            launch_axpy_x(x, c->p[0], c->p[1], c->sc, n, s);
-            launch_apply_A(c->fg, c->kt, x, b, c->r, 1, s);
-            si.replacements += 1;
-            last_replace = k;
-            restart = true;
         }
     }
     read_scalars(c, s);
@@ -1066,16 +1105,18 @@ extern "C" int specmg_set_profiling(specmg_ctx* c, int32_t on) {
 extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, double* bytes) {
     if (!c) return fail(SPECMG_EINVAL, "null context");
     const double n = (double)c->n;
-    const double w = c->fp32 ? 4.0 : 8.0;          // V-cycle word size
+    const double w = (c->fp32 || c->fp32_store) ? 4.0 : 8.0;   // stored word of the fine V-cycle
     const double phi_cells = 512.0 * c->lev[0].dim; // sum over elements of 512 * nkeep
     double b[8] = {0};
     b[PC_SPMV] = n * 8.0 * 7.0;                      // z, p_old, x, kappa~ in; p, q, x out
     b[PC_PRE] = n * (8.0 * 3.0 + 2.0 * w + w);       // r, q in, r out; kappa~, 1/d in; u out
-    const double wb = c->fp32_basis ? 4.0 : w;       // basis word size
+    const double wb = (c->fp32_basis || c->fp32_store) ? 4.0 : w;   // basis word size
     b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * wb;  // u, kappa~, r; phi
     b[PC_PROLONG] = n * 2.0 * w + phi_cells * wb;            // u in/out; phi
-    b[PC_POST] = n * (4.0 * w + 8.0 * 2.0 + (c->fp32 ? 8.0 : 0.0));  // t, kappa~, 1/d, u, r in; z out (q)
+    b[PC_POST] = n * (4.0 * w + 8.0 * 2.0 + (c->flexible ? 8.0 : 0.0));  // t, kappa~, 1/d, u, r in; z out (q)
     b[PC_POSTRES] = n * (3.0 * w + 8.0);                                // u, kappa~, r in; t out
+    b[PC_COARSE] = c->coarse_bytes;
+    b[PC_COARSEST] = c->coarsest_bytes;
     for (int i = 0; i < 8; ++i) {
         if (ms) ms[i] = c->prof_ms[i];
         if (launches) launches[i] = c->prof_count[i];

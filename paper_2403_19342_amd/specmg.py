@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspecmg.so")
 
 OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7, -8
-FP64, FP32_VCYCLE, FP32_BASIS = 0, 1, 2
+FP64, FP32_VCYCLE, FP32_BASIS, FP32_STORE = 0, 1, 2, 3
 WS_NONE, WS_CNN = 0, 1
 
 EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve",
@@ -26,7 +26,7 @@ EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
             "specmg_cnn_loss_backward", "specmg_cnn_adam", "specmg_total_mobility", "specmg_transport"]
-PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_levels",
+PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_part",
                    "coarsest", "post_residual"]
 
 

@@ -200,7 +200,7 @@ class Workload:
     n: int
     levels: int
     eigs: int
-    precision: str           # "fp64" or "fp32_vcycle"
+    precision: str           # default form: "fp64" (every workload); the mixed forms are options
     seed: int
     kind: str                # field generator
     source: str
@@ -211,10 +211,10 @@ class Workload:
 WORKLOADS = {
     "boxes32": Workload("boxes32", 32, 2, 4, "fp64", 0, "boxes", "corner"),
     "gauss128": Workload("gauss128", 128, 3, 6, "fp64", 1, "gauss", "quarter_five_spot"),
-    "channels256": Workload("channels256", 256, 3, 8, "fp32_vcycle", 2, "channels", "five_spot"),
+    "channels256": Workload("channels256", 256, 3, 8, "fp64", 2, "channels", "five_spot"),
     # 32^3-cell coarse elements hold up to ~9 inclusions: 2x aggregation and
     # 10 vectors per coarse element keep every inclusion mode in the hierarchy
-    "inclusions512": Workload("inclusions512", 512, 4, 6, "fp32_vcycle", 3, "inclusions", "five_spot", 2, 10),
+    "inclusions512": Workload("inclusions512", 512, 4, 6, "fp64", 3, "inclusions", "five_spot", 2, 10),
 }
 
 

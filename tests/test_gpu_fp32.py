@@ -1,9 +1,10 @@
-"""FP32 V-cycle inside FP64 CG (the mixed-precision extension) against the
-FP64 oracle.
+"""The mixed-precision forms of the V-cycle inside FP64 CG against the FP64
+oracle: the FP32 V-cycle (fine level stored and computed in float32) and the
+float32-storage form (fine level stored in float32, computed in float64).
 
-There is no exactness pin: the V-cycle rounds to float32 while CG, its dot
-products, the residual replacement and the coarsest pseudo-inverse stay in
-float64.  Each result is reported as its error against the FP64 oracle and
+There is no exactness pin: the V-cycle (fine and coarse levels) rounds to
+float32 while CG, its dot products, the true-residual confirmation and the
+coarsest pseudo-inverse stay in float64.  Each result is reported as its error against the FP64 oracle and
 must satisfy:
   P^{-1} r   max(1e-4, 1e-6 / lambda_min+(A_L)) relative (mean-projected):
              float32 rounding (6e-8) of the smoother and of the coarse
@@ -29,21 +30,25 @@ CASES = [
     ("gauss32_l3", 32, "gauss", 1, 3, 6, 2),
     ("incl32_l3", 32, "inclusions", 3, 3, 6, 4),
 ]
+MODES = ["fp32_vcycle", "fp32_store"]
 
 
-def _ctx(perm, levels, eigs, agg):
-    from paper_2403_19342_amd.specmg import SpecMG, FP32_VCYCLE
-    return SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, precision=FP32_VCYCLE)
+def _ctx(perm, levels, eigs, agg, mode="fp32_vcycle", eigs_coarse=0):
+    from paper_2403_19342_amd.specmg import SpecMG, FP32_VCYCLE, FP32_STORE
+    prec = {"fp32_vcycle": FP32_VCYCLE, "fp32_store": FP32_STORE}[mode]
+    return SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, precision=prec,
+                  eigs_coarse=eigs_coarse)
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name,n,kind,seed,levels,eigs,agg", CASES)
-def test_fp32_apply_precond(name, n, kind, seed, levels, eigs, agg):
+def test_fp32_apply_precond(name, n, kind, seed, levels, eigs, agg, mode):
     import torch
     perm = make_field(kind, n, seed)
     g = Grid.unit_cube(n)
     hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
     pre = Preconditioner(hier)
-    ctx = _ctx(perm, levels, eigs, agg)
+    ctx = _ctx(perm, levels, eigs, agg, mode)
     wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
     tol = max(1e-4, 1e-6 / wL[1])
     for s in range(2):
@@ -55,19 +60,20 @@ def test_fp32_apply_precond(name, n, kind, seed, levels, eigs, agg):
         zg -= zg.mean()
         zo -= zo.mean()
         err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
-        print(f"{name}: FP32 V-cycle P^-1 r error vs FP64 oracle {err:.2e} (bound {tol:.1e})")
+        print(f"{name} {mode}: P^-1 r error vs FP64 oracle {err:.2e} (bound {tol:.1e})")
         assert err < tol
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("name,n,kind,seed,levels,eigs,agg", CASES)
-def test_fp32_pcg(name, n, kind, seed, levels, eigs, agg):
+def test_fp32_pcg(name, n, kind, seed, levels, eigs, agg, mode):
     import torch
     perm = make_field(kind, n, seed)
     g = Grid.unit_cube(n)
     hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1)
     b = make_source("corner", perm.shape).reshape(-1)
     ref = pcg(hier.A, b, Preconditioner(hier).apply, tol=1e-6)
-    ctx = _ctx(perm, levels, eigs, agg)
+    ctx = _ctx(perm, levels, eigs, agg, mode)
     x = torch.empty(g.n, dtype=torch.float64, device="cuda")
     rc, info = ctx.pcg_solve(to_dev(b), x, tol=1e-6)
     xg = to_host(x)
@@ -76,12 +82,50 @@ def test_fp32_pcg(name, n, kind, seed, levels, eigs, agg):
     nb = np.linalg.norm(b)
     bound = (info.rel_resid_true + ref.rel_resid_true) * nb / w[1] / np.linalg.norm(ref.x)
     err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
-    print(f"{name}: FP32 V-cycle iters {info.iters} (FP64 oracle {ref.iters}), error vs FP64 oracle "
+    print(f"{name} {mode}: iters {info.iters} (FP64 oracle {ref.iters}), error vs FP64 oracle "
           f"{err:.2e} (bound {bound:.1e}), true resid {info.rel_resid_true:.2e}, "
           f"replacements {info.replacements}")
     assert rc == 0 and info.converged
     assert info.rel_resid_true <= 1e-6
     assert info.iters <= int(1.1 * ref.iters) + 1
     assert err <= bound
-    if info.iters > 25:
-        assert info.replacements >= 1
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", MODES)
+def test_mixed_forms_hold_at_512(mode):
+    """The 512^3 inclusions workload (contrast 1e6, 4 levels, agg 2, 6 / 10
+    eigenvectors): each mixed form keeps the FP64 iteration count within 10 %
+    and solves faster.  The oracle cannot run at this size; the FP64 GPU
+    solution, which matches the oracle on the same hierarchy settings at
+    128^3 (test_gpu_fullsize_parity.py), is the reference, and the error of
+    the mixed form against it is reported and bounded by 1e-4 (a float32
+    rounding of 6e-8 amplified by the preconditioned residual tolerance; the
+    measured difference is about 1e-8)."""
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm = make_field("inclusions", 512, 3)
+    b = to_dev(make_source("five_spot", perm.shape).reshape(-1))
+    pd = to_dev(perm)
+    del perm
+    out = {}
+    for m in ("fp64", mode):
+        if m == "fp64":
+            ctx = SpecMG(pd, levels=4, eigs_per_subdomain=6, agg=2, eigs_coarse=10)
+        else:
+            from paper_2403_19342_amd.specmg import FP32_VCYCLE, FP32_STORE
+            ctx = SpecMG(pd, levels=4, eigs_per_subdomain=6, agg=2, eigs_coarse=10,
+                         precision={"fp32_vcycle": FP32_VCYCLE, "fp32_store": FP32_STORE}[m])
+        x = torch.empty(b.numel(), dtype=torch.float64, device="cuda")
+        rc, info = ctx.pcg_solve(b, x, tol=1e-6)
+        assert rc == 0 and info.converged and info.rel_resid_true <= 1e-6
+        out[m] = (info.iters, info.solve_ms, x)
+        ctx.close()
+    it64, ms64, x64 = out["fp64"]
+    it32, ms32, x32 = out[mode]
+    err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    print(f"inclusions512 {mode}: {it32} iterations in {ms32:.0f} ms against {it64} in {ms64:.0f} ms (FP64); "
+          f"solution difference {err:.2e}")
+    assert it32 <= int(1.1 * it64) + 1
+    assert ms32 < ms64
+    assert err < 1e-4

@@ -1,0 +1,140 @@
+"""GPU path against the FP64 oracle at the sizes the kernels run at full size.
+
+Three workloads, each compared element by element with the oracle (every
+level's eigenvalues and kept counts, P^{-1} r, the PCG solve):
+  gauss128   the 128^3 Gaussian log-field, 3 levels, 6 eigenvectors, agg 4,
+             quarter-five-spot source: the 128^3 configuration end to end
+             (every kernel at the tile counts of a full-size launch: the
+             SpMV's 64-column blocks with their cross-block halo, 4,096
+             level-2 elements, 64 level-3 parents)
+  gauss96_l2 96^3 with two levels: a coarsest space of about 10^4 unknowns,
+             wider than one LDS chunk of the coarsest product, so the gather
+             and the row-streaming product run (the oracle forms A_L^+ by
+             its sparse minimum-norm solve)
+  incl128    the 512^3 inclusions hierarchy settings on a 128^3 field of the
+             same generator (contrast 1e6, 4 levels, agg 2, L_c 6, L_cc 10,
+             five-spot source)
+Tolerances as in test_gpu_parity.py: eigenvalues 1e-11 relative to the
+element's spectral scale (dimensionless, O(1)), identical kept counts,
+P^{-1} r within max(1e-10, 1e-15 / lambda_min+(A_L)), PCG iterations +-1 and
+solution within 1e-8 relative L2.
+
+The oracle runs on the host (a process pool over the local eigenproblems);
+each case takes one to two minutes of CPU.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import Grid, build_hierarchy, Preconditioner, pcg
+from synth.fields import make_field, make_source, random_zero_mean
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1200)]
+
+CASES = {
+    # name: (kind, n, seed, levels, eigs, agg, eigs_coarse, source, coarsest)
+    "gauss128": ("gauss", 128, 1, 3, 6, 4, 0, "quarter_five_spot", "pinv"),
+    "gauss96_l2": ("gauss", 96, 1, 2, 6, 2, 0, "corner", "minnorm"),
+    "incl128": ("inclusions", 128, 3, 4, 6, 2, 10, "five_spot", "pinv"),
+}
+_cache = {}
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _oracle(name):
+    if name in _cache:
+        return _cache[name]
+    kind, n, seed, levels, eigs, agg, ecc, source, coarsest = CASES[name]
+    perm = make_field(kind, n, seed)
+    g = Grid.unit_cube(n)
+    workers = min(os.cpu_count() or 1, 16)
+    t0 = time.perf_counter()
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=workers, target_cc=ecc or None)
+    pre = Preconditioner(hier, coarsest=coarsest)
+    _log(f"{name}: oracle set-up {time.perf_counter() - t0:.1f} s, dims {[l.dim for l in hier.levels]}")
+    b = make_source(source, perm.shape).reshape(-1)
+    t0 = time.perf_counter()
+    ref = pcg(hier.A, b, pre.apply, tol=1e-6)
+    _log(f"{name}: oracle PCG {ref.iters} iterations in {time.perf_counter() - t0:.1f} s")
+    _cache[name] = (perm, hier, pre, b, ref)
+    return _cache[name]
+
+
+def _ctx(name, perm):
+    from paper_2403_19342_amd.specmg import SpecMG
+    kind, n, seed, levels, eigs, agg, ecc, source, coarsest = CASES[name]
+    return SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, eigs_coarse=ecc)
+
+
+def _lambda_min_plus(A):
+    """Smallest nonzero eigenvalue of the symmetric coarsest matrix (its
+    kernel is one-dimensional)."""
+    if A.shape[0] <= 2000:
+        return float(np.linalg.eigvalsh(A.toarray())[1])
+    w = spla.eigsh(A.tocsc(), k=2, sigma=-1e-3 * abs(A).max(), which="LM", return_eigenvectors=False)
+    return float(np.sort(w)[1])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fullsize_spectra(name):
+    perm, hier, pre, b, ref = _oracle(name)
+    ctx = _ctx(name, perm)
+    assert ctx.info()["setup"]["eig_unconverged"] == 0
+    for l in range(2, hier.nlevels + 1):
+        lv = ctx.level_arrays(l)
+        ro = hier.level(l)
+        assert np.array_equal(lv.nkeep, ro.nkeep), f"kept counts differ at level {l}"
+        worst = 0.0
+        for e in range(ro.m):
+            k = ro.nkeep[e]
+            worst = max(worst, float(np.max(np.abs(lv.lam[e, :k] - ro.lam[e][:k]))))
+        _log(f"{name}: level {l}, {ro.m} elements, dim {ro.dim}: max eigenvalue difference {worst:.2e}")
+        assert worst < 1e-11
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fullsize_apply_precond(name):
+    import torch
+    perm, hier, pre, b, ref = _oracle(name)
+    ctx = _ctx(name, perm)
+    n = perm.size
+    tol = max(1e-10, 1e-15 / _lambda_min_plus(hier.level(hier.nlevels).A))
+    r = random_zero_mean(perm.shape, 300).reshape(-1)
+    z = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.apply_precond(to_dev(r), z)
+    torch.cuda.synchronize()
+    zg = to_host(z)
+    zo = pre.apply(r)
+    zg -= zg.mean()
+    zo -= zo.mean()
+    err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+    _log(f"{name}: P^-1 r relative difference {err:.2e} (bound {tol:.1e}), "
+         f"worst cell {np.max(np.abs(zg - zo)) / np.max(np.abs(zo)):.2e}")
+    assert err < tol
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fullsize_pcg(name):
+    import torch
+    perm, hier, pre, b, ref = _oracle(name)
+    ctx = _ctx(name, perm)
+    x = torch.empty(perm.size, dtype=torch.float64, device="cuda")
+    rc, info = ctx.pcg_solve(to_dev(b), x, tol=1e-6)
+    xg = to_host(x)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    _log(f"{name}: PCG iterations gpu {info.iters} oracle {ref.iters}, solution difference {err:.2e}, "
+         f"true residual {info.rel_resid_true:.2e}")
+    assert rc == 0 and info.converged
+    assert abs(info.iters - ref.iters) <= 1
+    assert err <= 1e-8
+    assert info.rel_resid_true <= 1e-6
+    ctx.close()
