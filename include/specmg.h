@@ -242,6 +242,22 @@ int specmg_transport(const specmg_grid* grid, const double* phi_dev, const doubl
                      const double* vy_dev, const double* vz_dev, double* s_dev, int32_t substeps, double ds_max,
                      double* work_dev, double* t_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): specmg_transport
+ * without the work argument.  The workspace is a device array built into the
+ * library, one per GPU, for grids of at most SPECMG_TRANSPORT_NOALLOC_MAX_CELLS
+ * cells (32 MiB + 16 KiB, held from the library's load until the process
+ * ends); its address is looked up once per device on the first call there.
+ * The call allocates nothing.  All calls on one GPU share that workspace:
+ * calls that overlap on one GPU (other threads or streams) race, so callers
+ * serialise them.  Arguments, layout, results and asynchrony as for
+ * specmg_transport.  Errors: SPECMG_EINVAL (as specmg_transport, or more
+ * than SPECMG_TRANSPORT_NOALLOC_MAX_CELLS cells), SPECMG_EDEVICE. */
+#define SPECMG_TRANSPORT_NOALLOC_MAX_CELLS 2097152
+int specmg_transport_noalloc(const specmg_grid* grid, const double* phi_dev, const double* q_dev,
+                             const double* vx_dev, const double* vy_dev, const double* vz_dev, double* s_dev,
+                             int32_t substeps, double ds_max, double* t_dev, void* stream);
+
 /* Set-up information: dims[l-1] = dim W_l for l = 1..levels, the element
  * counts per level, and widths[l-1] = the padded per-element width of level
  * l (its target count plus 3; widths[0] = 1).  Arrays must hold 8 entries;

@@ -23,6 +23,7 @@
 // blocks at one L2 address; the slot array keeps the reduction in plain
 // loads and stores.  Nothing is copied to the host between sub-steps.
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "common.hpp"
@@ -172,18 +173,12 @@ extern "C" int specmg_total_mobility(const double* perm_dev, const double* s_dev
     return e == hipSuccess ? SPECMG_OK : device_error(e, "k_total_mobility");
 }
 
-extern "C" int specmg_transport(const specmg_grid* grid, const double* phi_dev, const double* q_dev,
-                                const double* vx_dev, const double* vy_dev, const double* vz_dev, double* s_dev,
-                                int32_t substeps, double ds_max, double* work_dev, double* t_dev, void* stream) {
-    if (!grid || !phi_dev || !q_dev || !vx_dev || !vy_dev || !vz_dev || !s_dev || !work_dev || !t_dev)
-        return fail_message(SPECMG_EINVAL, "null argument");
-    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail_message(SPECMG_EINVAL, "grid sizes must be >= 1");
-    if (!(grid->hx > 0) || !(grid->hy > 0) || !(grid->hz > 0))
-        return fail_message(SPECMG_EINVAL, "spacings must be positive");
-    if (substeps < 0) return fail_message(SPECMG_EINVAL, "substeps must be >= 0");
-    if (!(ds_max > 0) || ds_max > 1.0) return fail_message(SPECMG_EINVAL, "ds_max must be in (0, 1]");
+// Checks and launches shared by specmg_transport and its allocation-free
+// variant; work holds 2 n + kMaxRateBlocks doubles (rates, f_w, block maxima).
+static int run_transport(const specmg_grid* grid, const double* phi_dev, const double* q_dev, const double* vx_dev,
+                         const double* vy_dev, const double* vz_dev, double* s_dev, int32_t substeps, double ds_max,
+                         double* work_dev, double* t_dev, hipStream_t s) {
     const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
-    const hipStream_t s = (hipStream_t)stream;
     double* rate = work_dev;
     double* fw = work_dev + n;
     double* block_max = work_dev + 2 * n;
@@ -198,4 +193,80 @@ extern "C" int specmg_transport(const specmg_grid* grid, const double* phi_dev, 
     }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPECMG_OK : device_error(e, "saturation sub-steps");
+}
+
+static int check_transport_args(const specmg_grid* grid, const double* phi_dev, const double* q_dev,
+                                const double* vx_dev, const double* vy_dev, const double* vz_dev, const double* s_dev,
+                                int32_t substeps, double ds_max, const double* t_dev) {
+    if (!grid || !phi_dev || !q_dev || !vx_dev || !vy_dev || !vz_dev || !s_dev || !t_dev)
+        return fail_message(SPECMG_EINVAL, "null argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail_message(SPECMG_EINVAL, "grid sizes must be >= 1");
+    if (!(grid->hx > 0) || !(grid->hy > 0) || !(grid->hz > 0))
+        return fail_message(SPECMG_EINVAL, "spacings must be positive");
+    if (substeps < 0) return fail_message(SPECMG_EINVAL, "substeps must be >= 0");
+    if (!(ds_max > 0) || ds_max > 1.0) return fail_message(SPECMG_EINVAL, "ds_max must be in (0, 1]");
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_transport(const specmg_grid* grid, const double* phi_dev, const double* q_dev,
+                                const double* vx_dev, const double* vy_dev, const double* vz_dev, double* s_dev,
+                                int32_t substeps, double ds_max, double* work_dev, double* t_dev, void* stream) {
+    if (!work_dev) return fail_message(SPECMG_EINVAL, "null argument");
+    const int rc = check_transport_args(grid, phi_dev, q_dev, vx_dev, vy_dev, vz_dev, s_dev, substeps, ds_max, t_dev);
+    if (rc != SPECMG_OK) return rc;
+    return run_transport(grid, phi_dev, q_dev, vx_dev, vy_dev, vz_dev, s_dev, substeps, ds_max, work_dev, t_dev,
+                         (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the workspace is a file-scope device array,
+// `scratch`, sized for SPECMG_TRANSPORT_NOALLOC_MAX_CELLS cells.  Each GPU
+// holds its own copy (32 MiB + 16 KiB) from the library's load until the
+// process ends.  Its device address is looked up once per device (with that
+// device current) by hipGetSymbolAddress; host code never passes the
+// array's name itself to a kernel.  Nothing in it needs clearing: every
+// sub-step writes the rates and slots before reading them and the first
+// kernel writes f_w.  Calls that overlap on one GPU share the array and race.
+constexpr int64_t kNoAllocMaxCells = SPECMG_TRANSPORT_NOALLOC_MAX_CELLS;
+constexpr int64_t kScratchDoubles = 2 * kNoAllocMaxCells + kMaxRateBlocks;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// device address of this device's scratch array (looked up on first use)
+static int scratch_address(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail_message(SPECMG_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return device_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "scratch address");
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPECMG_OK;
+}
+
+extern "C" int specmg_transport_noalloc(const specmg_grid* grid, const double* phi_dev, const double* q_dev,
+                                        const double* vx_dev, const double* vy_dev, const double* vz_dev,
+                                        double* s_dev, int32_t substeps, double ds_max, double* t_dev, void* stream) {
+    const int rc = check_transport_args(grid, phi_dev, q_dev, vx_dev, vy_dev, vz_dev, s_dev, substeps, ds_max, t_dev);
+    if (rc != SPECMG_OK) return rc;
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    if (n > kNoAllocMaxCells)
+        return fail_message(SPECMG_EINVAL, ("grid of " + std::to_string(n) + " cells exceeds the " +
+                                            std::to_string(kNoAllocMaxCells) + " cells of the built-in workspace")
+                                               .c_str());
+    double* work = nullptr;
+    const int ra = scratch_address(&work);
+    if (ra != SPECMG_OK) return ra;
+    return run_transport(grid, phi_dev, q_dev, vx_dev, vy_dev, vz_dev, s_dev, substeps, ds_max, work, t_dev,
+                         (hipStream_t)stream);
 }

@@ -25,7 +25,9 @@ EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
             "specmg_cnn_destroy", "specmg_cnn_load", "specmg_cnn_patches", "specmg_cnn_forward",
-            "specmg_cnn_loss_backward", "specmg_cnn_adam", "specmg_total_mobility", "specmg_transport"]
+            "specmg_cnn_loss_backward", "specmg_cnn_adam", "specmg_total_mobility", "specmg_transport",
+            "specmg_transport_noalloc"]
+TRANSPORT_NOALLOC_MAX_CELLS = 2097152   # SPECMG_TRANSPORT_NOALLOC_MAX_CELLS
 PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_part",
                    "coarsest", "post_residual"]
 
@@ -125,6 +127,8 @@ def load_library(path: str = LIB_PATH):
     lib.specmg_total_mobility.restype = ctypes.c_int
     lib.specmg_transport.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp, i32, dbl, vp, vp, vp]
     lib.specmg_transport.restype = ctypes.c_int
+    lib.specmg_transport_noalloc.argtypes = [ctypes.POINTER(Grid), vp, vp, vp, vp, vp, vp, i32, dbl, vp, vp]
+    lib.specmg_transport_noalloc.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -198,6 +202,27 @@ def transport(phi, q, vx, vy, vz, s, h, substeps: int, ds_max: float, work, t):
     _check(lib.specmg_transport(ctypes.byref(g), _dev_ptr(phi), _dev_ptr(q), _dev_ptr(vx), _dev_ptr(vy),
                                 _dev_ptr(vz), _dev_ptr(s), int(substeps), float(ds_max), _dev_ptr(work),
                                 _dev_ptr(t), _stream()))
+
+
+def transport_noalloc(phi, q, vx, vy, vz, s, h, substeps: int, ds_max: float, t):
+    """specmg_transport without a workspace argument (specmg_transport_noalloc):
+    the library's built-in per-GPU workspace, for grids of at most
+    TRANSPORT_NOALLOC_MAX_CELLS cells; calls that overlap on one GPU race."""
+    lib = load_library()
+    if s.dim() != 3:
+        raise ValueError("s must have shape (nz, ny, nx)")
+    nz, ny, nx = s.shape
+    n = s.numel()
+    for a in (phi, q, vx, vy, vz):
+        if a.numel() != n:
+            raise ValueError("every field must have s.numel() entries")
+    if t.numel() < 1:
+        raise ValueError("t needs one double")
+    hx, hy, hz = _spacings(h)
+    g = Grid(nx, ny, nz, hx, hy, hz, 8, 2)
+    _check(lib.specmg_transport_noalloc(ctypes.byref(g), _dev_ptr(phi), _dev_ptr(q), _dev_ptr(vx), _dev_ptr(vy),
+                                        _dev_ptr(vz), _dev_ptr(s), int(substeps), float(ds_max), _dev_ptr(t),
+                                        _stream()))
 
 
 @dataclass
