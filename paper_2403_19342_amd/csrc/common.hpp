@@ -5,6 +5,8 @@
 #include <hip/hip_ext.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace specmg {
 
 // Event pair for the next timed kernel launch: hipExtLaunchKernelGGL stamps
@@ -267,6 +269,18 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
 template <typename T>
 void launch_coarsest(int n, int np, const double* Pinv, const int* cmap, const T* r, T* e, double* rc,
                      const Scalars* sc, int check_done, hipStream_t s);
+// values of the coarsest right-hand side staged in LDS at a time; wider
+// coarsest spaces use the symmetric product below
+constexpr int kCoarsestChunk = 8192;
+// coarsest product over the packed lower tiles of the symmetric inverse
+// (spaces wider than one LDS chunk); np a multiple of coarsest_sym_tile()
+int coarsest_sym_tile();
+size_t coarsest_sym_packed_doubles(int np);
+std::vector<int2> coarsest_sym_chunks(int np, int* maxc);
+void launch_pack_lower_tiles(const double* dense, int np, double* packed, hipStream_t s);
+void launch_coarsest_sym(int n, int np, const double* packed, const int2* chunks, int nchunks, int maxc,
+                         const int* cmap, const double* r, double* e, double* rc, double* P, double* Q,
+                         const Scalars* sc, int check_done, hipStream_t s);
 
 // set-up (k_coarse.hip)
 void launch_galerkin2(const FineGeom& g, const double* kt, const double* phi, const int* nkeep, int L,

@@ -17,6 +17,8 @@
 // so that every hyperplane step is a single product:
 //   forward   y_c = D_c^{-1} r_c - sum_lower G y_c'
 //   backward  z_c = y_c - sum_upper G z_c''.
+#include <vector>
+
 #include "common.hpp"
 
 namespace specmg {
@@ -338,7 +340,6 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
 // block kCoarsestRows consecutive rows that the whole block streams one row
 // at a time (64 KB contiguous per row and chunk: concurrent streams of many
 // rows a full row apart share few HBM channels and ran at 2.2 TB/s).
-constexpr int kCoarsestChunk = 8192;
 constexpr int kCoarsestRows = 16;
 
 template <typename T>
@@ -419,6 +420,107 @@ __global__ __launch_bounds__(256) void k_coarsest(int n, int np, const double* _
         const double s = wave_sum(acc[q]);
         if (lane == 0 && i0 + q < n) e[cmap[i0 + q]] = (T)s;
     }
+}
+
+// Coarsest product for spaces wider than one LDS chunk, reading the
+// symmetric inverse once: only its tiles (I, J) with I >= J are stored,
+// packed tile after tile (tile (I, J) at index I (I + 1) / 2 + J, each tile
+// kSymT x kSymT row-major and contiguous), half the bytes of the full
+// matrix.  Tile (I, J) contributes B_IJ r_J to e_I and, below the diagonal,
+// B_IJ^T r_I to e_J.  A workgroup streams a chunk of up to kSymChunk tiles of
+// one tile row I: lane l of wave w holds columns 2l, 2l + 1 and rows
+// w, w + 4, ... of every tile, so each row of a tile is one coalesced 1 KB
+// load per wave.  The row contributions accumulate in registers over the
+// chunk and are written once per chunk to Q[I][chunk]; the column
+// contributions of each off-diagonal tile are combined over the four waves
+// and written to P[J][I].  k_coarsest_sym_reduce then sums, for every
+// output tile I, its chunks' Q and the P written by the tiles below it, in a
+// fixed order (no atomics: results are reproducible).
+constexpr int kSymT = 128;
+constexpr int kSymChunk = 8;
+constexpr int kSymWaves = 8;                  // 512 threads per workgroup
+constexpr int kSymRows = kSymT / kSymWaves;   // rows per wave and tile
+
+__global__ void k_pack_lower_tiles(const double* __restrict__ dense, int np, double* __restrict__ packed) {
+    const int t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    double* dst = packed + (size_t)t * kSymT * kSymT;
+    for (int k = threadIdx.x; k < kSymT * kSymT; k += blockDim.x) {
+        const int i = k / kSymT, j = k % kSymT;
+        dst[k] = dense[(size_t)(I * kSymT + i) * np + (size_t)J * kSymT + j];
+    }
+}
+
+__global__ __launch_bounds__(64 * kSymWaves) void k_coarsest_sym(int nT, const int2* __restrict__ chunks,
+                                                                 const double* __restrict__ packed,
+                                                                 const double* __restrict__ rc,
+                                                                 double* __restrict__ P, double* __restrict__ Q,
+                                                                 int maxc, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    __shared__ double sri[kSymT];
+    __shared__ double scol[kSymWaves][kSymT];
+    const int2 ch = chunks[blockIdx.x];   // (tile row I, first tile J0)
+    const int I = ch.x, J0 = ch.y, J1 = min(I + 1, J0 + kSymChunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x < kSymT) sri[threadIdx.x] = rc[(size_t)I * kSymT + threadIdx.x];
+    __syncthreads();
+    double racc[kSymRows];
+#pragma unroll
+    for (int k = 0; k < kSymRows; ++k) racc[k] = 0.0;
+    for (int J = J0; J < J1; ++J) {
+        const double* tile = packed + ((size_t)I * (I + 1) / 2 + J) * kSymT * kSymT + (size_t)w * kSymT + 2 * lane;
+        const double2 rj = *reinterpret_cast<const double2*>(rc + (size_t)J * kSymT + 2 * lane);
+        double c0 = 0.0, c1 = 0.0;
+        // all 16 rows of the wave in flight (16 KB per wave), then the sums
+        double2 b[kSymRows];
+#pragma unroll
+        for (int k = 0; k < kSymRows; ++k)
+            b[k] = *reinterpret_cast<const double2*>(tile + (size_t)(kSymWaves * k) * kSymT);
+#pragma unroll
+        for (int k = 0; k < kSymRows; ++k) {
+            const double ri = sri[w + kSymWaves * k];
+            racc[k] += b[k].x * rj.x + b[k].y * rj.y;
+            c0 += b[k].x * ri;
+            c1 += b[k].y * ri;
+        }
+        if (J < I) {
+            scol[w][2 * lane] = c0;
+            scol[w][2 * lane + 1] = c1;
+            __syncthreads();
+            if (threadIdx.x < kSymT) {
+                const int j = threadIdx.x;
+                double v = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < kSymWaves; ++ww) v += scol[ww][j];
+                P[((size_t)J * nT + I) * kSymT + j] = v;
+            }
+            __syncthreads();
+        }
+    }
+    const int c = J0 / kSymChunk;
+#pragma unroll
+    for (int k = 0; k < kSymRows; ++k) {
+        const double v = wave_sum(racc[k]);
+        if (lane == 0) Q[((size_t)I * maxc + c) * kSymT + w + kSymWaves * k] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSymT) void k_coarsest_sym_reduce(int nT, int n, const double* __restrict__ P,
+                                                               const double* __restrict__ Q, int maxc,
+                                                               const int* __restrict__ cmap, T* __restrict__ e,
+                                                               const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    const int I = blockIdx.x, i = threadIdx.x;
+    const int nc = (I + kSymChunk) / kSymChunk;   // chunks of tile row I (I + 1 tiles)
+    double v = 0.0;
+    for (int c = 0; c < nc; ++c) v += Q[((size_t)I * maxc + c) * kSymT + i];
+    for (int K = I + 1; K < nT; ++K) v += P[((size_t)I * nT + K) * kSymT + i];
+    const int row = I * kSymT + i;
+    if (row < n) e[cmap[row]] = (T)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -835,6 +937,40 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
     if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
     SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
                                                1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+}
+
+int coarsest_sym_tile() { return kSymT; }
+
+size_t coarsest_sym_packed_doubles(int np) {
+    const size_t nT = (size_t)np / kSymT;
+    return nT * (nT + 1) / 2 * kSymT * kSymT;
+}
+
+// host-side chunk table of the symmetric product: (tile row, first tile)
+std::vector<int2> coarsest_sym_chunks(int np, int* maxc) {
+    const int nT = np / kSymT;
+    std::vector<int2> ch;
+    *maxc = (nT + kSymChunk - 1) / kSymChunk;
+    for (int I = 0; I < nT; ++I)
+        for (int J0 = 0; J0 <= I; J0 += kSymChunk) ch.push_back(make_int2(I, J0));
+    return ch;
+}
+
+void launch_pack_lower_tiles(const double* dense, int np, double* packed, hipStream_t s) {
+    const int nT = np / kSymT;
+    hipLaunchKernelGGL(k_pack_lower_tiles, dim3(nT * (nT + 1) / 2), dim3(256), 0, s, dense, np, packed);
+}
+
+void launch_coarsest_sym(int n, int np, const double* packed, const int2* chunks, int nchunks, int maxc,
+                         const int* cmap, const double* r, double* e, double* rc, double* P, double* Q,
+                         const Scalars* sc, int check_done, hipStream_t s) {
+    const int nT = np / kSymT;
+    hipLaunchKernelGGL((k_gather_compact<double>), dim3(std::min((n + 255) / 256, 1024)), dim3(256), 0, s, n, cmap,
+                       r, rc, sc, check_done);
+    SPECMG_TIMED_LAUNCH(k_coarsest_sym, dim3(nchunks), dim3(64 * kSymWaves), 0, s, nT, chunks, packed, rc, P, Q,
+                        maxc, sc, check_done);
+    hipLaunchKernelGGL((k_coarsest_sym_reduce<double>), dim3(nT), dim3(kSymT), 0, s, nT, n, P, Q, maxc, cmap, e, sc,
+                       check_done);
 }
 
 template <typename T>

@@ -3,6 +3,7 @@
 // the kernels of k_fine / k_coarse / k_eig / k_dense; this file only sizes
 // buffers, sequences launches and moves a few scalars.
 #include <chrono>
+#include <memory>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -94,7 +95,11 @@ struct specmg_ctx {
     float* invd32 = nullptr;
     std::vector<Level> lev;    // lev[0] = level 2
     int nL = 0, npL = 0;
-    double* Pinv = nullptr;
+    double* Pinv = nullptr;     // dense inverse (coarsest spaces of one LDS chunk)
+    double* Psym = nullptr;     // packed lower tiles of the inverse (wider spaces)
+    int2* sym_chunks = nullptr;
+    int sym_nchunks = 0, sym_maxc = 0;
+    double *sym_P = nullptr, *sym_Q = nullptr;   // column and row partial sums of the tiles
     int* cmap = nullptr;
     double* rc = nullptr;       // coarsest right-hand side, compact
     // CG state
@@ -222,7 +227,11 @@ void coarse_cycle(specmg_ctx* c, size_t li, int check, hipStream_t s) {
     double* e = lv.e;
     if (li + 1 == c->lev.size()) {
         const size_t ev = prof_begin(c, s);
-        launch_coarsest<double>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->rc, c->sc, check, s);
+        if (c->Psym)
+            launch_coarsest_sym(c->nL, c->npL, c->Psym, c->sym_chunks, c->sym_nchunks, c->sym_maxc, c->cmap, r, e,
+                                c->rc, c->sym_P, c->sym_Q, c->sc, check, s);
+        else
+            launch_coarsest<double>(c->nL, c->npL, c->Pinv, c->cmap, r, e, c->rc, c->sc, check, s);
         prof_end(c, ev, PC_COARSEST, s);
         return;
     }
@@ -373,7 +382,8 @@ static void coarse_traffic(specmg_ctx* c) {
     }
     double nl = 0.0;
     for (int k : c->lev.back().nkeep_h) nl += k;
-    c->coarsest_bytes = 8.0 * (nl * nl + 3.0 * nl);
+    // the whole inverse, or its lower triangle beyond one LDS chunk
+    c->coarsest_bytes = 8.0 * ((nl > kCoarsestChunk ? 0.5 * nl * (nl + 1.0) : nl * nl) + 3.0 * nl);
     c->coarse_bytes = 8.0 * words + c->coarsest_bytes;
     if (c->fp32) c->coarse_bytes += 2.0 * 12.0 * c->lev[0].dim;   // level-2 vectors widened and narrowed
 }
@@ -540,15 +550,26 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
                 cmap.push_back(e * L + a);
             }
         const int nL = (int)cmap.size();
-        const int np = ((nL + 31) / 32) * 32;
+        // spaces wider than one LDS chunk keep only the lower tiles of the
+        // symmetric inverse (the dense matrix is then a set-up workspace)
+        const bool sym = nL > kCoarsestChunk;
+        const int pad = sym ? coarsest_sym_tile() : 32;
+        const int np = ((nL + pad - 1) / pad) * pad;
         c->nL = nL;
         c->npL = np;
         c->cmap = c->alloc<int>(nL);
-        c->rc = c->alloc<double>(nL);
+        c->rc = c->alloc<double>(np);
+        HIPCHK(hipMemsetAsync(c->rc, 0, (size_t)np * sizeof(double), s));
         int* dcinv = c->alloc<int>(cinv.size());
         HIPCHK(hipMemcpyAsync(c->cmap, cmap.data(), nL * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(dcinv, cinv.data(), cinv.size() * sizeof(int), hipMemcpyHostToDevice, s));
-        c->Pinv = c->alloc<double>((size_t)np * np);
+        std::unique_ptr<DevBuf> dense_ws;
+        if (sym) {
+            dense_ws.reset(new DevBuf((size_t)np * np * sizeof(double)));
+            c->Pinv = (double*)dense_ws->p;
+        } else {
+            c->Pinv = c->alloc<double>((size_t)np * np);
+        }
         double* work = (double*)nullptr;
         HIPCHK(hipMalloc((void**)&work, (size_t)np * np * sizeof(double)));
         HIPCHK(hipMemsetAsync(c->Pinv, 0, (size_t)np * np * sizeof(double), s));
@@ -587,6 +608,19 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         HIPCHK(hipStreamSynchronize(s));
         (void)hipFree(work);
         if (de != 0) return fail(SPECMG_EDEVICE, std::string("coarsest inverse: ") + hipGetErrorString((hipError_t)de));
+        if (sym) {
+            const int nT = np / coarsest_sym_tile();
+            c->Psym = c->alloc<double>(coarsest_sym_packed_doubles(np));
+            launch_pack_lower_tiles(c->Pinv, np, c->Psym, s);
+            const std::vector<int2> ch = coarsest_sym_chunks(np, &c->sym_maxc);
+            c->sym_nchunks = (int)ch.size();
+            c->sym_chunks = c->alloc<int2>(ch.size());
+            HIPCHK(hipMemcpyAsync(c->sym_chunks, ch.data(), ch.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+            c->sym_P = c->alloc<double>((size_t)nT * nT * coarsest_sym_tile());
+            c->sym_Q = c->alloc<double>((size_t)nT * c->sym_maxc * coarsest_sym_tile());
+            HIPCHK(hipStreamSynchronize(s));
+            c->Pinv = nullptr;   // the dense workspace is released at scope exit
+        }
     }
     // ---- float32 copy of the level-2 basis for the mixed-precision fine level
     if (c->fp32 || c->fp32_basis || c->fp32_store) {

@@ -1,16 +1,18 @@
 """GPU path against the FP64 oracle at the sizes the kernels run at full size.
 
-Three workloads, each compared element by element with the oracle (every
+Four workloads, each compared element by element with the oracle (every
 level's eigenvalues and kept counts, P^{-1} r, the PCG solve):
   gauss128   the 128^3 Gaussian log-field, 3 levels, 6 eigenvectors, agg 4,
              quarter-five-spot source: the 128^3 configuration end to end
              (every kernel at the tile counts of a full-size launch: the
              SpMV's 64-column blocks with their cross-block halo, 4,096
              level-2 elements, 64 level-3 parents)
-  gauss96_l2 96^3 with two levels: a coarsest space of about 10^4 unknowns,
-             wider than one LDS chunk of the coarsest product, so the gather
-             and the row-streaming product run (the oracle forms A_L^+ by
-             its sparse minimum-norm solve)
+  gauss96_l2 96^3 with two levels: a coarsest space of 10,368 unknowns,
+             wider than one LDS chunk of the coarsest product, so the product
+             over the packed lower tiles of the symmetric inverse runs (the
+             oracle forms A_L^+ by its sparse minimum-norm solve)
+  chan96_l2  the same with 5 eigenvectors on a channel field: a coarsest
+             space that is not a whole number of 128-wide tiles (padding)
   incl128    the 512^3 inclusions hierarchy settings on a 128^3 field of the
              same generator (contrast 1e6, 4 levels, agg 2, L_c 6, L_cc 10,
              five-spot source)
@@ -39,6 +41,7 @@ CASES = {
     # name: (kind, n, seed, levels, eigs, agg, eigs_coarse, source, coarsest)
     "gauss128": ("gauss", 128, 1, 3, 6, 4, 0, "quarter_five_spot", "pinv"),
     "gauss96_l2": ("gauss", 96, 1, 2, 6, 2, 0, "corner", "minnorm"),
+    "chan96_l2": ("channels", 96, 2, 2, 5, 2, 0, "five_spot", "minnorm"),
     "incl128": ("inclusions", 128, 3, 4, 6, 2, 10, "five_spot", "pinv"),
 }
 _cache = {}
