@@ -66,12 +66,13 @@ def trace(path: str, top: int = 30) -> None:
 
 # kernel-name prefix -> profiling class of the solve (see specmg_get_profile)
 CLASSES = {"k_spmv_pcg": "cg_spmv", "k_pre_smooth": "pre_smooth", "k_resid_restrict": "resid_restrict",
-           "k_prolong": "prolong", "k_post_smooth": "post_smooth", "k_residual": "post_residual"}
-TRAFFIC_SOURCES = ("csrc/k_fine.hip", "csrc/common.hpp")
+           "k_prolong": "prolong", "k_post_smooth": "post_smooth", "k_residual": "post_residual",
+           "k_coarsest_sym": "coarsest"}
+TRAFFIC_SOURCES = ("csrc/k_fine.hip", "csrc/k_coarse.hip", "csrc/common.hpp")
 
 
 def source_hash() -> str:
-    """sha256 over the sources of the fine-level kernels."""
+    """sha256 over the sources of the solve kernels whose traffic is recorded."""
     import hashlib
     import os
     h = hashlib.sha256()
