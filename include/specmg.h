@@ -119,6 +119,20 @@ typedef struct {
     int32_t nu_c;            /* coarse-level sweeps nu_c (1 or 2); 0 = nu */
 } specmg_opts;
 
+/* Device allocator for a context's memory (specmg_setup_alloc): alloc
+ * returns `bytes` bytes of device memory usable on `stream` (the stream
+ * given to set-up), or NULL; free releases a pointer alloc returned.  `user`
+ * is passed back unchanged.  The callbacks are called from the calling
+ * thread during specmg_setup_alloc, during the first specmg_gmres_solve
+ * calls (its workspace) and during specmg_destroy, so they and `user` must
+ * stay valid until the context is destroyed.  A PyTorch binding passes its
+ * caching allocator here, so that PyTorch owns every device byte. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} specmg_allocator;
+
 /* Outcome of a solve.  iters counts products A p (one per CG iteration). */
 typedef struct {
     int32_t iters;
@@ -145,6 +159,15 @@ typedef struct {
  * returned; info reports the count), SPECMG_EFACT, SPECMG_EDEVICE. */
 int specmg_setup(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
                  const specmg_opts* opts, void* stream, specmg_ctx** out);
+
+/* specmg_setup with every device allocation of the context (its arrays, the
+ * set-up's transient workspaces, the GMRES workspace) taken from `allocator`
+ * (NULL: hipMalloc and hipFree, as specmg_setup).  Errors as specmg_setup,
+ * plus SPECMG_EINVAL for an allocator without both callbacks and
+ * SPECMG_EDEVICE when alloc returns NULL. */
+int specmg_setup_alloc(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
+                       const specmg_opts* opts, const specmg_allocator* allocator, void* stream,
+                       specmg_ctx** out);
 
 /* One application of the preconditioner, z = P^{-1} r: Algorithm 1 applied
  * recursively (pre-smooth, restrict, coarse map, prolong, post-smooth) with

@@ -36,6 +36,33 @@ struct HipError {
     const char* what;
 };
 
+// Device memory of a context: the caller's allocator callbacks when given
+// (specmg_setup_alloc), hipMalloc / hipFree otherwise.  get() throws
+// HipError when no memory is returned.
+struct DevAlloc {
+    void* (*alloc)(size_t, void*, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* user = nullptr;
+    hipStream_t stream = nullptr;
+    void* get(size_t bytes) const {
+        if (bytes == 0) bytes = 1;
+        void* p = nullptr;
+        if (alloc) {
+            p = alloc(bytes, (void*)stream, user);
+            if (!p) throw HipError{hipErrorOutOfMemory, "allocator callback returned no memory"};
+        } else {
+            const hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) throw HipError{e, "hipMalloc"};
+        }
+        return p;
+    }
+    void put(void* p) const {
+        if (!p) return;
+        if (release) release(p, user);
+        else (void)hipFree(p);
+    }
+};
+
 constexpr int kSub = 8;             // level-2 element edge in cells
 constexpr int kSub3 = 512;          // cells per level-2 element
 constexpr int kPlanes = 22;         // hyperplanes i+j+k = s in an 8^3 block
@@ -323,7 +350,8 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
                    double* Aint, double* zup, int* status, hipStream_t s);
 
 // dense coarsest factorization (k_dense.hip); np is a multiple of 32
-int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s);
+int dense_spd_inverse(double* a, int np, double* work, double* tbuf, int* bad, hipStream_t s);
+size_t dense_spd_inverse_tbuf_doubles(int np);
 void launch_add_rank1(double* a, int np, int n, const double* z, double alpha, hipStream_t s);
 void launch_pad_identity(double* a, int np, int n, hipStream_t s);
 

@@ -291,7 +291,9 @@ void launch_pad_identity(double* a, int np, int n, hipStream_t s) {
     if (np > n) hipLaunchKernelGGL(k_pad_identity, dim3((np - n + 63) / 64), dim3(64), 0, s, a, np, n);
 }
 
-int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s) {
+size_t dense_spd_inverse_tbuf_doubles(int np) { return (size_t)np * KB; }
+
+int dense_spd_inverse(double* a, int np, double* work, double* tbuf, int* bad, hipStream_t s) {
     if (np % NB) return (int)hipErrorInvalidValue;
     // ---- Cholesky, panels of KB columns
     for (int k0 = 0; k0 < np; k0 += KB) {
@@ -313,14 +315,8 @@ int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s) 
         }
     }
     // ---- W = L^{-1}, panels from the bottom-right
-    double* tbuf = nullptr;
-    hipError_t e = hipMalloc((void**)&tbuf, (size_t)np * KB * sizeof(double));
+    hipError_t e = hipMemsetAsync(work, 0, (size_t)np * np * sizeof(double), s);
     if (e != hipSuccess) return (int)e;
-    e = hipMemsetAsync(work, 0, (size_t)np * np * sizeof(double), s);
-    if (e != hipSuccess) {
-        (void)hipFree(tbuf);
-        return (int)e;
-    }
     const int last = ((np - 1) / KB) * KB;
     for (int j0 = last; j0 >= 0; j0 -= KB) {
         const int kb = std::min(KB, np - j0);
@@ -338,7 +334,6 @@ int dense_spd_inverse(double* a, int np, double* work, int* bad, hipStream_t s) 
         hipLaunchKernelGGL(k_wtw, dim3(T * (T + 1) / 2), dim3(256), 0, s, work, a, np);
     }
     e = hipStreamSynchronize(s);
-    (void)hipFree(tbuf);
     if (e != hipSuccess) return (int)e;
     return (int)hipGetLastError();
 }

@@ -64,11 +64,13 @@ struct Level {
 
 }  // namespace
 
-// device buffer released at scope exit (transient set-up workspaces)
+// device buffer released at scope exit (transient set-up workspaces), from
+// the context's allocator
 struct DevBuf {
+    const DevAlloc& al;
     void* p = nullptr;
-    explicit DevBuf(size_t bytes) { HIPCHK(hipMalloc(&p, bytes ? bytes : 1)); }
-    ~DevBuf() { (void)hipFree(p); }
+    DevBuf(const DevAlloc& a, size_t bytes) : al(a) { p = al.get(bytes); }
+    ~DevBuf() { al.put(p); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
 };
@@ -129,19 +131,20 @@ struct specmg_ctx {
     double coarse_bytes = 0.0;     // algorithmic bytes of one V-cycle's coarse part (levels >= 2)
     double coarsest_bytes = 0.0;   // of the coarsest product alone
 
+    DevAlloc al;   // device memory of the context (caller's allocator or hipMalloc)
+
     template <typename T>
     T* alloc(size_t count) {
-        void* ptr = nullptr;
-        if (count == 0) count = 1;
-        HIPCHK(hipMalloc(&ptr, count * sizeof(T)));
+        void* ptr = al.get((count ? count : 1) * sizeof(T));
         allocs.push_back(ptr);
         return (T*)ptr;
     }
     ~specmg_ctx() {
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        for (void* a : allocs) (void)hipFree(a);
-        if (gm_buf) (void)hipFree(gm_buf);
-        if (gm_state) (void)hipFree(gm_state);
+        if (!allocs.empty() || gm_buf || gm_state) (void)hipDeviceSynchronize();
+        for (void* a : allocs) al.put(a);
+        al.put(gm_buf);
+        al.put(gm_state);
         if (sc_host) (void)hipHostFree(sc_host);
     }
 };
@@ -461,9 +464,10 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
             // output consumed by the eigensolves of the same batch
             const int k = c->target, kp = k + (k & 1);
             const int batch = m < kCnnSetupBatch ? m : kCnnSetupBatch;
-            DevBuf packs(cnn_pack_words(kp) * sizeof(uint32_t)), patches((size_t)batch * 1000 * sizeof(float)),
-                a1((size_t)batch * 32 * 512 * sizeof(float)), a2((size_t)batch * 32 * 512 * sizeof(float)),
-                xw((size_t)batch * kp * 512 * sizeof(float));
+            DevBuf packs(c->al, cnn_pack_words(kp) * sizeof(uint32_t)),
+                patches(c->al, (size_t)batch * 1000 * sizeof(float)),
+                a1(c->al, (size_t)batch * 32 * 512 * sizeof(float)), a2(c->al, (size_t)batch * 32 * 512 * sizeof(float)),
+                xw(c->al, (size_t)batch * kp * 512 * sizeof(float));
             c->ws_fb = c->alloc<int>(m);
             const double wtol = c->opts.ws_resid_tol > 0 ? c->opts.ws_resid_tol : 1e-3;
             launch_cnn_pack(nullptr, (const uint16_t*)c->opts.cnn_weights, k, kp, packs.p, s);
@@ -565,13 +569,14 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         HIPCHK(hipMemcpyAsync(dcinv, cinv.data(), cinv.size() * sizeof(int), hipMemcpyHostToDevice, s));
         std::unique_ptr<DevBuf> dense_ws;
         if (sym) {
-            dense_ws.reset(new DevBuf((size_t)np * np * sizeof(double)));
+            dense_ws.reset(new DevBuf(c->al, (size_t)np * np * sizeof(double)));
             c->Pinv = (double*)dense_ws->p;
         } else {
             c->Pinv = c->alloc<double>((size_t)np * np);
         }
-        double* work = (double*)nullptr;
-        HIPCHK(hipMalloc((void**)&work, (size_t)np * np * sizeof(double)));
+        DevBuf work_buf(c->al, (size_t)np * np * sizeof(double));
+        DevBuf tbuf(c->al, dense_spd_inverse_tbuf_doubles(np) * sizeof(double));
+        double* work = (double*)work_buf.p;
         HIPCHK(hipMemsetAsync(c->Pinv, 0, (size_t)np * np * sizeof(double), s));
         launch_build_coarsest(top.g, top.Ad, top.Aoff, dcinv, np, c->Pinv, s);
         launch_pad_identity(c->Pinv, np, nL, s);
@@ -589,10 +594,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
             tr += ad[((size_t)e * L + a) * L + a];
         }
         zn = std::sqrt(zn);
-        if (!(zn > 0.0)) {
-            (void)hipFree(work);
-            return fail(SPECMG_EFACT, "constant function not found in the coarsest space");
-        }
+        if (!(zn > 0.0)) return fail(SPECMG_EFACT, "constant function not found in the coarsest space");
         for (double& v : zc) v /= zn;
         const double alpha = tr / nL;
         double* dz = c->alloc<double>(nL);
@@ -604,9 +606,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         // stays positive definite when rounding spoils the inverse of an
         // ill-conditioned A_L.
         launch_add_rank1(c->Pinv, np, nL, dz, alpha, s);
-        const int de = dense_spd_inverse(c->Pinv, np, work, c->dflag + 3, s);
+        const int de = dense_spd_inverse(c->Pinv, np, work, (double*)tbuf.p, c->dflag + 3, s);
         HIPCHK(hipStreamSynchronize(s));
-        (void)hipFree(work);
         if (de != 0) return fail(SPECMG_EDEVICE, std::string("coarsest inverse: ") + hipGetErrorString((hipError_t)de));
         if (sym) {
             const int nT = np / coarsest_sym_tile();
@@ -683,8 +684,16 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
 
 extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
                             const specmg_opts* opts, void* stream, specmg_ctx** out) {
+    return specmg_setup_alloc(perm_dev, perm_components, grid, opts, nullptr, stream, out);
+}
+
+extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_components, const specmg_grid* grid,
+                                  const specmg_opts* opts, const specmg_allocator* allocator, void* stream,
+                                  specmg_ctx** out) {
     g_last_error.clear();
     if (!out || !grid || !opts || !perm_dev) return fail(SPECMG_EINVAL, "null argument");
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(SPECMG_EINVAL, "allocator needs both alloc and free");
     *out = nullptr;
     if (perm_components != 1) return fail(SPECMG_EINVAL, "only isotropic permeability (1 component) is supported");
     const specmg_grid& G = *grid;
@@ -721,6 +730,12 @@ extern "C" int specmg_setup(const double* perm_dev, int32_t perm_components, con
         return fail(SPECMG_EINVAL, "nx, ny, nz must be positive multiples of 8*agg^(levels-2)");
     if ((long)G.nx * G.ny * G.nz / 512 < 2) return fail(SPECMG_EINVAL, "need at least two 8^3 elements");
     specmg_ctx* c = new specmg_ctx();
+    if (allocator) {
+        c->al.alloc = allocator->alloc;
+        c->al.release = allocator->free;
+        c->al.user = allocator->user;
+    }
+    c->al.stream = (hipStream_t)stream;
     c->grid = G;
     c->opts = *opts;
     c->levels = opts->levels;
@@ -947,14 +962,17 @@ static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int r
         return SPECMG_OK;
     }
     if (restart > c->gm_restart) {
-        if (c->gm_buf) HIPCHK(hipFree(c->gm_buf));
+        if (c->gm_buf) {
+            HIPCHK(hipStreamSynchronize(s));
+            c->al.put(c->gm_buf);
+        }
         c->gm_buf = nullptr;
         c->gm_restart = 0;
         const size_t doubles = (size_t)(2 * restart + 2) * (size_t)n + mdot_part_doubles();
-        HIPCHK(hipMalloc(&c->gm_buf, doubles * sizeof(double)));
+        c->gm_buf = (double*)c->al.get(doubles * sizeof(double));
         c->gm_restart = restart;
     }
-    if (!c->gm_state) HIPCHK(hipMalloc(&c->gm_state, sizeof(GmresState)));
+    if (!c->gm_state) c->gm_state = (GmresState*)c->al.get(sizeof(GmresState));
     double* V = c->gm_buf;                          // restart + 1 vectors
     double* Z = V + (size_t)(restart + 1) * n;      // restart vectors
     double* w = Z + (size_t)restart * n;

@@ -20,7 +20,7 @@ OK, EINVAL, EINVAL_PERM, ERHS, ENOCONV, EBREAKDOWN, EEIG, EFACT, EDEVICE = 0, -1
 FP64, FP32_VCYCLE, FP32_BASIS, FP32_STORE = 0, 1, 2, 3
 WS_NONE, WS_CNN = 0, 1
 
-EXPORTED = ["specmg_setup", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve",
+EXPORTED = ["specmg_setup", "specmg_setup_alloc", "specmg_apply_precond", "specmg_pcg_solve", "specmg_gmres_solve",
             "specmg_recover_flux", "specmg_mass_balance", "specmg_apply_operator",
             "specmg_get_info", "specmg_copy_level", "specmg_set_profiling", "specmg_get_profile",
             "specmg_destroy", "specmg_last_error", "specmg_cnn_param_count", "specmg_cnn_create",
@@ -45,6 +45,37 @@ class Opts(ctypes.Structure):
                 ("eig_tol", ctypes.c_double), ("cluster_rtol", ctypes.c_double),
                 ("ws_resid_tol", ctypes.c_double), ("eigs_coarse", ctypes.c_int32),
                 ("eig_threshold_coarse", ctypes.c_double), ("nu_c", ctypes.c_int32)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator():
+    """specmg_allocator callbacks over PyTorch's caching allocator (the
+    returned object keeps the callbacks alive; hold it as long as the
+    context)."""
+    import torch
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(ptr, user):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    return Allocator(fa, ff, None), (fa, ff)
 
 
 class SolveInfo(ctypes.Structure):
@@ -81,6 +112,9 @@ def load_library(path: str = LIB_PATH):
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     lib.specmg_setup.argtypes = [vp, i32, ctypes.POINTER(Grid), ctypes.POINTER(Opts), vp, ctypes.POINTER(vp)]
     lib.specmg_setup.restype = ctypes.c_int
+    lib.specmg_setup_alloc.argtypes = [vp, i32, ctypes.POINTER(Grid), ctypes.POINTER(Opts), ctypes.POINTER(Allocator),
+                                       vp, ctypes.POINTER(vp)]
+    lib.specmg_setup_alloc.restype = ctypes.c_int
     lib.specmg_apply_precond.argtypes = [vp, vp, vp, vp]
     lib.specmg_apply_precond.restype = ctypes.c_int
     lib.specmg_pcg_solve.argtypes = [vp, vp, vp, i32, dbl, i32, ctypes.POINTER(SolveInfo), vp]
@@ -241,7 +275,10 @@ class SpecMG:
     def __init__(self, perm, levels: int, eigs_per_subdomain: int, h=None,
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
                  allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3,
-                 eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0, nu: int = 1, nu_c: int = 0):
+                 eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0, nu: int = 1, nu_c: int = 0,
+                 allocator: str = "torch"):
+        """allocator: "torch" (the context's device memory comes from PyTorch's
+        caching allocator through specmg_setup_alloc) or "hip" (hipMalloc)."""
         lib = load_library()
         import torch
         if perm.dim() != 3:
@@ -265,8 +302,15 @@ class SpecMG:
                          eigs_coarse, eig_threshold_coarse, nu_c)
         ctx = ctypes.c_void_p()
         perm = perm.contiguous()
-        rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
-                              ctypes.byref(ctx))
+        if allocator == "torch":
+            self._alloc, self._alloc_keep = torch_allocator()
+            rc = lib.specmg_setup_alloc(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts),
+                                        ctypes.byref(self._alloc), _stream(), ctypes.byref(ctx))
+        elif allocator == "hip":
+            rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
+                                  ctypes.byref(ctx))
+        else:
+            raise ValueError("allocator must be 'torch' or 'hip'")
         if rc == EEIG and allow_unconverged:
             pass
         elif rc != OK:
