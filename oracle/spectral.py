@@ -186,13 +186,14 @@ def _children(egrid_parent, agg, egrid_child):
 
 def build_hierarchy(perm, grid: Grid, nlevels: int, target: int, sub: int = 8, agg: int = 4,
                     workers: int | None = None, A=None, target_cc: int | None = None,
-                    threshold_cc: float = 0.0) -> Hierarchy:
+                    threshold_cc: float = 0.0, threshold_c: float = 0.0) -> Hierarchy:
     """Set-up phase: local spectral problems and the Galerkin chain.
 
     `target` is the count per level-2 element (L_c of Section 5); levels >= 3
-    use `target_cc` (L_cc, default `target`) and, when `threshold_cc` > 0,
-    keep only the eigenvalues below it (B_cc, strategy 2 of Section 5), with
-    `target_cc` as the number of candidates."""
+    use `target_cc` (L_cc, default `target`).  Strategy 2 of Section 5: when
+    `threshold_c` > 0 the level-2 elements keep only the eigenvalues below it
+    (B_c) out of `target` candidates, and when `threshold_cc` > 0 the coarser
+    elements those below B_cc out of `target_cc` candidates."""
     if nlevels < 2:
         raise ValueError("need at least two levels")
     if target_cc is None:
@@ -215,7 +216,8 @@ def build_hierarchy(perm, grid: Grid, nlevels: int, target: int, sub: int = 8, a
         return _payload(aloc[c][:, c]), S[c]
 
     res = _solve_all(m2, get2, target, CLUSTER_EXTRA, workers)
-    nkeep = np.array([cluster_cut(w, target) for (w, _) in res], dtype=np.int64)
+    nkeep = np.array([cluster_cut(w, threshold_target(w, target, threshold_c)) for (w, _) in res],
+                     dtype=np.int64)
     offsets = np.concatenate([[0], np.cumsum(nkeep)])
     rows, cols, vals = [], [], []
     for e, (w, v) in enumerate(res):

@@ -494,3 +494,22 @@ def test_threshold_strategy_caps_at_candidates():
     assert list(h.level(3).nkeep) == [4]
     assert threshold_target(ref, 4, 0.0) == 4            # strategy 1
     assert threshold_target(ref, 4, 1e-300) == 1         # never below one vector
+
+
+@pytest.mark.parametrize("b_between,expect", [((0, 1), 1), ((3, 4), 4), ((6, 7), 7)])
+def test_level2_threshold_strategy_counts_ladder(b_between, expect):
+    # B_c between two rungs of a homogeneous element's ladder keeps exactly the
+    # eigenvalues below it on every level-2 element (at most L_c = 8 candidates)
+    g = Grid.unit_cube(16)
+    ref = _dct_ladder(8)
+    lo, hi = b_between
+    h = build_hierarchy(np.ones(g.shape), g, 2, 8, sub=8, workers=1, threshold_c=0.5 * (ref[lo] + ref[hi]))
+    assert list(h.level(2).nkeep) == [expect] * 8
+
+
+def test_level2_threshold_caps_at_candidates():
+    # more eigenvalues below B_c than the L_c = 4 candidates: 4 of them (a clean cut)
+    g = Grid.unit_cube(16)
+    ref = _dct_ladder(8)
+    h = build_hierarchy(np.ones(g.shape), g, 2, 4, sub=8, workers=1, threshold_c=0.5 * (ref[10] + ref[11]))
+    assert list(h.level(2).nkeep) == [4] * 8
