@@ -80,7 +80,8 @@ typedef struct {
 
 /* Options.  levels >= 2 is the number of grids (Algorithm 1 has three);
  * eigs_per_subdomain (1..8) is the target count of eigenvectors kept per
- * level-2 element (L_c, strategy 1 of Section 5), grown or shrunk by at most
+ * level-2 element (L_c, strategy 1 of Section 5; with eig_threshold > 0 the
+ * number of candidates of strategy 2), grown or shrunk by at most
  * 3 so that no cluster of equal eigenvalues is split (relative gap
  * cluster_rtol).  Levels >= 3 use eigs_coarse (L_cc) the same way, or, when
  * eig_threshold_coarse > 0, keep the eigenvectors whose eigenvalues lie below
@@ -117,6 +118,12 @@ typedef struct {
                                 Eigenvalues are those of eq. spectral cc with
                                 S-normalised bases (dimensionless) */
     int32_t nu_c;            /* coarse-level sweeps nu_c (1 or 2); 0 = nu */
+    double eig_threshold;    /* B_c >= 0; 0 = fixed count eigs_per_subdomain.
+                                Strategy 2 of Section 5 at the level-2
+                                elements: keep the eigenvalues of eq. spepb
+                                below B_c (S-normalised, dimensionless), at
+                                least one and at most eigs_per_subdomain
+                                candidates, then the cluster rule */
 } specmg_opts;
 
 /* Device allocator for a context's memory (specmg_setup_alloc): alloc

@@ -327,7 +327,7 @@ void launch_convert(const S* src, T* dst, int64_t n, hipStream_t s, const Scalar
 // local eigensolves (k_eig.hip)
 void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
                  double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, int e0, int count,
-                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, hipStream_t s);
+                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, double thr, hipStream_t s);
 
 // learned warm start (k_cnn.hip)
 int64_t cnn_param_count(int k);

@@ -609,7 +609,8 @@ __device__ void rayleigh_ritz(const OP& op, double* Y, int ld, int n, double (&X
 // through their eigenvalues (error <= residual^2 / gap), so sqrt(tol)*bnd,
 // unless their Ritz value already lies 5 % above the last kept one: then the
 // decision cannot change (a partner of a kept eigenvalue would have been
-// amplified like the kept vectors, which have converged).  Without that
+// amplified like the kept vectors, which have converged; under the threshold
+// rule this needs at least one filter cycle).  Without that
 // exception a degenerate cluster straddling the block's end (the Laplace
 // ladder of a homogeneous element) is never resolved: the filter's cut sits
 // on the cluster.
@@ -634,7 +635,11 @@ __device__ int chefsi(const OP& op, double* Y, int ld, int n, double (&X)[R][M],
         bool ok = true;
         for (int j = 0; j < need; ++j) {
             const double rj = sqrt(sh.nrm[j]);
-            const bool sep = j >= nk && nk > 0 && sh.th[j] - sh.th[nk - 1] > 0.05 * fabs(sh.th[j]);
+            // under the threshold rule the 5 % separation counts only after
+            // a filter cycle: an eigenvalue below the threshold that the start
+            // block misses has not been amplified yet and would change the count
+            const bool sep = (thr <= 0.0 || cyc > 0) && j >= nk && nk > 0 &&
+                             sh.th[j] - sh.th[nk - 1] > 0.05 * fabs(sh.th[j]);
             ok = ok && (rj <= (j < nk ? tol : sqrt(tol)) * bnd || sep);
         }
         if (ok) return cyc;
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     FineGeom g, const double* __restrict__ kt, int target, int L, double tol, double crtol,
     double* __restrict__ phi, double* __restrict__ lam, int* __restrict__ nkeep, double* __restrict__ Aint,
     double* __restrict__ zc, int* __restrict__ status, int e0, const float* __restrict__ warm, int kp, int kw,
-    double ws_tol, int* __restrict__ ws_fb) {
+    double ws_tol, int* __restrict__ ws_fb, double thr) {
     constexpr int LD = 513;
     __shared__ double sY[M * LD];
     __shared__ EigShared<M> sh;
@@ -748,7 +753,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int need = (target + 4 < M - 2) ? target + 4 : M - 2;
     int cyc = -1, spent = 0;
     if (warm) {
-        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, 0.0, sh, kWarmCycles, kDeg);
+        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, ws_tol, target, crtol, thr, sh, kWarmCycles, kDeg);
         const bool fb = cyc < 0;
         if (fb) {
             spent = kWarmCycles + 1;
@@ -763,12 +768,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
     }
     if (cyc < 0) {
-        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, 0.0, sh);
+        cyc = chefsi<M, 1>(op, sY, LD, 512, X, AX, bnd, need, tol, target, crtol, thr, sh);
         if (cyc >= 0) cyc += spent;
     }
 
     if (threadIdx.x == 0) {
-        const int nk = cluster_cut_dev(sh.th, M, target, crtol, 0.0);
+        const int nk = cluster_cut_dev(sh.th, M, target, crtol, thr);
         sh.flag = nk;
         nkeep[e] = nk;
         status[e] = cyc;
@@ -894,9 +899,13 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
         rayleigh_ritz<M, 1>(op, dyn, ld, n, X, AX, sh, nval, 2.0 * bnd + 1.0);
     } else {
         // start block: the constant function, smooth weights of the
-        // children's constant modes, and noise on every kept slot
+        // children's constant modes, and noise on every kept slot.  The
+        // noise has one amplitude for the whole element: the constant
+        // function's coefficient zr vanishes on the children's non-constant
+        // slots, and noise scaled by it would leave the block without those
+        // directions, which a polynomial filter cannot restore
         const double pa = 3.14159265358979323846 / agg;
-        const double az = fabs(zr) + 1e-300;
+        const double az = block_max(op.valid ? fabs(zr) : 0.0, sh.misc) + 1e-300;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             double v = 0.05 * az * hash_noise((unsigned)E + 77u, (unsigned)j, (unsigned)row);
@@ -958,11 +967,11 @@ __global__ __launch_bounds__(768) void k_eig_up(CoarseGeom lo, CoarseGeom up, co
 
 void launch_eig2(const FineGeom& g, const double* kt, int target, int nvec, double tol, double crtol,
                  double* phi, double* lam, int* nkeep, double* Aint, int* status, double* zc, int e0, int count,
-                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, hipStream_t s) {
+                 const float* warm, int kp, int kw, double ws_tol, int* ws_fb, double thr, hipStream_t s) {
     const int L = target + 3;
     SPECMG_M_DISPATCH(nvec, hipLaunchKernelGGL((k_eig2<M>), dim3(count), dim3(512), 0, s, g, kt, target, L, tol,
                                                crtol, phi, lam, nkeep, Aint, zc, status, e0, warm, kp, kw, ws_tol,
-                                               ws_fb));
+                                               ws_fb, thr));
 }
 
 void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Aint_lo, const double* Dlo,

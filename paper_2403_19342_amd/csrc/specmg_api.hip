@@ -83,6 +83,7 @@ struct specmg_ctx {
     int levels = 0, target = 0, L = 0, nvec = 0;          // level 2 (L: padded width)
     int target_cc = 0, Lcc = 0, nvec_cc = 0;               // levels >= 3
     double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
+    double thr_c = 0.0;                                    // threshold rule at level 2 when > 0
     int fp32 = 0;
     int fp32_basis = 0;   // float64 fine level with a float32 copy of the level-2 basis
     int fp32_store = 0;   // fine level stored in float32 (kappa~, 1/d, basis, u, t), float64 arithmetic
@@ -477,12 +478,12 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
                 launch_cnn_forward(packs.p, kp, (const float*)patches.p, cnt, (float*)a1.p, (float*)a2.p,
                                    (float*)xw.p, s);
                 launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint,
-                            lv.status, lv.z, e0, cnt, (const float*)xw.p, kp, k, wtol, c->ws_fb, s);
+                            lv.status, lv.z, e0, cnt, (const float*)xw.p, kp, k, wtol, c->ws_fb, c->thr_c, s);
             }
             HIPCHK(hipStreamSynchronize(s));
         } else {
             launch_eig2(fg, c->kt, c->target, c->nvec, tol, crtol, lv.basis, lv.lam, lv.nkeep, lv.Aint, lv.status,
-                        lv.z, 0, m, nullptr, 0, 0, 0.0, nullptr, s);
+                        lv.z, 0, m, nullptr, 0, 0, 0.0, nullptr, c->thr_c, s);
         }
         launch_galerkin2(fg, c->kt, lv.basis, lv.nkeep, L, lv.D, lv.Aoff, s);
         launch_assemble_diag(lv.g, lv.Aint, lv.D, lv.Ad, s);
@@ -724,6 +725,8 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
         return fail(SPECMG_EINVAL, "agg 4 with four or more levels needs eigs_coarse <= 9");
     if (!(opts->eig_threshold_coarse >= 0.0) || !std::isfinite(opts->eig_threshold_coarse))
         return fail(SPECMG_EINVAL, "eig_threshold_coarse must be finite and >= 0");
+    if (!(opts->eig_threshold >= 0.0) || !std::isfinite(opts->eig_threshold))
+        return fail(SPECMG_EINVAL, "eig_threshold must be finite and >= 0");
     long div = 8;
     for (int l = 2; l < opts->levels; ++l) div *= G.agg;
     if (G.nx <= 0 || G.ny <= 0 || G.nz <= 0 || G.nx % div || G.ny % div || G.nz % div)
@@ -746,6 +749,7 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
     c->Lcc = tcc + 3;
     c->nvec_cc = nvec_for(tcc);
     c->thr_cc = opts->eig_threshold_coarse;
+    c->thr_c = opts->eig_threshold;
     c->fp32 = opts->precision == SPECMG_FP32_VCYCLE;
     c->fp32_basis = opts->precision == SPECMG_FP32_BASIS;
     c->fp32_store = opts->precision == SPECMG_FP32_STORE;

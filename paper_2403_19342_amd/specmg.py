@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("cnn_weights", ctypes.c_void_p),
                 ("eig_tol", ctypes.c_double), ("cluster_rtol", ctypes.c_double),
                 ("ws_resid_tol", ctypes.c_double), ("eigs_coarse", ctypes.c_int32),
-                ("eig_threshold_coarse", ctypes.c_double), ("nu_c", ctypes.c_int32)]
+                ("eig_threshold_coarse", ctypes.c_double), ("nu_c", ctypes.c_int32),
+                ("eig_threshold", ctypes.c_double)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -276,7 +277,7 @@ class SpecMG:
                  agg: int = 4, precision: int = FP64, eig_tol: float = 1e-12, cluster_rtol: float = 1e-6,
                  allow_unconverged: bool = False, cnn_weights=None, ws_resid_tol: float = 1e-3,
                  eigs_coarse: int = 0, eig_threshold_coarse: float = 0.0, nu: int = 1, nu_c: int = 0,
-                 allocator: str = "torch"):
+                 allocator: str = "torch", eig_threshold: float = 0.0):
         """allocator: "torch" (the context's device memory comes from PyTorch's
         caching allocator through specmg_setup_alloc) or "hip" (hipMalloc)."""
         lib = load_library()
@@ -299,7 +300,7 @@ class SpecMG:
                 raise ValueError("cnn_weights has the wrong length for eigs_per_subdomain")
             ws, wp = WS_CNN, ctypes.c_void_p(cnn_weights.data_ptr())
         self.opts = Opts(levels, eigs_per_subdomain, nu, precision, ws, wp, eig_tol, cluster_rtol, ws_resid_tol,
-                         eigs_coarse, eig_threshold_coarse, nu_c)
+                         eigs_coarse, eig_threshold_coarse, nu_c, eig_threshold)
         ctx = ctypes.c_void_p()
         perm = perm.contiguous()
         if allocator == "torch":

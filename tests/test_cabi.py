@@ -41,7 +41,7 @@ def test_binding_covers_header():
     ("eigs_per_subdomain", 9, -1), ("nu", 3, -1), ("nu", 0, -1), ("nu_c", 3, -1), ("nu_c", -1, -1), ("precision", 7, -1), ("hy", 0.0, -1),
     ("hz", -1.0, -1), ("hx", float("nan"), -1), ("hy", float("inf"), -1),
     ("eigs_coarse", 11, -1), ("eigs_coarse", -1, -1), ("eig_threshold_coarse", -1.0, -1),
-    ("eig_threshold_coarse", float("inf"), -1),
+    ("eig_threshold_coarse", float("inf"), -1), ("eig_threshold", -1.0, -1), ("eig_threshold", float("nan"), -1),
 ])
 def test_setup_rejects_bad_arguments(field, value, code):
     lib = _lib()

@@ -1,5 +1,6 @@
-"""Separate coarse-coarse counts (L_cc) and the threshold rule (B_cc,
-strategy 2 of Section 5) on the GPU against the FP64 oracle.
+"""Separate coarse-coarse counts (L_cc) and the threshold rule (strategy 2
+of Section 5: B_c at the level-2 elements, B_cc above) on the GPU against
+the FP64 oracle.
 
 Same tolerances as the other parity tests: kept counts bit-exact, kept
 eigenvalues 1e-11 absolute, P^{-1} r max(1e-10, 1e-15 / lambda_min+(A_L))
@@ -17,32 +18,37 @@ from tests.gpu_util import to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # (name, kind, seed, levels, eigs, agg, eigs_coarse, threshold)
-    ("gauss32_l3_cc8", "gauss", 1, 3, 4, 2, 8, 0.0),
-    ("incl32_l4_thr", "inclusions", 3, 4, 6, 2, 10, 1e-3),
-    ("chan32_l3_thr", "channels", 2, 3, 6, 4, 9, 1e-3),
+    # (name, kind, seed, levels, eigs, agg, eigs_coarse, threshold B_cc, threshold B_c)
+    ("gauss32_l3_cc8", "gauss", 1, 3, 4, 2, 8, 0.0, 0.0),
+    ("incl32_l4_thr", "inclusions", 3, 4, 6, 2, 10, 1e-3, 0.0),
+    ("chan32_l3_thr", "channels", 2, 3, 6, 4, 9, 1e-3, 0.0),
+    # B_c: one to three of 8 candidates on the inclusion elements, one to four
+    # of 6 on the channel elements
+    ("incl32_l3_bc", "inclusions", 3, 3, 8, 2, 0, 0.0, 0.03),
+    ("chan32_l2_bc", "channels", 2, 2, 6, 2, 0, 0.0, 0.03),
 ]
 
 
-def _both(kind, seed, levels, eigs, agg, cc, thr):
+def _both(kind, seed, levels, eigs, agg, cc, thr, thr_c):
     from paper_2403_19342_amd.specmg import SpecMG
     perm = make_field(kind, 32, seed)
     g = Grid.unit_cube(32)
-    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1, target_cc=cc, threshold_cc=thr)
-    if thr > 0:
-        for l in range(3, levels + 1):
+    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1, target_cc=cc or None,
+                           threshold_cc=thr, threshold_c=thr_c)
+    for l, t in [(l, thr) for l in range(3, levels + 1)] + [(2, thr_c)]:
+        if t > 0:
             for lam in hier.level(l).lam:
-                assert np.min(np.abs(np.asarray(lam) - thr)) > 1e-2 * thr, "threshold too close to an eigenvalue"
+                assert np.min(np.abs(np.asarray(lam) - t)) > 1e-2 * t, "threshold too close to an eigenvalue"
     ctx = SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, eigs_coarse=cc,
-                 eig_threshold_coarse=thr)
+                 eig_threshold_coarse=thr, eig_threshold=thr_c)
     return perm, g, hier, ctx
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
-def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr):
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
     widths = ctx.info()["widths"]
-    assert widths[1] == eigs + 3 and all(w == cc + 3 for w in widths[2:])
+    assert widths[1] == eigs + 3 and all(w == (cc or eigs) + 3 for w in widths[2:])
     for l in range(2, levels + 1):
         lv = ctx.level_arrays(l)
         ref = hier.level(l)
@@ -52,10 +58,10 @@ def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr):
         assert worst < 1e-11
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
-def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr):
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
     import torch
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
     pre = Preconditioner(hier)
     wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
     tol = max(1e-10, 1e-15 / wL[1])
@@ -72,10 +78,10 @@ def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr):
         assert err < tol
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr", CASES)
-def test_pcg(name, kind, seed, levels, eigs, agg, cc, thr):
+@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_pcg(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
     import torch
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr)
+    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
     b = make_source("corner", perm.shape).reshape(-1)
     ref = pcg(hier.A, b, Preconditioner(hier).apply, tol=1e-6)
     x = torch.empty(g.n, dtype=torch.float64, device="cuda")
