@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--nu-c", type=int, default=0, help="sweeps on the coarse levels (0: same as --nu)")
     ap.add_argument("--eig-threshold-coarse", type=float, default=0.0,
                     help="B_cc > 0: keep the coarse-coarse eigenvalues below it (strategy 2), at most L_cc")
+    ap.add_argument("--eig-threshold", type=float, default=0.0,
+                    help="B_c > 0: keep the level-2 eigenvalues below it (strategy 2), at most L_c")
     ap.add_argument("--forms", default="",
                     help="comma-separated extra forms timed once each after the bench steps and reported "
                          "under 'forms': fp32_vcycle, fp32_basis, fp32_store, learned (CNN warm start)")
@@ -144,7 +146,8 @@ def main():
     def make_ctx(precision_, cnn=None):
         ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision_,
                      eigs_coarse=wl.eigs_coarse, eig_threshold_coarse=args.eig_threshold_coarse,
-                     nu=args.nu, nu_c=args.nu_c, allow_unconverged=True, cnn_weights=cnn)
+                     eig_threshold=args.eig_threshold, nu=args.nu, nu_c=args.nu_c, allow_unconverged=True,
+                     cnn_weights=cnn)
         unconv = ctx.info()["setup"]["eig_unconverged"]
         if unconv and not args.allow_unconverged:
             ctx.close()
@@ -251,6 +254,7 @@ def main():
                    "field": wl.kind, "source": wl.source,
                    **({} if args.contrast is None else {"contrast": args.contrast}),
                    **({"eig_threshold_coarse": args.eig_threshold_coarse} if args.eig_threshold_coarse > 0 else {}),
+                   **({"eig_threshold": args.eig_threshold} if args.eig_threshold > 0 else {}),
                    **({"nu": args.nu, "nu_c": args.nu_c or args.nu} if (args.nu, args.nu_c) != (1, 0) else {}),
                    "tol": 1e-6, "precision": prec},
         "solve_ms": solve_s * 1e3,
