@@ -27,11 +27,17 @@ from .assembly import Grid
 
 
 def recover_flux(perm: np.ndarray, grid: Grid, p) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """(vx, vy, vz), each (nz, ny, nx): the flux through each cell's + face."""
-    kappa = np.asarray(perm, dtype=np.float64).reshape(grid.shape)
+    """(vx, vy, vz), each (nz, ny, nx): the flux through each cell's + face.
+
+    `perm` is isotropic (nz, ny, nx) or orthotropic (3, nz, ny, nx) holding
+    kappa^x, kappa^y, kappa^z (Section 2.1): the faces of one axis take the
+    harmonic mean of that axis's component, K being diagonal."""
+    perm = np.asarray(perm, dtype=np.float64)
+    comps = perm.reshape((3,) + grid.shape) if perm.size == 3 * grid.n else None
     p = np.asarray(p, dtype=np.float64).reshape(grid.shape)
     out = []
-    for axis, h in ((2, grid.hx), (1, grid.hy), (0, grid.hz)):
+    for comp, (axis, h) in enumerate(((2, grid.hx), (1, grid.hy), (0, grid.hz))):
+        kappa = comps[comp] if comps is not None else perm.reshape(grid.shape)
         v = np.zeros(grid.shape)
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
