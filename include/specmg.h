@@ -4,7 +4,7 @@
  * implemented with hand-written HIP kernels for gfx950 (MI355X).
  *
  * Problem (Section 2): -div(K grad p) = f in the unit box with no-flow
- * boundaries, K = kappa I, discretised by lowest-order Raviart-Thomas
+ * boundaries, K = kappa I or diag(kappa_x, kappa_y, kappa_z), discretised by lowest-order Raviart-Thomas
  * elements with trapezoidal quadrature; eliminating the velocity gives the
  * symmetric positive semidefinite system A p = f (eq. p), a 7-point stencil
  * whose face coefficients are harmonic means of kappa/h^2 (eq. discrete
@@ -159,8 +159,13 @@ typedef struct {
  * local spectral problems on every element of every coarse level (eq. spepb,
  * eq. spectral cc), Galerkin coarse operators A_{l+1} = R A_l R^T, IC(0)
  * and block-IC(0) smoother factors, and the factored coarsest operator.
- * perm_dev: device float64 array of kappa, nx*ny*nz values (perm_components
- * must be 1: isotropic K = kappa I).  Read during the call only.
+ * perm_dev: device float64 permeability, read during the call only:
+ * perm_components = 1: kappa, nx*ny*nz values (isotropic K = kappa I);
+ * perm_components = 3: kappa_x, kappa_y, kappa_z one after the other, 3 nx*ny*nz
+ * values (orthotropic K = diag(kappa_x, kappa_y, kappa_z), Section 2.1; the
+ * faces of axis d take the harmonic mean of kappa_d / h_d^2, the weight of
+ * eq. spepb is the sum of the three; needs precision SPECMG_FP64 or
+ * SPECMG_FP32_BASIS and no learned warm start).
  * On success *out receives a new context, released with specmg_destroy.
  * Errors: SPECMG_EINVAL, SPECMG_EINVAL_PERM, SPECMG_EEIG (context still
  * returned; info reports the count), SPECMG_EFACT, SPECMG_EDEVICE. */

@@ -203,6 +203,11 @@ struct FineGeom {
     // kappa / hx^2, so a y (z) face coefficient is cy (cz) times the
     // harmonic mean of kappa~; exactly 1 on equal spacings
     double cy = 1.0, cz = 1.0;
+    // orthotropic K = diag(kappa_x, kappa_y, kappa_z): kappa~ holds three
+    // arrays of n values, kappa_d / h_d^2, and faces of axis d take the
+    // harmonic mean of array d (cy = cz = 1)
+    int ortho = 0;
+    __host__ __device__ size_t ncell() const { return (size_t)nx * ny * nz; }
 };
 
 // Coarse level l >= 2: elements on an (mx,my,mz) grid, padded width L.
@@ -244,6 +249,9 @@ void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* i
                      hipStream_t s);
 void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n,
                        int* bad, hipStream_t s);
+// three components: kt[d n + i] = perm[d n + i] * scale[d]
+void launch_perm3_to_kt(const double* perm, double* kt, double sx, double sy, double sz, int64_t n, int* bad,
+                        hipStream_t s);
 
 // vector utilities (k_fine.hip)
 void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,

@@ -557,7 +557,9 @@ __global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __r
         const bool inside = nx_ >= 0 && nx_ < g.nx && ny_ >= 0 && ny_ < g.ny && nz_ >= 0 && nz_ < g.nz;
         double T = 0.0;
         if (inside) {
-            const double a = kt[gid(gx, gy, gz)], b = kt[gid(nx_, ny_, nz_)];
+            // kappa~ of this face's direction (three arrays for orthotropic K)
+            const size_t off = g.ortho ? (size_t)ax * g.ncell() : 0;
+            const double a = kt[off + gid(gx, gy, gz)], b = kt[off + gid(nx_, ny_, nz_)];
             T = 2.0 * a * b / (a + b) * (ax == 0 ? 1.0 : (ax == 1 ? g.cy : g.cz));
         }
         sT[d][f] = T;

@@ -714,10 +714,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     auto gid = [&](int x, int y, int z) {
         return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
     };
-    const double kc = kt[gid(ex * 8 + i, ey * 8 + j, ez * 8 + k)];
-    // weight tr K~ = kappa~ (1 + cy + cz); y and z faces carry cy and cz
+    // kappa~ per face direction: one array (isotropic) or three (orthotropic)
+    const size_t N = g.ortho ? g.ncell() : 0;
+    const size_t gc = gid(ex * 8 + i, ey * 8 + j, ez * 8 + k);
+    const double kc[3] = {kt[gc], kt[N + gc], kt[2 * N + gc]};
+    // weight tr K~: kappa~ (1 + cy + cz) with the y and z faces carrying cy
+    // and cz, or the sum of the three components
     const double wsum = 1.0 + g.cy + g.cz;
-    const double S = wsum * kc;
+    auto weight = [&](size_t q) { return g.ortho ? kt[q] + kt[N + q] + kt[2 * N + q] : wsum * kt[q]; };
+    const double S = weight(gc);
     const double sq = sqrt(S);
     Op2 op;
     double diag = 0.0, rowsum = 0.0;
@@ -729,10 +734,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         op.off[d] = 0.0;
         op.nb[d] = c;
         if (ii >= 0 && ii < 8 && jj >= 0 && jj < 8 && kk >= 0 && kk < 8) {
-            const double kn = kt[gid(ex * 8 + ii, ey * 8 + jj, ez * 8 + kk)];
-            const double T = harm_e(kc, kn) * (d < 2 ? 1.0 : (d < 4 ? g.cy : g.cz));
+            const int ax = d >> 1;
+            const size_t gn = gid(ex * 8 + ii, ey * 8 + jj, ez * 8 + kk);
+            const double T = harm_e(kc[ax], kt[ax * N + gn]) * (ax == 0 ? 1.0 : (ax == 1 ? g.cy : g.cz));
             diag += T;
-            op.off[d] = T / (sq * sqrt(wsum * kn));
+            op.off[d] = T / (sq * sqrt(weight(gn)));
             op.nb[d] = ii + 8 * (jj + 8 * kk);
             rowsum += op.off[d];
         }

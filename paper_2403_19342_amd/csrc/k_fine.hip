@@ -9,6 +9,8 @@
 // plus a one-cell halo in LDS; the IC(0) sweeps walk the 22 hyperplanes
 // i+j+k = s of each element (cells on a hyperplane only depend on the
 // previous one for lexicographic IC(0)).
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace specmg {
@@ -396,13 +398,43 @@ __device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8
     (void)jk;
 }
 
+// The same from three kappa~ pencils (orthotropic K): each axis's faces take
+// the harmonic mean of its own component.
+template <typename T>
+__device__ __forceinline__ void pencil_faces3(const T (&kx)[8], const T (&ky)[8], const T (&kz)[8], T (&fx)[8],
+                                              T (&fy)[8], T (&fz)[8]) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        fx[r] = harm(kx[r], kx[(r + 7) & 7]);
+        fy[r] = harm(ky[r], from_ym(ky, r));
+        fz[r] = harm(kz[r], from_zm(kz, r));
+    }
+}
+
+// minus-face transmissibilities of the lane's pencil (rotated slot order)
+template <bool O, typename T, typename C>
+__device__ __forceinline__ void load_faces(const FineGeom& g, const T* __restrict__ kt, size_t row, int jk,
+                                           C (&fx)[8], C (&fy)[8], C (&fz)[8]) {
+    C kc[8];
+    load_pencil(kt + row, kc, jk);
+    if constexpr (O) {
+        const size_t N = g.ncell();
+        C ky[8], kz[8];
+        load_pencil(kt + N + row, ky, jk);
+        load_pencil(kt + 2 * N + row, kz, jk);
+        pencil_faces3(kc, ky, kz, fx, fy, fz);
+    } else {
+        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // pre-smoothing: (optionally r -= alpha q with ||r||^2) then u = M^{-1} r
 // mode bit0: update r and reduce ||r||^2 (sets the converged flag)
 // mode bit1: return at once when the solve is finished
 // T: stored word of kappa~, 1/d and u; C: arithmetic (T, or float64 with
-// float32 storage)
-template <int EX, typename T, typename C>
+// float32 storage); O: three kappa~ arrays (orthotropic K)
+template <int EX, typename T, typename C, bool O>
 __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __restrict__ kt,
                                                         const T* __restrict__ invd, double* r,
                                                         const double* __restrict__ q, T* __restrict__ u,
@@ -418,11 +450,7 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     // phases in order, each one's registers released before the next
     // (faces first, then the residual update, then the pivots)
     C fx[8], fy[8], fz[8];
-    {
-        C kc[8];
-        load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
-    }
+    load_faces<O>(g, kt, row, jk, fx, fy, fz);
     __builtin_amdgcn_sched_barrier(0);
     C y[8];
     double rr = 0.0;
@@ -505,11 +533,12 @@ __device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T
 
 // s = r - A u on the x-pencil of row (j, k) of an element (x0 = the
 // element's first x, (y, z) the row), natural order; row = index of (x0, y, z)
-template <typename T, typename C>
+template <bool O, typename T, typename C>
 __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
                                                 const double* __restrict__ r, size_t row, int x0, int y, int z,
                                                 int lane, int j, int k, C (&s)[8]) {
     const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+    const size_t N = O ? g.ncell() : 0;   // offsets of the y and z arrays
     C uc[8], kc[8];
     load8(u + row, uc);
     load8(kt + row, kc);
@@ -531,17 +560,25 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
     }
     if (x0 > 0) s[0] -= harm(kc[0], (C)kt[row - 1]) * (uc[0] - (C)u[row - 1]);
     if (x0 + 8 < g.nx) s[7] -= harm(kc[7], (C)kt[row + 8]) * (uc[7] - (C)u[row + 8]);
-    // y and z neighbours, one direction at a time
+    // y and z neighbours, one direction at a time (orthotropic: the y and z
+    // faces take the y and z arrays, own pencil included)
 #pragma unroll 1
     for (int d = 0; d < 4; ++d) {
-        C nu[8], nk[8];
+        C nu[8], nk[8], ko[8];
+        const size_t ka = O ? (d < 2 ? N : 2 * N) : 0;
+        if constexpr (O) {
+            load8(kt + ka + row, ko);
+        } else {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) ko[x] = kc[x];
+        }
         // source lane of the neighbour row: -1, +1, -8, +8 (wrapping lanes are
         // the element's edge lanes, which load instead)
         const int src = (lane + (d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -8 : 8)))) & 63;
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
             nu[x] = __shfl(uc[x], src, 64);
-            nk[x] = __shfl(kc[x], src, 64);
+            nk[x] = __shfl(ko[x], src, 64);
         }
         const bool edge = d == 0 ? j == 0 : (d == 1 ? j == 7 : (d == 2 ? k == 0 : k == 7));
         if (edge) {
@@ -549,20 +586,20 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
             if (inside) {
                 const size_t o = d == 0 ? row - sy : (d == 1 ? row + sy : (d == 2 ? row - sz : row + sz));
                 load8(u + o, nu);
-                load8(kt + o, nk);
+                load8(kt + ka + o, nk);
             } else {
 #pragma unroll
                 for (int x = 0; x < 8; ++x) nk[x] = C(0);
             }
         }
-        face_pencil(s, uc, kc, nu, nk, (C)(d < 2 ? g.cy : g.cz));
+        face_pencil(s, uc, ko, nu, nk, (C)(d < 2 ? g.cy : g.cz));
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
 // T: stored word of kappa~ and u; TB: stored word of the basis; C: the
 // arithmetic and the word of the level-2 residual r2
-template <typename T, typename TB, typename C>
+template <typename T, typename TB, typename C, bool O>
 __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __restrict__ kt,
                                                        const T* __restrict__ u, const double* __restrict__ r,
                                                        const TB* __restrict__ phi, const int* __restrict__ nkeep,
@@ -581,7 +618,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
     const size_t row = (size_t)x0 + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
     C s[8];
-    pencil_residual(g, kt, u, r, row, x0, y, z, lane, j, k, s);
+    pencil_residual<O>(g, kt, u, r, row, x0, y, z, lane, j, k, s);
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
@@ -636,7 +673,7 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
 // kappa~ in registers; x- and y-neighbours come from the L1 cache.
 // Faces leaving the domain have zero transmissibility.
 constexpr int kResZ = 8;
-template <typename T, typename C>
+template <typename T, typename C, bool O>
 __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, C cy, C cz, const T* __restrict__ kt,
                                                   const T* __restrict__ u, const double* __restrict__ r,
                                                   T* __restrict__ t, const Scalars* sc, int check_done) {
@@ -648,20 +685,25 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, C cy, 
     const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
     size_t gi = (size_t)x + sy * y + sz * z0;
     const bool xm = x > 0, xp = x + 1 < nx, ym = y > 0, yp = y + 1 < ny;
-    C uc = u[gi], kc = kt[gi];
-    C um = z0 > 0 ? (C)u[gi - sz] : C(0), km = z0 > 0 ? (C)kt[gi - sz] : C(0);
+    // orthotropic: the y and z faces read the y and z arrays
+    const size_t N = (size_t)nx * ny * nz;
+    const T* ky = O ? kt + N : kt;
+    const T* kz = O ? kt + 2 * N : kt;
+    C uc = u[gi], kc = kz[gi];
+    C um = z0 > 0 ? (C)u[gi - sz] : C(0), km = z0 > 0 ? (C)kz[gi - sz] : C(0);
 #pragma unroll 2
     for (int z = z0; z < z0 + kResZ; ++z, gi += sz) {
         const bool zp = z + 1 < nz;
-        const C up = zp ? (C)u[gi + sz] : C(0), kp = zp ? (C)kt[gi + sz] : C(0);
+        const C up = zp ? (C)u[gi + sz] : C(0), kp = zp ? (C)kz[gi + sz] : C(0);
+        const C kcx = O ? (C)kt[gi] : kc, kcy = O ? (C)ky[gi] : kc;
         const C uxm = xm ? (C)u[gi - 1] : C(0), kxm = xm ? (C)kt[gi - 1] : C(0);
         const C uxp = xp ? (C)u[gi + 1] : C(0), kxp = xp ? (C)kt[gi + 1] : C(0);
-        const C uym = ym ? (C)u[gi - sy] : C(0), kym = ym ? (C)kt[gi - sy] : C(0);
-        const C uyp = yp ? (C)u[gi + sy] : C(0), kyp = yp ? (C)kt[gi + sy] : C(0);
-        C a = harm(kc, kxm) * (uc - uxm);
-        a += harm(kc, kxp) * (uc - uxp);
-        a += harm(kc, kym) * cy * (uc - uym);
-        a += harm(kc, kyp) * cy * (uc - uyp);
+        const C uym = ym ? (C)u[gi - sy] : C(0), kym = ym ? (C)ky[gi - sy] : C(0);
+        const C uyp = yp ? (C)u[gi + sy] : C(0), kyp = yp ? (C)ky[gi + sy] : C(0);
+        C a = harm(kcx, kxm) * (uc - uxm);
+        a += harm(kcx, kxp) * (uc - uxp);
+        a += harm(kcy, kym) * cy * (uc - uym);
+        a += harm(kcy, kyp) * cy * (uc - uyp);
         a += harm(kc, km) * cz * (uc - um);
         a += harm(kc, kp) * cz * (uc - up);
         t[gi] = (T)((C)r[gi] - a);
@@ -675,7 +717,7 @@ __global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, C cy, 
 // post-smoothing (Algorithm 1 step 9): z = u + M^{-1} t with t = r - A u
 // from k_residual.  mode bit0: reduce r.z (and z.q when flexible) and update
 // the CG beta; bit1: return at once when the solve is finished.
-template <int EX, typename T, typename C>
+template <int EX, typename T, typename C, bool O>
 __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __restrict__ kt,
                                                          const T* __restrict__ invd,
                                                          const T* __restrict__ u, const T* __restrict__ tres,
@@ -691,11 +733,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
     const int j = lane & 7, k = lane >> 3, jk = j + k;
     const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);
     C fx[8], fy[8], fz[8];
-    {
-        C kc[8];
-        load_pencil(kt + row, kc, jk);
-        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
-    }
+    load_faces<O>(g, kt, row, jk, fx, fy, fz);
     __builtin_amdgcn_sched_barrier(0);
     C y[8], ix[8];
     load_pencil(tres + row, y, jk);
@@ -735,6 +773,9 @@ __global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __
 // ids are remapped so that each XCD walks a contiguous range of tiles.
 constexpr int kSpY = 4, kSpZ = 8;
 
+// O (orthotropic K): the x faces read kappa~_x from the LDS tile, the y
+// faces kappa~_y from a second tile, the z faces kappa~_z from registers.
+template <bool O>
 __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
                                                        const double* __restrict__ zv,
                                                        const double* __restrict__ pold,
@@ -744,7 +785,11 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
     if (sc->done) return;
     __shared__ double sp[2][kSpY + 2][66];
     __shared__ double sk[2][kSpY + 2][66];
+    __shared__ double sky[O ? 2 : 1][O ? kSpY + 2 : 1][O ? 66 : 1];
     __shared__ double sred[kSpY];
+    const size_t N = O ? g.ncell() : 0;
+    const double* kty = kt + N;          // y array (orthotropic; kt itself otherwise)
+    const double* ktz = kt + 2 * N;      // z array
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nb = gridDim.x * gridDim.y * gridDim.z;
@@ -773,9 +818,11 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
     auto pval = [&](size_t i) { return first ? zv[i] : zv[i] + beta * pold[i]; };
     double po = (in && !first) ? pold[gi] : 0.0;
     double pc = in ? (first ? zv[gi] : zv[gi] + beta * po) : 0.0, kc = in ? kt[gi] : 0.0;
-    double pyh = hyv ? pval(ghy) : 0.0, kyh = hyv ? kt[ghy] : 0.0;
+    double pyh = hyv ? pval(ghy) : 0.0, kyh = hyv ? kty[ghy] : 0.0;
     double pxh = hxv ? pval(ghx) : 0.0, kxh = hxv ? kt[ghx] : 0.0;
-    double pm = (in && z0 > 0) ? pval(gi - sz) : 0.0, km = (in && z0 > 0) ? kt[gi - sz] : 0.0;
+    double pm = (in && z0 > 0) ? pval(gi - sz) : 0.0, km = (in && z0 > 0) ? ktz[gi - sz] : 0.0;
+    // orthotropic: this cell's y and z components (isotropic: kc itself)
+    double kcy = (O && in) ? kty[gi] : 0.0, kcz = (O && in) ? ktz[gi] : 0.0;
     // x of the deferred update x += alpha p_old, loaded a plane ahead like
     // the stencil operands (loaded and used in the same plane, its latency
     // was exposed once per plane)
@@ -785,9 +832,11 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         const int buf = zz & 1;
         sp[buf][w + 1][lane + 1] = pc;
         sk[buf][w + 1][lane + 1] = kc;
+        if constexpr (O) sky[buf][w + 1][lane + 1] = kcy;
         if (hrow_w) {
             sp[buf][hrow][lane + 1] = pyh;
-            sk[buf][hrow][lane + 1] = kyh;
+            if constexpr (O) sky[buf][hrow][lane + 1] = kyh;
+            else sk[buf][hrow][lane + 1] = kyh;
         }
         if (hcol_l) {
             sp[buf][w + 1][hcol] = pxh;
@@ -798,13 +847,14 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         const size_t o = (size_t)(zz + 1) * sz;
         const double pon = (in && zp && !first) ? pold[gi + sz] : 0.0;
         const double pp = (in && zp) ? (first ? zv[gi + sz] : zv[gi + sz] + beta * pon) : 0.0;
-        const double kp = (in && zp) ? kt[gi + sz] : 0.0;
+        const double kp = (in && zp) ? ktz[gi + sz] : 0.0;
+        const double kpx = (O && in && zp) ? kt[gi + sz] : 0.0, kpy = (O && in && zp) ? kty[gi + sz] : 0.0;
         const double xvn = (in && zp && ax != 0.0 && zz + 1 < kSpZ) ? x[gi + sz] : 0.0;
         double pyh2 = 0.0, kyh2 = 0.0, pxh2 = 0.0, kxh2 = 0.0;
         if (zz + 1 < kSpZ && zp) {
             if (hyv) {
                 pyh2 = pval(ghy + o);
-                kyh2 = kt[ghy + o];
+                kyh2 = kty[ghy + o];
             }
             if (hxv) {
                 pxh2 = pval(ghx + o);
@@ -814,14 +864,15 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
         __syncthreads();
         const double pxm = sp[buf][w + 1][lane], kxm = sk[buf][w + 1][lane];
         const double pxp = sp[buf][w + 1][lane + 2], kxp = sk[buf][w + 1][lane + 2];
-        const double pym = sp[buf][w][lane + 1], kym = sk[buf][w][lane + 1];
-        const double pyp = sp[buf][w + 2][lane + 1], kyp = sk[buf][w + 2][lane + 1];
+        const double pym = sp[buf][w][lane + 1], kym = O ? sky[buf][w][lane + 1] : sk[buf][w][lane + 1];
+        const double pyp = sp[buf][w + 2][lane + 1], kyp = O ? sky[buf][w + 2][lane + 1] : sk[buf][w + 2][lane + 1];
+        const double ky0 = O ? kcy : kc, kz0 = O ? kcz : kc;
         double a = harm(kc, kxm) * (pc - pxm);
         a += harm(kc, kxp) * (pc - pxp);
-        a += harm(kc, kym) * g.cy * (pc - pym);
-        a += harm(kc, kyp) * g.cy * (pc - pyp);
-        a += harm(kc, km) * g.cz * (pc - pm);
-        a += harm(kc, kp) * g.cz * (pc - pp);
+        a += harm(ky0, kym) * g.cy * (pc - pym);
+        a += harm(ky0, kyp) * g.cy * (pc - pyp);
+        a += harm(kz0, km) * g.cz * (pc - pm);
+        a += harm(kz0, kp) * g.cz * (pc - pp);
         if (in) {
             if (ax != 0.0) x[gi] = xv + ax * po;
             pnew[gi] = pc;
@@ -829,9 +880,15 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
             pq += pc * a;
         }
         pm = pc;
-        km = kc;
+        km = O ? kcz : kc;
         pc = pp;
-        kc = kp;
+        if constexpr (O) {
+            kc = kpx;
+            kcy = kpy;
+            kcz = kp;
+        } else {
+            kc = kp;
+        }
         po = pon;
         xv = xvn;
         pyh = pyh2;
@@ -844,8 +901,9 @@ __global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
 }
 
-// y = A x  (resid = 0)   or   y = b - A x  (resid = 1)
-template <int EX>
+// y = A x  (resid = 0)   or   y = b - A x  (resid = 1); O: orthotropic K
+// (kappa~_y and kappa~_z in two more haloed tiles)
+template <int EX, bool O>
 __global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* __restrict__ kt,
                                                      const double* __restrict__ xv,
                                                      const double* __restrict__ b,
@@ -853,15 +911,27 @@ __global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* _
     using TT = TileT<EX>;
     __shared__ double sX[TT::NHP];
     __shared__ double sK[TT::NHP];
+    __shared__ double sKy[O ? TT::NHP : 1];
+    __shared__ double sKz[O ? TT::NHP : 1];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     load_halo2<EX>(g, xv, sX, kt, sK, x0, y0, z0);
+    if constexpr (O) load_halo2<EX>(g, kt + g.ncell(), sKy, kt + 2 * g.ncell(), sKz, x0, y0, z0);
     __syncthreads();
     const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
     for (int zz = 0; zz < 8; ++zz) {
         const int h = hidx<EX>(tx, ty, zz);
         const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        const double a = apply_stencil<EX, double>(sX, sK, h, g.cy, g.cz);
+        double a;
+        if constexpr (O) {
+            constexpr int HX = TT::HX, HXY = TT::HXY;
+            const double uc = sX[h];
+            a = harm(sK[h], sK[h - 1]) * (uc - sX[h - 1]) + harm(sK[h], sK[h + 1]) * (uc - sX[h + 1]);
+            a += harm(sKy[h], sKy[h - HX]) * (uc - sX[h - HX]) + harm(sKy[h], sKy[h + HX]) * (uc - sX[h + HX]);
+            a += harm(sKz[h], sKz[h - HXY]) * (uc - sX[h - HXY]) + harm(sKz[h], sKz[h + HXY]) * (uc - sX[h + HXY]);
+        } else {
+            a = apply_stencil<EX, double>(sX, sK, h, g.cy, g.cz);
+        }
         y[gi] = resid ? b[gi] - a : a;
     }
 }
@@ -873,15 +943,17 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
                                                       double* __restrict__ invd, float* invd32,
                                                       int* bad) {
     using TT = TileT<EX>;
-    __shared__ double sK[TT::NHP];
+    __shared__ double sK[3][TT::NHP];
     __shared__ double sDg[TT::NCP];
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
+    // kappa~ of each face direction (one array, or three for orthotropic K)
+    const size_t N = g.ortho ? g.ncell() : 0;
     for (int h = threadIdx.x; h < TT::NH; h += TT::NT) {
         size_t gi;
         int ph;
         const bool in = halo_cell<EX>(g, h, x0, y0, z0, gi, ph);
-        sK[ph] = in ? kt[gi] : 0.0;
+        for (int d = 0; d < 3; ++d) sK[d][ph] = in ? kt[d * N + gi] : 0.0;
     }
     __syncthreads();
     constexpr int HX = TT::HX, HXY = TT::HXY, TX = TT::TX;
@@ -894,20 +966,20 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
             const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
             const int ti = 8 * w + i + TX * (j + 8 * k);
             const int h = hidx<EX>(8 * w + i, j, k);
-            const double kc = sK[h];
-            double diag = harm(kc, sK[h - 1]) + harm(kc, sK[h + 1]) + harm(kc, sK[h - HX]) * g.cy +
-                          harm(kc, sK[h + HX]) * g.cy + harm(kc, sK[h - HXY]) * g.cz +
-                          harm(kc, sK[h + HXY]) * g.cz;
+            const double kx = sK[0][h], ky = sK[1][h], kz = sK[2][h];
+            double diag = harm(kx, sK[0][h - 1]) + harm(kx, sK[0][h + 1]) + harm(ky, sK[1][h - HX]) * g.cy +
+                          harm(ky, sK[1][h + HX]) * g.cy + harm(kz, sK[2][h - HXY]) * g.cz +
+                          harm(kz, sK[2][h + HXY]) * g.cz;
             if (i > 0) {
-                const double t = harm(kc, sK[h - 1]);
+                const double t = harm(kx, sK[0][h - 1]);
                 diag -= t * t / sDg[ti - 1];
             }
             if (j > 0) {
-                const double t = harm(kc, sK[h - HX]) * g.cy;
+                const double t = harm(ky, sK[1][h - HX]) * g.cy;
                 diag -= t * t / sDg[ti - TX];
             }
             if (k > 0) {
-                const double t = harm(kc, sK[h - HXY]) * g.cz;
+                const double t = harm(kz, sK[2][h - HXY]) * g.cz;
                 diag -= t * t / sDg[ti - 8 * TX];
             }
             sDg[ti] = diag;
@@ -933,6 +1005,16 @@ __global__ void k_perm_to_kt(const double* __restrict__ perm, double* __restrict
         const double v = p * scale;
         kt[i] = v;
         if (kt32) kt32[i] = (float)v;
+    }
+}
+
+__global__ void k_perm3_to_kt(const double* __restrict__ perm, double* __restrict__ kt, double sx, double sy,
+                              double sz, int64_t n, int* bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double p = perm[i];
+        if (!(p > 0.0) || !isfinite(p)) atomicOr(bad, 1);
+        kt[i] = p * (i < n ? sx : (i < 2 * n ? sy : sz));
     }
 }
 
@@ -1086,12 +1168,9 @@ static inline int grid_1d(int64_t n) {
     return (int)b;
 }
 
+// tiles of 2 elements (mx even) or 1; set-up never builds wider ones
 #define SPECMG_EX_DISPATCH(EXV, ...)          \
     switch (EXV) {                            \
-        case 4: {                             \
-            constexpr int EX = 4;             \
-            __VA_ARGS__;                      \
-        } break;                              \
         case 2: {                             \
             constexpr int EX = 2;             \
             __VA_ARGS__;                      \
@@ -1102,11 +1181,28 @@ static inline int grid_1d(int64_t n) {
         } break;                              \
     }
 
+// O = g.ortho as a compile-time flag; orthotropic kernels exist for float64
+// coefficients only (set-up rejects the float32 fine level with three
+// components)
+#define SPECMG_O_DISPATCH(T, ...)                                                          \
+    if (g.ortho) {                                                                         \
+        if constexpr (std::is_same<T, double>::value) {                                    \
+            constexpr bool O = true;                                                       \
+            __VA_ARGS__;                                                                   \
+        } else {                                                                           \
+            throw HipError{hipErrorInvalidValue, "orthotropic K needs float64 coefficients"}; \
+        }                                                                                  \
+    } else {                                                                               \
+        constexpr bool O = false;                                                          \
+        __VA_ARGS__;                                                                       \
+    }
+
 template <typename T, typename C>
 void launch_pre_smooth(const FineGeom& g, const T* kt, const T* invd, double* r, const double* q, T* u,
                        Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_pre_smooth<EX, T, C>), dim3(g.ntiles), dim3(64 * EX), 0, s,
-                                                g, kt, invd, r, q, u, sc, rb, mode));
+    SPECMG_O_DISPATCH(T, SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_pre_smooth<EX, T, C, O>), dim3(g.ntiles),
+                                                                      dim3(64 * EX), 0, s, g, kt, invd, r, q, u, sc,
+                                                                      rb, mode)));
     if (mode & 1) launch_finalize(RS_RR, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
@@ -1114,8 +1210,8 @@ template <typename T, typename TB, typename C>
 void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const double* r, const TB* phi,
                            const int* nkeep, int L, C* r2, Scalars* sc, int check_done, hipStream_t s) {
     const int m = g.mx * g.my * g.mz;
-    SPECMG_TIMED_LAUNCH((k_resid_restrict<T, TB, C>), dim3((m + 3) / 4), dim3(256), 0, s, g, kt, u, r, phi, nkeep, L,
-                        r2, sc, check_done);
+    SPECMG_O_DISPATCH(T, SPECMG_TIMED_LAUNCH((k_resid_restrict<T, TB, C, O>), dim3((m + 3) / 4), dim3(256), 0, s, g,
+                                             kt, u, r, phi, nkeep, L, r2, sc, check_done));
 }
 
 template <typename T, typename TB, typename C>
@@ -1130,15 +1226,17 @@ template <typename T, typename C>
 void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
                      int check_done, hipStream_t s) {
     if (g.ny % 4 || g.nz % kResZ) throw HipError{hipErrorInvalidValue, "residual tiling"};
-    SPECMG_TIMED_LAUNCH((k_residual<T, C>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ), dim3(256), 0, s, g.nx,
-                        g.ny, g.nz, (C)g.cy, (C)g.cz, kt, u, r, t, sc, check_done);
+    SPECMG_O_DISPATCH(T, SPECMG_TIMED_LAUNCH((k_residual<T, C, O>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ),
+                                             dim3(256), 0, s, g.nx, g.ny, g.nz, (C)g.cy, (C)g.cz, kt, u, r, t, sc,
+                                             check_done));
 }
 
 template <typename T, typename C>
 void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
                         const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T, C>), dim3(g.ntiles), dim3(64 * EX), 0,
-                                                 s, g, kt, invd, u, tres, r, q, z, sc, rb, mode));
+    SPECMG_O_DISPATCH(T, SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T, C, O>), dim3(g.ntiles),
+                                                                      dim3(64 * EX), 0, s, g, kt, invd, u, tres, r,
+                                                                      q, z, sc, rb, mode)));
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
@@ -1152,20 +1250,30 @@ void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const
     const dim3 grid((g.nx + 63) / 64, g.ny / kSpY, g.nz / kSpZ);
     const int nblocks = (int)(grid.x * grid.y * grid.z);
     if (nblocks > kMaxRedBlocks) throw HipError{hipErrorInvalidValue, "spmv grid too large for the reduction buffer"};
-    SPECMG_TIMED_LAUNCH(k_spmv_pcg, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f, pbuf);
+    if (g.ortho)
+        SPECMG_TIMED_LAUNCH(k_spmv_pcg<true>, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f, pbuf);
+    else
+        SPECMG_TIMED_LAUNCH(k_spmv_pcg<false>, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f,
+                            pbuf);
     launch_finalize(RS_PQ, nblocks, sc, rb, nullptr, 1, s);
 }
 
 void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
                     int resid, hipStream_t s) {
-    SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_apply_A<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
-                                                kt, x, b, y, resid));
+    SPECMG_O_DISPATCH(double, SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_apply_A<EX, O>), dim3(g.ntiles),
+                                                                           dim3(64 * EX), 0, s, g, kt, x, b, y,
+                                                                           resid)));
 }
 
 void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* invd32, int* bad,
                      hipStream_t s) {
     SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_ic_setup<EX>), dim3(g.ntiles), dim3(64 * EX), 0, s, g,
                                                 kt, invd, invd32, bad));
+}
+
+void launch_perm3_to_kt(const double* perm, double* kt, double sx, double sy, double sz, int64_t n, int* bad,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_perm3_to_kt, dim3(grid_1d(3 * n)), dim3(256), 0, s, perm, kt, sx, sy, sz, n, bad);
 }
 
 void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n, int* bad,

@@ -3,7 +3,8 @@
 // the two-point flux of eq. (velocity) on every interior face of axis d,
 //   v_{i+1/2} = -kappa_{i+1/2} (p_{i+1} - p_i) / h_d = -h_d c_d kappa~_{i+1/2} (p_{i+1} - p_i)
 // (kappa~ = kappa / hx^2 as stored, c_d = (hx/h_d)^2, harmonic mean on the
-// face), and zero on the no-flow boundary.  The mass balance of a cell is
+// face; for orthotropic K the stored kappa~ of axis d is kappa_d / h_d^2
+// and c_d = 1), and zero on the no-flow boundary.  The mass balance of a cell is
 // the face areas times the flux jumps over the cell volume, minus f_i,
 // which is (A p - f)_i up to rounding.  One thread per cell, grid-stride.
 #include "common.hpp"
@@ -15,17 +16,21 @@ __device__ __forceinline__ double face_harm(double a, double b) {
     return s > 0.0 ? (2.0 * a * b) / s : 0.0;
 }
 
+// ortho: kt holds kappa_d / h_d^2 for d = x, y, z in three arrays of n values
+// (cy = cz = 1); otherwise one array kappa / hx^2
 __global__ __launch_bounds__(256) void k_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy,
-                                              double cz, const double* __restrict__ kt,
+                                              double cz, const double* __restrict__ kt, int ortho,
                                               const double* __restrict__ p, double* __restrict__ vx,
                                               double* __restrict__ vy, double* __restrict__ vz) {
     const int64_t sy = nx, sz = (int64_t)nx * ny, n = sz * nz;
+    const double* ky = ortho ? kt + n : kt;
+    const double* kz = ortho ? kt + 2 * n : kt;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / sy) % ny), z = (int)(i / sz);
-        const double kc = kt[i], pc = p[i];
-        vx[i] = x + 1 < nx ? -hx * face_harm(kc, kt[i + 1]) * (p[i + 1] - pc) : 0.0;
-        vy[i] = y + 1 < ny ? -hy * (face_harm(kc, kt[i + sy]) * cy) * (p[i + sy] - pc) : 0.0;
-        vz[i] = z + 1 < nz ? -hz * (face_harm(kc, kt[i + sz]) * cz) * (p[i + sz] - pc) : 0.0;
+        const double pc = p[i];
+        vx[i] = x + 1 < nx ? -hx * face_harm(kt[i], kt[i + 1]) * (p[i + 1] - pc) : 0.0;
+        vy[i] = y + 1 < ny ? -hy * (face_harm(ky[i], ky[i + sy]) * cy) * (p[i + sy] - pc) : 0.0;
+        vz[i] = z + 1 < nz ? -hz * (face_harm(kz[i], kz[i + sz]) * cz) * (p[i + sz] - pc) : 0.0;
     }
 }
 
@@ -49,9 +54,9 @@ static int flux_blocks(int64_t n) {
 }
 
 void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
-                 const double* p, double* vx, double* vy, double* vz, hipStream_t s) {
+                 int ortho, const double* p, double* vx, double* vy, double* vz, hipStream_t s) {
     hipLaunchKernelGGL(k_flux, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, hx, hy, hz, cy,
-                       cz, kt, p, vx, vy, vz);
+                       cz, kt, ortho, p, vx, vy, vz);
 }
 
 void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,

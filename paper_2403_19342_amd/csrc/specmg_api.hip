@@ -84,6 +84,7 @@ struct specmg_ctx {
     int target_cc = 0, Lcc = 0, nvec_cc = 0;               // levels >= 3
     double thr_cc = 0.0;                                   // threshold rule at levels >= 3 when > 0
     double thr_c = 0.0;                                    // threshold rule at level 2 when > 0
+    int ncomp = 1;        // permeability components: 1 (kappa I) or 3 (diag(kappa_x, kappa_y, kappa_z))
     int fp32 = 0;
     int fp32_basis = 0;   // float64 fine level with a float32 copy of the level-2 basis
     int fp32_store = 0;   // fine level stored in float32 (kappa~, 1/d, basis, u, t), float64 arithmetic
@@ -415,20 +416,27 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     fg.ntz = fg.mz;
     fg.ntiles = fg.ntx * fg.nty * fg.ntz;
     fg.xcd_remap = (fg.ntiles % 8 == 0) ? 1 : 0;
-    fg.cy = (G.hx / G.hy) * (G.hx / G.hy);
-    fg.cz = (G.hx / G.hz) * (G.hx / G.hz);
+    fg.ortho = c->ncomp == 3 ? 1 : 0;
+    // isotropic: kappa~ = kappa / hx^2 and the y, z faces scaled by
+    // (hx/hy)^2, (hx/hz)^2; orthotropic: kappa~_d = kappa_d / h_d^2 per axis
+    fg.cy = fg.ortho ? 1.0 : (G.hx / G.hy) * (G.hx / G.hy);
+    fg.cz = fg.ortho ? 1.0 : (G.hx / G.hz) * (G.hx / G.hz);
     if (fg.ntiles > kMaxRedBlocks) return fail(SPECMG_EINVAL, "grid too large for the reduction buffer");
 
     c->dflag = c->alloc<int>(8);
     HIPCHK(hipMemsetAsync(c->dflag, 0, 8 * sizeof(int), s));
-    c->kt = c->alloc<double>(c->n);
+    c->kt = c->alloc<double>((size_t)c->ncomp * c->n);
     c->invd = c->alloc<double>(c->n);
     if (c->fp32 || c->fp32_store) {
         c->kt32 = c->alloc<float>(c->n);
         c->invd32 = c->alloc<float>(c->n);
     }
     const double h = G.hx;
-    launch_perm_to_kt(perm, c->kt, c->kt32, 1.0 / (h * h), c->n, c->dflag, s);
+    if (fg.ortho)
+        launch_perm3_to_kt(perm, c->kt, 1.0 / (G.hx * G.hx), 1.0 / (G.hy * G.hy), 1.0 / (G.hz * G.hz), c->n,
+                           c->dflag, s);
+    else
+        launch_perm_to_kt(perm, c->kt, c->kt32, 1.0 / (h * h), c->n, c->dflag, s);
     int flags[8];
     HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -696,7 +704,12 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
     if (allocator && (!allocator->alloc || !allocator->free))
         return fail(SPECMG_EINVAL, "allocator needs both alloc and free");
     *out = nullptr;
-    if (perm_components != 1) return fail(SPECMG_EINVAL, "only isotropic permeability (1 component) is supported");
+    if (perm_components != 1 && perm_components != 3)
+        return fail(SPECMG_EINVAL, "perm_components must be 1 (isotropic) or 3 (orthotropic)");
+    if (perm_components == 3 && (opts->precision == SPECMG_FP32_VCYCLE || opts->precision == SPECMG_FP32_STORE))
+        return fail(SPECMG_EINVAL, "orthotropic permeability needs a float64 fine level (FP64 or FP32_BASIS)");
+    if (perm_components == 3 && opts->warm_start == SPECMG_WS_CNN)
+        return fail(SPECMG_EINVAL, "the learned warm start needs isotropic permeability");
     const specmg_grid& G = *grid;
     if (G.sub != 8) return fail(SPECMG_EINVAL, "sub must be 8");
     if (G.agg != 2 && G.agg != 4) return fail(SPECMG_EINVAL, "agg must be 2 or 4");
@@ -741,6 +754,7 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
     c->al.stream = (hipStream_t)stream;
     c->grid = G;
     c->opts = *opts;
+    c->ncomp = perm_components;
     c->levels = opts->levels;
     c->target = opts->eigs_per_subdomain;
     c->L = c->target + 3;
@@ -1070,7 +1084,7 @@ extern "C" int specmg_gmres_solve(specmg_ctx* c, const double* rhs, double* x, i
 
 namespace specmg {
 void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
-                 const double* p, double* vx, double* vy, double* vz, hipStream_t s);
+                 int ortho, const double* p, double* vx, double* vy, double* vz, hipStream_t s);
 void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,
                          const double* vz, const double* f, double* res, hipStream_t s);
 }  // namespace specmg
@@ -1080,8 +1094,8 @@ extern "C" int specmg_recover_flux(specmg_ctx* c, const double* p, double* vx, d
     g_last_error.clear();
     if (!c || !p || !vx || !vy || !vz) return fail(SPECMG_EINVAL, "null argument");
     try {
-        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->grid.hy, c->grid.hz, c->fg.cy, c->fg.cz, c->kt, p, vx,
-                    vy, vz, (hipStream_t)stream);
+        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->grid.hy, c->grid.hz, c->fg.cy, c->fg.cz, c->kt,
+                    c->fg.ortho, p, vx, vy, vz, (hipStream_t)stream);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));

@@ -282,9 +282,14 @@ class SpecMG:
         caching allocator through specmg_setup_alloc) or "hip" (hipMalloc)."""
         lib = load_library()
         import torch
-        if perm.dim() != 3:
-            raise ValueError("perm must have shape (nz, ny, nx)")
-        nz, ny, nx = perm.shape
+        if perm.dim() == 4 and perm.shape[0] == 3:
+            ncomp = 3                      # (kappa_x, kappa_y, kappa_z) per cell
+            nz, ny, nx = perm.shape[1:]
+        elif perm.dim() == 3:
+            ncomp = 1
+            nz, ny, nx = perm.shape
+        else:
+            raise ValueError("perm must have shape (nz, ny, nx) or (3, nz, ny, nx)")
         self.shape = (nz, ny, nx)
         self.n = nx * ny * nz
         if h is None:
@@ -305,11 +310,11 @@ class SpecMG:
         perm = perm.contiguous()
         if allocator == "torch":
             self._alloc, self._alloc_keep = torch_allocator()
-            rc = lib.specmg_setup_alloc(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts),
+            rc = lib.specmg_setup_alloc(_dev_ptr(perm), ncomp, ctypes.byref(self.grid), ctypes.byref(self.opts),
                                         ctypes.byref(self._alloc), _stream(), ctypes.byref(ctx))
         elif allocator == "hip":
-            rc = lib.specmg_setup(_dev_ptr(perm), 1, ctypes.byref(self.grid), ctypes.byref(self.opts), _stream(),
-                                  ctypes.byref(ctx))
+            rc = lib.specmg_setup(_dev_ptr(perm), ncomp, ctypes.byref(self.grid), ctypes.byref(self.opts),
+                                  _stream(), ctypes.byref(ctx))
         else:
             raise ValueError("allocator must be 'torch' or 'hip'")
         if rc == EEIG and allow_unconverged:

@@ -113,3 +113,17 @@ def test_setup_alloc_rejects_incomplete_allocator():
     assert rc == -1
     assert ctx.value is None
     assert "allocator" in lib.specmg_last_error().decode()
+
+
+@pytest.mark.parametrize("components,precision,warm", [(2, 0, 0), (3, 1, 0), (3, 3, 0), (3, 0, 1)])
+def test_setup_rejects_unsupported_permeability_forms(components, precision, warm):
+    # two components do not exist; orthotropic K runs with a float64 fine
+    # level only and without the learned warm start (trained on kappa I)
+    lib = _lib()
+    from paper_2403_19342_amd.specmg import Grid, Opts
+    g = Grid(32, 32, 32, 1 / 32, 1 / 32, 1 / 32, 8, 4)
+    o = Opts(3, 6, 1, precision, warm, ctypes.c_void_p(0x2000) if warm else None, 1e-12, 1e-6, 1e-3)
+    ctx = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)
+    rc = lib.specmg_setup(fake, components, ctypes.byref(g), ctypes.byref(o), None, ctypes.byref(ctx))
+    assert rc == -1 and ctx.value is None
