@@ -234,12 +234,10 @@ void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const dou
 template <typename T, typename TB, typename C>
 void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const C* e2,
                     Scalars* sc, int check_done, hipStream_t s);
+// z = u + M^{-1} (r - A u) in one pass (the residual is not stored)
 template <typename T, typename C>
-void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
-                     int check_done, hipStream_t s);
-template <typename T, typename C>
-void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
-                        const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
+void launch_post_fused(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
+                       const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
 void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
                      double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first,
                      hipStream_t s);

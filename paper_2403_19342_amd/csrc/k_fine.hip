@@ -523,34 +523,57 @@ __device__ __forceinline__ void load8(const float* __restrict__ p, double (&v)[8
     }
 }
 
-// s -= T (u - u_nb) over the pencil for one neighbour pencil (nu, nk)
-template <typename T>
-__device__ __forceinline__ void face_pencil(T (&s)[8], const T (&uc)[8], const T (&kc)[8], const T (&nu)[8],
-                                            const T (&nk)[8], T cf) {
+// The cells beyond the element's four y and z faces (-y, +y, -z, +z), u and
+// kappa~ (the face's own component for orthotropic K), zero outside the
+// domain.  All 64 lanes load them together, one cell per face and array
+// (lane = (x, row) of the face, 64-byte rows), and stage them in the
+// wavefront's LDS area fu[4][64], fk[4][64] for the lanes on those faces.
+template <bool O, typename T, typename C>
+__device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
+                                               int x0, int y0, int z0, int lane, C* fu, C* fk) {
+    const int fx = lane & 7, fr = lane >> 3;
+    const size_t N = O ? g.ncell() : 0;
+    C vu[4], vk[4];
 #pragma unroll
-    for (int x = 0; x < 8; ++x) s[x] -= harm(kc[x], nk[x]) * cf * (uc[x] - nu[x]);
+    for (int f = 0; f < 4; ++f) {
+        const int yy = f < 2 ? (f == 0 ? y0 - 1 : y0 + 8) : y0 + fr;
+        const int zz = f < 2 ? z0 + fr : (f == 2 ? z0 - 1 : z0 + 8);
+        const bool in = yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz;
+        const size_t gi = in ? gidx(g, x0 + fx, yy, zz) : 0;
+        vu[f] = in ? (C)u[gi] : C(0);
+        vk[f] = in ? (C)kt[(f < 2 ? N : 2 * N) + gi] : C(0);
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        fu[f * 64 + lane] = vu[f];
+        fk[f * 64 + lane] = vk[f];
+    }
+    wave_lds_sync();
 }
 
-// s = r - A u on the x-pencil of row (j, k) of an element (x0 = the
-// element's first x, (y, z) the row), natural order; row = index of (x0, y, z)
+// s -= A u on the x-pencil of row (j, k) of an element whose first cell is
+// (x0, y0, z0), natural order; row = index of (x0, y0 + j, z0 + k).  The
+// row's u and kappa~ (kappa~_x for orthotropic K) are returned in uc, kc.
+// y and z neighbours inside the element come from the lanes -+1 and -+8,
+// those beyond the element's faces from the LDS staging area (fu, fk, see
+// stage_faces_yz), the pencil ends in x from memory; every load is issued
+// before the arithmetic, so a wavefront waits for memory once.
 template <bool O, typename T, typename C>
 __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
-                                                const double* __restrict__ r, size_t row, int x0, int y, int z,
-                                                int lane, int j, int k, C (&s)[8]) {
-    const size_t sy = (size_t)g.nx, sz = (size_t)g.nx * g.ny;
+                                                size_t row, int x0, int y0, int z0, int lane, int j, int k,
+                                                C* fu, C* fk, C (&s)[8], C (&uc)[8], C (&kc)[8]) {
     const size_t N = O ? g.ncell() : 0;   // offsets of the y and z arrays
-    C uc[8], kc[8];
     load8(u + row, uc);
     load8(kt + row, kc);
-    {
-        const double2* q = reinterpret_cast<const double2*>(r + row);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double2 d = q[i];
-            s[2 * i] = (C)d.x;
-            s[2 * i + 1] = (C)d.y;
-        }
+    C ky[8], kz[8];
+    if constexpr (O) {
+        load8(kt + N + row, ky);
+        load8(kt + 2 * N + row, kz);
     }
+    const bool xlo = x0 > 0, xhi = x0 + 8 < g.nx;
+    const C um = xlo ? (C)u[row - 1] : C(0), km = xlo ? (C)kt[row - 1] : C(0);
+    const C up = xhi ? (C)u[row + 8] : C(0), kp = xhi ? (C)kt[row + 8] : C(0);
+    stage_faces_yz<O>(g, kt, u, x0, y0, z0, lane, fu, fk);
     // x faces: inside the pencil, then the two ends
 #pragma unroll
     for (int x = 0; x < 7; ++x) {
@@ -558,41 +581,25 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
         s[x] -= d;
         s[x + 1] += d;
     }
-    if (x0 > 0) s[0] -= harm(kc[0], (C)kt[row - 1]) * (uc[0] - (C)u[row - 1]);
-    if (x0 + 8 < g.nx) s[7] -= harm(kc[7], (C)kt[row + 8]) * (uc[7] - (C)u[row + 8]);
-    // y and z neighbours, one direction at a time (orthotropic: the y and z
-    // faces take the y and z arrays, own pencil included)
+    if (xlo) s[0] -= harm(kc[0], km) * (uc[0] - um);
+    if (xhi) s[7] -= harm(kc[7], kp) * (uc[7] - up);
+    __builtin_amdgcn_sched_barrier(0);
+    // y and z faces, one direction at a time: -y, +y, -z, +z (orthotropic:
+    // the y and z faces take the y and z arrays, own pencil included)
 #pragma unroll 1
     for (int d = 0; d < 4; ++d) {
-        C nu[8], nk[8], ko[8];
-        const size_t ka = O ? (d < 2 ? N : 2 * N) : 0;
-        if constexpr (O) {
-            load8(kt + ka + row, ko);
-        } else {
-#pragma unroll
-            for (int x = 0; x < 8; ++x) ko[x] = kc[x];
-        }
-        // source lane of the neighbour row: -1, +1, -8, +8 (wrapping lanes are
-        // the element's edge lanes, which load instead)
         const int src = (lane + (d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -8 : 8)))) & 63;
+        const bool mem = d == 0 ? j == 0 : (d == 1 ? j == 7 : (d == 2 ? k == 0 : k == 7));
+        const int fo = d * 64 + 8 * (d < 2 ? k : j);
+        const C cf = (C)(d < 2 ? g.cy : g.cz);
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
-            nu[x] = __shfl(uc[x], src, 64);
-            nk[x] = __shfl(ko[x], src, 64);
+            const C ko = O ? (d < 2 ? ky[x] : kz[x]) : kc[x];
+            const C su = __shfl(uc[x], src, 64), sk = __shfl(ko, src, 64);
+            const C nu = mem ? fu[fo + x] : su;
+            const C nk = mem ? fk[fo + x] : sk;
+            s[x] -= harm(ko, nk) * cf * (uc[x] - nu);
         }
-        const bool edge = d == 0 ? j == 0 : (d == 1 ? j == 7 : (d == 2 ? k == 0 : k == 7));
-        if (edge) {
-            const bool inside = d == 0 ? y > 0 : (d == 1 ? y + 1 < g.ny : (d == 2 ? z > 0 : z + 1 < g.nz));
-            if (inside) {
-                const size_t o = d == 0 ? row - sy : (d == 1 ? row + sy : (d == 2 ? row - sz : row + sz));
-                load8(u + o, nu);
-                load8(kt + ka + o, nk);
-            } else {
-#pragma unroll
-                for (int x = 0; x < 8; ++x) nk[x] = C(0);
-            }
-        }
-        face_pencil(s, uc, ko, nu, nk, (C)(d < 2 ? g.cy : g.cz));
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -606,7 +613,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
                                                        int L, C* __restrict__ r2, const Scalars* sc,
                                                        int check_done) {
     if (check_done && sc->done) return;
-    const int lane = threadIdx.x & 63;
+    __shared__ C sfu[4][256], sfk[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int m = g.mx * g.my * g.mz;
     const int nb = gridDim.x;
     int b = blockIdx.x;
@@ -618,7 +626,17 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
     const size_t row = (size_t)x0 + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
     C s[8];
-    pencil_residual<O>(g, kt, u, r, row, x0, y, z, lane, j, k, s);
+    {
+        const double2* q = reinterpret_cast<const double2*>(r + row);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double2 d = q[i];
+            s[2 * i] = (C)d.x;
+            s[2 * i + 1] = (C)d.y;
+        }
+        C uc[8], kc[8];
+        pencil_residual<O>(g, kt, u, row, x0, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
+    }
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
@@ -668,95 +686,72 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
     }
 }
 
-// Residual t = r - A u, one cell per thread: the block covers 64 x 4 cells
-// of a plane and walks RZ planes in z, keeping the z-neighbours of u and
-// kappa~ in registers; x- and y-neighbours come from the L1 cache.
-// Faces leaving the domain have zero transmissibility.
-constexpr int kResZ = 8;
-template <typename T, typename C, bool O>
-__global__ __launch_bounds__(256) void k_residual(int nx, int ny, int nz, C cy, C cz, const T* __restrict__ kt,
-                                                  const T* __restrict__ u, const double* __restrict__ r,
-                                                  T* __restrict__ t, const Scalars* sc, int check_done) {
-    if (check_done && sc->done) return;
-    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int z0 = blockIdx.z * kResZ;
-    if (x >= nx) return;   // ragged last column of blocks (no barriers below)
-    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-    size_t gi = (size_t)x + sy * y + sz * z0;
-    const bool xm = x > 0, xp = x + 1 < nx, ym = y > 0, yp = y + 1 < ny;
-    // orthotropic: the y and z faces read the y and z arrays
-    const size_t N = (size_t)nx * ny * nz;
-    const T* ky = O ? kt + N : kt;
-    const T* kz = O ? kt + 2 * N : kt;
-    C uc = u[gi], kc = kz[gi];
-    C um = z0 > 0 ? (C)u[gi - sz] : C(0), km = z0 > 0 ? (C)kz[gi - sz] : C(0);
-#pragma unroll 2
-    for (int z = z0; z < z0 + kResZ; ++z, gi += sz) {
-        const bool zp = z + 1 < nz;
-        const C up = zp ? (C)u[gi + sz] : C(0), kp = zp ? (C)kz[gi + sz] : C(0);
-        const C kcx = O ? (C)kt[gi] : kc, kcy = O ? (C)ky[gi] : kc;
-        const C uxm = xm ? (C)u[gi - 1] : C(0), kxm = xm ? (C)kt[gi - 1] : C(0);
-        const C uxp = xp ? (C)u[gi + 1] : C(0), kxp = xp ? (C)kt[gi + 1] : C(0);
-        const C uym = ym ? (C)u[gi - sy] : C(0), kym = ym ? (C)ky[gi - sy] : C(0);
-        const C uyp = yp ? (C)u[gi + sy] : C(0), kyp = yp ? (C)ky[gi + sy] : C(0);
-        C a = harm(kcx, kxm) * (uc - uxm);
-        a += harm(kcx, kxp) * (uc - uxp);
-        a += harm(kcy, kym) * cy * (uc - uym);
-        a += harm(kcy, kyp) * cy * (uc - uyp);
-        a += harm(kc, km) * cz * (uc - um);
-        a += harm(kc, kp) * cz * (uc - up);
-        t[gi] = (T)((C)r[gi] - a);
-        um = uc;
-        km = kc;
-        uc = up;
-        kc = kp;
-    }
-}
-
-// post-smoothing (Algorithm 1 step 9): z = u + M^{-1} t with t = r - A u
-// from k_residual.  mode bit0: reduce r.z (and z.q when flexible) and update
-// the CG beta; bit1: return at once when the solve is finished.
+// Post-smoothing with its residual (Algorithm 1 step 9): t = r - A u on
+// the wavefront's element (pencil_residual), z = u + M^{-1} t, without t
+// going through memory.  The row's r and u wait in the wavefront's LDS area
+// while the IC(0) sweep holds the registers.  mode bit0: reduce r.z (and
+// z.q when flexible) for the CG beta; bit1: return at once when the solve is
+// finished.
 template <int EX, typename T, typename C, bool O>
-__global__ __launch_bounds__(64 * EX) void k_post_smooth(FineGeom g, const T* __restrict__ kt,
-                                                         const T* __restrict__ invd,
-                                                         const T* __restrict__ u, const T* __restrict__ tres,
-                                                         const double* __restrict__ r,
-                                                         const double* __restrict__ q,
-                                                         double* __restrict__ z, Scalars* sc, RedBuf rb,
-                                                         int mode) {
+__global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __restrict__ kt,
+                                                        const T* __restrict__ invd, const T* __restrict__ u,
+                                                        const double* __restrict__ r, const double* __restrict__ q,
+                                                        double* __restrict__ z, Scalars* sc, RedBuf rb, int mode) {
     if ((mode & 2) && sc->done) return;
     __shared__ double sred[EX];
+    __shared__ C sa[EX][512];        // y/z faces (fu, fk), then the row's u
+    __shared__ double srr[EX][512];  // the row's r
     int x0, y0, z0;
     tile_origin(g, x0, y0, z0);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = lane & 7, k = lane >> 3, jk = j + k;
-    const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);
-    C fx[8], fy[8], fz[8];
-    load_faces<O>(g, kt, row, jk, fx, fy, fz);
+    const int ex0 = x0 + 8 * w;
+    const size_t row = gidx(g, ex0, y0 + j, z0 + k);
+    C s[8], uc[8], kc[8];
+    {
+        double rv[8];
+        load8(r + row, rv);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            s[x] = (C)rv[x];
+            srr[w][x * 64 + lane] = rv[x];
+        }
+    }
+    pencil_residual<O>(g, kt, u, row, ex0, y0, z0, lane, j, k, sa[w], sa[w] + 256, s, uc, kc);
+    wave_lds_sync();
+#pragma unroll
+    for (int x = 0; x < 8; ++x) sa[w][x * 64 + lane] = uc[x];
     __builtin_amdgcn_sched_barrier(0);
-    C y[8], ix[8];
-    load_pencil(tres + row, y, jk);
+    // faces and pivots of the IC(0) sweep in slot order
+    C fx[8], fy[8], fz[8];
+    if constexpr (O) {
+        load_faces<true>(g, kt, row, jk, fx, fy, fz);
+    } else {
+        rotate_slots(kc, jk, false);
+        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
+    }
+    C ix[8];
     load_pencil(invd + row, ix, jk);
-    ic_pencil(y, ix, fx, fy, fz, j, k);
+    rotate_slots(s, jk, false);
+    ic_pencil(s, ix, fx, fy, fz, j, k);
+    rotate_slots(s, jk, true);
+    __builtin_amdgcn_sched_barrier(0);
     double rz = 0.0, zq = 0.0;
     const int flex = (mode & 1) ? sc->flexible : 0;
-    {
-        C uo[8];
-        double zv[8], rv[8], qv[8];
-        load_pencil(u + row, uo, jk);
-        if (mode & 1) load_pencil(r + row, rv, jk);
-        if (flex) load_pencil(q + row, qv, jk);
+    double qv[8];
+    if (flex) load8(q + row, qv);
+    double zv[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            zv[s] = (double)uo[s] + (double)y[s];
-            if (mode & 1) {
-                rz += rv[s] * zv[s];
-                if (flex) zq += zv[s] * qv[s];
-            }
+    for (int x = 0; x < 8; ++x) {
+        zv[x] = (double)sa[w][x * 64 + lane] + (double)s[x];
+        if (mode & 1) {
+            rz += srr[w][x * 64 + lane] * zv[x];
+            if (flex) zq += zv[x] * qv[x];
         }
-        store_pencil(z + row, zv, jk);
     }
+    double2* zo = reinterpret_cast<double2*>(z + row);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) zo[i] = make_double2(zv[2 * i], zv[2 * i + 1]);
     if (mode & 1) {
         double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
         write_partials<2>(v, rb);
@@ -1221,22 +1216,12 @@ void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, in
                        sc, check_done);
 }
 
-// t = r - A u (ny and nz are multiples of 8, nx any multiple of 8)
 template <typename T, typename C>
-void launch_residual(const FineGeom& g, const T* kt, const T* u, const double* r, T* t, const Scalars* sc,
-                     int check_done, hipStream_t s) {
-    if (g.ny % 4 || g.nz % kResZ) throw HipError{hipErrorInvalidValue, "residual tiling"};
-    SPECMG_O_DISPATCH(T, SPECMG_TIMED_LAUNCH((k_residual<T, C, O>), dim3((g.nx + 63) / 64, g.ny / 4, g.nz / kResZ),
-                                             dim3(256), 0, s, g.nx, g.ny, g.nz, (C)g.cy, (C)g.cz, kt, u, r, t, sc,
-                                             check_done));
-}
-
-template <typename T, typename C>
-void launch_post_smooth(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
-                        const double* q, double* z, T* tres, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
-    SPECMG_O_DISPATCH(T, SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_smooth<EX, T, C, O>), dim3(g.ntiles),
-                                                                      dim3(64 * EX), 0, s, g, kt, invd, u, tres, r,
-                                                                      q, z, sc, rb, mode)));
+void launch_post_fused(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
+                       const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s) {
+    SPECMG_O_DISPATCH(T, SPECMG_EX_DISPATCH(g.ex, SPECMG_TIMED_LAUNCH((k_post_fused<EX, T, C, O>), dim3(g.ntiles),
+                                                                      dim3(64 * EX), 0, s, g, kt, invd, u, r, q, z,
+                                                                      sc, rb, mode)));
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
@@ -1329,10 +1314,8 @@ void launch_pcg_init(Scalars* sc, double thresh2, int flexible, hipStream_t s) {
                                                   const int*, int, C*, Scalars*, int, hipStream_t);                \
     template void launch_prolong<T, TB, C>(const FineGeom&, T*, const TB*, const int*, int, const C*, Scalars*,    \
                                            int, hipStream_t);                                                      \
-    template void launch_residual<T, C>(const FineGeom&, const T*, const T*, const double*, T*, const Scalars*,     \
-                                        int, hipStream_t);                                                         \
-    template void launch_post_smooth<T, C>(const FineGeom&, const T*, const T*, const T*, const double*,           \
-                                           const double*, double*, T*, Scalars*, RedBuf, int, hipStream_t);
+    template void launch_post_fused<T, C>(const FineGeom&, const T*, const T*, const T*, const double*,            \
+                                          const double*, double*, Scalars*, RedBuf, int, hipStream_t);
 SPECMG_FINE_INST(double, double, double)
 SPECMG_FINE_INST(float, float, float)
 SPECMG_FINE_INST(float, float, double)

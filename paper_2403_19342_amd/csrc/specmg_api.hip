@@ -108,7 +108,6 @@ struct specmg_ctx {
     double* rc = nullptr;       // coarsest right-hand side, compact
     // CG state
     double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *u1 = nullptr;
-    double* tres = nullptr;     // r - A u of the post-smoother (float in FP32 mode)
     float* u1_32 = nullptr;
     double* dtmp = nullptr;     // scratch scalars
     int* dflag = nullptr;       // error flags
@@ -172,7 +171,7 @@ double now_ms() {
 // dispatch); prof_begin_range / prof_end record plain events around a group
 // of launches (the coarse levels).
 enum ProfClass { PC_SPMV = 0, PC_PRE = 1, PC_RESTRICT = 2, PC_PROLONG = 3, PC_POST = 4, PC_COARSE = 5,
-                 PC_COARSEST = 6, PC_POSTRES = 7 };
+                 PC_COARSEST = 6 };   // slot 7 is unused (zero)
 
 static size_t prof_events(specmg_ctx* c) {
     if (c->ev_used + 2 > c->ev_pool.size()) {
@@ -270,9 +269,7 @@ void extra_fine_sweep(specmg_ctx* c, double* r, double* z, int check, hipStream_
     const T* kt = pick<T>(c->kt, c->kt32);
     const T* invd = pick<T>(c->invd, c->invd32);
     T* u1 = pick<T>(c->u1, c->u1_32);
-    T* tres = pick<T>(c->tres, (float*)c->tres);
-    launch_residual<T, C>(c->fg, kt, u1, r, tres, c->sc, check, s);
-    launch_post_smooth<T, C>(c->fg, kt, invd, u1, r, nullptr, z, tres, c->sc, c->rb, check ? 2 : 0, s);
+    launch_post_fused<T, C>(c->fg, kt, invd, u1, r, nullptr, z, c->sc, c->rb, check ? 2 : 0, s);
     const Scalars* gate = check ? c->sc : nullptr;
     if constexpr (std::is_same<T, float>::value) launch_convert<double, float>(z, u1, c->n, s, gate);
     else launch_copy(u1, z, c->n, s, gate);
@@ -315,12 +312,8 @@ void vcycle_fine(specmg_ctx* c, double* r, double* z, const double* q, int pre_m
     launch_prolong<T, TB, C>(c->fg, u1, phi, l2.nkeep, l2.L, e2, c->sc, check, s);
     prof_end(c, ev, PC_PROLONG, s);
     for (int it = 1; it < c->nu; ++it) extra_fine_sweep<T, C>(c, r, z, check, s);
-    T* tres = pick<T>(c->tres, (float*)c->tres);
     ev = prof_begin(c, s);
-    launch_residual<T, C>(c->fg, kt, u1, r, tres, c->sc, (post_mode & 2) ? 1 : 0, s);
-    prof_end(c, ev, PC_POSTRES, s);
-    ev = prof_begin(c, s);
-    launch_post_smooth<T, C>(c->fg, kt, invd, u1, r, q, z, tres, c->sc, c->rb, post_mode, s);
+    launch_post_fused<T, C>(c->fg, kt, invd, u1, r, q, z, c->sc, c->rb, post_mode, s);
     prof_end(c, ev, PC_POST, s);
 }
 
@@ -661,7 +654,6 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->p[1] = c->alloc<double>(c->n);
     c->q = c->alloc<double>(c->n);
     c->u1 = c->alloc<double>(c->n);
-    c->tres = c->alloc<double>(c->n);
     if (c->fp32 || c->fp32_store) c->u1_32 = c->alloc<float>(c->n);
     c->dtmp = c->alloc<double>(8);
     c->sc = c->alloc<Scalars>(1);
@@ -1183,8 +1175,7 @@ extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, 
     const double wb = (c->fp32_basis || c->fp32_store) ? 4.0 : w;   // basis word size
     b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * wb;  // u, kappa~, r; phi
     b[PC_PROLONG] = n * 2.0 * w + phi_cells * wb;            // u in/out; phi
-    b[PC_POST] = n * (4.0 * w + 8.0 * 2.0 + (c->flexible ? 8.0 : 0.0));  // t, kappa~, 1/d, u, r in; z out (q)
-    b[PC_POSTRES] = n * (3.0 * w + 8.0);                                // u, kappa~, r in; t out
+    b[PC_POST] = n * (3.0 * w + 8.0 * 2.0 + (c->flexible ? 8.0 : 0.0));  // kappa~, 1/d, u, r in; z out (q)
     b[PC_COARSE] = c->coarse_bytes;
     b[PC_COARSEST] = c->coarsest_bytes;
     for (int i = 0; i < 8; ++i) {
