@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 256 << 20
 # profiling classes that are one kernel each (the coarse part is a group)
 SINGLE_KERNEL = {"cg_spmv": "k_spmv_pcg", "pre_smooth": "k_pre_smooth", "resid_restrict": "k_resid_restrict",
-                 "prolong": "k_prolong", "post_smooth": "k_post_fused",
+                 "prolong": "k_prolong", "post_smooth": "k_post_fused", "p_update": "k_p_update",
                  "coarsest": "k_coarsest_sym / k_coarsest"}
 
 

@@ -324,12 +324,12 @@ int specmg_set_profiling(specmg_ctx* ctx, int32_t on);
 /* Accumulated event times (ms) and launch counts per kernel class since
  * profiling was turned on, and the algorithmic bytes one launch of the class
  * moves (compulsory HBM traffic of its inputs and outputs).  Classes:
- * 0 CG operator (p update, A p, p.Ap)   1 pre-smoothing (r update, IC(0))
+ * 0 CG operator (A p, p.Ap)            1 pre-smoothing (r update, IC(0))
  * 2 residual + restriction             3 prolongation
  * 4 post-smoothing (its residual, IC(0), r.z)
  * 5 coarse part of the V-cycle (every kernel of levels 2..L, the coarsest
  *   product included)                  6 coarsest product alone
- * 7 unused (zero).
+ * 7 CG direction update (p = z + beta p, the deferred x update).
  * Bytes of classes 5 and 6 count kept widths (not the padded storage).
  * Arrays hold 8 entries. */
 int specmg_get_profile(specmg_ctx* ctx, double* ms, int32_t* launches, double* bytes);

@@ -210,6 +210,17 @@ struct FineGeom {
     __host__ __device__ size_t ncell() const { return (size_t)nx * ny * nz; }
 };
 
+// Element order of the fine-level arrays the library keeps (kappa~, the
+// IC(0) pivots, every vector of the solve): the 512 cells of each 8^3
+// level-2 element are contiguous, x fastest inside the element, and the
+// elements follow each other x fastest.  A wavefront's x-pencils of one
+// element are then one 4 KB block.  Arrays the caller passes (permeability,
+// sources, solutions, fluxes) keep the natural order x + nx (y + ny z).
+__host__ __device__ inline size_t eidx(const FineGeom& g, int x, int y, int z) {
+    const size_t e = (size_t)(x >> 3) + (size_t)g.mx * ((size_t)(y >> 3) + (size_t)g.my * (size_t)(z >> 3));
+    return e * 512 + (size_t)((x & 7) + 8 * ((y & 7) + 8 * (z & 7)));
+}
+
 // Coarse level l >= 2: elements on an (mx,my,mz) grid, padded width L.
 struct CoarseGeom {
     int mx, my, mz, m;
@@ -238,18 +249,25 @@ void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, in
 template <typename T, typename C>
 void launch_post_fused(const FineGeom& g, const T* kt, const T* invd, const T* u, const double* r,
                        const double* q, double* z, Scalars* sc, RedBuf rb, int mode, hipStream_t s);
-void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
-                     double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first,
-                     hipStream_t s);
+// p = z + beta p_old (p = z when first), x += alpha_x p_old
+void launch_p_update(const FineGeom& g, const double* z, const double* pold, double* pnew, double* x, Scalars* sc,
+                     int first, hipStream_t s);
+// q = A p, p.q; records pbuf (the p buffer index) for the final x update
+void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* p, double* q, Scalars* sc, RedBuf rb,
+                     int pbuf, hipStream_t s);
 void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
                     int resid, hipStream_t s);
 void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* invd32, int* bad,
                      hipStream_t s);
-void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n,
-                       int* bad, hipStream_t s);
-// three components: kt[d n + i] = perm[d n + i] * scale[d]
-void launch_perm3_to_kt(const double* perm, double* kt, double sx, double sy, double sz, int64_t n, int* bad,
-                        hipStream_t s);
+// kt (element order) = perm (natural order) * scale
+void launch_perm_to_kt(const FineGeom& g, const double* perm, double* kt, float* kt32, double scale, int* bad,
+                       hipStream_t s);
+// three components: array d of kt (element order) = component d of perm * scale[d]
+void launch_perm3_to_kt(const FineGeom& g, const double* perm, double* kt, double sx, double sy, double sz,
+                        int* bad, hipStream_t s);
+// natural order <-> element order of one cell array
+void launch_to_elem(const FineGeom& g, const double* nat, double* el, hipStream_t s);
+void launch_to_natural(const FineGeom& g, const double* el, double* nat, hipStream_t s);
 
 // vector utilities (k_fine.hip)
 void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,

@@ -538,9 +538,7 @@ __global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __r
     __shared__ double sN[3][kMaxL][64];    // neighbour face rows (+ faces)
     const int e = blockIdx.x;
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
-    auto gid = [&](int x, int y, int z) {
-        return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    };
+    auto gid = [&](int x, int y, int z) { return eidx(g, x, y, z); };
     for (int t = threadIdx.x; t < 6 * 64; t += blockDim.x) {
         const int d = t / 64, f = t % 64;
         const int ax = d >> 1;

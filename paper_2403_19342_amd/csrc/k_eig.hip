@@ -711,9 +711,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int c = threadIdx.x;
     const int i = c & 7, j = (c >> 3) & 7, k = c >> 6;
-    auto gid = [&](int x, int y, int z) {
-        return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    };
+    auto gid = [&](int x, int y, int z) { return eidx(g, x, y, z); };
     // kappa~ per face direction: one array (isotropic) or three (orthotropic)
     const size_t N = g.ortho ? g.ncell() : 0;
     const size_t gc = gid(ex * 8 + i, ey * 8 + j, ez * 8 + k);

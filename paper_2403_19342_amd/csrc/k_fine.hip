@@ -108,123 +108,15 @@ __device__ __forceinline__ bool halo_cell(const FineGeom& g, int h, int x0, int 
     const int hx = h % TT::LX;
     const int r = h / TT::LX;
     const int x = x0 + hx - 1, y = y0 + (r % 10) - 1, z = z0 + (r / 10) - 1;
-    gi = gidx(g, x, y, z);
+    const bool in = h < TT::NH && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
+    gi = in ? eidx(g, x, y, z) : 0;
     ph = hx + TT::HX * r;
-    return h < TT::NH && x >= 0 && x < g.nx && y >= 0 && y < g.ny && z >= 0 && z < g.nz;
-}
-
-template <int EX, typename S1, typename D1, typename S2, typename D2>
-__device__ __forceinline__ void load_halo2(const FineGeom& g, const S1* __restrict__ a, D1* da,
-                                           const S2* __restrict__ b, D2* db, int x0, int y0, int z0) {
-    using TT = TileT<EX>;
-    constexpr int IT = (TT::NH + TT::NT - 1) / TT::NT;
-    D1 va[IT];
-    D2 vb[IT];
-    int pp[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        size_t gi;
-        const bool in = halo_cell<EX>(g, threadIdx.x + it * TT::NT, x0, y0, z0, gi, pp[it]);
-        va[it] = in ? (D1)a[gi] : D1(0);
-        vb[it] = in ? (D2)b[gi] : D2(0);
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int h = threadIdx.x + it * TT::NT;
-        if (h < TT::NH) {
-            da[pp[it]] = va[it];
-            db[pp[it]] = vb[it];
-        }
-    }
-}
-
-// (A u) at haloed index h
-template <int EX, typename T>
-__device__ __forceinline__ T apply_stencil(const T* U, const T* K, int h, T cy, T cz) {
-    constexpr int HX = TileT<EX>::HX, HXY = TileT<EX>::HXY;
-    const T uc = U[h], kc = K[h];
-    T a = harm(kc, K[h - 1]) * (uc - U[h - 1]);
-    a += harm(kc, K[h + 1]) * (uc - U[h + 1]);
-    a += harm(kc, K[h - HX]) * cy * (uc - U[h - HX]);
-    a += harm(kc, K[h + HX]) * cy * (uc - U[h + HX]);
-    a += harm(kc, K[h - HXY]) * cz * (uc - U[h - HXY]);
-    a += harm(kc, K[h + HXY]) * cz * (uc - U[h + HXY]);
-    return a;
+    return in;
 }
 
 template <int EX>
 __device__ __forceinline__ int hidx(int x, int y, int z) {
     return (x + 1) + TileT<EX>::HX * ((y + 1) + 10 * (z + 1));
-}
-
-// Forward and backward IC(0) substitution on the element of this wavefront.
-// Y (tile layout, no halo): in t, out (D+L^T)^{-1} D (D+L)^{-1} t.
-// ID: inverse pivots (tile layout).  K: kappa~ in tile layout (HALO = 0) or
-// haloed layout (HALO = 1).  a_ij = -T_ij off the diagonal.
-// Forward and backward IC(0) substitution on the element of each
-// wavefront.  Y (tile layout): in t, out (D+L^T)^{-1} D (D+L)^{-1} t.
-// ID: inverse pivots; Tx, Ty, Tz: transmissibility of the +x, +y, +z face of
-// each cell (a_ij = -T off the diagonal).  Branch-free: neighbour indices are
-// clamped and the products masked, so each hyperplane step is one round of
-// LDS loads followed by fused multiply-adds.
-template <int EX, typename T>
-__device__ __forceinline__ void ic_sweep(T* Y, const T* ID, const T* Tx, const T* Ty, const T* Tz) {
-    constexpr int PX = TileT<EX>::PX;
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    // this lane's cell on every hyperplane (-1: idle), fetched once
-    // (cells packed two per register; 0xFFFF marks an idle lane)
-    unsigned myc[(kPlanes + 1) / 2];
-#pragma unroll
-    for (int s = 0; s < kPlanes; s += 2) {
-        unsigned v = 0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int o = kPT.off[s + h];
-            const int cnt = kPT.off[s + h + 1] - o;
-            const unsigned cell = lane < cnt ? (unsigned)kPT.cell[o + lane] : 0xFFFFu;
-            v |= cell << (16 * h);
-        }
-        myc[s / 2] = v;
-    }
-    // each wavefront sweeps its own element: only wavefront-level ordering
-    // of the LDS accesses is needed between hyperplanes
-#pragma unroll
-    for (int s = 0; s < kPlanes; ++s) {
-        const unsigned cw = (myc[s / 2] >> (16 * (s & 1))) & 0xFFFFu;
-        const int c = cw == 0xFFFFu ? -1 : (int)cw;
-        const int cc = c < 0 ? 0 : c;
-        const int i = cc & 7, j = (cc >> 3) & 7, k = cc >> 6;
-        const int ti = tidx<EX>(8 * w + i, j, k);
-        const int xi = i > 0 ? ti - 1 : ti, yi = j > 0 ? ti - PX : ti, zi = k > 0 ? ti - 8 * PX : ti;
-        const T tx = Tx[xi], ty = Ty[yi], tz = Tz[zi];
-        const T yx = Y[xi], yy = Y[yi], yz = Y[zi];
-        const T y0 = Y[ti], d = ID[ti];
-        T acc = y0;
-        acc += (i > 0 ? tx : T(0)) * yx;
-        acc += (j > 0 ? ty : T(0)) * yy;
-        acc += (k > 0 ? tz : T(0)) * yz;
-        if (c >= 0) Y[ti] = acc * d;
-        wave_lds_sync();
-    }
-#pragma unroll
-    for (int s = kPlanes - 1; s >= 0; --s) {
-        const unsigned cw = (myc[s / 2] >> (16 * (s & 1))) & 0xFFFFu;
-        const int c = cw == 0xFFFFu ? -1 : (int)cw;
-        const int cc = c < 0 ? 0 : c;
-        const int i = cc & 7, j = (cc >> 3) & 7, k = cc >> 6;
-        const int ti = tidx<EX>(8 * w + i, j, k);
-        const int xi = i < 7 ? ti + 1 : ti, yi = j < 7 ? ti + PX : ti, zi = k < 7 ? ti + 8 * PX : ti;
-        const T tx = Tx[ti], ty = Ty[ti], tz = Tz[ti];
-        const T yx = Y[xi], yy = Y[yi], yz = Y[zi];
-        const T y0 = Y[ti], d = ID[ti];
-        T acc = (i < 7 ? tx : T(0)) * yx;
-        acc += (j < 7 ? ty : T(0)) * yy;
-        acc += (k < 7 ? tz : T(0)) * yz;
-        if (c >= 0) Y[ti] = y0 + d * acc;
-        wave_lds_sync();
-    }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -445,7 +337,7 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     tile_origin(g, x0, y0, z0);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = lane & 7, k = lane >> 3, jk = j + k;
-    const size_t row = gidx(g, x0 + 8 * w, y0 + j, z0 + k);   // cell (0, j, k) of the element
+    const size_t row = eidx(g, x0 + 8 * w, y0 + j, z0 + k);   // cell (0, j, k) of the element
     const double alpha = (mode & 1) ? sc->alpha : 0.0;
     // phases in order, each one's registers released before the next
     // (faces first, then the residual update, then the pivots)
@@ -523,14 +415,22 @@ __device__ __forceinline__ void load8(const float* __restrict__ p, double (&v)[8
     }
 }
 
-// The cells beyond the element's four y and z faces (-y, +y, -z, +z), u and
-// kappa~ (the face's own component for orthotropic K), zero outside the
-// domain.  All 64 lanes load them together, one cell per face and array
-// (lane = (x, row) of the face, 64-byte rows), and stage them in the
-// wavefront's LDS area fu[4][64], fk[4][64] for the lanes on those faces.
-template <bool O, typename T, typename C>
-__device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
-                                               int x0, int y0, int z0, int lane, C* fu, C* fk) {
+// 8 contiguous float64 values (the lane's pencil) with 16-byte stores
+__device__ __forceinline__ void store8(double* p, const double (&v)[8]) {
+    double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+
+// The cells beyond the element's four y and z faces (-y, +y, -z, +z): the
+// vector value val(i) (i an element-order index) and kappa~ (the face's own
+// component for orthotropic K), zero outside the domain.  All 64 lanes load
+// them together, one cell per face and array (lane = (x, row) of the face,
+// 64-byte rows), and stage them in the wavefront's LDS area fu[4][64],
+// fk[4][64] for the lanes on those faces.
+template <bool O, typename T, typename C, typename VF>
+__device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __restrict__ kt, VF val, int x0, int y0,
+                                               int z0, int lane, C* fu, C* fk) {
     const int fx = lane & 7, fr = lane >> 3;
     const size_t N = O ? g.ncell() : 0;
     C vu[4], vk[4];
@@ -539,8 +439,8 @@ __device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __res
         const int yy = f < 2 ? (f == 0 ? y0 - 1 : y0 + 8) : y0 + fr;
         const int zz = f < 2 ? z0 + fr : (f == 2 ? z0 - 1 : z0 + 8);
         const bool in = yy >= 0 && yy < g.ny && zz >= 0 && zz < g.nz;
-        const size_t gi = in ? gidx(g, x0 + fx, yy, zz) : 0;
-        vu[f] = in ? (C)u[gi] : C(0);
+        const size_t gi = in ? eidx(g, x0 + fx, yy, zz) : 0;
+        vu[f] = in ? (C)val(gi) : C(0);
         vk[f] = in ? (C)kt[(f < 2 ? N : 2 * N) + gi] : C(0);
     }
 #pragma unroll
@@ -551,29 +451,17 @@ __device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __res
     wave_lds_sync();
 }
 
-// s -= A u on the x-pencil of row (j, k) of an element whose first cell is
-// (x0, y0, z0), natural order; row = index of (x0, y0 + j, z0 + k).  The
-// row's u and kappa~ (kappa~_x for orthotropic K) are returned in uc, kc.
-// y and z neighbours inside the element come from the lanes -+1 and -+8,
-// those beyond the element's faces from the LDS staging area (fu, fk, see
-// stage_faces_yz), the pencil ends in x from memory; every load is issued
-// before the arithmetic, so a wavefront waits for memory once.
-template <bool O, typename T, typename C>
-__device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
-                                                size_t row, int x0, int y0, int z0, int lane, int j, int k,
-                                                C* fu, C* fk, C (&s)[8], C (&uc)[8], C (&kc)[8]) {
-    const size_t N = O ? g.ncell() : 0;   // offsets of the y and z arrays
-    load8(u + row, uc);
-    load8(kt + row, kc);
-    C ky[8], kz[8];
-    if constexpr (O) {
-        load8(kt + N + row, ky);
-        load8(kt + 2 * N + row, kz);
-    }
-    const bool xlo = x0 > 0, xhi = x0 + 8 < g.nx;
-    const C um = xlo ? (C)u[row - 1] : C(0), km = xlo ? (C)kt[row - 1] : C(0);
-    const C up = xhi ? (C)u[row + 8] : C(0), kp = xhi ? (C)kt[row + 8] : C(0);
-    stage_faces_yz<O>(g, kt, u, x0, y0, z0, lane, fu, fk);
+// s -= A u on the x-pencil of row (j, k) of an element, natural order
+// inside the pencil: uc, kc the row's u and kappa~ (kappa~_x for orthotropic
+// K; ky, kz its y and z components), um, km and up, kp u and kappa~ of the
+// cells before and after the pencil in x (used when xlo, xhi: inside the
+// domain), fu, fk the staged y and z face cells (stage_faces_yz).  y and z
+// neighbours inside the element come from the lanes -+1 and -+8.
+template <bool O, typename C>
+__device__ __forceinline__ void pencil_apply(const FineGeom& g, int lane, int j, int k, const C (&uc)[8],
+                                             const C (&kc)[8], const C (&ky)[8], const C (&kz)[8], C um, C km,
+                                             C up, C kp, bool xlo, bool xhi, const C* fu, const C* fk,
+                                             C (&s)[8]) {
     // x faces: inside the pencil, then the two ends
 #pragma unroll
     for (int x = 0; x < 7; ++x) {
@@ -604,6 +492,32 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
     }
 }
 
+// s -= A u on the x-pencil of row (j, k) of the element whose first cell is
+// (x0, y0, z0); row = element-order index of (x0, y0 + j, z0 + k).  The
+// row's u and kappa~ (kappa~_x for orthotropic K) are returned in uc, kc.
+// Every load (the row, the pencil ends in x, the staged faces) is issued
+// before the arithmetic, so a wavefront waits for memory once.
+template <bool O, typename T, typename C>
+__device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
+                                                size_t row, int x0, int y0, int z0, int lane, int j, int k,
+                                                C* fu, C* fk, C (&s)[8], C (&uc)[8], C (&kc)[8]) {
+    const size_t N = O ? g.ncell() : 0;   // offsets of the y and z arrays
+    load8(u + row, uc);
+    load8(kt + row, kc);
+    C ky[8], kz[8];
+    if constexpr (O) {
+        load8(kt + N + row, ky);
+        load8(kt + 2 * N + row, kz);
+    }
+    const bool xlo = x0 > 0, xhi = x0 + 8 < g.nx;
+    const size_t im = xlo ? eidx(g, x0 - 1, y0 + j, z0 + k) : row;
+    const size_t ip = xhi ? eidx(g, x0 + 8, y0 + j, z0 + k) : row;
+    const C um = xlo ? (C)u[im] : C(0), km = xlo ? (C)kt[im] : C(0);
+    const C up = xhi ? (C)u[ip] : C(0), kp = xhi ? (C)kt[ip] : C(0);
+    stage_faces_yz<O>(g, kt, [&](size_t i) { return u[i]; }, x0, y0, z0, lane, fu, fk);
+    pencil_apply<O>(g, lane, j, k, uc, kc, ky, kz, um, km, up, kp, xlo, xhi, fu, fk, s);
+}
+
 // T: stored word of kappa~ and u; TB: stored word of the basis; C: the
 // arithmetic and the word of the level-2 residual r2
 template <typename T, typename TB, typename C, bool O>
@@ -623,8 +537,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     if (e >= m) return;   // whole wavefront; no block barriers below
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int j = lane & 7, k = lane >> 3;
-    const int x0 = ex * 8, y = ey * 8 + j, z = ez * 8 + k;
-    const size_t row = (size_t)x0 + (size_t)g.nx * ((size_t)y + (size_t)g.ny * z);
+    const int x0 = ex * 8;
+    const size_t row = (size_t)e * kSub3 + 8 * lane;
     C s[8];
     {
         const double2* q = reinterpret_cast<const double2*>(r + row);
@@ -670,7 +584,6 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
                                                   int check_done) {
     if (check_done && sc->done) return;
     const int e = blockIdx.x;
-    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int nk = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3;
     const C* ee = e2 + (size_t)e * L;
@@ -681,7 +594,7 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
             const int jc = jj < nk ? jj : nk - 1;
             acc += (jj < nk ? (C)ph[(size_t)jc * kSub3 + c] : C(0)) * ee[jc];
         }
-        const size_t gi = gidx(g, ex * 8 + (c & 7), ey * 8 + ((c >> 3) & 7), ez * 8 + (c >> 6));
+        const size_t gi = (size_t)e * kSub3 + c;
         u[gi] = (T)((C)u[gi] + acc);
     }
 }
@@ -706,7 +619,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int j = lane & 7, k = lane >> 3, jk = j + k;
     const int ex0 = x0 + 8 * w;
-    const size_t row = gidx(g, ex0, y0 + j, z0 + k);
+    const size_t row = eidx(g, ex0, y0 + j, z0 + k);
     C s[8], uc[8], kc[8];
     {
         double rv[8];
@@ -758,177 +671,99 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
     }
 }
 
-// One CG step of the fused direction update: p = z + beta p_old (p = z on
-// the first iteration), q = A p, x += alpha_x p_old (the x update deferred
-// from the previous iteration) and the block sums of p.q.  A block owns 64 x
-// kSpY columns and marches kSpZ planes in z.  Each plane's p and kappa~ are
-// staged in a double-buffered LDS tile with a one-cell halo in x and y, so
-// p is formed once per cell; the z neighbours stay in registers, and the
-// next plane's values are loaded before the current plane's barrier.  Block
-// ids are remapped so that each XCD walks a contiguous range of tiles.
-constexpr int kSpY = 4, kSpZ = 8;
-
-// O (orthotropic K): the x faces read kappa~_x from the LDS tile, the y
-// faces kappa~_y from a second tile, the z faces kappa~_z from registers.
-template <bool O>
-__global__ __launch_bounds__(64 * kSpY) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
-                                                       const double* __restrict__ zv,
-                                                       const double* __restrict__ pold,
-                                                       double* __restrict__ pnew, double* __restrict__ x,
-                                                       double* __restrict__ q, Scalars* sc, RedBuf rb, int first,
-                                                       int pbuf) {
-    if (sc->done) return;
-    __shared__ double sp[2][kSpY + 2][66];
-    __shared__ double sk[2][kSpY + 2][66];
-    __shared__ double sky[O ? 2 : 1][O ? kSpY + 2 : 1][O ? 66 : 1];
-    __shared__ double sred[kSpY];
-    const size_t N = O ? g.ncell() : 0;
-    const double* kty = kt + N;          // y array (orthotropic; kt itself otherwise)
-    const double* ktz = kt + 2 * N;      // z array
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nb = gridDim.x * gridDim.y * gridDim.z;
-    int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+// Element of the wavefront in kernels that run four level-2 elements per
+// 256-thread block (block ids remapped so that each XCD walks a contiguous
+// range of elements).
+__device__ __forceinline__ int block_element4() {
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
     if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    const int bx = b % gridDim.x, by = (b / gridDim.x) % gridDim.y, bz = b / (gridDim.x * gridDim.y);
-    const int xi = bx * 64 + lane, yi = by * kSpY + w, z0 = bz * kSpZ;
-    const bool in = xi < nx;
-    const int xc = in ? xi : nx - 1;
-    const double beta = first ? 0.0 : sc->beta;
-    const double ax = first ? 0.0 : sc->alpha_x;
-    const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-    // halo duties: waves 0 and kSpY-1 also carry rows y0-1 and y0+kSpY,
-    // lanes 0 and 63 columns x0-1 and x0+64 (zero outside the domain)
-    const bool hrow_w = (w == 0 || w == kSpY - 1);
-    const int hy = (w == 0) ? yi - 1 : yi + 1;
-    const bool hyv = in && hrow_w && hy >= 0 && hy < ny;
-    const int hx = (lane == 0) ? xi - 1 : xi + 1;
-    const bool hcol_l = (lane == 0 || lane == 63);
-    const bool hxv = hcol_l && hx >= 0 && hx < nx;
-    const int hrow = (w == 0) ? 0 : kSpY + 1;
-    const int hcol = (lane == 0) ? 0 : 65;
-    size_t gi = (size_t)xc + sy * yi + sz * z0;
-    const size_t ghy = (size_t)xc + sy * (hyv ? hy : yi) + sz * z0;
-    const size_t ghx = (size_t)(hxv ? hx : xc) + sy * yi + sz * z0;
-    auto pval = [&](size_t i) { return first ? zv[i] : zv[i] + beta * pold[i]; };
-    double po = (in && !first) ? pold[gi] : 0.0;
-    double pc = in ? (first ? zv[gi] : zv[gi] + beta * po) : 0.0, kc = in ? kt[gi] : 0.0;
-    double pyh = hyv ? pval(ghy) : 0.0, kyh = hyv ? kty[ghy] : 0.0;
-    double pxh = hxv ? pval(ghx) : 0.0, kxh = hxv ? kt[ghx] : 0.0;
-    double pm = (in && z0 > 0) ? pval(gi - sz) : 0.0, km = (in && z0 > 0) ? ktz[gi - sz] : 0.0;
-    // orthotropic: this cell's y and z components (isotropic: kc itself)
-    double kcy = (O && in) ? kty[gi] : 0.0, kcz = (O && in) ? ktz[gi] : 0.0;
-    // x of the deferred update x += alpha p_old, loaded a plane ahead like
-    // the stencil operands (loaded and used in the same plane, its latency
-    // was exposed once per plane)
-    double xv = (in && ax != 0.0) ? x[gi] : 0.0;
+    return b * 4 + (threadIdx.x >> 6);
+}
+
+// First half of a CG step: p = z + beta p_old (p = z on the first
+// iteration) and x += alpha_x p_old (the x update deferred from the
+// previous iteration), one double2 per thread.
+__global__ __launch_bounds__(256) void k_p_update(const double2* __restrict__ z, const double2* __restrict__ pold,
+                                                  double2* __restrict__ pnew, double2* __restrict__ x,
+                                                  const Scalars* sc, int first, int64_t n2) {
+    if (sc->done) return;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    double2 p = z[i];
+    if (!first) {
+        const double beta = sc->beta, ax = sc->alpha_x;
+        const double2 po = pold[i];
+        p.x += beta * po.x;
+        p.y += beta * po.y;
+        if (ax != 0.0) {
+            double2 xv = x[i];
+            xv.x += ax * po.x;
+            xv.y += ax * po.y;
+            x[i] = xv;
+        }
+    }
+    pnew[i] = p;
+}
+
+// Second half: q = A p and the block sums of p.q, one level-2 element per
+// wavefront (pencil_residual with a zero right-hand side).
+template <bool O>
+__global__ __launch_bounds__(256) void k_spmv_pcg(FineGeom g, const double* __restrict__ kt,
+                                                  const double* __restrict__ p, double* __restrict__ q,
+                                                  Scalars* sc, RedBuf rb, int pbuf) {
+    if (sc->done) return;
+    __shared__ double sfu[4][256], sfk[4][256];
+    __shared__ double sred[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = block_element4();
     double pq = 0.0;
-    for (int zz = 0; zz < kSpZ; ++zz, gi += sz) {
-        const int buf = zz & 1;
-        sp[buf][w + 1][lane + 1] = pc;
-        sk[buf][w + 1][lane + 1] = kc;
-        if constexpr (O) sky[buf][w + 1][lane + 1] = kcy;
-        if (hrow_w) {
-            sp[buf][hrow][lane + 1] = pyh;
-            if constexpr (O) sky[buf][hrow][lane + 1] = kyh;
-            else sk[buf][hrow][lane + 1] = kyh;
+    if (e < g.mx * g.my * g.mz) {   // whole wavefront; the block sum below is reached by all
+        const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+        const int j = lane & 7, k = lane >> 3;
+        const size_t row = (size_t)e * kSub3 + 8 * lane;
+        double s[8], pc[8], kc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = 0.0;
+        pencil_residual<O>(g, kt, p, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, pc, kc);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            s[i] = -s[i];
+            pq += pc[i] * s[i];
         }
-        if (hcol_l) {
-            sp[buf][w + 1][hcol] = pxh;
-            sk[buf][w + 1][hcol] = kxh;
-        }
-        // the next plane, in flight across the barrier
-        const bool zp = z0 + zz + 1 < nz;
-        const size_t o = (size_t)(zz + 1) * sz;
-        const double pon = (in && zp && !first) ? pold[gi + sz] : 0.0;
-        const double pp = (in && zp) ? (first ? zv[gi + sz] : zv[gi + sz] + beta * pon) : 0.0;
-        const double kp = (in && zp) ? ktz[gi + sz] : 0.0;
-        const double kpx = (O && in && zp) ? kt[gi + sz] : 0.0, kpy = (O && in && zp) ? kty[gi + sz] : 0.0;
-        const double xvn = (in && zp && ax != 0.0 && zz + 1 < kSpZ) ? x[gi + sz] : 0.0;
-        double pyh2 = 0.0, kyh2 = 0.0, pxh2 = 0.0, kxh2 = 0.0;
-        if (zz + 1 < kSpZ && zp) {
-            if (hyv) {
-                pyh2 = pval(ghy + o);
-                kyh2 = kty[ghy + o];
-            }
-            if (hxv) {
-                pxh2 = pval(ghx + o);
-                kxh2 = kt[ghx + o];
-            }
-        }
-        __syncthreads();
-        const double pxm = sp[buf][w + 1][lane], kxm = sk[buf][w + 1][lane];
-        const double pxp = sp[buf][w + 1][lane + 2], kxp = sk[buf][w + 1][lane + 2];
-        const double pym = sp[buf][w][lane + 1], kym = O ? sky[buf][w][lane + 1] : sk[buf][w][lane + 1];
-        const double pyp = sp[buf][w + 2][lane + 1], kyp = O ? sky[buf][w + 2][lane + 1] : sk[buf][w + 2][lane + 1];
-        const double ky0 = O ? kcy : kc, kz0 = O ? kcz : kc;
-        double a = harm(kc, kxm) * (pc - pxm);
-        a += harm(kc, kxp) * (pc - pxp);
-        a += harm(ky0, kym) * g.cy * (pc - pym);
-        a += harm(ky0, kyp) * g.cy * (pc - pyp);
-        a += harm(kz0, km) * g.cz * (pc - pm);
-        a += harm(kz0, kp) * g.cz * (pc - pp);
-        if (in) {
-            if (ax != 0.0) x[gi] = xv + ax * po;
-            pnew[gi] = pc;
-            q[gi] = a;
-            pq += pc * a;
-        }
-        pm = pc;
-        km = O ? kcz : kc;
-        pc = pp;
-        if constexpr (O) {
-            kc = kpx;
-            kcy = kpy;
-            kcz = kp;
-        } else {
-            kc = kp;
-        }
-        po = pon;
-        xv = xvn;
-        pyh = pyh2;
-        kyh = kyh2;
-        pxh = pxh2;
-        kxh = kxh2;
+        store8(q + row, s);
     }
     double v[1] = {block_sum(pq, sred)};
     write_partials<1>(v, rb);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->pbuf = pbuf;
 }
 
-// y = A x  (resid = 0)   or   y = b - A x  (resid = 1); O: orthotropic K
-// (kappa~_y and kappa~_z in two more haloed tiles)
-template <int EX, bool O>
-__global__ __launch_bounds__(64 * EX) void k_apply_A(FineGeom g, const double* __restrict__ kt,
-                                                     const double* __restrict__ xv,
-                                                     const double* __restrict__ b,
-                                                     double* __restrict__ y, int resid) {
-    using TT = TileT<EX>;
-    __shared__ double sX[TT::NHP];
-    __shared__ double sK[TT::NHP];
-    __shared__ double sKy[O ? TT::NHP : 1];
-    __shared__ double sKz[O ? TT::NHP : 1];
-    int x0, y0, z0;
-    tile_origin(g, x0, y0, z0);
-    load_halo2<EX>(g, xv, sX, kt, sK, x0, y0, z0);
-    if constexpr (O) load_halo2<EX>(g, kt + g.ncell(), sKy, kt + 2 * g.ncell(), sKz, x0, y0, z0);
-    __syncthreads();
-    const int tx = threadIdx.x % TT::TX, ty = threadIdx.x / TT::TX;
-    for (int zz = 0; zz < 8; ++zz) {
-        const int h = hidx<EX>(tx, ty, zz);
-        const size_t gi = gidx(g, x0 + tx, y0 + ty, z0 + zz);
-        double a;
-        if constexpr (O) {
-            constexpr int HX = TT::HX, HXY = TT::HXY;
-            const double uc = sX[h];
-            a = harm(sK[h], sK[h - 1]) * (uc - sX[h - 1]) + harm(sK[h], sK[h + 1]) * (uc - sX[h + 1]);
-            a += harm(sKy[h], sKy[h - HX]) * (uc - sX[h - HX]) + harm(sKy[h], sKy[h + HX]) * (uc - sX[h + HX]);
-            a += harm(sKz[h], sKz[h - HXY]) * (uc - sX[h - HXY]) + harm(sKz[h], sKz[h + HXY]) * (uc - sX[h + HXY]);
-        } else {
-            a = apply_stencil<EX, double>(sX, sK, h, g.cy, g.cz);
-        }
-        y[gi] = resid ? b[gi] - a : a;
+// y = A x (resid = 0) or y = b - A x (resid = 1), element order; O:
+// orthotropic K
+template <bool O>
+__global__ __launch_bounds__(256) void k_apply_A(FineGeom g, const double* __restrict__ kt,
+                                                 const double* __restrict__ xv, const double* __restrict__ b,
+                                                 double* __restrict__ y, int resid) {
+    __shared__ double sfu[4][256], sfk[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int e = block_element4();
+    if (e >= g.mx * g.my * g.mz) return;   // whole wavefront; no block barriers
+    const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
+    const int j = lane & 7, k = lane >> 3;
+    const size_t row = (size_t)e * kSub3 + 8 * lane;
+    double s[8], uc[8], kc[8];
+    if (resid) {
+        load8(b + row, s);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = 0.0;
     }
+    pencil_residual<O>(g, kt, xv, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
+    if (!resid) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[i] = -s[i];
+    }
+    store8(y + row, s);
 }
 
 // IC(0) pivots of every 8^3 block: d_i = a_ii - sum_{j<i} a_ij^2 / d_j, with
@@ -984,37 +819,58 @@ __global__ __launch_bounds__(64 * EX) void k_ic_setup(FineGeom g, const double* 
     }
     for (int c = threadIdx.x; c < TT::NC; c += TT::NT) {
         const int x = c % TX, y = (c / TX) & 7, z = c / (TX * 8);
-        const size_t gi = gidx(g, x0 + x, y0 + y, z0 + z);
+        const size_t gi = eidx(g, x0 + x, y0 + y, z0 + z);
         const double v = 1.0 / sDg[c];
         invd[gi] = v;
         if (invd32) invd32[gi] = (float)v;
     }
 }
 
-__global__ void k_perm_to_kt(const double* __restrict__ perm, double* __restrict__ kt, float* kt32,
-                             double scale, int64_t n, int* bad) {
+// kappa~ = perm * scale, read in natural order and written in element order
+__global__ void k_perm_to_kt(FineGeom g, const double* __restrict__ perm, double* __restrict__ kt, float* kt32,
+                             double scale, int* bad) {
+    const int64_t n = (int64_t)g.ncell();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double p = perm[i];
         if (!(p > 0.0) || !isfinite(p)) atomicOr(bad, 1);
         const double v = p * scale;
-        kt[i] = v;
-        if (kt32) kt32[i] = (float)v;
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((int64_t)g.nx * g.ny));
+        const size_t ei = eidx(g, x, y, z);
+        kt[ei] = v;
+        if (kt32) kt32[ei] = (float)v;
     }
 }
-
-__global__ void k_perm3_to_kt(const double* __restrict__ perm, double* __restrict__ kt, double sx, double sy,
-                              double sz, int64_t n, int* bad) {
+__global__ void k_perm3_to_kt(FineGeom g, const double* __restrict__ perm, double* __restrict__ kt, double sx,
+                              double sy, double sz, int* bad) {
+    const int64_t n = (int64_t)g.ncell();
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double p = perm[i];
         if (!(p > 0.0) || !isfinite(p)) atomicOr(bad, 1);
-        kt[i] = p * (i < n ? sx : (i < 2 * n ? sy : sz));
+        const int64_t d = i / n, c = i - d * n;
+        const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((int64_t)g.nx * g.ny));
+        kt[(size_t)d * n + eidx(g, x, y, z)] = p * (d == 0 ? sx : (d == 1 ? sy : sz));
+    }
+}
+// one cell array between natural order and element order
+__global__ void k_to_elem(FineGeom g, const double* __restrict__ nat, double* __restrict__ el) {
+    const int64_t n = (int64_t)g.ncell();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((int64_t)g.nx * g.ny));
+        el[eidx(g, x, y, z)] = nat[i];
+    }
+}
+__global__ void k_to_natural(FineGeom g, const double* __restrict__ el, double* __restrict__ nat) {
+    const int64_t n = (int64_t)g.ncell();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % g.nx), y = (int)((i / g.nx) % g.ny), z = (int)(i / ((int64_t)g.nx * g.ny));
+        nat[i] = el[eidx(g, x, y, z)];
     }
 }
 
-// ---------------------------------------------------------------------------
-// vector utilities
 __global__ __launch_bounds__(256) void k_dot(const double* __restrict__ a, const double* __restrict__ b,
                                               int64_t n, RedBuf rb) {
     __shared__ double sred[4];
@@ -1225,29 +1081,30 @@ void launch_post_fused(const FineGeom& g, const T* kt, const T* invd, const T* u
     if (mode & 1) launch_finalize(RS_RZ, g.ntiles, sc, rb, nullptr, (mode & 2) ? 1 : 0, s);
 }
 
-void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* z, const double* pold,
-                     double* pnew, double* x, double* q, Scalars* sc, RedBuf rb, int first, hipStream_t s) {
-    // pnew is buffer index 0 or 1 as chosen by the caller; recorded for the
-    // final x update
-    const int pbuf = first & 2 ? 1 : 0;
-    const int f = first & 1;
-    if (g.ny % kSpY || g.nz % kSpZ) throw HipError{hipErrorInvalidValue, "spmv tiling"};
-    const dim3 grid((g.nx + 63) / 64, g.ny / kSpY, g.nz / kSpZ);
-    const int nblocks = (int)(grid.x * grid.y * grid.z);
+void launch_p_update(const FineGeom& g, const double* z, const double* pold, double* pnew, double* x, Scalars* sc,
+                     int first, hipStream_t s) {
+    const int64_t n2 = (int64_t)g.ncell() / 2;
+    SPECMG_TIMED_LAUNCH(k_p_update, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s,
+                        reinterpret_cast<const double2*>(z), reinterpret_cast<const double2*>(pold),
+                        reinterpret_cast<double2*>(pnew), reinterpret_cast<double2*>(x), sc, first, n2);
+}
+
+void launch_spmv_pcg(const FineGeom& g, const double* kt, const double* p, double* q, Scalars* sc, RedBuf rb,
+                     int pbuf, hipStream_t s) {
+    const int nblocks = (g.mx * g.my * g.mz + 3) / 4;
     if (nblocks > kMaxRedBlocks) throw HipError{hipErrorInvalidValue, "spmv grid too large for the reduction buffer"};
     if (g.ortho)
-        SPECMG_TIMED_LAUNCH(k_spmv_pcg<true>, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f, pbuf);
+        SPECMG_TIMED_LAUNCH(k_spmv_pcg<true>, dim3(nblocks), dim3(256), 0, s, g, kt, p, q, sc, rb, pbuf);
     else
-        SPECMG_TIMED_LAUNCH(k_spmv_pcg<false>, grid, dim3(64 * kSpY), 0, s, g, kt, z, pold, pnew, x, q, sc, rb, f,
-                            pbuf);
+        SPECMG_TIMED_LAUNCH(k_spmv_pcg<false>, dim3(nblocks), dim3(256), 0, s, g, kt, p, q, sc, rb, pbuf);
     launch_finalize(RS_PQ, nblocks, sc, rb, nullptr, 1, s);
 }
 
 void launch_apply_A(const FineGeom& g, const double* kt, const double* x, const double* b, double* y,
                     int resid, hipStream_t s) {
-    SPECMG_O_DISPATCH(double, SPECMG_EX_DISPATCH(g.ex, hipLaunchKernelGGL((k_apply_A<EX, O>), dim3(g.ntiles),
-                                                                           dim3(64 * EX), 0, s, g, kt, x, b, y,
-                                                                           resid)));
+    const int m = g.mx * g.my * g.mz;
+    if (g.ortho) hipLaunchKernelGGL(k_apply_A<true>, dim3((m + 3) / 4), dim3(256), 0, s, g, kt, x, b, y, resid);
+    else hipLaunchKernelGGL(k_apply_A<false>, dim3((m + 3) / 4), dim3(256), 0, s, g, kt, x, b, y, resid);
 }
 
 void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* invd32, int* bad,
@@ -1256,14 +1113,24 @@ void launch_ic_setup(const FineGeom& g, const double* kt, double* invd, float* i
                                                 kt, invd, invd32, bad));
 }
 
-void launch_perm3_to_kt(const double* perm, double* kt, double sx, double sy, double sz, int64_t n, int* bad,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_perm3_to_kt, dim3(grid_1d(3 * n)), dim3(256), 0, s, perm, kt, sx, sy, sz, n, bad);
+void launch_perm3_to_kt(const FineGeom& g, const double* perm, double* kt, double sx, double sy, double sz,
+                        int* bad, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm3_to_kt, dim3(grid_1d(3 * (int64_t)g.ncell())), dim3(256), 0, s, g, perm, kt, sx, sy,
+                       sz, bad);
 }
 
-void launch_perm_to_kt(const double* perm, double* kt, float* kt32, double scale, int64_t n, int* bad,
+void launch_perm_to_kt(const FineGeom& g, const double* perm, double* kt, float* kt32, double scale, int* bad,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_to_kt, dim3(grid_1d(n)), dim3(256), 0, s, perm, kt, kt32, scale, n, bad);
+    hipLaunchKernelGGL(k_perm_to_kt, dim3(grid_1d((int64_t)g.ncell())), dim3(256), 0, s, g, perm, kt, kt32, scale,
+                       bad);
+}
+
+void launch_to_elem(const FineGeom& g, const double* nat, double* el, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_elem, dim3(grid_1d((int64_t)g.ncell())), dim3(256), 0, s, g, nat, el);
+}
+
+void launch_to_natural(const FineGeom& g, const double* el, double* nat, hipStream_t s) {
+    hipLaunchKernelGGL(k_to_natural, dim3(grid_1d((int64_t)g.ncell())), dim3(256), 0, s, g, el, nat);
 }
 
 void launch_dot(const double* a, const double* b, int64_t n, double* out, RedBuf rb, int site,

@@ -16,21 +16,24 @@ __device__ __forceinline__ double face_harm(double a, double b) {
     return s > 0.0 ? (2.0 * a * b) / s : 0.0;
 }
 
-// ortho: kt holds kappa_d / h_d^2 for d = x, y, z in three arrays of n values
-// (cy = cz = 1); otherwise one array kappa / hx^2
-__global__ __launch_bounds__(256) void k_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy,
-                                              double cz, const double* __restrict__ kt, int ortho,
-                                              const double* __restrict__ p, double* __restrict__ vx,
-                                              double* __restrict__ vy, double* __restrict__ vz) {
+// kt is in element order (eidx): kappa_d / h_d^2 for d = x, y, z in three
+// arrays (g.ortho, cy = cz = 1), otherwise one array kappa / hx^2; p and the
+// fluxes are in natural order
+__global__ __launch_bounds__(256) void k_flux(FineGeom g, double hx, double hy, double hz,
+                                              const double* __restrict__ kt, const double* __restrict__ p,
+                                              double* __restrict__ vx, double* __restrict__ vy,
+                                              double* __restrict__ vz) {
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny, n = sz * nz;
-    const double* ky = ortho ? kt + n : kt;
-    const double* kz = ortho ? kt + 2 * n : kt;
+    const double* ky = g.ortho ? kt + n : kt;
+    const double* kz = g.ortho ? kt + 2 * n : kt;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int x = (int)(i % nx), y = (int)((i / sy) % ny), z = (int)(i / sz);
         const double pc = p[i];
-        vx[i] = x + 1 < nx ? -hx * face_harm(kt[i], kt[i + 1]) * (p[i + 1] - pc) : 0.0;
-        vy[i] = y + 1 < ny ? -hy * (face_harm(ky[i], ky[i + sy]) * cy) * (p[i + sy] - pc) : 0.0;
-        vz[i] = z + 1 < nz ? -hz * (face_harm(kz[i], kz[i + sz]) * cz) * (p[i + sz] - pc) : 0.0;
+        const size_t ei = eidx(g, x, y, z);
+        vx[i] = x + 1 < nx ? -hx * face_harm(kt[ei], kt[eidx(g, x + 1, y, z)]) * (p[i + 1] - pc) : 0.0;
+        vy[i] = y + 1 < ny ? -hy * (face_harm(ky[ei], ky[eidx(g, x, y + 1, z)]) * g.cy) * (p[i + sy] - pc) : 0.0;
+        vz[i] = z + 1 < nz ? -hz * (face_harm(kz[ei], kz[eidx(g, x, y, z + 1)]) * g.cz) * (p[i + sz] - pc) : 0.0;
     }
 }
 
@@ -53,10 +56,10 @@ static int flux_blocks(int64_t n) {
     return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
 }
 
-void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
-                 int ortho, const double* p, double* vx, double* vy, double* vz, hipStream_t s) {
-    hipLaunchKernelGGL(k_flux, dim3(flux_blocks((int64_t)nx * ny * nz)), dim3(256), 0, s, nx, ny, nz, hx, hy, hz, cy,
-                       cz, kt, ortho, p, vx, vy, vz);
+void launch_flux(const FineGeom& g, double hx, double hy, double hz, const double* kt, const double* p, double* vx,
+                 double* vy, double* vz, hipStream_t s) {
+    hipLaunchKernelGGL(k_flux, dim3(flux_blocks((int64_t)g.ncell())), dim3(256), 0, s, g, hx, hy, hz, kt, p, vx, vy,
+                       vz);
 }
 
 void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,

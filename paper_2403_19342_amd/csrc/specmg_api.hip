@@ -106,8 +106,11 @@ struct specmg_ctx {
     double *sym_P = nullptr, *sym_Q = nullptr;   // column and row partial sums of the tiles
     int* cmap = nullptr;
     double* rc = nullptr;       // coarsest right-hand side, compact
-    // CG state
+    // CG state (element order, see eidx)
     double *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr, *u1 = nullptr;
+    // the caller's source and solution in element order (and the scratch of
+    // apply_precond / apply_operator)
+    double *b_e = nullptr, *x_e = nullptr;
     float* u1_32 = nullptr;
     double* dtmp = nullptr;     // scratch scalars
     int* dflag = nullptr;       // error flags
@@ -171,7 +174,7 @@ double now_ms() {
 // dispatch); prof_begin_range / prof_end record plain events around a group
 // of launches (the coarse levels).
 enum ProfClass { PC_SPMV = 0, PC_PRE = 1, PC_RESTRICT = 2, PC_PROLONG = 3, PC_POST = 4, PC_COARSE = 5,
-                 PC_COARSEST = 6 };   // slot 7 is unused (zero)
+                 PC_COARSEST = 6, PC_PUPDATE = 7 };
 
 static size_t prof_events(specmg_ctx* c) {
     if (c->ev_used + 2 > c->ev_pool.size()) {
@@ -426,10 +429,10 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     }
     const double h = G.hx;
     if (fg.ortho)
-        launch_perm3_to_kt(perm, c->kt, 1.0 / (G.hx * G.hx), 1.0 / (G.hy * G.hy), 1.0 / (G.hz * G.hz), c->n,
+        launch_perm3_to_kt(fg, perm, c->kt, 1.0 / (G.hx * G.hx), 1.0 / (G.hy * G.hy), 1.0 / (G.hz * G.hz),
                            c->dflag, s);
     else
-        launch_perm_to_kt(perm, c->kt, c->kt32, 1.0 / (h * h), c->n, c->dflag, s);
+        launch_perm_to_kt(fg, perm, c->kt, c->kt32, 1.0 / (h * h), c->dflag, s);
     int flags[8];
     HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -655,6 +658,8 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->q = c->alloc<double>(c->n);
     c->u1 = c->alloc<double>(c->n);
     if (c->fp32 || c->fp32_store) c->u1_32 = c->alloc<float>(c->n);
+    c->b_e = c->alloc<double>(c->n);
+    c->x_e = c->alloc<double>(c->n);
     c->dtmp = c->alloc<double>(8);
     c->sc = c->alloc<Scalars>(1);
     HIPCHK(hipHostMalloc((void**)&c->sc_host, sizeof(Scalars), hipHostMallocDefault));
@@ -779,7 +784,10 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
 extern "C" int specmg_apply_operator(specmg_ctx* c, const double* x, double* y, void* stream) {
     if (!c || !x || !y) return fail(SPECMG_EINVAL, "null argument");
     try {
-        launch_apply_A(c->fg, c->kt, x, nullptr, y, 0, (hipStream_t)stream);
+        const hipStream_t s = (hipStream_t)stream;
+        launch_to_elem(c->fg, x, c->b_e, s);
+        launch_apply_A(c->fg, c->kt, c->b_e, nullptr, c->x_e, 0, s);
+        launch_to_natural(c->fg, c->x_e, y, s);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -791,7 +799,10 @@ extern "C" int specmg_apply_precond(specmg_ctx* c, const double* r, double* z, v
     if (!c || !r || !z) return fail(SPECMG_EINVAL, "null argument");
     if (r == z) return fail(SPECMG_EINVAL, "r and z must not alias");
     try {
-        run_vcycle(c, const_cast<double*>(r), z, nullptr, 0, 0, 0, (hipStream_t)stream);
+        const hipStream_t s = (hipStream_t)stream;
+        launch_to_elem(c->fg, r, c->b_e, s);
+        run_vcycle(c, c->b_e, c->x_e, nullptr, 0, 0, 0, s);
+        launch_to_natural(c->fg, c->x_e, z, s);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -816,7 +827,7 @@ static double dev_dot(specmg_ctx* c, const double* a, const double* b, hipStream
 
 __global__ void k_reset_done(Scalars* sc) { sc->done = 0; }
 
-static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, double tol, int max_iter,
+static int do_solve(specmg_ctx* c, const double* b_nat, double* x_nat, int use_x0, double tol, int max_iter,
                     specmg_solve_info* info, hipStream_t s) {
     const double t0 = now_ms();
     const int64_t n = c->n;
@@ -828,19 +839,24 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
     si.converged = 0;
     si.replacements = 0;
     // compatibility of the source: |sum f| <= 1e-12 sum |f|
-    launch_sum_abs(b, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    launch_sum_abs(b_nat, n, c->dtmp, c->dtmp + 1, c->rb, s);
     double sa[2];
     HIPCHK(hipMemcpyAsync(sa, c->dtmp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (std::fabs(sa[0]) > 1e-12 * sa[1]) return fail(SPECMG_ERHS, "source does not sum to zero");
-    const double nb = std::sqrt(dev_dot(c, b, b, s));
+    const double nb = std::sqrt(dev_dot(c, b_nat, b_nat, s));
     if (nb == 0.0) {
-        launch_fill(x, 0.0, n, s);
+        launch_fill(x_nat, 0.0, n, s);
         si.converged = 1;
         si.solve_ms = now_ms() - t0;
         if (info) *info = si;
         return SPECMG_OK;
     }
+    // the solve runs in element order
+    const double* b = c->b_e;
+    double* x = c->x_e;
+    launch_to_elem(c->fg, b_nat, c->b_e, s);
+    if (use_x0) launch_to_elem(c->fg, x_nat, c->x_e, s);
     if (use_x0) launch_apply_A(c->fg, c->kt, x, b, c->r, 1, s);
     else {
         launch_fill(x, 0.0, n, s);
@@ -865,8 +881,11 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
             const int first = (k == 0) ? 1 : 0;
             const int pb = k & 1;
             c->cur_iter = k + 1;
-            const size_t ev = prof_begin(c, s);
-            launch_spmv_pcg(c->fg, c->kt, c->z, c->p[pb ^ 1], c->p[pb], x, c->q, c->sc, c->rb, first | (pb << 1), s);
+            size_t ev = prof_begin(c, s);
+            launch_p_update(c->fg, c->z, c->p[pb ^ 1], c->p[pb], x, c->sc, first, s);
+            prof_end(c, ev, PC_PUPDATE, s);
+            ev = prof_begin(c, s);
+            launch_spmv_pcg(c->fg, c->kt, c->p[pb], c->q, c->sc, c->rb, pb, s);
             prof_end(c, ev, PC_SPMV, s);
             run_vcycle(c, c->r, c->z, c->q, 1 | 2, 1 | 2, 1, s);
         }
@@ -906,6 +925,7 @@ static int do_solve(specmg_ctx* c, const double* b, double* x, int use_x0, doubl
     launch_sum_abs(x, n, c->dtmp, c->dtmp + 1, c->rb, s);
     launch_sub_mean(x, n, c->dtmp, s);
     launch_apply_A(c->fg, c->kt, x, b, c->q, 1, s);
+    launch_to_natural(c->fg, x, x_nat, s);
     si.rel_resid_true = std::sqrt(dev_dot(c, c->q, c->q, s)) / nb;
     si.converged = converged ? 1 : 0;
     HIPCHK(hipStreamSynchronize(s));
@@ -943,8 +963,8 @@ extern "C" int specmg_pcg_solve(specmg_ctx* c, const double* rhs, double* x, int
 // x = x0 + Z_k y_k with z_j = P^{-1} v_j; classical Gram-Schmidt twice per
 // Arnoldi step; the Arnoldi residual |g_{j+1}| decides the end of a cycle,
 // the true residual b - A x the end of the solve (else a restart from it).
-static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int restart, double tol, int max_iter,
-                    specmg_solve_info* info, hipStream_t s) {
+static int do_gmres(specmg_ctx* c, const double* b_nat, double* x_nat, int use_x0, int restart, double tol,
+                    int max_iter, specmg_solve_info* info, hipStream_t s) {
     const double t0 = now_ms();
     const int64_t n = c->n;
     specmg_solve_info si = c->setup_info;
@@ -958,14 +978,14 @@ static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int r
         int v;
         ~Restore() { c->prof_on = v; }
     } restore{c, prof_saved};
-    launch_sum_abs(b, n, c->dtmp, c->dtmp + 1, c->rb, s);
+    launch_sum_abs(b_nat, n, c->dtmp, c->dtmp + 1, c->rb, s);
     double sa[2];
     HIPCHK(hipMemcpyAsync(sa, c->dtmp, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (std::fabs(sa[0]) > 1e-12 * sa[1]) return fail(SPECMG_ERHS, "source does not sum to zero");
-    const double nb = std::sqrt(dev_dot(c, b, b, s));
+    const double nb = std::sqrt(dev_dot(c, b_nat, b_nat, s));
     if (nb == 0.0) {
-        launch_fill(x, 0.0, n, s);
+        launch_fill(x_nat, 0.0, n, s);
         si.converged = 1;
         si.solve_ms = now_ms() - t0;
         if (info) *info = si;
@@ -1000,6 +1020,11 @@ static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int r
         HIPCHK(hipStreamSynchronize(s));
         HIPCHK(hipGetLastError());
     };
+    // the solve runs in element order
+    const double* b = c->b_e;
+    double* x = c->x_e;
+    launch_to_elem(c->fg, b_nat, c->b_e, s);
+    if (use_x0) launch_to_elem(c->fg, x_nat, c->x_e, s);
     // r0 into V_0
     if (use_x0) launch_apply_A(c->fg, c->kt, x, b, V, 1, s);
     else {
@@ -1050,6 +1075,7 @@ static int do_gmres(specmg_ctx* c, const double* b, double* x, int use_x0, int r
     launch_sum_abs(x, n, c->dtmp, c->dtmp + 1, c->rb, s);
     launch_sub_mean(x, n, c->dtmp, s);
     launch_apply_A(c->fg, c->kt, x, b, w, 1, s);
+    launch_to_natural(c->fg, x, x_nat, s);
     si.rel_resid_true = std::sqrt(dev_dot(c, w, w, s)) / nb;
     si.converged = converged ? 1 : 0;
     HIPCHK(hipStreamSynchronize(s));
@@ -1075,8 +1101,8 @@ extern "C" int specmg_gmres_solve(specmg_ctx* c, const double* rhs, double* x, i
 }
 
 namespace specmg {
-void launch_flux(int nx, int ny, int nz, double hx, double hy, double hz, double cy, double cz, const double* kt,
-                 int ortho, const double* p, double* vx, double* vy, double* vz, hipStream_t s);
+void launch_flux(const FineGeom& g, double hx, double hy, double hz, const double* kt, const double* p, double* vx,
+                 double* vy, double* vz, hipStream_t s);
 void launch_mass_balance(int nx, int ny, int nz, double hx, double hy, double hz, const double* vx, const double* vy,
                          const double* vz, const double* f, double* res, hipStream_t s);
 }  // namespace specmg
@@ -1086,8 +1112,7 @@ extern "C" int specmg_recover_flux(specmg_ctx* c, const double* p, double* vx, d
     g_last_error.clear();
     if (!c || !p || !vx || !vy || !vz) return fail(SPECMG_EINVAL, "null argument");
     try {
-        launch_flux(c->fg.nx, c->fg.ny, c->fg.nz, c->grid.hx, c->grid.hy, c->grid.hz, c->fg.cy, c->fg.cz, c->kt,
-                    c->fg.ortho, p, vx, vy, vz, (hipStream_t)stream);
+        launch_flux(c->fg, c->grid.hx, c->grid.hy, c->grid.hz, c->kt, p, vx, vy, vz, (hipStream_t)stream);
         HIPCHK(hipGetLastError());
     } catch (const HipError& e) {
         return fail(SPECMG_EDEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -1170,7 +1195,8 @@ extern "C" int specmg_get_profile(specmg_ctx* c, double* ms, int32_t* launches, 
     const double w = (c->fp32 || c->fp32_store) ? 4.0 : 8.0;   // stored word of the fine V-cycle
     const double phi_cells = 512.0 * c->lev[0].dim; // sum over elements of 512 * nkeep
     double b[8] = {0};
-    b[PC_SPMV] = n * 8.0 * 7.0;                      // z, p_old, x, kappa~ in; p, q, x out
+    b[PC_SPMV] = n * 8.0 * 3.0;                      // p, kappa~ in; q out
+    b[PC_PUPDATE] = n * 8.0 * 5.0;                   // z, p_old, x in; p, x out
     b[PC_PRE] = n * (8.0 * 3.0 + 2.0 * w + w);       // r, q in, r out; kappa~, 1/d in; u out
     const double wb = (c->fp32_basis || c->fp32_store) ? 4.0 : w;   // basis word size
     b[PC_RESTRICT] = n * (2.0 * w + 8.0) + phi_cells * wb;  // u, kappa~, r; phi

@@ -66,7 +66,7 @@ def trace(path: str, top: int = 30) -> None:
 
 # kernel-name prefix -> profiling class of the solve (see specmg_get_profile)
 CLASSES = {"k_spmv_pcg": "cg_spmv", "k_pre_smooth": "pre_smooth", "k_resid_restrict": "resid_restrict",
-           "k_prolong": "prolong", "k_post_fused": "post_smooth",
+           "k_prolong": "prolong", "k_post_fused": "post_smooth", "k_p_update": "p_update",
            "k_coarsest_sym": "coarsest"}
 TRAFFIC_SOURCES = ("csrc/k_fine.hip", "csrc/k_coarse.hip", "csrc/common.hpp")
 

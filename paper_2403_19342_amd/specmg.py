@@ -29,7 +29,7 @@ EXPORTED = ["specmg_setup", "specmg_setup_alloc", "specmg_apply_precond", "specm
             "specmg_transport_noalloc"]
 TRANSPORT_NOALLOC_MAX_CELLS = 2097152   # SPECMG_TRANSPORT_NOALLOC_MAX_CELLS
 PROFILE_CLASSES = ["cg_spmv", "pre_smooth", "resid_restrict", "prolong", "post_smooth", "coarse_part",
-                   "coarsest", "unused"]
+                   "coarsest", "p_update"]
 
 
 class Grid(ctypes.Structure):
