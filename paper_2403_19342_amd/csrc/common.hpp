@@ -65,6 +65,12 @@ struct DevAlloc {
 
 constexpr int kSub = 8;             // level-2 element edge in cells
 constexpr int kSub3 = 512;          // cells per level-2 element
+
+// Position of cell c = x + 8 l (l = y + 8 z, the pencil) of a level-2
+// element inside a column of its spectral basis: pairs of x interleaved
+// over the 64 pencils, pos = (x / 2) 128 + 2 l + x % 2, so that one 16-byte
+// load per lane of pair i (lane = pencil) reads 1 KB contiguous.
+__host__ __device__ constexpr int phi_pos(int c) { return ((c & 7) >> 1) * 128 + 2 * (c >> 3) + (c & 1); }
 constexpr int kPlanes = 22;         // hyperplanes i+j+k = s in an 8^3 block
 constexpr int kMaxRedBlocks = 262144;
 

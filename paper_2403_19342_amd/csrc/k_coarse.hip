@@ -196,20 +196,24 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     // (one memory round less), wider ones follow the forward sweep so that
     // the two sets are never live together
     constexpr bool kUpperEarly = LP <= 8;
+    // couplings to children outside the parent are never loaded (with
+    // agg = 2 half of them)
     T gl[3][LP], gu[3][LP], dv[LP];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
+        const bool in = wgt[2 * ax] != T(0);
 #pragma unroll
-        for (int b = 0; b < LP; ++b) gl[ax][b] = G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] * wgt[2 * ax];
+        for (int b = 0; b < LP; ++b) gl[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] : T(0);
     }
 #pragma unroll
     for (int b = 0; b < LP; ++b) dv[b] = Dinv[row * LP + b];
     if (kUpperEarly) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
+            const bool in = wgt[2 * ax + 1] != T(0);
 #pragma unroll
             for (int b = 0; b < LP; ++b)
-                gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
+                gu[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] : T(0);
         }
     }
     __syncthreads();
@@ -240,9 +244,10 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     if (!kUpperEarly) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
+            const bool in = wgt[2 * ax + 1] != T(0);
 #pragma unroll
             for (int b = 0; b < LP; ++b)
-                gu[ax][b] = G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] * wgt[2 * ax + 1];
+                gu[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] : T(0);
         }
     }
     T z = T(0);
@@ -562,13 +567,13 @@ __global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __r
         }
         sT[d][f] = T;
         const int c = i + 8 * (j + 8 * k);
-        for (int jj = 0; jj < L; ++jj) sP[d][jj][f] = phi[((size_t)e * L + jj) * 512 + c];
+        for (int jj = 0; jj < L; ++jj) sP[d][jj][f] = phi[((size_t)e * L + jj) * 512 + phi_pos(c)];
         if (plus) {
             const int en = e + (ax == 0 ? 1 : (ax == 1 ? g.mx : g.mx * g.my));
             const int ci = ax == 0 ? 0 : i, cj = ax == 1 ? 0 : j, ck = ax == 2 ? 0 : k;
             const int cn = ci + 8 * (cj + 8 * ck);
             for (int jj = 0; jj < L; ++jj)
-                sN[ax][jj][f] = inside ? phi[((size_t)en * L + jj) * 512 + cn] : 0.0;
+                sN[ax][jj][f] = inside ? phi[((size_t)en * L + jj) * 512 + phi_pos(cn)] : 0.0;
         }
     }
     __syncthreads();

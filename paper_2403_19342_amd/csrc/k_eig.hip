@@ -801,7 +801,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     column_sums<M, 1>(zv, zc + (size_t)e * L, L, nk, sh.red);
 #pragma unroll
     for (int jj = 0; jj < M; ++jj) {
-        if (jj < L) phi[((size_t)e * L + jj) * 512 + c] = (jj < nk) ? X[0][jj] / sq : 0.0;
+        if (jj < L) phi[((size_t)e * L + jj) * 512 + phi_pos(c)] = (jj < nk) ? X[0][jj] / sq : 0.0;
     }
 }
 

@@ -94,6 +94,16 @@ __device__ __forceinline__ void tile_origin(const FineGeom& g, int& x0, int& y0,
     z0 = (r / g.nty) * 8;
 }
 
+// Element of the wavefront in kernels that run four level-2 elements per
+// 256-thread block (block ids remapped so that each XCD walks a contiguous
+// range of elements).
+__device__ __forceinline__ int block_element4() {
+    const int nb = gridDim.x;
+    int b = blockIdx.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+    return b * 4 + (threadIdx.x >> 6);
+}
+
 __device__ __forceinline__ size_t gidx(const FineGeom& g, int x, int y, int z) {
     return (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
 }
@@ -415,6 +425,39 @@ __device__ __forceinline__ void load8(const float* __restrict__ p, double (&v)[8
     }
 }
 
+// The lane's 8 values of one basis column (phi_pos layout): pair i at
+// col + 128 i + 2 lane, so each load instruction reads one contiguous block.
+template <typename TB, typename C>
+__device__ __forceinline__ void load_col(const TB* __restrict__ col, int lane, C (&v)[8]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (sizeof(TB) == 8) {
+            const double2 d = reinterpret_cast<const double2*>(col)[i * 64 + lane];
+            v[2 * i] = (C)d.x;
+            v[2 * i + 1] = (C)d.y;
+        } else {
+            const float2 d = reinterpret_cast<const float2*>(col)[i * 64 + lane];
+            v[2 * i] = (C)d.x;
+            v[2 * i + 1] = (C)d.y;
+        }
+    }
+}
+
+// the lane's pencil (8 contiguous values of word T) from arithmetic values C
+template <typename T, typename C>
+__device__ __forceinline__ void store8c(T* p, const C (&v)[8]) {
+    if constexpr (sizeof(T) == 8) {
+        double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] = make_double2((double)v[2 * i], (double)v[2 * i + 1]);
+    } else {
+        float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
+    }
+}
+
 // 8 contiguous float64 values (the lane's pencil) with 16-byte stores
 __device__ __forceinline__ void store8(double* p, const double (&v)[8]) {
     double2* q = reinterpret_cast<double2*>(p);
@@ -553,14 +596,14 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     }
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
-    const TB* ph = phi + (size_t)e * L * kSub3 + 8 * (j + 8 * k);
+    const TB* ph = phi + (size_t)e * L * kSub3;
     C acc[kMaxCols];
 #pragma unroll
     for (int jj = 0; jj < kMaxCols; ++jj) {
         C a = C(0);
         if (jj < nkp) {
-            TB pv[8];
-            load8(ph + (size_t)jj * kSub3, pv);
+            C pv[8];
+            load_col(ph + (size_t)jj * kSub3, lane, pv);
 #pragma unroll
             for (int x = 0; x < 8; ++x) a += (C)pv[x] * s[x];
         }
@@ -575,28 +618,36 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     }
 }
 
-// u += phi e2 on every element (prolongation, Algorithm 1 step 8); the sum
-// is formed in C, the word of e2
+// u += phi e2 on every element (prolongation, Algorithm 1 step 8), one
+// wavefront per element: lane = pencil, the basis read column by column
+// (load_col); the sum is formed in C, the word of e2
 template <typename T, typename TB, typename C>
 __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __restrict__ phi,
                                                   const int* __restrict__ nkeep, int L,
                                                   const C* __restrict__ e2, const Scalars* sc,
                                                   int check_done) {
     if (check_done && sc->done) return;
-    const int e = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int e = block_element4();
+    if (e >= g.mx * g.my * g.mz) return;   // whole wavefront; no block barriers
     const int nk = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3;
     const C* ee = e2 + (size_t)e * L;
-    for (int c = threadIdx.x; c < kSub3; c += 256) {
-        C acc = C(0);
+    const size_t row = (size_t)e * kSub3 + 8 * lane;
+    C uc[8];
+    load8(u + row, uc);
 #pragma unroll
-        for (int jj = 0; jj < kMaxCols; ++jj) {
-            const int jc = jj < nk ? jj : nk - 1;
-            acc += (jj < nk ? (C)ph[(size_t)jc * kSub3 + c] : C(0)) * ee[jc];
+    for (int jj = 0; jj < kMaxCols; ++jj) {
+        if (jj < nk) {
+            C pv[8];
+            load_col(ph + (size_t)jj * kSub3, lane, pv);
+            const C a = ee[jj];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) uc[x] += pv[x] * a;
         }
-        const size_t gi = (size_t)e * kSub3 + c;
-        u[gi] = (T)((C)u[gi] + acc);
+        if (jj % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
+    store8c(u + row, uc);
 }
 
 // Post-smoothing with its residual (Algorithm 1 step 9): t = r - A u on
@@ -669,16 +720,6 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
         double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
         write_partials<2>(v, rb);
     }
-}
-
-// Element of the wavefront in kernels that run four level-2 elements per
-// 256-thread block (block ids remapped so that each XCD walks a contiguous
-// range of elements).
-__device__ __forceinline__ int block_element4() {
-    const int nb = gridDim.x;
-    int b = blockIdx.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-    return b * 4 + (threadIdx.x >> 6);
 }
 
 // First half of a CG step: p = z + beta p_old (p = z on the first
@@ -1068,8 +1109,8 @@ void launch_resid_restrict(const FineGeom& g, const T* kt, const T* u, const dou
 template <typename T, typename TB, typename C>
 void launch_prolong(const FineGeom& g, T* u, const TB* phi, const int* nkeep, int L, const C* e2,
                     Scalars* sc, int check_done, hipStream_t s) {
-    SPECMG_TIMED_LAUNCH((k_prolong<T, TB, C>), dim3(g.mx * g.my * g.mz), dim3(256), 0, s, g, u, phi, nkeep, L, e2,
-                       sc, check_done);
+    SPECMG_TIMED_LAUNCH((k_prolong<T, TB, C>), dim3((g.mx * g.my * g.mz + 3) / 4), dim3(256), 0, s, g, u, phi, nkeep,
+                        L, e2, sc, check_done);
 }
 
 template <typename T, typename C>

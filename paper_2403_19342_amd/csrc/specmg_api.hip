@@ -1174,6 +1174,17 @@ extern "C" int specmg_copy_level(specmg_ctx* c, int32_t level, int32_t which, vo
         default: return fail(SPECMG_EINVAL, "unknown array");
     }
     if (bytes != need) return fail(SPECMG_EINVAL, "size mismatch: expected " + std::to_string(need));
+    if (which == 2 && level == 2) {
+        // the level-2 basis is stored in the phi_pos order; exported with the
+        // cells of each column in natural order x + 8 (y + 8 z)
+        std::vector<double> tmp(m * L * 512);
+        if (hipMemcpy(tmp.data(), src, need, hipMemcpyDeviceToHost) != hipSuccess)
+            return fail(SPECMG_EDEVICE, "copy failed");
+        double* out = static_cast<double*>(dst);
+        for (size_t col = 0; col < m * L; ++col)
+            for (int cc = 0; cc < 512; ++cc) out[col * 512 + cc] = tmp[col * 512 + phi_pos(cc)];
+        return SPECMG_OK;
+    }
     if (hipMemcpy(dst, src, need, hipMemcpyDeviceToHost) != hipSuccess)
         return fail(SPECMG_EDEVICE, "copy failed");
     return SPECMG_OK;
