@@ -6,17 +6,16 @@
 // columns carry an identity).  Cholesky A = L L^T is right-looking in panels
 // of KB = 256 columns: inside a panel, 32 x 32 diagonal tiles in LDS, a panel
 // solve and rank-32 updates restricted to the panel; after the panel, one
-// rank-KB update of the trailing lower triangle.  W = L^{-1} is built from the
-// bottom-right panel upwards: W_JJ = L_JJ^{-1}, then
-// W[J+1:, J] = -(W[J+1:, J+1:] L[J+1:, J]) W_JJ.  Finally A^{-1} = W^T W.
-// The rank-KB updates and the three products share one register-tiled
-// FP64 tile product (64 x 64 outputs per 256-thread workgroup, 4 x 4 per
-// thread, 16-deep k chunks staged in LDS).
+// rank-KB update of the trailing lower triangle.  W = L^{-1}: every KB x KB
+// diagonal block inverted at once, then halves joined bottom-up,
+// W21 = -W22 (L21 W11).  Finally A^{-1} = W^T W.  The rank-KB updates and
+// the products run on the FP64 matrix cores (k_gemm).
 #include "common.hpp"
 
 namespace specmg {
 
 constexpr int NB = 32;
+constexpr int KB = 256;   // panel width of the Cholesky factorisation, leaf of the triangular inverse
 
 __global__ __launch_bounds__(256) void k_potrf_diag(double* A, int np, int k0, int* bad) {
     __shared__ double T[NB][NB + 1];
@@ -103,54 +102,8 @@ __global__ __launch_bounds__(256) void k_syrk_panel(double* A, int np, int kk, i
     }
 }
 
-// ---------------------------------------------------------------------------
-// register-tiled FP64 tile product
-constexpr int KB = 256;   // outer panel width
-constexpr int TG = 64;    // output tile edge
-constexpr int TK = 16;    // k chunk
 enum { OPN = 0, OPT = 1 };
-
-// acc[r][c] += sum_{k in [kbeg, kend)} a(i, k) b(k, j) for the rows
-// i = i0 + ty + 16 r and columns j = j0 + tx + 16 c of a 64 x 64 tile, with
-//   a(i, k) = A[i lda + k] (AOP = OPN) or A[k lda + i] (OPT),
-//   b(k, j) = B[k ldb + j] (BOP = OPN) or B[j ldb + k] (OPT);
-// rows >= M and columns >= N read zero.  Called by all 256 threads.
-template <int AOP, int BOP>
-__device__ __forceinline__ void tile_product(const double* __restrict__ A, int lda, const double* __restrict__ B,
-                                             int ldb, int M, int N, int i0, int j0, int kbeg, int kend,
-                                             double (&acc)[4][4], double (*As)[TG + 1], double (*Bs)[TG + 1]) {
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = t + 256 * u;
-            const int ia = AOP == OPN ? e / TK : e % TG, ka = AOP == OPN ? e % TK : e / TG;
-            const int gi = i0 + ia, gka = k0 + ka;
-            double v = 0.0;
-            if (gi < M && gka < kend) v = AOP == OPN ? A[(size_t)gi * lda + gka] : A[(size_t)gka * lda + gi];
-            As[ka][ia] = v;
-            const int jb = BOP == OPN ? e % TG : e / TK, kb = BOP == OPN ? e / TG : e % TK;
-            const int gj = j0 + jb, gkb = k0 + kb;
-            double w = 0.0;
-            if (gj < N && gkb < kend) w = BOP == OPN ? B[(size_t)gkb * ldb + gj] : B[(size_t)gj * ldb + gkb];
-            Bs[kb][jb] = w;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < TK; ++k) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) av[r] = As[k][ty + 16 * r];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) bv[c] = Bs[k][tx + 16 * c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_fma(av[r], bv[c], acc[r][c]);
-        }
-        __syncthreads();
-    }
-}
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // lower tile (ti >= tj) of a T x T tile grid from a linear block index
 __device__ __forceinline__ void lower_tile(int b, int& ti, int& tj) {
@@ -161,31 +114,16 @@ __device__ __forceinline__ void lower_tile(int b, int& ti, int& tj) {
     tj = b - i * (i + 1) / 2;
 }
 
-// after a panel [k0, k0+kw): A[i][j] -= sum_k A[i][k] A[j][k] for i >= j >= j0
-__global__ __launch_bounds__(256) void k_chol_update(double* A, int np, int k0, int kw, int j0) {
-    __shared__ double As[TK][TG + 1], Bs[TK][TG + 1];
-    int ti, tj;
-    lower_tile(blockIdx.x, ti, tj);
-    const int i0 = j0 + ti * TG, c0 = j0 + tj * TG;
-    double acc[4][4] = {};
-    tile_product<OPN, OPT>(A, np, A, np, np, np, i0, c0, k0, k0 + kw, acc, As, Bs);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + ty + 16 * r, j = c0 + tx + 16 * c;
-            if (i < np && j < np && i >= j) A[(size_t)i * np + j] -= acc[r][c];
-        }
-}
-
-// W_JJ = L_JJ^{-1} for the kb x kb diagonal block at o: one workgroup per
-// 32-column strip of the block, rows marched downwards
-__global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ Lm, double* W, int np, int o,
-                                                    int nbk) {
+// W_JJ = L_JJ^{-1} for every KB x KB diagonal block (blockIdx.y; the last
+// one may be narrower): one workgroup per 32-column strip of the block, rows
+// marched downwards
+__global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ Lm, double* W, int np) {
     __shared__ double Lii[NB][NB + 1];
     __shared__ double R[NB][NB + 1];
+    const int o = blockIdx.y * KB;
+    const int nbk = min(KB, np - o) / NB;
     const int J = blockIdx.x;
+    if (J >= nbk) return;   // whole workgroup
     const int j0 = o + J * NB;
     for (int I = J; I < nbk; ++I) {
         const int i0 = o + I * NB;
@@ -215,63 +153,153 @@ __global__ __launch_bounds__(256) void k_trtri_diag(const double* __restrict__ L
     }
 }
 
-// T[i][c] = sum_{k in [r0, i]} W[i][k] L[k][j0 + c] for rows i >= r0 = j0 + kb
-// (W lower triangular, zero above the diagonal), columns c < kb
-__global__ __launch_bounds__(256) void k_trmm_panel(const double* __restrict__ W, const double* __restrict__ Lm,
-                                                    double* __restrict__ T, int np, int j0, int kb) {
-    __shared__ double As[TK][TG + 1], Bs[TK][TG + 1];
-    const int r0 = j0 + kb;
-    const int i0 = r0 + blockIdx.x * TG, c0 = blockIdx.y * TG;
-    double acc[4][4] = {};
-    const int kend = min(i0 + TG, np);
-    tile_product<OPN, OPN>(W, np, Lm + j0, np, np, kb, i0, c0, r0, kend, acc, As, Bs);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + ty + 16 * r, j = c0 + tx + 16 * c;
-            if (i < np && j < kb) T[(size_t)i * KB + j] = acc[r][c];
-        }
-}
+// ---------------------------------------------------------------------------
+// FP64 matrix-core GEMM: C (M x N) = alpha op(A) op(B) over k in [kbeg, kend),
+// a 128 x 128 tile per 256-thread workgroup, wave w owning the 64 x 64
+// quarter (rows 64 (w >> 1), columns 64 (w & 1)) as 4 x 4 blocks of
+// v_mfma_f64_16x16x4f64.  Operand lanes: A(i, k) with i = lane % 16,
+// k = lane / 16; B(k, j) with j = lane % 16, k = lane / 16; result element r
+// of a block in lane l is (l / 16 + 4 r, l % 16) of the block.  k chunks of
+// 16 are staged through LDS; the next chunk's loads are issued before the
+// current chunk's products.
+//   kb_mode: 0 kbeg = 0; 1 kbeg = j0 (B lower triangular); 2 kbeg = i0 (A^T
+//            of a lower triangular matrix)
+//   ke_mode: 0 kend = K; 1 kend = min(i0 + 128, K) (A lower triangular)
+//   lower:   the grid enumerates the lower tiles (ti >= tj) of a square C
+//   EPI 0: C = alpha acc;  1: C -= acc on i >= j;  2: C = acc on i >= j, mirrored
+constexpr int GT = 128;
+constexpr int GK = 16;
 
-// W[i][j0 + c] = -sum_k T[i][k] W[j0 + k][j0 + c] for rows i >= j0 + kb
-__global__ __launch_bounds__(256) void k_panel_times_diag(const double* __restrict__ T, double* W, int np, int j0,
-                                                          int kb) {
-    __shared__ double As[TK][TG + 1], Bs[TK][TG + 1];
-    const int r0 = j0 + kb;
-    const int i0 = r0 + blockIdx.x * TG, c0 = blockIdx.y * TG;
-    double acc[4][4] = {};
-    tile_product<OPN, OPN>(T, KB, W + (size_t)j0 * np + j0, np, np, kb, i0, c0, c0, kb, acc, As, Bs);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + ty + 16 * r, j = c0 + tx + 16 * c;
-            if (i < np && j < kb) W[(size_t)i * np + j0 + j] = -acc[r][c];
-        }
-}
+struct GemmArgs {
+    const double* A;
+    const double* B;
+    double* C;
+    int lda, ldb, ldc;
+    int M, N, K;
+    double alpha;
+    int kb_mode, ke_mode, lower;
+};
 
-// A = W^T W on lower tiles (ti >= tj), mirrored: W[k][i] = 0 for k < i
-__global__ __launch_bounds__(256) void k_wtw(const double* __restrict__ W, double* A, int np) {
-    __shared__ double As[TK][TG + 1], Bs[TK][TG + 1];
+template <int AOP, int BOP, int EPI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gemm(GemmArgs g) {
+    __shared__ double As[GK][GT + 1], Bs[GK][GT + 1];
     int ti, tj;
-    lower_tile(blockIdx.x, ti, tj);
-    const int i0 = ti * TG, c0 = tj * TG;
-    double acc[4][4] = {};
-    tile_product<OPT, OPN>(W, np, W, np, np, np, i0, c0, i0, np, acc, As, Bs);
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    if (g.lower) {
+        lower_tile(blockIdx.x, ti, tj);
+    } else {
+        ti = blockIdx.x;
+        tj = blockIdx.y;
+    }
+    const int i0 = ti * GT, j0 = tj * GT;
+    const int kbeg = g.kb_mode == 1 ? j0 : (g.kb_mode == 2 ? i0 : 0);
+    const int kend = g.ke_mode == 1 ? min(i0 + GT, g.K) : g.K;
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int wr = 64 * (w >> 1), wc = 64 * (w & 1);
+    const int li = l & 15, lk = l >> 4;
+    dbl4 acc[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int i = i0 + ty + 16 * r, j = c0 + tx + 16 * c;
-            if (i < np && j < np && i >= j) {
-                A[(size_t)i * np + j] = acc[r][c];
-                A[(size_t)j * np + i] = acc[r][c];
+        for (int n = 0; n < 4; ++n) acc[m][n] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // staging: 4 pairs of A and 4 of B per thread and chunk, each pair two
+    // elements adjacent in memory (along k for OPN A / OPT B, along i or j
+    // otherwise); K bounds are multiples of 16, so a pair never straddles kend
+    double2 ra[4], rb[4];
+    auto a_slot = [&](int u, int& ia, int& ka) {
+        const int e = t + 256 * u;
+        if (AOP == OPN) { ia = e >> 3; ka = 2 * (e & 7); }
+        else { ia = 2 * (e & 63); ka = e >> 6; }
+    };
+    auto b_slot = [&](int u, int& jb, int& kb) {
+        const int e = t + 256 * u;
+        if (BOP == OPN) { jb = 2 * (e & 63); kb = e >> 6; }
+        else { jb = e >> 3; kb = 2 * (e & 7); }
+    };
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int ia, ka, jb, kb;
+            a_slot(u, ia, ka);
+            b_slot(u, jb, kb);
+            const int gi = i0 + ia, gka = k0 + ka;
+            const bool va = gi < g.M && gka < kend;
+            ra[u] = va ? *reinterpret_cast<const double2*>(AOP == OPN ? g.A + (size_t)gi * g.lda + gka
+                                                                      : g.A + (size_t)gka * g.lda + gi)
+                       : double2{0.0, 0.0};
+            const int gj = j0 + jb, gkb = k0 + kb;
+            const bool vb = gj < g.N && gkb < kend;
+            rb[u] = vb ? *reinterpret_cast<const double2*>(BOP == OPN ? g.B + (size_t)gkb * g.ldb + gj
+                                                                      : g.B + (size_t)gj * g.ldb + gkb)
+                       : double2{0.0, 0.0};
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int ia, ka, jb, kb;
+            a_slot(u, ia, ka);
+            b_slot(u, jb, kb);
+            if (AOP == OPN) {
+                As[ka][ia] = ra[u].x;
+                As[ka + 1][ia] = ra[u].y;
+            } else {
+                As[ka][ia] = ra[u].x;
+                As[ka][ia + 1] = ra[u].y;
+            }
+            if (BOP == OPN) {
+                Bs[kb][jb] = rb[u].x;
+                Bs[kb][jb + 1] = rb[u].y;
+            } else {
+                Bs[kb][jb] = rb[u].x;
+                Bs[kb + 1][jb] = rb[u].y;
             }
         }
+        __syncthreads();
+        if (k0 + GK < kend) load(k0 + GK);
+#pragma unroll
+        for (int kk = 0; kk < GK / 4; ++kk) {
+            const int k = 4 * kk + lk;
+            double a[4], b[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) a[m] = As[k][wr + 16 * m + li];
+#pragma unroll
+            for (int n = 0; n < 4; ++n) b[n] = Bs[k][wc + 16 * n + li];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[n], acc[m][n], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + 16 * m + lk + 4 * r, j = j0 + wc + 16 * n + li;
+                if (i >= g.M || j >= g.N) continue;
+                const double v = acc[m][n][r];
+                if (EPI == 0) {
+                    g.C[(size_t)i * g.ldc + j] = g.alpha * v;
+                } else if (EPI == 1) {
+                    if (i >= j) g.C[(size_t)i * g.ldc + j] -= v;
+                } else {
+                    if (i >= j) {
+                        g.C[(size_t)i * g.ldc + j] = v;
+                        g.C[(size_t)j * g.ldc + i] = v;
+                    }
+                }
+            }
+}
+
+template <int AOP, int BOP, int EPI>
+static void launch_gemm(const GemmArgs& g, hipStream_t s) {
+    const int tm = (g.M + GT - 1) / GT, tn = (g.N + GT - 1) / GT;
+    const dim3 grid = g.lower ? dim3(tm * (tm + 1) / 2) : dim3(tm, tn);
+    if (tm > 0 && tn > 0) hipLaunchKernelGGL((k_gemm<AOP, BOP, EPI>), grid, dim3(256), 0, s, g);
 }
 
 __global__ void k_rank1(double* A, int np, int n, const double* __restrict__ z, double alpha) {
@@ -291,11 +319,55 @@ void launch_pad_identity(double* a, int np, int n, hipStream_t s) {
     if (np > n) hipLaunchKernelGGL(k_pad_identity, dim3((np - n + 63) / 64), dim3(64), 0, s, a, np, n);
 }
 
-size_t dense_spd_inverse_tbuf_doubles(int np) { return (size_t)np * KB; }
+// W[o:e, o:e] = L[o:e, o:e]^{-1} for the KB-blocks [b0, b1) (o = KB b0,
+// e = min(KB b1, np)), leaves already inverted: inv([L11 0; L21 L22]) =
+// [W11 0; -W22 L21 W11  W22], the two halves first (post-order), then
+// P = L21 W11 (W11 lower triangular: k >= j) and W21 = -W22 P (W22 lower
+// triangular: k <= i) as matrix-core GEMMs; P lives in tbuf.
+static void trtri_node(const double* Lm, double* W, double* P, int np, int b0, int b1, hipStream_t s) {
+    if (b1 - b0 < 2) return;
+    const int bm = (b0 + b1) / 2;
+    trtri_node(Lm, W, P, np, b0, bm, s);
+    trtri_node(Lm, W, P, np, bm, b1, s);
+    const int o = KB * b0, h = KB * (bm - b0), n = std::min(KB * b1, np) - o;
+    GemmArgs g{};
+    g.A = Lm + (size_t)(o + h) * np + o;
+    g.lda = np;
+    g.B = W + (size_t)o * np + o;
+    g.ldb = np;
+    g.C = P;
+    g.ldc = h;
+    g.M = n - h;
+    g.N = h;
+    g.K = h;
+    g.alpha = 1.0;
+    g.kb_mode = 1;
+    launch_gemm<OPN, OPN, 0>(g, s);
+    GemmArgs q{};
+    q.A = W + (size_t)(o + h) * np + o + h;
+    q.lda = np;
+    q.B = P;
+    q.ldb = h;
+    q.C = W + (size_t)(o + h) * np + o;
+    q.ldc = np;
+    q.M = n - h;
+    q.N = h;
+    q.K = n - h;
+    q.alpha = -1.0;
+    q.ke_mode = 1;
+    launch_gemm<OPN, OPN, 0>(q, s);
+}
+
+size_t dense_spd_inverse_tbuf_doubles(int np) {
+    // P of the root node of trtri_node, the largest
+    const int nb = (np + KB - 1) / KB;
+    const size_t h = (size_t)KB * (nb / 2);
+    return nb < 2 ? 1 : (size_t)(np - h) * h;
+}
 
 int dense_spd_inverse(double* a, int np, double* work, double* tbuf, int* bad, hipStream_t s) {
     if (np % NB) return (int)hipErrorInvalidValue;
-    // ---- Cholesky, panels of KB columns
+    // ---- Cholesky, panels of KB columns; the trailing update on the matrix cores
     for (int k0 = 0; k0 < np; k0 += KB) {
         const int kw = std::min(KB, np - k0);
         for (int kk = k0; kk < k0 + kw; kk += NB) {
@@ -310,28 +382,41 @@ int dense_spd_inverse(double* a, int np, double* work, double* tbuf, int* bad, h
         }
         const int j0 = k0 + kw;
         if (j0 < np) {
-            const int T = (np - j0 + TG - 1) / TG;
-            hipLaunchKernelGGL(k_chol_update, dim3(T * (T + 1) / 2), dim3(256), 0, s, a, np, k0, kw, j0);
+            // A[i][j] -= sum_{k in panel} A[i][k] A[j][k], i >= j >= j0
+            GemmArgs g{};
+            g.A = a + (size_t)j0 * np + k0;
+            g.lda = np;
+            g.B = g.A;
+            g.ldb = np;
+            g.C = a + (size_t)j0 * np + j0;
+            g.ldc = np;
+            g.M = g.N = np - j0;
+            g.K = kw;
+            g.alpha = 1.0;
+            g.lower = 1;
+            launch_gemm<OPN, OPT, 1>(g, s);
         }
     }
-    // ---- W = L^{-1}, panels from the bottom-right
+    // ---- W = L^{-1}: the KB x KB diagonal blocks, then the recursive halves
     hipError_t e = hipMemsetAsync(work, 0, (size_t)np * np * sizeof(double), s);
     if (e != hipSuccess) return (int)e;
-    const int last = ((np - 1) / KB) * KB;
-    for (int j0 = last; j0 >= 0; j0 -= KB) {
-        const int kb = std::min(KB, np - j0);
-        hipLaunchKernelGGL(k_trtri_diag, dim3(kb / NB), dim3(256), 0, s, a, work, np, j0, kb / NB);
-        const int m = np - j0 - kb;
-        if (m > 0) {
-            const dim3 grid((m + TG - 1) / TG, (kb + TG - 1) / TG);
-            hipLaunchKernelGGL(k_trmm_panel, grid, dim3(256), 0, s, work, a, tbuf, np, j0, kb);
-            hipLaunchKernelGGL(k_panel_times_diag, grid, dim3(256), 0, s, tbuf, work, np, j0, kb);
-        }
-    }
-    // ---- A^{-1} = W^T W
+    const int nb = (np + KB - 1) / KB;
+    hipLaunchKernelGGL(k_trtri_diag, dim3(KB / NB, nb), dim3(256), 0, s, a, work, np);
+    trtri_node(a, work, tbuf, np, 0, nb, s);
+    // ---- A^{-1} = W^T W (lower tiles, mirrored; W[k][i] = 0 for k < i)
     {
-        const int T = (np + TG - 1) / TG;
-        hipLaunchKernelGGL(k_wtw, dim3(T * (T + 1) / 2), dim3(256), 0, s, work, a, np);
+        GemmArgs g{};
+        g.A = work;
+        g.lda = np;
+        g.B = work;
+        g.ldb = np;
+        g.C = a;
+        g.ldc = np;
+        g.M = g.N = g.K = np;
+        g.alpha = 1.0;
+        g.kb_mode = 2;
+        g.lower = 1;
+        launch_gemm<OPT, OPN, 2>(g, s);
     }
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return (int)e;
