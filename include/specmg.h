@@ -112,8 +112,12 @@ typedef struct {
                                 eig_tol); an element that does not reach it
                                 within 4 Chebyshev cycles falls back to the
                                 exact solve (eig_tol) from the cold start */
-    int32_t eigs_coarse;     /* L_cc, 0..10; 0 = eigs_per_subdomain.  With
-                                agg 4 and four or more levels at most 9 */
+    int32_t eigs_coarse;     /* L_cc, 0..20; 0 = eigs_per_subdomain.  With
+                                agg 4 and four or more levels at most 9.
+                                Above 10 the coarse-coarse eigensolves use a
+                                block of 20 or 26 vectors, and a level of
+                                width L_cc + 3 > 13 runs the wide (spilling)
+                                form of the coarse smoother */
     double eig_threshold_coarse; /* B_cc >= 0; 0 = fixed count eigs_coarse.
                                 Eigenvalues are those of eq. spectral cc with
                                 S-normalised bases (dimensionless) */

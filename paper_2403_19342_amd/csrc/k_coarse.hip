@@ -71,7 +71,8 @@ __device__ void build_planes(int agg, int* pos, int* off) {
     __syncthreads();
 }
 
-constexpr int kMaxLc = 13;   // padded widths up to target 10 + 3
+constexpr int kMaxLc = 23;   // padded widths up to target 20 + 3 (levels >= 3)
+constexpr int kNarrow = 13;  // widths up to target 10 + 3 get their own instantiations
 
 // y_c = (A_l u)_c for row a of child element c; all block-row loads of the
 // thread are issued before the products
@@ -122,7 +123,8 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
 
 constexpr int kCoarseThreads = 1024;   // upper bound; launches use agg^3 L rounded to waves
 constexpr int kMaxChildren = 64;   // agg <= 4
-constexpr int kMaxL = 16;
+constexpr int kMaxL = kMaxLc;      // set-up arrays of the levels >= 3
+constexpr int kMaxL2 = 16;         // level 2 (target <= 10)
 
 // Level-l smoother on parent E, both substitutions in one kernel:
 //   t = r (mode 0) or t = r - A_l u (mode 1)
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
 }
 
 // s = r - A_l u on the children of E, then r_up[E] = V_E^T s
-template <typename T, int LP>
+template <typename T, int LP, int LU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Aoff, const T* __restrict__ r,
     const T* __restrict__ u, const T* __restrict__ V, const int* __restrict__ nkeep_up, int Lup,
@@ -286,21 +288,21 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     }
     __syncthreads();
     const int nk = nkeep_up[E];
-    double acc[kMaxLc];
+    double acc[LU];
 #pragma unroll
-    for (int j = 0; j < kMaxLc; ++j) acc[j] = 0.0;
+    for (int j = 0; j < LU; ++j) acc[j] = 0.0;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const double sv = (double)sS[t];
 #pragma unroll
-        for (int j = 0; j < kMaxLc; ++j) {
+        for (int j = 0; j < LU; ++j) {
             const int jj = j < nk ? j : nk - 1;
             acc[j] += (j < nk ? (double)V[((size_t)E * Lup + jj) * n + t] : 0.0) * sv;
         }
     }
-    __shared__ double sacc[kCoarseThreads / 64][kMaxLc];
+    __shared__ double sacc[kCoarseThreads / 64][LU];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-    for (int j = 0; j < kMaxLc; ++j) {
+    for (int j = 0; j < LU; ++j) {
         const double v = wave_sum(acc[j]);
         if (lane == 0) sacc[w][j] = v;
     }
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
 }
 
 // u += V_E e_up[E] on the children of E
-template <typename T>
+template <typename T, int LU>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g, T* __restrict__ u,
                                                                   const T* __restrict__ V,
                                                                   const int* __restrict__ nkeep_up, int Lup,
@@ -329,7 +331,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_prolong(CoarseGeom g,
         const int p = t / L, a = t % L;
         T acc = T(0);
 #pragma unroll
-        for (int j = 0; j < kMaxLc; ++j) {
+        for (int j = 0; j < LU; ++j) {
             const int jj = j < nk ? j : nk - 1;
             acc += (j < nk ? V[((size_t)E * Lup + jj) * n + t] : T(0)) * ee[jj];
         }
@@ -539,8 +541,8 @@ __global__ __launch_bounds__(256) void k_galerkin2(FineGeom g, const double* __r
                                                    const double* __restrict__ phi, const int* __restrict__ nkeep,
                                                    int L, double* __restrict__ D, double* __restrict__ Aoff) {
     __shared__ double sT[6][64];
-    __shared__ double sP[6][kMaxL][64];    // own face rows
-    __shared__ double sN[3][kMaxL][64];    // neighbour face rows (+ faces)
+    __shared__ double sP[6][kMaxL2][64];    // own face rows
+    __shared__ double sN[3][kMaxL2][64];    // neighbour face rows (+ faces)
     const int e = blockIdx.x;
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     auto gid = [&](int x, int y, int z) { return eidx(g, x, y, z); };
@@ -756,7 +758,7 @@ __global__ __launch_bounds__(64 * kMaxPlane) void k_blockic_setup(CoarseGeom g, 
                                                                    const int* __restrict__ nkeep, double* Dinv,
                                                                    int* bad) {
     __shared__ int pos[kMaxChildren], off[12];
-    __shared__ double work[kMaxPlane][3][kMaxL * kMaxL];
+    extern __shared__ double work_lds[];   // [children of the widest plane][3][L * L]
     __shared__ int flags[kMaxPlane];
     const int E = blockIdx.x;
     const int L = g.L, agg = g.agg, LL = L * L;
@@ -768,9 +770,9 @@ __global__ __launch_bounds__(64 * kMaxPlane) void k_blockic_setup(CoarseGeom g, 
         if (w < cnt) {
             const int p = pos[off[s] + w];
             const int c = child_of(g, E, p);
-            double* P = work[w][0];
-            double* T = work[w][1];
-            double* Lw = work[w][2];
+            double* P = work_lds + (size_t)(3 * w) * LL;
+            double* T = P + LL;
+            double* Lw = T + LL;
             for (int t = lane; t < LL; t += 64) P[t] = Ad[(size_t)c * LL + t];
             const int q[3] = {p % agg, (p / agg) % agg, p / (agg * agg)};
             const int cstep[3] = {1, g.mx, g.mx * g.my};
@@ -896,7 +898,8 @@ __global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_
         case 10: { constexpr int LP = 10; __VA_ARGS__; } break;   \
         case 11: { constexpr int LP = 11; __VA_ARGS__; } break;   \
         case 12: { constexpr int LP = 12; __VA_ARGS__; } break;   \
-        default: { constexpr int LP = 13; __VA_ARGS__; } break;   \
+        case 13: { constexpr int LP = 13; __VA_ARGS__; } break;   \
+        default: { constexpr int LP = kMaxLc; __VA_ARGS__; } break; \
     }
 
 template <typename T>
@@ -906,8 +909,14 @@ void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aof
     const int rows = g.agg * g.agg * g.agg * g.L;
     const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
     if (g.L < 4 || g.L > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual width"};
-    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict<T, LP>), dim3(g.M), dim3(th), 0, s, g, Ad,
-                                               Aoff, r, u, V, nkeep_up, Lup, rup, sc, check_done));
+    if (Lup > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual upper width"};
+    if (Lup <= kNarrow) {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict<T, LP, kNarrow>), dim3(g.M), dim3(th), 0,
+                                                   s, g, Ad, Aoff, r, u, V, nkeep_up, Lup, rup, sc, check_done));
+    } else {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict<T, LP, kMaxLc>), dim3(g.M), dim3(th), 0,
+                                                   s, g, Ad, Aoff, r, u, V, nkeep_up, Lup, rup, sc, check_done));
+    }
 }
 
 template <typename T>
@@ -915,8 +924,13 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
                            const Scalars* sc, int check_done, hipStream_t s) {
     const int rows = g.agg * g.agg * g.agg * g.L;
     const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
-    hipLaunchKernelGGL((k_coarse_prolong<T>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup,
-                       sc, check_done);
+    if (Lup > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse prolongation upper width"};
+    if (Lup <= kNarrow)
+        hipLaunchKernelGGL((k_coarse_prolong<T, kNarrow>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup, sc,
+                           check_done);
+    else
+        hipLaunchKernelGGL((k_coarse_prolong<T, kMaxLc>), dim3(g.M), dim3(th), 0, s, g, u, V, nkeep_up, Lup, eup, sc,
+                           check_done);
 }
 
 // dynamic LDS of the sweep kernels; couplings are staged when they fit
@@ -1009,7 +1023,11 @@ void launch_assemble_diag(const CoarseGeom& g, const double* Aint, const double*
 
 void launch_blockic_setup(const CoarseGeom& g, const double* Ad, const double* Aoff, const int* nkeep,
                           double* Dinv, double* G, int* bad, hipStream_t s) {
-    hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64 * kMaxPlane), 0, s, g, Ad, Aoff, nkeep, Dinv, bad);
+    // widest hyperplane of the parent's children: 3 (agg 2) or 12 (agg 4)
+    const int wmax = g.agg == 2 ? 3 : kMaxPlane;
+    const size_t shmem = (size_t)wmax * 3 * g.L * g.L * sizeof(double);
+    if (g.L > kMaxL || shmem > 64 * 1024) throw HipError{hipErrorInvalidValue, "block-IC set-up shape"};
+    hipLaunchKernelGGL(k_blockic_setup, dim3(g.M), dim3(64 * kMaxPlane), shmem, s, g, Ad, Aoff, nkeep, Dinv, bad);
     hipLaunchKernelGGL(k_blockic_couple, dim3(g.m), dim3(256), 0, s, g, Aoff, Dinv, G);
 }
 

@@ -86,7 +86,7 @@ __device__ __forceinline__ void jac_rot(const double* H, int M, int p, int q, do
 // receives the eigenvectors as columns.  Must be called by all threads.
 template <int M>
 __device__ __forceinline__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
-    static_assert(M % 2 == 0 && M <= 16, "Jacobi block size");
+    static_assert(M % 2 == 0 && M <= 26, "Jacobi block size");
     constexpr int MM = M * M;
     constexpr int PER = (MM + 63) / 64;
     (void)scr;
@@ -460,7 +460,7 @@ struct Op2 {
 // diagonal block stays in registers; the coupling rows of the six directions
 // are re-read (from L2) on every apply, the loads of a direction issued
 // together; a missing neighbour reads its own child with weight zero.
-constexpr int kMaxLP = 13;   // lower-level widths up to target 10 + 3
+constexpr int kMaxLP = 23;   // lower-level widths up to target 20 + 3
 
 // LPT > 0: the width is a compile-time constant; LPT = 0: run-time width lp
 // (arrays sized for kMaxLP, slots beyond lp masked)
@@ -985,7 +985,7 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
     hipLaunchKernelGGL(k_build_hd, dim3(lo.m), dim3(128), 0, s, lo, Aint_lo, Dlo, Hd_work);
     const int n = lo.agg * lo.agg * lo.agg * lo.L;
     const int threads = (n + 63) / 64 * 64;
-    if (up.L != target + 3 || lo.L > kMaxLP || threads > 768 || target < 1 || target > 10 || nvec < target + 6)
+    if (up.L != target + 3 || lo.L > kMaxLP || threads > 768 || target < 1 || target > 20 || nvec < target + 6)
         throw HipError{hipErrorInvalidValue, "eig_up shape"};
     const size_t shmem = (size_t)nvec * (n | 1) * sizeof(double);
     // compile-time widths for the pairs (block size, lower width) that occur
@@ -1005,8 +1005,10 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
         case 1007: SPECMG_EIG_UP(10, 7)
         case 1208: SPECMG_EIG_UP(12, 8)
         case 1209: SPECMG_EIG_UP(12, 9)
+        case 1409: SPECMG_EIG_UP(14, 9)
         case 1410: SPECMG_EIG_UP(14, 10)
         case 1411: SPECMG_EIG_UP(14, 11)
+        case 1609: SPECMG_EIG_UP(16, 9)
         case 1612: SPECMG_EIG_UP(16, 12)
         case 1613: SPECMG_EIG_UP(16, 13)
         default: break;
@@ -1016,6 +1018,8 @@ void launch_eig_up(const CoarseGeom& lo, const CoarseGeom& up, const double* Ain
         case 12: SPECMG_EIG_UP(12, 0)
         case 14: SPECMG_EIG_UP(14, 0)
         case 16: SPECMG_EIG_UP(16, 0)
+        case 20: SPECMG_EIG_UP(20, 0)
+        case 26: SPECMG_EIG_UP(26, 0)
         default: break;
     }
 #undef SPECMG_EIG_UP

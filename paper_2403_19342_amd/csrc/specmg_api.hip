@@ -330,10 +330,12 @@ void run_vcycle(specmg_ctx* c, double* r, double* z, const double* q, int pre_mo
 
 int nvec_for(int target) {
     // block size: eigenvalues through index target+3 are needed by the
-    // cluster rule, plus two guard vectors; even sizes 10/12/14 are built
+    // cluster rule, plus two guard vectors; even sizes 10 ... 16 are built,
+    // and 20 and 26 for the wide coarse-coarse counts (targets 11 ... 20)
     int m = target + 6;
     if (m % 2) ++m;
     if (m < 10) m = 10;
+    if (m > 16) m = m <= 20 ? 20 : 26;
     return m;
 }
 
@@ -730,7 +732,7 @@ extern "C" int specmg_setup_alloc(const double* perm_dev, int32_t perm_component
     if (opts->warm_start == SPECMG_WS_CNN && (opts->eigs_per_subdomain & 1))
         return fail(SPECMG_EINVAL, "warm_start CNN needs an even eigs_per_subdomain");
     const int tcc = opts->eigs_coarse > 0 ? opts->eigs_coarse : opts->eigs_per_subdomain;
-    if (opts->eigs_coarse < 0 || tcc > 10) return fail(SPECMG_EINVAL, "eigs_coarse must be in [0, 10]");
+    if (opts->eigs_coarse < 0 || tcc > 20) return fail(SPECMG_EINVAL, "eigs_coarse must be in [0, 20]");
     if (G.agg == 4 && opts->levels >= 4 && tcc > 9)
         return fail(SPECMG_EINVAL, "agg 4 with four or more levels needs eigs_coarse <= 9");
     if (!(opts->eig_threshold_coarse >= 0.0) || !std::isfinite(opts->eig_threshold_coarse))

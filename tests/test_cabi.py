@@ -40,7 +40,7 @@ def test_binding_covers_header():
     ("sub", 4, -1), ("agg", 3, -1), ("nx", 36, -1), ("levels", 1, -1), ("eigs_per_subdomain", 0, -1),
     ("eigs_per_subdomain", 9, -1), ("nu", 3, -1), ("nu", 0, -1), ("nu_c", 3, -1), ("nu_c", -1, -1), ("precision", 7, -1), ("hy", 0.0, -1),
     ("hz", -1.0, -1), ("hx", float("nan"), -1), ("hy", float("inf"), -1),
-    ("eigs_coarse", 11, -1), ("eigs_coarse", -1, -1), ("eig_threshold_coarse", -1.0, -1),
+    ("eigs_coarse", 21, -1), ("eigs_coarse", -1, -1), ("eig_threshold_coarse", -1.0, -1),
     ("eig_threshold_coarse", float("inf"), -1), ("eig_threshold", -1.0, -1), ("eig_threshold", float("nan"), -1),
 ])
 def test_setup_rejects_bad_arguments(field, value, code):

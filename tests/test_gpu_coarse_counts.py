@@ -7,6 +7,13 @@ eigenvalues 1e-11 absolute, P^{-1} r max(1e-10, 1e-15 / lambda_min+(A_L))
 relative, PCG iterations within +-1 and the solution within 1e-8.  Each
 threshold lies at least 1e-2 (relative) away from every eigenvalue of the
 oracle, so that both sides count the same eigenvalues below it.
+
+The wide cases take the coarse-coarse count to the paper's 11, 17 and 20
+candidates (Section 5.2 and the second approach of Section 5.3, where
+B_cc = 1e12 falls back to the first strategy with L_cc = 20): a coarsest
+level of width 20 and, on 64^3 with four levels, a non-coarsest level of
+width 23 (the wide smoother, restriction and prolongation) above a coarsest
+eigensolve on 184-row local problems.
 """
 import numpy as np
 import pytest
@@ -18,35 +25,45 @@ from tests.gpu_util import to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # (name, kind, seed, levels, eigs, agg, eigs_coarse, threshold B_cc, threshold B_c)
-    ("gauss32_l3_cc8", "gauss", 1, 3, 4, 2, 8, 0.0, 0.0),
-    ("incl32_l4_thr", "inclusions", 3, 4, 6, 2, 10, 1e-3, 0.0),
-    ("chan32_l3_thr", "channels", 2, 3, 6, 4, 9, 1e-3, 0.0),
+    # (name, kind, n, seed, levels, eigs, agg, eigs_coarse, threshold B_cc, threshold B_c)
+    ("gauss32_l3_cc8", "gauss", 32, 1, 3, 4, 2, 8, 0.0, 0.0),
+    ("incl32_l4_thr", "inclusions", 32, 3, 4, 6, 2, 10, 1e-3, 0.0),
+    ("chan32_l3_thr", "channels", 32, 2, 3, 6, 4, 9, 1e-3, 0.0),
     # B_c: one to three of 8 candidates on the inclusion elements, one to four
     # of 6 on the channel elements
-    ("incl32_l3_bc", "inclusions", 3, 3, 8, 2, 0, 0.0, 0.03),
-    ("chan32_l2_bc", "channels", 2, 2, 6, 2, 0, 0.0, 0.03),
+    ("incl32_l3_bc", "inclusions", 32, 3, 3, 8, 2, 0, 0.0, 0.03),
+    ("chan32_l2_bc", "channels", 32, 2, 2, 6, 2, 0, 0.0, 0.03),
+    # wide coarse-coarse counts (Sections 5.2 and 5.3)
+    ("gauss32_l3_cc11", "gauss", 32, 1, 3, 6, 2, 11, 0.0, 0.0),
+    ("chan32_l3_cc17", "channels", 32, 2, 3, 6, 2, 17, 0.0, 0.0),
+    ("incl64_l4_cc20", "inclusions", 64, 3, 4, 6, 2, 20, 0.0, 0.0),
+    ("incl64_l4_bcc1e12", "inclusions", 64, 3, 4, 6, 2, 20, 1e12, 0.0),
 ]
+_cache = {}
 
 
-def _both(kind, seed, levels, eigs, agg, cc, thr, thr_c):
+def _both(kind, n, seed, levels, eigs, agg, cc, thr, thr_c):
     from paper_2403_19342_amd.specmg import SpecMG
-    perm = make_field(kind, 32, seed)
-    g = Grid.unit_cube(32)
-    hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1, target_cc=cc or None,
-                           threshold_cc=thr, threshold_c=thr_c)
-    for l, t in [(l, thr) for l in range(3, levels + 1)] + [(2, thr_c)]:
-        if t > 0:
-            for lam in hier.level(l).lam:
-                assert np.min(np.abs(np.asarray(lam) - t)) > 1e-2 * t, "threshold too close to an eigenvalue"
+    key = (kind, n, seed, levels, eigs, agg, cc, thr, thr_c)
+    if key not in _cache:
+        perm = make_field(kind, n, seed)
+        g = Grid.unit_cube(n)
+        hier = build_hierarchy(perm, g, levels, eigs, sub=8, agg=agg, workers=1 if n <= 32 else 8,
+                               target_cc=cc or None, threshold_cc=thr, threshold_c=thr_c)
+        for l, t in [(l, thr) for l in range(3, levels + 1)] + [(2, thr_c)]:
+            if 0 < t < 1e6:
+                for lam in hier.level(l).lam:
+                    assert np.min(np.abs(np.asarray(lam) - t)) > 1e-2 * t, "threshold too close to an eigenvalue"
+        _cache[key] = (perm, g, hier)
+    perm, g, hier = _cache[key]
     ctx = SpecMG(to_dev(perm), levels=levels, eigs_per_subdomain=eigs, agg=agg, eigs_coarse=cc,
                  eig_threshold_coarse=thr, eig_threshold=thr_c)
     return perm, g, hier, ctx
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
-def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
+@pytest.mark.parametrize("name,kind,n,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_counts_and_spectra(name, kind, n, seed, levels, eigs, agg, cc, thr, thr_c):
+    perm, g, hier, ctx = _both(kind, n, seed, levels, eigs, agg, cc, thr, thr_c)
     widths = ctx.info()["widths"]
     assert widths[1] == eigs + 3 and all(w == (cc or eigs) + 3 for w in widths[2:])
     for l in range(2, levels + 1):
@@ -58,10 +75,10 @@ def test_counts_and_spectra(name, kind, seed, levels, eigs, agg, cc, thr, thr_c)
         assert worst < 1e-11
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
-def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
+@pytest.mark.parametrize("name,kind,n,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_apply_precond(name, kind, n, seed, levels, eigs, agg, cc, thr, thr_c):
     import torch
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
+    perm, g, hier, ctx = _both(kind, n, seed, levels, eigs, agg, cc, thr, thr_c)
     pre = Preconditioner(hier)
     wL = np.linalg.eigvalsh(hier.level(levels).A.toarray())
     tol = max(1e-10, 1e-15 / wL[1])
@@ -78,10 +95,10 @@ def test_apply_precond(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
         assert err < tol
 
 
-@pytest.mark.parametrize("name,kind,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
-def test_pcg(name, kind, seed, levels, eigs, agg, cc, thr, thr_c):
+@pytest.mark.parametrize("name,kind,n,seed,levels,eigs,agg,cc,thr,thr_c", CASES)
+def test_pcg(name, kind, n, seed, levels, eigs, agg, cc, thr, thr_c):
     import torch
-    perm, g, hier, ctx = _both(kind, seed, levels, eigs, agg, cc, thr, thr_c)
+    perm, g, hier, ctx = _both(kind, n, seed, levels, eigs, agg, cc, thr, thr_c)
     b = make_source("corner", perm.shape).reshape(-1)
     ref = pcg(hier.A, b, Preconditioner(hier).apply, tol=1e-6)
     x = torch.empty(g.n, dtype=torch.float64, device="cuda")
