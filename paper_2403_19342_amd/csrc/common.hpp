@@ -233,6 +233,7 @@ struct CoarseGeom {
     int L;                 // padded per-element width (target + 3)
     int agg;               // children per axis of a parent (level l+1)
     int px, py, pz, M;     // parents per axis / total (0 if l is the coarsest)
+    const int* nkeep = nullptr;   // kept slots per element (device); rows beyond are zero
 };
 
 // ---------------------------------------------------------------------------

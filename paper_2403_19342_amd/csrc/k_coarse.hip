@@ -164,10 +164,13 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
         nb[d] = (agg == 4 ? kCP.rank4[pn] : kCP.rank2[pn]) * LP;
         wgt[d] = in ? T(1) : T(0);
     }
+    // slots beyond the child's kept count are zero rows of every block: their
+    // threads load nothing and carry zeros
+    const bool live = row_ok && (g.nkeep == nullptr || a < g.nkeep[c]);
     // right-hand side t = r (- A_l u): all loads of the row first
     const size_t row = (size_t)c * LP + a;
-    T tv = r[row];
-    if (mode) {
+    T tv = live ? r[row] : T(0);
+    if (mode && live) {
         const int cx = c % g.mx, cy = (c / g.mx) % g.my, cz = c / (g.mx * g.my);
         T acc = T(0);
 #pragma unroll
@@ -203,16 +206,16 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     T gl[3][LP], gu[3][LP], dv[LP];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const bool in = wgt[2 * ax] != T(0);
+        const bool in = live && wgt[2 * ax] != T(0);
 #pragma unroll
         for (int b = 0; b < LP; ++b) gl[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] : T(0);
     }
 #pragma unroll
-    for (int b = 0; b < LP; ++b) dv[b] = Dinv[row * LP + b];
+    for (int b = 0; b < LP; ++b) dv[b] = live ? Dinv[row * LP + b] : T(0);
     if (kUpperEarly) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const bool in = wgt[2 * ax + 1] != T(0);
+            const bool in = live && wgt[2 * ax + 1] != T(0);
 #pragma unroll
             for (int b = 0; b < LP; ++b)
                 gu[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] : T(0);
@@ -246,7 +249,7 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     if (!kUpperEarly) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const bool in = wgt[2 * ax + 1] != T(0);
+            const bool in = live && wgt[2 * ax + 1] != T(0);
 #pragma unroll
             for (int b = 0; b < LP; ++b)
                 gu[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax + 1) * LP + a) * LP + b] : T(0);
@@ -284,7 +287,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_resid_restrict(
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int p = t / L, a = t % L;
         const int c = child_of(g, E, p);
-        sS[t] = r[(size_t)c * L + a] - block_row_apply<T, LP>(g, Ad, Aoff, u, c, a);
+        const bool live = g.nkeep == nullptr || a < g.nkeep[c];   // zero rows beyond the kept slots
+        sS[t] = live ? r[(size_t)c * L + a] - block_row_apply<T, LP>(g, Ad, Aoff, u, c, a) : T(0);
     }
     __syncthreads();
     const int nk = nkeep_up[E];

@@ -458,6 +458,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         lv.g.L = L;
         const int m = lv.g.m;
         lv.nkeep = c->alloc<int>(m);
+        lv.g.nkeep = lv.nkeep;
         lv.status = c->alloc<int>(m);
         lv.lam = c->alloc<double>((size_t)m * L);
         lv.basis = c->alloc<double>((size_t)m * L * 512);
@@ -515,6 +516,7 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
         lo.g.M = up.g.m;
         const int m = up.g.m;
         up.nkeep = c->alloc<int>(m);
+        up.g.nkeep = up.nkeep;
         up.status = c->alloc<int>(m);
         up.lam = c->alloc<double>((size_t)m * Lu);
         up.basis = c->alloc<double>((size_t)m * Lu * up.rows);
