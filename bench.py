@@ -59,9 +59,12 @@ def parse():
                     help="B_cc > 0: keep the coarse-coarse eigenvalues below it (strategy 2), at most L_cc")
     ap.add_argument("--eig-threshold", type=float, default=0.0,
                     help="B_c > 0: keep the level-2 eigenvalues below it (strategy 2), at most L_c")
-    ap.add_argument("--forms", default="",
+    ap.add_argument("--forms", default="fp32_vcycle,fp32_store,learned,learned+fp32_vcycle",
                     help="comma-separated extra forms timed once each after the bench steps and reported "
-                         "under 'forms': fp32_vcycle, fp32_basis, fp32_store, learned (CNN warm start)")
+                         "under 'forms': fp32_vcycle, fp32_basis, fp32_store, learned (CNN warm start), "
+                         "learned+<precision>; empty for none")
+    ap.add_argument("--ws-tol", type=float, default=1e-4,
+                    help="relative residual the learned warm start's local eigensolves accept")
     ap.add_argument("--allow-unconverged", action="store_true",
                     help="report a value even when local eigensolves hit their cycle cap")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -147,7 +150,7 @@ def main():
         ctx = SpecMG(perm, levels=levels, eigs_per_subdomain=wl.eigs, agg=agg, precision=precision_,
                      eigs_coarse=wl.eigs_coarse, eig_threshold_coarse=args.eig_threshold_coarse,
                      eig_threshold=args.eig_threshold, nu=args.nu, nu_c=args.nu_c, allow_unconverged=True,
-                     cnn_weights=cnn)
+                     cnn_weights=cnn, ws_resid_tol=args.ws_tol)
         unconv = ctx.info()["setup"]["eig_unconverged"]
         if unconv and not args.allow_unconverged:
             ctx.close()
@@ -277,6 +280,10 @@ def main():
             xf = torch.zeros_like(x)
             cnn = None
             pf = precision
+            if f.startswith("learned") and not os.path.exists(
+                    os.path.join(ROOT, "paper_2403_19342_amd", "weights", f"cnn_k{wl.eigs}_bf16.npy")):
+                log(f"bench: form {f} skipped (no trained network for {wl.eigs} eigenvectors)")
+                continue
             if f == "learned":
                 wpath = os.path.join(ROOT, "paper_2403_19342_amd", "weights", f"cnn_k{wl.eigs}_bf16.npy")
                 cnn = torch.as_tensor(np.load(wpath).astype(np.int16), device=dev)
