@@ -79,17 +79,17 @@ __device__ __forceinline__ void jac_rot(const double* H, int M, int p, int q, do
 
 // Symmetric eigendecomposition H = Q diag(th) Q^T, eigenvalues ascending,
 // by parallel cyclic Jacobi in wavefront 0: each round applies M/2 disjoint
-// rotations at once; every lane derives the rotations of the rows and
-// columns of its own elements, so a round costs one read phase and one
-// write phase.  Stops when the largest off-diagonal entry is below
-// 1e-15 times the largest diagonal entry.  H (M*M) is destroyed; Q (M*M)
+// rotations at once; lanes 0..M-1 derive the round's rotations (scr holds
+// the cosines and sines), then every lane applies them to its own elements:
+// a round is one rotation phase, one read phase and one write phase.  Stops
+// when the largest off-diagonal entry is below 1e-15 times the largest
+// diagonal entry.  H (M*M) is destroyed; Q (M*M)
 // receives the eigenvectors as columns.  Must be called by all threads.
 template <int M>
 __device__ __forceinline__ void jacobi_eig(double* H, double* Q, double* th, double* scr, int* iscr) {
     static_assert(M % 2 == 0 && M <= 26, "Jacobi block size");
     constexpr int MM = M * M;
     constexpr int PER = (MM + 63) / 64;
-    (void)scr;
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         int ei[PER], ej[PER];
@@ -117,6 +117,16 @@ __device__ __forceinline__ void jacobi_eig(double* H, double* Q, double* th, dou
             if (off <= 1e-15 * dg || off == 0.0) break;
 #pragma unroll 1
             for (int r = 0; r < M - 1; ++r) {
+                // the round's M/2 rotations, once each: lane i < M stores the
+                // rotation of its pair (both members hold the same one)
+                if (lane < M) {
+                    const int pl = jac_partner<M>(lane, r);
+                    double cl, sl;
+                    jac_rot(H, M, lane < pl ? lane : pl, lane < pl ? pl : lane, cl, sl);
+                    scr[lane] = cl;
+                    scr[M + lane] = sl;
+                }
+                wave_sync();
                 double nh[PER], nq[PER];
 #pragma unroll
                 for (int u = 0; u < PER; ++u) {
@@ -124,9 +134,7 @@ __device__ __forceinline__ void jacobi_eig(double* H, double* Q, double* th, dou
                     const int pi = jac_partner<M>(i, r), pj = jac_partner<M>(j, r);
                     const int ai = i < pi ? i : pi, bi = i < pi ? pi : i;
                     const int aj = j < pj ? j : pj, bj = j < pj ? pj : j;
-                    double ci, si, cj, sj;
-                    jac_rot(H, M, ai, bi, ci, si);
-                    jac_rot(H, M, aj, bj, cj, sj);
+                    const double ci = scr[i], si = scr[M + i], cj = scr[j], sj = scr[M + j];
                     const double wra = (i == ai) ? ci : si, wrb = (i == ai) ? -si : ci;
                     const double wca = (j == aj) ? cj : sj, wcb = (j == aj) ? -sj : cj;
                     nh[u] = wra * (wca * H[ai * M + aj] + wcb * H[ai * M + bj]) +
