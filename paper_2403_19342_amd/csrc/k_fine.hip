@@ -227,16 +227,30 @@ __device__ __forceinline__ void store_pencil(float* p, double (&v)[8], int jk) {
         q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
 }
 
+// Lane shifts by one in y.  DP: DPP row shifts inside the 16-lane rows
+// (row_shr:1 / row_shl:1), lane l receives lane l - 1 (l + 1) on the vector
+// ALU; otherwise bpermute through the LDS crossbar.  The lanes whose partner
+// lies outside a DPP row or the wavefront are lanes j = 0 (j = 7) of a pencil
+// row, the element's y faces, which the callers mask or replace.  DPP reads
+// a source lane that is off in EXEC as out of range: call these on every
+// lane, never inside a branch.
+template <bool DP, typename T>
+__device__ __forceinline__ T lane_prev(T v) {
+    if constexpr (DP) return dpp_move<0x111>(v);
+    else return __shfl_up(v, 1, 64);
+}
+template <bool DP, typename T>
+__device__ __forceinline__ T lane_next(T v) {
+    if constexpr (DP) return dpp_move<0x101>(v);
+    else return __shfl_down(v, 1, 64);
+}
+
 // value of the same cell in lanes -+1 (y) and -+8 (z); lanes at the edge of
-// the wavefront get their own value, which the callers mask
-template <typename T>
-__device__ __forceinline__ T from_ym(const T (&v)[8], int r) { return __shfl_up(v[(r + 7) & 7], 1, 64); }
-template <typename T>
-__device__ __forceinline__ T from_yp(const T (&v)[8], int r) { return __shfl_down(v[(r + 1) & 7], 1, 64); }
+// the wavefront or of a DPP row get other values, which the callers mask
+template <bool DP, typename T>
+__device__ __forceinline__ T from_ym(const T (&v)[8], int r) { return lane_prev<DP>(v[(r + 7) & 7]); }
 template <typename T>
 __device__ __forceinline__ T from_zm(const T (&v)[8], int r) { return __shfl_up(v[(r + 7) & 7], 8, 64); }
-template <typename T>
-__device__ __forceinline__ T from_zp(const T (&v)[8], int r) { return __shfl_down(v[(r + 1) & 7], 8, 64); }
 
 // Forward and backward IC(0) substitution of the wavefront's element.
 // y: in t, out (D+L^T)^{-1} D (D+L)^{-1} t.  ix: inverse pivots; fx, fy, fz:
@@ -245,7 +259,7 @@ __device__ __forceinline__ T from_zp(const T (&v)[8], int r) { return __shfl_dow
 // with the neighbour's value; its plus face in x is fx of the next slot.
 // Faces that leave the element are dropped here: in y and z by the lane's
 // position, in x at the pencil's ends.
-template <typename T>
+template <bool DP, typename T>
 __device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (&fx)[8], const T (&fy)[8],
                                           const T (&fz)[8], int j, int k) {
     const int jk = j + k;
@@ -255,7 +269,7 @@ __device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (
 #pragma unroll
     for (int s = 0; s < kPlanes; ++s) {
         const int r = s & 7, rp = (s + 7) & 7;
-        const T ny = __shfl_up(cur, 1, 64);
+        const T ny = lane_prev<DP>(cur);
         const T nz = __shfl_up(cur, 8, 64);
         const T xm = s - jk > 0 ? y[rp] : T(0);
         T acc = y[r];
@@ -271,9 +285,9 @@ __device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (
 #pragma unroll
     for (int s = kPlanes - 1; s >= 0; --s) {
         const int r = s & 7, rn = (s + 1) & 7;
-        const T ny = __shfl_down(cur, 1, 64);
+        const T ny = lane_next<DP>(cur);
         const T nz = __shfl_down(cur, 8, 64);
-        const T gy = __shfl_down(fy[rn], 1, 64) * wyp;
+        const T gy = lane_next<DP>(fy[rn]) * wyp;
         const T gz = __shfl_down(fz[rn], 8, 64) * wzp;
         const T xp = s - jk < 7 ? y[rn] : T(0);
         T acc = fx[rn] * xp;
@@ -288,13 +302,13 @@ __device__ __forceinline__ void ic_pencil(T (&y)[8], const T (&ix)[8], const T (
 
 // Minus-face transmissibilities of the pencil's cells inside the element
 // (the neighbour's copy of kappa~ comes from the lane below).
-template <typename T>
+template <bool DP, typename T>
 __device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8], T (&fy)[8], T (&fz)[8], T cy,
                                              T cz) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         fx[r] = harm(kc[r], kc[(r + 7) & 7]);
-        fy[r] = harm(kc[r], from_ym(kc, r)) * cy;
+        fy[r] = harm(kc[r], from_ym<DP>(kc, r)) * cy;
         fz[r] = harm(kc[r], from_zm(kc, r)) * cz;
     }
     (void)jk;
@@ -302,19 +316,19 @@ __device__ __forceinline__ void pencil_faces(const T (&kc)[8], int jk, T (&fx)[8
 
 // The same from three kappa~ pencils (orthotropic K): each axis's faces take
 // the harmonic mean of its own component.
-template <typename T>
+template <bool DP, typename T>
 __device__ __forceinline__ void pencil_faces3(const T (&kx)[8], const T (&ky)[8], const T (&kz)[8], T (&fx)[8],
                                               T (&fy)[8], T (&fz)[8]) {
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         fx[r] = harm(kx[r], kx[(r + 7) & 7]);
-        fy[r] = harm(ky[r], from_ym(ky, r));
+        fy[r] = harm(ky[r], from_ym<DP>(ky, r));
         fz[r] = harm(kz[r], from_zm(kz, r));
     }
 }
 
 // minus-face transmissibilities of the lane's pencil (rotated slot order)
-template <bool O, typename T, typename C>
+template <bool O, bool DP, typename T, typename C>
 __device__ __forceinline__ void load_faces(const FineGeom& g, const T* __restrict__ kt, size_t row, int jk,
                                            C (&fx)[8], C (&fy)[8], C (&fz)[8]) {
     C kc[8];
@@ -324,9 +338,9 @@ __device__ __forceinline__ void load_faces(const FineGeom& g, const T* __restric
         C ky[8], kz[8];
         load_pencil(kt + N + row, ky, jk);
         load_pencil(kt + 2 * N + row, kz, jk);
-        pencil_faces3(kc, ky, kz, fx, fy, fz);
+        pencil_faces3<DP>(kc, ky, kz, fx, fy, fz);
     } else {
-        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
+        pencil_faces<DP>(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
     }
 }
 
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     // phases in order, each one's registers released before the next
     // (faces first, then the residual update, then the pivots)
     C fx[8], fy[8], fz[8];
-    load_faces<O>(g, kt, row, jk, fx, fy, fz);
+    load_faces<O, false>(g, kt, row, jk, fx, fy, fz);
     __builtin_amdgcn_sched_barrier(0);
     C y[8];
     double rr = 0.0;
@@ -374,7 +388,7 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
     __builtin_amdgcn_sched_barrier(0);
     C ix[8];
     load_pencil(invd + row, ix, jk);
-    ic_pencil(y, ix, fx, fy, fz, j, k);
+    ic_pencil<false>(y, ix, fx, fy, fz, j, k);
     store_pencil(u + row, y, jk);
     if (mode & 1) {
         double v[1] = {block_sum(rr, sred)};
@@ -499,8 +513,11 @@ __device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __res
 // K; ky, kz its y and z components), um, km and up, kp u and kappa~ of the
 // cells before and after the pencil in x (used when xlo, xhi: inside the
 // domain), fu, fk the staged y and z face cells (stage_faces_yz).  y and z
-// neighbours inside the element come from the lanes -+1 and -+8.
-template <bool O, typename C>
+// neighbours inside the element come from the lanes -+1 and -+8: through the
+// LDS crossbar (bpermute), or with DY the y neighbours by DPP row shifts,
+// which take VALU issue slots and registers instead (the better trade where
+// the crossbar also carries an IC(0) sweep).
+template <bool O, bool DY, typename C>
 __device__ __forceinline__ void pencil_apply(const FineGeom& g, int lane, int j, int k, const C (&uc)[8],
                                              const C (&kc)[8], const C (&ky)[8], const C (&kz)[8], C um, C km,
                                              C up, C kp, bool xlo, bool xhi, const C* fu, const C* fk,
@@ -515,10 +532,39 @@ __device__ __forceinline__ void pencil_apply(const FineGeom& g, int lane, int j,
     if (xlo) s[0] -= harm(kc[0], km) * (uc[0] - um);
     if (xhi) s[7] -= harm(kc[7], kp) * (uc[7] - up);
     __builtin_amdgcn_sched_barrier(0);
-    // y and z faces, one direction at a time: -y, +y, -z, +z (orthotropic:
-    // the y and z faces take the y and z arrays, own pencil included)
+    if constexpr (DY) {
+        // -y, +y: the face lanes (j = 0, j = 7) take the staged cells.  The
+        // shifts run on every lane before the select: a DPP source lane that
+        // is switched off in EXEC reads as out of range, so a shift inside
+        // the branch would zero the neighbours of lanes j = 1 and j = 6.
+        const C cf = (C)g.cy;
+        const int fo0 = 8 * k, fo1 = 64 + 8 * k;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const C ko = O ? ky[x] : kc[x];
+            const C pu = lane_prev<true>(uc[x]), pk = lane_prev<true>(ko);
+            const C nu = j == 0 ? fu[fo0 + x] : pu;
+            const C nk = j == 0 ? fk[fo0 + x] : pk;
+            s[x] -= harm(ko, nk) * cf * (uc[x] - nu);
+            if (x % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const C ko = O ? ky[x] : kc[x];
+            const C pu = lane_next<true>(uc[x]), pk = lane_next<true>(ko);
+            const C nu = j == 7 ? fu[fo1 + x] : pu;
+            const C nk = j == 7 ? fk[fo1 + x] : pk;
+            s[x] -= harm(ko, nk) * cf * (uc[x] - nu);
+            if (x % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // the remaining faces one direction at a time (-y, +y,) -z, +z
+    // (orthotropic: the y and z faces take the y and z arrays, own pencil
+    // included)
 #pragma unroll 1
-    for (int d = 0; d < 4; ++d) {
+    for (int d = DY ? 2 : 0; d < 4; ++d) {
         const int src = (lane + (d == 0 ? -1 : (d == 1 ? 1 : (d == 2 ? -8 : 8)))) & 63;
         const bool mem = d == 0 ? j == 0 : (d == 1 ? j == 7 : (d == 2 ? k == 0 : k == 7));
         const int fo = d * 64 + 8 * (d < 2 ? k : j);
@@ -540,7 +586,7 @@ __device__ __forceinline__ void pencil_apply(const FineGeom& g, int lane, int j,
 // row's u and kappa~ (kappa~_x for orthotropic K) are returned in uc, kc.
 // Every load (the row, the pencil ends in x, the staged faces) is issued
 // before the arithmetic, so a wavefront waits for memory once.
-template <bool O, typename T, typename C>
+template <bool O, bool DY, typename T, typename C>
 __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __restrict__ kt, const T* __restrict__ u,
                                                 size_t row, int x0, int y0, int z0, int lane, int j, int k,
                                                 C* fu, C* fk, C (&s)[8], C (&uc)[8], C (&kc)[8]) {
@@ -558,7 +604,7 @@ __device__ __forceinline__ void pencil_residual(const FineGeom& g, const T* __re
     const C um = xlo ? (C)u[im] : C(0), km = xlo ? (C)kt[im] : C(0);
     const C up = xhi ? (C)u[ip] : C(0), kp = xhi ? (C)kt[ip] : C(0);
     stage_faces_yz<O>(g, kt, [&](size_t i) { return u[i]; }, x0, y0, z0, lane, fu, fk);
-    pencil_apply<O>(g, lane, j, k, uc, kc, ky, kz, um, km, up, kp, xlo, xhi, fu, fk, s);
+    pencil_apply<O, DY>(g, lane, j, k, uc, kc, ky, kz, um, km, up, kp, xlo, xhi, fu, fk, s);
 }
 
 // T: stored word of kappa~ and u; TB: stored word of the basis; C: the
@@ -592,7 +638,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
             s[2 * i + 1] = (C)d.y;
         }
         C uc[8], kc[8];
-        pencil_residual<O>(g, kt, u, row, x0, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
+        pencil_residual<O, false>(g, kt, u, row, x0, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
     }
     // restriction onto the element's kept basis vectors
     const int nkp = nkeep[e];
@@ -681,7 +727,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
             srr[w][x * 64 + lane] = rv[x];
         }
     }
-    pencil_residual<O>(g, kt, u, row, ex0, y0, z0, lane, j, k, sa[w], sa[w] + 256, s, uc, kc);
+    pencil_residual<O, true>(g, kt, u, row, ex0, y0, z0, lane, j, k, sa[w], sa[w] + 256, s, uc, kc);
     wave_lds_sync();
 #pragma unroll
     for (int x = 0; x < 8; ++x) sa[w][x * 64 + lane] = uc[x];
@@ -689,15 +735,15 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
     // faces and pivots of the IC(0) sweep in slot order
     C fx[8], fy[8], fz[8];
     if constexpr (O) {
-        load_faces<true>(g, kt, row, jk, fx, fy, fz);
+        load_faces<true, true>(g, kt, row, jk, fx, fy, fz);
     } else {
         rotate_slots(kc, jk, false);
-        pencil_faces(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
+        pencil_faces<true>(kc, jk, fx, fy, fz, (C)g.cy, (C)g.cz);
     }
     C ix[8];
     load_pencil(invd + row, ix, jk);
     rotate_slots(s, jk, false);
-    ic_pencil(s, ix, fx, fy, fz, j, k);
+    ic_pencil<true>(s, ix, fx, fy, fz, j, k);
     rotate_slots(s, jk, true);
     __builtin_amdgcn_sched_barrier(0);
     double rz = 0.0, zq = 0.0;
@@ -766,7 +812,7 @@ __global__ __launch_bounds__(256) void k_spmv_pcg(FineGeom g, const double* __re
         double s[8], pc[8], kc[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.0;
-        pencil_residual<O>(g, kt, p, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, pc, kc);
+        pencil_residual<O, false>(g, kt, p, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, pc, kc);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             s[i] = -s[i];
@@ -799,7 +845,7 @@ __global__ __launch_bounds__(256) void k_apply_A(FineGeom g, const double* __res
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.0;
     }
-    pencil_residual<O>(g, kt, xv, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
+    pencil_residual<O, false>(g, kt, xv, row, ex * 8, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
     if (!resid) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = -s[i];
