@@ -4,14 +4,15 @@ nu, nu_c in {1, 2}; a repeated sweep is u += M^-1 (f - A u)).
 
 PCG parity as for one sweep: iterations within +-1 and zero-mean solutions
 within 1e-8 relative L2, on three levels (so both the fine and a coarse
-smoother repeat).  The FP32 V-cycle with two fine sweeps converges within
+smoother repeat).  Flexible GMRES with two sweeps on both levels matches
+the oracle's flexible GMRES to the same bar (steps and restarts +-1).  The FP32 V-cycle with two fine sweeps converges within
 10 % + 1 of the FP64 count, and the preconditioner with two sweeps stays
 symmetric (1e-9) and positive.
 """
 import numpy as np
 import pytest
 
-from oracle import Grid, Preconditioner, build_hierarchy, pcg
+from oracle import Grid, Preconditioner, build_hierarchy, fgmres, pcg
 from synth.fields import make_field, make_source, random_zero_mean
 from tests.gpu_util import to_dev, to_host
 
@@ -45,6 +46,27 @@ def test_pcg_matches_oracle(problem, nu, nu_c):
     assert abs(info.iters - ref.iters) <= 1
     assert err <= 1e-8
     ctx.close()
+
+
+def test_gmres_two_sweeps_matches_oracle(problem):
+    import torch
+    from paper_2403_19342_amd.specmg import SpecMG
+    perm, g, hier, b = problem
+    restart = 12
+    ref = fgmres(hier.A, b, Preconditioner(hier, nu=2, nu_c=2).apply, tol=1e-6, restart=restart)
+    ctx = SpecMG(to_dev(perm), levels=3, eigs_per_subdomain=4, agg=2, nu=2, nu_c=2)
+    x = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    rc, info = ctx.gmres_solve(to_dev(b), x, restart=restart, tol=1e-6)
+    ctx.close()
+    xg = to_host(x)
+    err = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"GMRES, (nu, nu_c) = (2, 2): steps gpu {info.iters} oracle {ref.iters}, restarts gpu "
+          f"{info.replacements} oracle {ref.restarts}, rel err {err:.2e}")
+    assert rc == 0 and info.converged and ref.converged
+    assert abs(info.iters - ref.iters) <= 1
+    assert abs(info.replacements - ref.restarts) <= 1
+    assert info.rel_resid_true <= 1e-6
+    assert err <= 1e-8
 
 
 def test_two_sweeps_symmetric_and_fp32(problem):
