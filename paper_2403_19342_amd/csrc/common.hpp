@@ -218,13 +218,16 @@ struct FineGeom {
 
 // Element order of the fine-level arrays the library keeps (kappa~, the
 // IC(0) pivots, every vector of the solve): the 512 cells of each 8^3
-// level-2 element are contiguous, x fastest inside the element, and the
-// elements follow each other x fastest.  A wavefront's x-pencils of one
-// element are then one 4 KB block.  Arrays the caller passes (permeability,
-// sources, solutions, fluxes) keep the natural order x + nx (y + ny z).
+// level-2 element are one contiguous 4 KB block, and the elements follow
+// each other x fastest.  Inside the block cell (x, j, k) sits at phi_pos(c),
+// c = x + 8 (j + 8 k), the layout of the level-2 basis columns: the x-pencil
+// of row (j, k) is four pairs 128 words apart, so when lane j + 8 k loads
+// pair i of its pencil, the wavefront reads one contiguous 1 KB block.
+// Arrays the caller passes (permeability, sources, solutions, fluxes) keep
+// the natural order x + nx (y + ny z).
 __host__ __device__ inline size_t eidx(const FineGeom& g, int x, int y, int z) {
     const size_t e = (size_t)(x >> 3) + (size_t)g.mx * ((size_t)(y >> 3) + (size_t)g.my * (size_t)(z >> 3));
-    return e * 512 + (size_t)((x & 7) + 8 * ((y & 7) + 8 * (z & 7)));
+    return e * 512 + (size_t)phi_pos((x & 7) + 8 * ((y & 7) + 8 * (z & 7)));
 }
 
 // Coarse level l >= 2: elements on an (mx,my,mz) grid, padded width L.

@@ -168,63 +168,49 @@ __device__ __forceinline__ void rotate_slots(T (&v)[8], int jk, bool inverse) {
     }
 }
 
-// v[slot] = p[pencil cell of slot], p points at cell (0, j, k)
-__device__ __forceinline__ void load_pencil(const double* __restrict__ p, double (&v)[8], int jk) {
-    const double2* q = reinterpret_cast<const double2*>(p);
+// Pencil access in element order: the cells x = 2i, 2i + 1 of lane (j, k)'s
+// x-pencil are the pair at p + kPair i, p the lane's cell (0, j, k), so the
+// wavefront's load of pair i reads one contiguous block (see eidx).  Stored
+// word T, values C (conversions on the way).
+constexpr int kPair = 128;
+
+template <typename T, typename C>
+__device__ __forceinline__ void load8(const T* __restrict__ p, C (&v)[8]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const double2 d = q[i];
-        v[2 * i] = d.x;
-        v[2 * i + 1] = d.y;
+        if constexpr (sizeof(T) == 8) {
+            const double2 d = *reinterpret_cast<const double2*>(p + kPair * i);
+            v[2 * i] = (C)d.x;
+            v[2 * i + 1] = (C)d.y;
+        } else {
+            const float2 d = *reinterpret_cast<const float2*>(p + kPair * i);
+            v[2 * i] = (C)d.x;
+            v[2 * i + 1] = (C)d.y;
+        }
     }
-    rotate_slots(v, jk, false);
 }
-__device__ __forceinline__ void load_pencil(const float* __restrict__ p, float (&v)[8], int jk) {
-    const float4* q = reinterpret_cast<const float4*>(p);
+template <typename T, typename C>
+__device__ __forceinline__ void store8(T* p, const C (&v)[8]) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float4 d = q[i];
-        v[4 * i] = d.x;
-        v[4 * i + 1] = d.y;
-        v[4 * i + 2] = d.z;
-        v[4 * i + 3] = d.w;
+    for (int i = 0; i < 4; ++i) {
+        if constexpr (sizeof(T) == 8)
+            *reinterpret_cast<double2*>(p + kPair * i) = make_double2((double)v[2 * i], (double)v[2 * i + 1]);
+        else
+            *reinterpret_cast<float2*>(p + kPair * i) = make_float2((float)v[2 * i], (float)v[2 * i + 1]);
     }
+}
+
+// v[slot] = p[pencil cell of slot] (slot order of the IC(0) sweep)
+template <typename T, typename C>
+__device__ __forceinline__ void load_pencil(const T* __restrict__ p, C (&v)[8], int jk) {
+    load8(p, v);
     rotate_slots(v, jk, false);
 }
 // p[pencil cell of slot] = v[slot] (v is consumed)
-__device__ __forceinline__ void store_pencil(double* p, double (&v)[8], int jk) {
+template <typename T, typename C>
+__device__ __forceinline__ void store_pencil(T* p, C (&v)[8], int jk) {
     rotate_slots(v, jk, true);
-    double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
-}
-__device__ __forceinline__ void store_pencil(float* p, float (&v)[8], int jk) {
-    rotate_slots(v, jk, true);
-    float4* q = reinterpret_cast<float4*>(p);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) q[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
-}
-
-// Float32-stored pencils with float64 arithmetic: converted on the load
-// (before the rotation) and on the store (after it).
-__device__ __forceinline__ void load_pencil(const float* __restrict__ p, double (&v)[8], int jk) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float4 d = q[i];
-        v[4 * i] = (double)d.x;
-        v[4 * i + 1] = (double)d.y;
-        v[4 * i + 2] = (double)d.z;
-        v[4 * i + 3] = (double)d.w;
-    }
-    rotate_slots(v, jk, false);
-}
-__device__ __forceinline__ void store_pencil(float* p, double (&v)[8], int jk) {
-    rotate_slots(v, jk, true);
-    float4* q = reinterpret_cast<float4*>(p);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-        q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
+    store8(p, v);
 }
 
 // Lane shifts by one in y.  DP: DPP row shifts inside the 16-lane rows
@@ -397,48 +383,6 @@ __global__ __launch_bounds__(64 * EX) void k_pre_smooth(FineGeom g, const T* __r
 }
 
 // s = r - A u, then r2[e][j] = sum_c phi[e][j][c] s_c for every element.
-// One wavefront per 8^3 element, lane (j, k) holding the x-pencil of row
-// (j, k) in its natural order; y and z neighbours come from the lanes +-1
-// and +-8, the element's boundary pencils and pencil ends from global
-// memory (zero kappa~ outside the domain).  No LDS; the basis is read one
-// column (a contiguous 64-byte pencil per lane) at a time.
-template <typename T>
-__device__ __forceinline__ void load8(const T* __restrict__ p, T (&v)[8]);
-template <>
-__device__ __forceinline__ void load8<double>(const double* __restrict__ p, double (&v)[8]) {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const double2 d = q[i];
-        v[2 * i] = d.x;
-        v[2 * i + 1] = d.y;
-    }
-}
-template <>
-__device__ __forceinline__ void load8<float>(const float* __restrict__ p, float (&v)[8]) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float4 d = q[i];
-        v[4 * i] = d.x;
-        v[4 * i + 1] = d.y;
-        v[4 * i + 2] = d.z;
-        v[4 * i + 3] = d.w;
-    }
-}
-
-__device__ __forceinline__ void load8(const float* __restrict__ p, double (&v)[8]) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float4 d = q[i];
-        v[4 * i] = (double)d.x;
-        v[4 * i + 1] = (double)d.y;
-        v[4 * i + 2] = (double)d.z;
-        v[4 * i + 3] = (double)d.w;
-    }
-}
-
 // The lane's 8 values of one basis column (phi_pos layout): pair i at
 // col + 128 i + 2 lane, so each load instruction reads one contiguous block.
 template <typename TB, typename C>
@@ -457,34 +401,13 @@ __device__ __forceinline__ void load_col(const TB* __restrict__ col, int lane, C
     }
 }
 
-// the lane's pencil (8 contiguous values of word T) from arithmetic values C
-template <typename T, typename C>
-__device__ __forceinline__ void store8c(T* p, const C (&v)[8]) {
-    if constexpr (sizeof(T) == 8) {
-        double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] = make_double2((double)v[2 * i], (double)v[2 * i + 1]);
-    } else {
-        float4* q = reinterpret_cast<float4*>(p);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-            q[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
-    }
-}
-
-// 8 contiguous float64 values (the lane's pencil) with 16-byte stores
-__device__ __forceinline__ void store8(double* p, const double (&v)[8]) {
-    double2* q = reinterpret_cast<double2*>(p);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) q[i] = make_double2(v[2 * i], v[2 * i + 1]);
-}
 
 // The cells beyond the element's four y and z faces (-y, +y, -z, +z): the
 // vector value val(i) (i an element-order index) and kappa~ (the face's own
 // component for orthotropic K), zero outside the domain.  All 64 lanes load
-// them together, one cell per face and array (lane = (x, row) of the face,
-// 64-byte rows), and stage them in the wavefront's LDS area fu[4][64],
-// fk[4][64] for the lanes on those faces.
+// them together, one cell per face and array (lane = (x, row) of the face),
+// and stage them in the wavefront's LDS area fu[4][64], fk[4][64] for the
+// lanes on those faces.
 template <bool O, typename T, typename C, typename VF>
 __device__ __forceinline__ void stage_faces_yz(const FineGeom& g, const T* __restrict__ kt, VF val, int x0, int y0,
                                                int z0, int lane, C* fu, C* fk) {
@@ -627,16 +550,10 @@ __global__ __launch_bounds__(256) void k_resid_restrict(FineGeom g, const T* __r
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int j = lane & 7, k = lane >> 3;
     const int x0 = ex * 8;
-    const size_t row = (size_t)e * kSub3 + 8 * lane;
+    const size_t row = (size_t)e * kSub3 + 2 * lane;   // cell (0, j, k)
     C s[8];
     {
-        const double2* q = reinterpret_cast<const double2*>(r + row);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const double2 d = q[i];
-            s[2 * i] = (C)d.x;
-            s[2 * i + 1] = (C)d.y;
-        }
+        load8(r + row, s);
         C uc[8], kc[8];
         pencil_residual<O, false>(g, kt, u, row, x0, ey * 8, ez * 8, lane, j, k, sfu[w], sfk[w], s, uc, kc);
     }
@@ -679,7 +596,7 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
     const int nk = nkeep[e];
     const TB* ph = phi + (size_t)e * L * kSub3;
     const C* ee = e2 + (size_t)e * L;
-    const size_t row = (size_t)e * kSub3 + 8 * lane;
+    const size_t row = (size_t)e * kSub3 + 2 * lane;   // cell (0, j, k)
     C uc[8];
     load8(u + row, uc);
 #pragma unroll
@@ -693,7 +610,7 @@ __global__ __launch_bounds__(256) void k_prolong(FineGeom g, T* u, const TB* __r
         }
         if (jj % 4 == 3) __builtin_amdgcn_sched_barrier(0);
     }
-    store8c(u + row, uc);
+    store8(u + row, uc);
 }
 
 // Post-smoothing with its residual (Algorithm 1 step 9): t = r - A u on
@@ -759,9 +676,7 @@ __global__ __launch_bounds__(64 * EX) void k_post_fused(FineGeom g, const T* __r
             if (flex) zq += zv[x] * qv[x];
         }
     }
-    double2* zo = reinterpret_cast<double2*>(z + row);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) zo[i] = make_double2(zv[2 * i], zv[2 * i + 1]);
+    store8(z + row, zv);
     if (mode & 1) {
         double v[2] = {block_sum(rz, sred), block_sum(zq, sred)};
         write_partials<2>(v, rb);
@@ -808,7 +723,7 @@ __global__ __launch_bounds__(256) void k_spmv_pcg(FineGeom g, const double* __re
     if (e < g.mx * g.my * g.mz) {   // whole wavefront; the block sum below is reached by all
         const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
         const int j = lane & 7, k = lane >> 3;
-        const size_t row = (size_t)e * kSub3 + 8 * lane;
+        const size_t row = (size_t)e * kSub3 + 2 * lane;   // cell (0, j, k)
         double s[8], pc[8], kc[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) s[i] = 0.0;
@@ -837,7 +752,7 @@ __global__ __launch_bounds__(256) void k_apply_A(FineGeom g, const double* __res
     if (e >= g.mx * g.my * g.mz) return;   // whole wavefront; no block barriers
     const int ex = e % g.mx, ey = (e / g.mx) % g.my, ez = e / (g.mx * g.my);
     const int j = lane & 7, k = lane >> 3;
-    const size_t row = (size_t)e * kSub3 + 8 * lane;
+    const size_t row = (size_t)e * kSub3 + 2 * lane;   // cell (0, j, k)
     double s[8], uc[8], kc[8];
     if (resid) {
         load8(b + row, s);
