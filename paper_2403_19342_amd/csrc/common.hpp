@@ -99,7 +99,14 @@ struct Scalars {
 // one arrival counter per reduction site.
 struct RedBuf {
     double* partial;      // [kMaxRedBlocks * 2]
+    double* partial2;     // [kFinBlocks * 2]: block sums of the finalize's first stage
+    unsigned* ticket;     // finalize blocks done so far; zero between launches
 };
+// the finalize: kFinThreads threads per block, kFinPer partials per thread
+constexpr int kFinThreads = 256;
+constexpr int kFinPer = 8;
+constexpr int kFinSpan = kFinThreads * kFinPer;
+constexpr int kFinBlocks = kMaxRedBlocks / kFinSpan;
 
 void launch_finalize(int site, int nblocks, Scalars* sc, RedBuf rb, double* out, int check_done,
                      hipStream_t s);

@@ -519,19 +519,39 @@ __global__ __launch_bounds__(64 * kSymWaves) void k_coarsest_sym(int nT, const i
     }
 }
 
+// One workgroup per output tile I: kSymRedGroups groups of kSymT threads
+// split the tile's partial vectors (group q takes the chunks c = q mod G and
+// the tiles K = I + 1 + q mod G, four loads in flight), then the group sums
+// are added in group order, so the result does not depend on timing.
+constexpr int kSymRedGroups = 8;
+
 template <typename T>
-__global__ __launch_bounds__(kSymT) void k_coarsest_sym_reduce(int nT, int n, const double* __restrict__ P,
-                                                               const double* __restrict__ Q, int maxc,
-                                                               const int* __restrict__ cmap, T* __restrict__ e,
-                                                               const Scalars* sc, int check_done) {
+__global__ __launch_bounds__(kSymT * kSymRedGroups) void k_coarsest_sym_reduce(
+    int nT, int n, const double* __restrict__ P, const double* __restrict__ Q, int maxc,
+    const int* __restrict__ cmap, T* __restrict__ e, const Scalars* sc, int check_done) {
     if (check_done && sc->done) return;
-    const int I = blockIdx.x, i = threadIdx.x;
+    __shared__ double part[kSymRedGroups][kSymT];
+    constexpr int G = kSymRedGroups;
+    const int I = blockIdx.x, i = threadIdx.x % kSymT, q = threadIdx.x / kSymT;
     const int nc = (I + kSymChunk) / kSymChunk;   // chunks of tile row I (I + 1 tiles)
     double v = 0.0;
-    for (int c = 0; c < nc; ++c) v += Q[((size_t)I * maxc + c) * kSymT + i];
-    for (int K = I + 1; K < nT; ++K) v += P[((size_t)I * nT + K) * kSymT + i];
+    for (int c = q; c < nc; c += G) v += Q[((size_t)I * maxc + c) * kSymT + i];
+    const double* pr = P + (size_t)I * nT * kSymT + i;
+    int K = I + 1 + q;
+    for (; K + 3 * G < nT; K += 4 * G) {
+        const double a0 = pr[(size_t)K * kSymT], a1 = pr[(size_t)(K + G) * kSymT];
+        const double a2 = pr[(size_t)(K + 2 * G) * kSymT], a3 = pr[(size_t)(K + 3 * G) * kSymT];
+        v += (a0 + a1) + (a2 + a3);
+    }
+    for (; K < nT; K += G) v += pr[(size_t)K * kSymT];
+    part[q][i] = v;
+    __syncthreads();
+    if (q != 0) return;
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) t += part[g][i];
     const int row = I * kSymT + i;
-    if (row < n) e[cmap[row]] = (T)v;
+    if (row < n) e[cmap[row]] = (T)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -992,7 +1012,7 @@ void launch_coarsest_sym(int n, int np, const double* packed, const int2* chunks
                        r, rc, sc, check_done);
     SPECMG_TIMED_LAUNCH(k_coarsest_sym, dim3(nchunks), dim3(64 * kSymWaves), 0, s, nT, chunks, packed, rc, P, Q,
                         maxc, sc, check_done);
-    hipLaunchKernelGGL((k_coarsest_sym_reduce<double>), dim3(nT), dim3(kSymT), 0, s, nT, n, P, Q, maxc, cmap, e, sc,
+    hipLaunchKernelGGL((k_coarsest_sym_reduce<double>), dim3(nT), dim3(kSymT * kSymRedGroups), 0, s, nT, n, P, Q, maxc, cmap, e, sc,
                        check_done);
 }
 

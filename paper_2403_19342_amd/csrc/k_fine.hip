@@ -894,40 +894,50 @@ __global__ __launch_bounds__(256) void k_sum_abs(const double* __restrict__ a, i
     write_partials<2>(v, rb);
 }
 
-// Sums the block partials of one reduction in block order and applies the
-// CG scalar update of the reduction site.
-// one 1024-thread block sums the block partials in a fixed order (16 loads in
-// flight per thread: a 65,536-partial sum is four rounds)
-constexpr int kFinThreads = 1024;
-
+// Sums the block partials of one reduction and applies the CG scalar update
+// of the reduction site.  Two stages in one launch: block b sums partials
+// [b kFinSpan, (b + 1) kFinSpan) (all its loads in flight at once) and
+// publishes the sum; the block that arrives last (an agent-scope ticket,
+// reset by that block) adds the block sums in block order.  Every sum runs
+// in a fixed order, so the result does not depend on timing.
 __global__ __launch_bounds__(kFinThreads) void k_finalize(int site, int nb, Scalars* sc, RedBuf rb, double* out,
                                                           int check_done) {
     if (check_done && sc->done) return;
-    __shared__ double sh[2][kFinThreads / 64];
+    __shared__ double sred[kFinThreads / 64];
+    __shared__ int last;
     const int nv = (site == RS_RZ || site == RS_GEN2) ? 2 : 1;
+    const int b0 = blockIdx.x * kFinSpan, lim = min(kFinSpan, nb - b0);
     double t[2] = {0.0, 0.0};
     for (int k = 0; k < nv; ++k) {
-        const double* pk = rb.partial + (size_t)k * kMaxRedBlocks;
-        double a[16];
-        for (int base = 0; base < nb; base += kFinThreads * 16) {
+        const double* pk = rb.partial + (size_t)k * kMaxRedBlocks + b0;
+        double a[kFinPer];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int i = base + u * kFinThreads + threadIdx.x;
-                a[u] = i < nb ? pk[i] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 16; ++u) t[k] += a[u];
+        for (int u = 0; u < kFinPer; ++u) {
+            const int i = u * kFinThreads + threadIdx.x;
+            a[u] = i < lim ? pk[i] : 0.0;
         }
-        t[k] = wave_sum(t[k]);
-        if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = t[k];
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < kFinPer; ++u) v += a[u];
+        t[k] = block_sum(v, sred);
+    }
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nv; ++k)
+            __hip_atomic_store(rb.partial2 + k * kFinBlocks + blockIdx.x, t[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(rb.ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int k = 0; k < nv; ++k) {
-        double v = 0.0;
-        for (int w = 0; w < kFinThreads / 64; ++w) v += sh[k][w];
-        t[k] = v;
+        const double v = threadIdx.x < gridDim.x ? atomic_load_relaxed(rb.partial2 + k * kFinBlocks + threadIdx.x)
+                                                 : 0.0;
+        t[k] = block_sum(v, sred);
     }
+    if (threadIdx.x != 0) return;
+    __hip_atomic_store(rb.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (site == RS_PQ) {
         sc->pq = t[0];
         sc->iter += 1;
@@ -959,7 +969,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int site, int nb, Scal
 
 void launch_finalize(int site, int nblocks, Scalars* sc, RedBuf rb, double* out, int check_done,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, site, nblocks, sc, rb, out, check_done);
+    const int nfb = nblocks > 0 ? (nblocks + kFinSpan - 1) / kFinSpan : 1;
+    hipLaunchKernelGGL(k_finalize, dim3(nfb), dim3(kFinThreads), 0, s, site, nblocks, sc, rb, out, check_done);
 }
 
 __global__ void k_axpy_x(double* x, const double* __restrict__ p0, const double* __restrict__ p1,

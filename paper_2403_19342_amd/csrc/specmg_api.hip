@@ -668,6 +668,9 @@ static int do_setup(specmg_ctx* c, const double* perm, hipStream_t s) {
     c->sc = c->alloc<Scalars>(1);
     HIPCHK(hipHostMalloc((void**)&c->sc_host, sizeof(Scalars), hipHostMallocDefault));
     c->rb.partial = c->alloc<double>((size_t)2 * kMaxRedBlocks);
+    c->rb.partial2 = c->alloc<double>((size_t)2 * kFinBlocks);
+    c->rb.ticket = c->alloc<unsigned>(1);
+    HIPCHK(hipMemsetAsync(c->rb.ticket, 0, sizeof(unsigned), s));
     launch_pcg_init(c->sc, 0.0, 0, s);
     HIPCHK(hipMemcpyAsync(flags, c->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
