@@ -74,8 +74,12 @@ __device__ void build_planes(int agg, int* pos, int* off) {
 constexpr int kMaxLc = 23;   // padded widths up to target 20 + 3 (levels >= 3)
 constexpr int kNarrow = 13;  // widths up to target 10 + 3 get their own instantiations
 
-// y_c = (A_l u)_c for row a of child element c; all block-row loads of the
-// thread are issued before the products
+// y_c = (A_l u)_c for row a of child element c.  Blocks up to 9 wide: the
+// diagonal block, then one axis at a time both coupling blocks, every load
+// of an axis issued before its products (at the domain boundary from valid
+// stand-in rows of the element itself, whose sums a select then drops), so
+// a row waits for memory four times.  Wider blocks (register budget): the
+// diagonal block, then each coupling block inside the domain in turn.
 template <typename T, int LP = kMaxLc>
 __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __restrict__ Ad,
                                              const T* __restrict__ Aoff, const T* __restrict__ u, int c,
@@ -95,26 +99,51 @@ __device__ __forceinline__ T block_row_apply(const CoarseGeom& g, const T* __res
             acc += (b < L ? ad[bb] : T(0)) * uc[bb];
         }
     }
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        if (cc[ax] + 1 < ext[ax]) {
-            const int cn = c + stride[ax];
-            const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
-            const T* un = u + (size_t)cn * L;
+    if constexpr (LP <= 9) {
+#pragma unroll 1
+        for (int ax = 0; ax < 3; ++ax) {
+            const int cca = ax == 0 ? cx : (ax == 1 ? cy : cz);
+            const int exa = ax == 0 ? g.mx : (ax == 1 ? g.my : g.mz);
+            const int sta = ax == 0 ? 1 : (ax == 1 ? g.mx : g.mx * g.my);
+            const bool hp = cca + 1 < exa, hm = cca > 0;
+            const int cp = hp ? c + sta : c, cm = hm ? c - sta : c;
+            // A(c, c+e) = Aoff[c][ax]; A(c, c-e) = Aoff[c-e][ax]^T
+            const T* op = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
+            const T* om = Aoff + ((size_t)cm * 3 + ax) * L * L + a;
+            const T* up = u + (size_t)cp * L;
+            const T* um = u + (size_t)cm * L;
+            T sp = T(0), sm = T(0);
 #pragma unroll
             for (int b = 0; b < LP; ++b) {
                 const int bb = b < L ? b : L - 1;
-                acc += (b < L ? o[bb] : T(0)) * un[bb];
+                sp += (b < L ? op[bb] : T(0)) * up[bb];
+                sm += (b < L ? om[(size_t)bb * L] : T(0)) * um[bb];
             }
+            acc += hp ? sp : T(0);
+            acc += hm ? sm : T(0);
         }
-        if (cc[ax] > 0) {
-            const int cn = c - stride[ax];
-            const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
-            const T* un = u + (size_t)cn * L;
+    } else {
 #pragma unroll
-            for (int b = 0; b < LP; ++b) {
-                const int bb = b < L ? b : L - 1;
-                acc += (b < L ? o[bb * L + a] : T(0)) * un[bb];
+        for (int ax = 0; ax < 3; ++ax) {
+            if (cc[ax] + 1 < ext[ax]) {
+                const int cn = c + stride[ax];
+                const T* o = Aoff + (((size_t)c * 3 + ax) * L + a) * L;
+                const T* un = u + (size_t)cn * L;
+#pragma unroll
+                for (int b = 0; b < LP; ++b) {
+                    const int bb = b < L ? b : L - 1;
+                    acc += (b < L ? o[bb] : T(0)) * un[bb];
+                }
+            }
+            if (cc[ax] > 0) {
+                const int cn = c - stride[ax];
+                const T* o = Aoff + ((size_t)cn * 3 + ax) * L * L;
+                const T* un = u + (size_t)cn * L;
+#pragma unroll
+                for (int b = 0; b < LP; ++b) {
+                    const int bb = b < L ? b : L - 1;
+                    acc += (b < L ? o[bb * L + a] : T(0)) * un[bb];
+                }
             }
         }
     }
@@ -135,7 +164,7 @@ constexpr int kMaxL2 = 16;         // level 2 (target <= 10)
 // the rows of its lower and upper couplings G in registers; only y lives in
 // LDS.  A plane step is one LDS read per coupling entry, the products, a store
 // and a barrier.  Missing neighbours read the thread's own child with weight 0.
-template <typename T, int LP>
+template <typename T, int LP, bool A2>
 __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, const T* __restrict__ Ad,
                                                       const T* __restrict__ Aoff, const T* __restrict__ Dinv,
                                                       const T* __restrict__ G, const T* __restrict__ r,
@@ -200,15 +229,20 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     // while the block synchronises; at widths up to 8 the upper rows too
     // (one memory round less), wider ones follow the forward sweep so that
     // the two sets are never live together
-    constexpr bool kUpperEarly = LP <= 8;
+    // A2 (agg = 2): along each axis a child couples to exactly one sibling,
+    // below or above it, so gl[ax] holds that one coupling row, all loaded
+    // here, and the sweeps weight it by direction (gu unused)
+    constexpr bool kUpperEarly = LP <= 8 && !A2;
     // couplings to children outside the parent are never loaded (with
     // agg = 2 half of them)
     T gl[3][LP], gu[3][LP], dv[LP];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const bool in = live && wgt[2 * ax] != T(0);
+        const bool lo = wgt[2 * ax] != T(0);
+        const bool in = live && (A2 || lo);
+        const int d = (A2 && !lo) ? 2 * ax + 1 : 2 * ax;
 #pragma unroll
-        for (int b = 0; b < LP; ++b) gl[ax][b] = in ? G[(((size_t)c * 6 + 2 * ax) * LP + a) * LP + b] : T(0);
+        for (int b = 0; b < LP; ++b) gl[ax][b] = in ? G[(((size_t)c * 6 + d) * LP + a) * LP + b] : T(0);
     }
 #pragma unroll
     for (int b = 0; b < LP; ++b) dv[b] = live ? Dinv[row * LP + b] : T(0);
@@ -240,13 +274,18 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
                 s1 += gl[1][b] * sY[nb[2] + b];
                 s2 += gl[2][b] * sY[nb[4] + b];
             }
+            if (A2) {
+                s0 *= wgt[0];
+                s1 *= wgt[2];
+                s2 *= wgt[4];
+            }
             y = w - (s0 + s1 + s2);
             sY[t] = y;
         }
         __syncthreads();
     }
     // backward: z = y - sum_upper G z
-    if (!kUpperEarly) {
+    if (!kUpperEarly && !A2) {
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const bool in = live && wgt[2 * ax + 1] != T(0);
@@ -259,11 +298,23 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     for (int s = nplanes - 1; s >= 0; --s) {
         if (row_ok && plane == s) {
             T s0 = T(0), s1 = T(0), s2 = T(0);
+            if constexpr (A2) {
 #pragma unroll
-            for (int b = 0; b < LP; ++b) {
-                s0 += gu[0][b] * sY[nb[1] + b];
-                s1 += gu[1][b] * sY[nb[3] + b];
-                s2 += gu[2][b] * sY[nb[5] + b];
+                for (int b = 0; b < LP; ++b) {
+                    s0 += gl[0][b] * sY[nb[1] + b];
+                    s1 += gl[1][b] * sY[nb[3] + b];
+                    s2 += gl[2][b] * sY[nb[5] + b];
+                }
+                s0 *= wgt[1];
+                s1 *= wgt[3];
+                s2 *= wgt[5];
+            } else {
+#pragma unroll
+                for (int b = 0; b < LP; ++b) {
+                    s0 += gu[0][b] * sY[nb[1] + b];
+                    s1 += gu[1][b] * sY[nb[3] + b];
+                    s2 += gu[2][b] * sY[nb[5] + b];
+                }
             }
             z = y - (s0 + s1 + s2);
             sY[t] = z;
@@ -968,9 +1019,15 @@ template <typename T>
 void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const T* r, T* u, const Scalars* sc,
                           int check_done, hipStream_t s) {
     if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
-    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
-                                               0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
-                                               (const T*)nullptr, u, sc, check_done));
+    if (g.agg == 2) {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(g.M), dim3(sweep_threads(g)), 0,
+                                                   s, g, 0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
+                                                   (const T*)nullptr, u, sc, check_done));
+    } else {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(g.M), dim3(sweep_threads(g)), 0,
+                                                   s, g, 0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
+                                                   (const T*)nullptr, u, sc, check_done));
+    }
 }
 
 // e = u + M_l^{-1} (r - A_l u)
@@ -978,8 +1035,13 @@ template <typename T>
 void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv, const T* Aoff, const T* G,
                                 const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
     if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
-    SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP>), dim3(g.M), dim3(sweep_threads(g)), 0, s, g,
-                                               1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+    if (g.agg == 2) {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(g.M), dim3(sweep_threads(g)), 0,
+                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+    } else {
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(g.M), dim3(sweep_threads(g)), 0,
+                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+    }
 }
 
 int coarsest_sym_tile() { return kSymT; }
