@@ -47,8 +47,20 @@ constexpr int kMaxCols = 12;   // padded basis width (target <= 8, plus 3)
 template <typename T>
 __device__ __forceinline__ T harm(T a, T b) {
     // harmonic mean 2ab/(a+b); zero when a neighbour is outside the domain
+    // (a + b = 0).  1/(a+b) by Newton's iteration r <- r (2 - s r) from the
+    // hardware reciprocal: two steps in float64, one in float32; no branch
     const T s = a + b;
-    return s > T(0) ? (T(2) * a * b) / s : T(0);
+    T r;
+    if constexpr (sizeof(T) == 8) {
+        r = __builtin_amdgcn_rcp(s);
+        r = fma(fma(-s, r, 1.0), r, r);
+        r = fma(fma(-s, r, 1.0), r, r);
+    } else {
+        r = __builtin_amdgcn_rcpf(s);
+        r = fmaf(fmaf(-s, r, 1.0f), r, r);
+    }
+    const T v = (T(2) * a * b) * r;
+    return s > T(0) ? v : T(0);
 }
 
 // LDS layouts use odd row pitches so that cells of one hyperplane spread
