@@ -168,15 +168,20 @@ template <typename T, int LP, bool A2>
 __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, const T* __restrict__ Ad,
                                                       const T* __restrict__ Aoff, const T* __restrict__ Dinv,
                                                       const T* __restrict__ G, const T* __restrict__ r,
-                                                      const T* u, T* out, const Scalars* sc, int check_done) {
+                                                      const T* u, T* out, const Scalars* sc, int check_done,
+                                                      int npar) {
     if (check_done && sc->done) return;
     __shared__ T sY[kMaxChildren * LP];
-    const int E = blockIdx.x;
     const int agg = g.agg, nc = agg * agg * agg, sh = log2_agg(agg);
     const int nplanes = 3 * (agg - 1) + 1;
-    const int t = threadIdx.x;
-    const bool row_ok = t < nc * LP;
-    const int k = row_ok ? t / LP : 0, a = t % LP;
+    // npar parents per workgroup (several when a parent has few rows, so
+    // that the wavefronts are full), each with its own nc * LP rows of sY
+    const int per = nc * LP;
+    const int t = threadIdx.x, qp = t / per, tt = t - qp * per;
+    const int E = blockIdx.x * npar + qp;
+    const bool row_ok = qp < npar && E < g.M;
+    const int base = row_ok ? qp * per : 0;
+    const int k = row_ok ? tt / LP : 0, a = tt % LP;
     const int p = agg == 4 ? kCP.pos4[k] : kCP.pos2[k];
     const int q[3] = {p & (agg - 1), (p >> sh) & (agg - 1), p >> (2 * sh)};
     const int plane = q[0] + q[1] + q[2];
@@ -190,7 +195,7 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
         const bool in = (d & 1) ? (q[ax] < agg - 1) : (q[ax] > 0);
         const int step = 1 << (sh * ax);
         const int pn = in ? ((d & 1) ? p + step : p - step) : p;
-        nb[d] = (agg == 4 ? kCP.rank4[pn] : kCP.rank2[pn]) * LP;
+        nb[d] = base + (agg == 4 ? kCP.rank4[pn] : kCP.rank2[pn]) * LP;
         wgt[d] = in ? T(1) : T(0);
     }
     // slots beyond the child's kept count are zero rows of every block: their
@@ -258,7 +263,7 @@ __global__ __launch_bounds__(768) void k_coarse_sweep(CoarseGeom g, int mode, co
     __syncthreads();
     T w = T(0);
     {
-        const T* ty = sY + k * LP;
+        const T* ty = sY + base + k * LP;
 #pragma unroll
         for (int b = 0; b < LP; ++b) w += dv[b] * ty[b];
     }
@@ -1009,9 +1014,21 @@ void launch_coarse_prolong(const CoarseGeom& g, T* u, const T* V, const int* nke
 }
 
 // dynamic LDS of the sweep kernels; couplings are staged when they fit
-static int sweep_threads(const CoarseGeom& g) {
+// parents per sweep workgroup: with 2x aggregation as many as fill about
+// 512 threads (a parent has 8 L rows), otherwise one
+static int sweep_parents(const CoarseGeom& g) {
     const int rows = g.agg * g.agg * g.agg * g.L;
+    if (g.agg != 2) return 1;
+    const int p = 512 / rows;
+    return p < 1 ? 1 : (p > kMaxChildren / 8 ? kMaxChildren / 8 : p);
+}
+static int sweep_threads(const CoarseGeom& g) {
+    const int rows = sweep_parents(g) * g.agg * g.agg * g.agg * g.L;
     return (rows + 63) / 64 * 64;
+}
+static int sweep_blocks(const CoarseGeom& g) {
+    const int np = sweep_parents(g);
+    return (g.M + np - 1) / np;
 }
 
 // u = M_l^{-1} r
@@ -1020,13 +1037,13 @@ void launch_coarse_smooth(const CoarseGeom& g, const T* Dinv, const T* G, const 
                           int check_done, hipStream_t s) {
     if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
     if (g.agg == 2) {
-        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(g.M), dim3(sweep_threads(g)), 0,
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(sweep_blocks(g)), dim3(sweep_threads(g)), 0,
                                                    s, g, 0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
-                                                   (const T*)nullptr, u, sc, check_done));
+                                                   (const T*)nullptr, u, sc, check_done, sweep_parents(g)));
     } else {
-        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(g.M), dim3(sweep_threads(g)), 0,
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(sweep_blocks(g)), dim3(sweep_threads(g)), 0,
                                                    s, g, 0, (const T*)nullptr, (const T*)nullptr, Dinv, G, r,
-                                                   (const T*)nullptr, u, sc, check_done));
+                                                   (const T*)nullptr, u, sc, check_done, sweep_parents(g)));
     }
 }
 
@@ -1036,11 +1053,11 @@ void launch_coarse_resid_smooth(const CoarseGeom& g, const T* Ad, const T* Dinv,
                                 const T* r, const T* u, T* e, const Scalars* sc, int check_done, hipStream_t s) {
     if (g.L < 4 || g.L > kMaxLc || sweep_threads(g) > 768) throw HipError{hipErrorInvalidValue, "coarse sweep shape"};
     if (g.agg == 2) {
-        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(g.M), dim3(sweep_threads(g)), 0,
-                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, true>), dim3(sweep_blocks(g)), dim3(sweep_threads(g)), 0,
+                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done, sweep_parents(g)));
     } else {
-        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(g.M), dim3(sweep_threads(g)), 0,
-                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done));
+        SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_sweep<T, LP, false>), dim3(sweep_blocks(g)), dim3(sweep_threads(g)), 0,
+                                                   s, g, 1, Ad, Aoff, Dinv, G, r, u, e, sc, check_done, sweep_parents(g)));
     }
 }
 
