@@ -191,9 +191,9 @@ __device__ __forceinline__ double atomic_load_relaxed(const double* p) {
 }
 
 // Grid-wide reductions: every block writes its NV block sums to
-// partial[k * kMaxRedBlocks + block] (no atomics: a shared arrival counter
-// serialises thousands of same-address atomics); a one-block finalize kernel
-// launched right after sums them in block order, so results are reproducible.
+// partial[k * kMaxRedBlocks + block] (no floating-point atomics); the
+// finalize kernel launched right after sums them in a fixed order (ranges
+// of partials, then the range sums), so results are reproducible.
 template <int NV>
 __device__ __forceinline__ void write_partials(const double (&v)[NV], RedBuf rb) {
     if (threadIdx.x == 0) {
