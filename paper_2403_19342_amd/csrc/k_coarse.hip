@@ -982,6 +982,54 @@ __global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_
         default: { constexpr int LP = kMaxLc; __VA_ARGS__; } break; \
     }
 
+// The same for 2x aggregation: one wavefront per parent.  Its lanes take
+// the kept rows of the 8 children in turn (row q of the parent is slot a of
+// child position p, q = the kept rows of the positions before p, plus a),
+// 64 rows per pass, so the dead padded slots take no lanes; the restriction
+// sums are wavefront reductions, with no LDS and no block barrier.
+template <typename T, int LP, int LU>
+__global__ __launch_bounds__(256) void k_coarse_resid_restrict_w(
+    CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Aoff, const T* __restrict__ r,
+    const T* __restrict__ u, const T* __restrict__ V, const int* __restrict__ nkeep_up, int Lup,
+    T* __restrict__ rup, const Scalars* sc, int check_done) {
+    if (check_done && sc->done) return;
+    const int lane = threadIdx.x & 63;
+    const int E = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (E >= g.M) return;   // whole wavefront; no block barriers below
+    const int L = g.L, n = 8 * L;
+    int pre[9];
+    pre[0] = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) pre[q + 1] = pre[q] + (g.nkeep ? g.nkeep[child_of(g, E, q)] : L);
+    const int rows = pre[8];
+    const int nk = nkeep_up[E];
+    double acc[LU];
+#pragma unroll
+    for (int j = 0; j < LU; ++j) acc[j] = 0.0;
+    for (int q0 = 0; q0 < rows; q0 += 64) {
+        const int qr = q0 + lane;
+        if (qr < rows) {
+            int p = 0;
+#pragma unroll
+            for (int q = 1; q < 8; ++q) p += qr >= pre[q] ? 1 : 0;
+            const int a = qr - pre[p];
+            const int c = child_of(g, E, p);
+            const double sv = (double)(r[(size_t)c * L + a] - block_row_apply<T, LP>(g, Ad, Aoff, u, c, a));
+            const T* vc = V + (size_t)E * Lup * n + (size_t)p * L + a;
+#pragma unroll
+            for (int j = 0; j < LU; ++j)
+                if (j < nk) acc[j] += (double)vc[(size_t)j * n] * sv;
+        }
+    }
+    double mine = 0.0;
+#pragma unroll
+    for (int j = 0; j < LU; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == j) mine = v;
+    }
+    if (lane < Lup) rup[(size_t)E * Lup + lane] = lane < nk ? (T)mine : T(0);
+}
+
 template <typename T>
 void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aoff, const T* r, const T* u,
                                   const T* V, const int* nkeep_up, int Lup, T* rup, const Scalars* sc,
@@ -990,7 +1038,18 @@ void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aof
     const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
     if (g.L < 4 || g.L > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual width"};
     if (Lup > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual upper width"};
-    if (Lup <= kNarrow) {
+    if (g.agg == 2) {
+        const int nb = (g.M + 3) / 4;
+        if (Lup <= kNarrow) {
+            SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict_w<T, LP, kNarrow>), dim3(nb),
+                                                       dim3(256), 0, s, g, Ad, Aoff, r, u, V, nkeep_up, Lup, rup, sc,
+                                                       check_done));
+        } else {
+            SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict_w<T, LP, kMaxLc>), dim3(nb),
+                                                       dim3(256), 0, s, g, Ad, Aoff, r, u, V, nkeep_up, Lup, rup, sc,
+                                                       check_done));
+        }
+    } else if (Lup <= kNarrow) {
         SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict<T, LP, kNarrow>), dim3(g.M), dim3(th), 0,
                                                    s, g, Ad, Aoff, r, u, V, nkeep_up, Lup, rup, sc, check_done));
     } else {
