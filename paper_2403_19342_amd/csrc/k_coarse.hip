@@ -982,11 +982,12 @@ __global__ void k_convert(const S* __restrict__ src, T* __restrict__ dst, int64_
         default: { constexpr int LP = kMaxLc; __VA_ARGS__; } break; \
     }
 
-// The same for 2x aggregation: one wavefront per parent.  Its lanes take
-// the kept rows of the 8 children in turn (row q of the parent is slot a of
-// child position p, q = the kept rows of the positions before p, plus a),
-// 64 rows per pass, so the dead padded slots take no lanes; the restriction
-// sums are wavefront reductions, with no LDS and no block barrier.
+// The same for 2x aggregation and widths up to 9: one wavefront per parent.
+// Its lanes take the kept rows of the 8 children in turn (row q of the
+// parent is slot a of child position p, q = the kept rows of the positions
+// before p, plus a), 64 rows per pass, so the dead padded slots take no
+// lanes; the restriction sums are wavefront reductions, with no LDS and no
+// block barrier.
 template <typename T, int LP, int LU>
 __global__ __launch_bounds__(256) void k_coarse_resid_restrict_w(
     CoarseGeom g, const T* __restrict__ Ad, const T* __restrict__ Aoff, const T* __restrict__ r,
@@ -1038,7 +1039,9 @@ void launch_coarse_resid_restrict(const CoarseGeom& g, const T* Ad, const T* Aof
     const int th = std::min(kCoarseThreads, (rows + 63) / 64 * 64);
     if (g.L < 4 || g.L > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual width"};
     if (Lup > kMaxLc) throw HipError{hipErrorInvalidValue, "coarse residual upper width"};
-    if (g.agg == 2) {
+    // wider blocks keep about 8 L > 64 rows per parent, two passes of the
+    // wavefront: there the workgroup form is faster
+    if (g.agg == 2 && g.L <= 9) {
         const int nb = (g.M + 3) / 4;
         if (Lup <= kNarrow) {
             SPECMG_LP_DISPATCH(g.L, hipLaunchKernelGGL((k_coarse_resid_restrict_w<T, LP, kNarrow>), dim3(nb),
